@@ -1,0 +1,47 @@
+"""Named workloads: a mesh plus a problem, built from fixed seeds.
+
+* periodic_vortex    32 x 32 jittered periodic grid on [0,10]^2 (2048 cells), vortex
+* quadrant_delaunay  Poisson-disk Delaunay mesh of the unit square, four-quadrant
+                     Riemann data (rho in [0.14,1.5], p in [0.03,1.5])
+* blast_delaunay     Delaunay mesh of [-1.1,1.1]^2 with the origin as a vertex,
+                     near-vacuum blast (ambient p = 1e-10, E_total = 0.25)
+* batch_instances    n meshes with log-uniform sizes, P1/P2 split, two-state data
+"""
+
+import numpy as np
+
+from .mesh import periodic_jittered_grid, poisson_delaunay, find_vertex
+from .problems import (PROBLEM_VORTEX, PROBLEM_QUADRANT, PROBLEM_BLAST, PROBLEM_TWO_STATE,
+                       vortex_params, quadrant_riemann_params, blast_params, two_state_params)
+from .rng import Stream
+
+
+def periodic_vortex(n=32, seed=1):
+    m = periodic_jittered_grid(n=n, length=10.0, jitter=0.1, seed=seed)
+    return m, PROBLEM_VORTEX, vortex_params()
+
+
+def quadrant_delaunay(n_cells=200_000, seed=2):
+    m = poisson_delaunay(n_cells, lo=(0.0, 0.0), hi=(1.0, 1.0), seed=seed,
+                         name=f"quadrant{n_cells}")
+    return m, PROBLEM_QUADRANT, quadrant_riemann_params(seed)
+
+
+def blast_delaunay(n_cells=1_000_000, seed=3):
+    m = poisson_delaunay(n_cells, lo=(-1.1, -1.1), hi=(1.1, 1.1), seed=seed,
+                         extra_points=np.array([[0.0, 0.0]]), name=f"blast{n_cells}")
+    ov = find_vertex(m, (0.0, 0.0))
+    assert ov >= 0
+    return m, PROBLEM_BLAST, blast_params(ov)
+
+
+def batch_sizes(n_inst=64, lo=5_000, hi=500_000, seed=4):
+    st = Stream(seed * 31 + 1)
+    sizes = st.log_uniform(n_inst, lo, hi).astype(np.int64)
+    degree = np.where(st.uniform(n_inst) < 0.5, 1, 2)
+    return sizes, degree
+
+
+def batch_instance(i, size, seed=4):
+    m = poisson_delaunay(int(size), seed=seed * 1000 + i, name=f"inst{i}")
+    return m, PROBLEM_TWO_STATE, two_state_params(seed * 1000 + i)
