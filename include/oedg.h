@@ -1,0 +1,168 @@
+/*
+ * oedg.h -- C ABI of the MI355X (gfx950) BP RI-OEDG stage library.
+ *
+ * One SSP-RK3 stage of the bound-preserving, rotation-invariant
+ * oscillation-eliminating discontinuous Galerkin scheme of Ding, Cui and Wu
+ * (arXiv 2409.09620) for the 2D Euler equations on triangles, degree k = 1, 2:
+ *   - the semi-discrete DG operator with the Lax-Friedrichs flux
+ *     (eq. DGSystem:Dis, eq. fluxLF) and the SSP-RK3 combination (eq. RKTime);
+ *   - the RIOE filter (eq. oe:sys with the coefficients of eqs. oe:sysdelta2,
+ *     RIOESys:CoefM/Coef1/Coef2, OEScalar:beta/Coef2, normalised by eq. normOmg);
+ *   - the Zhang-Shu-type BP limiter at the nodes of the optimal convex
+ *     decomposition (Sec. 4.4, eqs. 1944/1981; nodes from eqs. 1040 and 1139);
+ *   - the max wave speed (eq. 1250) and the optimal BP time step
+ *     Delta t = C_SSP / alpha * min_K C^DCW_{K,k} |K| (Sec. 5, eqs. 1692, 1713).
+ *
+ * Conventions
+ *   - Every call returns a dg_status; nothing throws or aborts.  The first error
+ *     of a context is kept (dg_last_error) and later calls return it.
+ *   - A context is bound to one HIP device and one stream and is NOT thread-safe.
+ *     All device work is ordered on that stream.  Calls that return host data
+ *     (dg_readback, dg_diag, dg_step_to, dg_step with dt_out) synchronise it.
+ *   - Host arrays passed in are copied; the library never keeps host pointers.
+ *   - Modal coefficients use the layout [var rho, m1, m2, E][mode l][cell] in
+ *     float64, l = 0..L_k with L_1 = 2, L_2 = 5 and the basis of eq. basisfunc.
+ *   - Device memory: the library allocates its buffers unless the caller binds a
+ *     workspace (dg_bind_workspace) large enough for the mesh, which the caller
+ *     owns and must keep alive until dg_destroy.
+ */
+#ifndef OEDG_H
+#define OEDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_ctx dg_ctx;
+
+typedef enum {
+    DG_OK = 0,
+    DG_E_ARG = -1,     /* invalid argument (null pointer, bad size, bad flag) */
+    DG_E_MESH = -2,    /* invalid mesh (bad vertex id, zero area, an edge shared by >2 cells, no cells) */
+    DG_E_NOMEM = -3,   /* device or host allocation failed, or bound workspace too small */
+    DG_E_HIP = -4,     /* a HIP runtime call failed */
+    DG_E_BOUNDS = -5,  /* a cell average left the admissible set (rho <= 0 or rho e <= 0) */
+    DG_E_STATE = -6    /* call out of order (e.g. dg_stage before dg_init) */
+} dg_status;
+
+enum { DG_OE_RI = 0, DG_OE_CW = 1 };           /* rotation-invariant (Sec. 3.3) or component-wise (Sec. 3.2) */
+enum { DG_PREC_FP64 = 0 };
+
+typedef struct {
+    int k;             /* polynomial degree, 1 or 2 */
+    double gamma;      /* adiabatic index (1.4 in the paper's Euler tests) */
+    double c_ssp;      /* SSP coefficient of the RK3 scheme (1) */
+    int oe_enable;     /* 1: apply the OE filter after every stage */
+    int oe_mode;       /* DG_OE_RI or DG_OE_CW */
+    int bp_enable;     /* 1: apply the BP limiter after every stage and at init */
+    int precision;     /* DG_PREC_FP64 */
+} dg_config;
+
+/* Fills *cfg with the defaults: k = 2, gamma = 1.4, c_ssp = 1, OE on (RI), BP on, FP64. */
+void dg_config_default(dg_config* cfg);
+
+/* Creates a context on HIP device `hip_device`.  `hip_stream` is a hipStream_t
+ * owned by the caller (may be NULL: the null stream is used).  hip_device =
+ * DG_HOST_ONLY gives a context without a device: dg_mesh_upload builds the host
+ * tables (readable with dg_mesh_tables) and every device call returns DG_E_STATE. */
+#define DG_HOST_ONLY (-1)
+dg_status dg_create(dg_ctx** out, int hip_device, void* hip_stream);
+
+/* Device bytes the library needs for a mesh of n_cell cells at degree k. */
+dg_status dg_workspace_bytes(int32_t n_cell, int k, size_t* bytes);
+
+/* Hands the library caller-owned device memory (at least dg_workspace_bytes),
+ * used by the next dg_mesh_upload instead of its own allocation. */
+dg_status dg_bind_workspace(dg_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Uploads a mesh and builds, on the host, what the paper's notation fixes
+ * (Sec. 2 and Sec. 4.3): counter-clockwise orientation, the edge table (local
+ * edge i is opposite local vertex i and runs from vertex i+1 to vertex i+2; the
+ * neighbour across it and its local edge), per-cell geometry, the optimal
+ * convex decomposition's limiter nodes and min_K C^DCW_{K,k}|K|.
+ *   xy       host, 2*n_vert doubles (x, y per vertex)
+ *   tri      host, 3*n_cell vertex ids (any orientation)
+ *   cell_xy  host, 6*n_cell doubles or NULL: per-cell vertex coordinates used for
+ *            the geometry instead of xy[tri] (periodic meshes: unwrapped images)
+ *   edge_bc  host, 3*n_cell ints or NULL: tag of unmatched edges; only 0
+ *            (transmissive: exterior trace = interior trace) is defined
+ *   k        degree (1 or 2) the decomposition and the buffers are built for;
+ *            dg_init must be called with the same degree
+ * Errors: DG_E_ARG, DG_E_MESH (the context is then unusable), DG_E_NOMEM, DG_E_HIP. */
+dg_status dg_mesh_upload(dg_ctx* ctx, int k, int32_t n_vert, const double* xy, int32_t n_cell,
+                         const int32_t* tri, const double* cell_xy, const int32_t* edge_bc);
+
+/* Host copies of the mesh tables built by dg_mesh_upload (any pointer may be NULL):
+ * tri 3*n_cell (oriented), nbr 3*n_cell (-1 on the boundary), nbe 3*n_cell
+ * (neighbour's local edge), perm 3*n_cell (local edges by decreasing length,
+ * stable), node_ref 4*n_cell (reference coordinates (xi, eta) of the two extra
+ * limiter points: P1 the vertices opposite the two longest edges (eq. 1944),
+ * P2 the two internal nodes of eq. 1139), ck n_cell (C^DCW_{K,k}|K|), minck. */
+dg_status dg_mesh_tables(dg_ctx* ctx, int32_t* tri, int32_t* nbr, int32_t* nbe, int32_t* perm,
+                         double* node_ref, double* ck, double* minck);
+
+/* Sets the configuration and the initial state u^0 (host, modal, layout above),
+ * applies the BP limiter (no OE), computes alpha^0 and Delta t^0.  t = 0. */
+dg_status dg_init(dg_ctx* ctx, const dg_config* cfg, const double* u0_modal);
+
+/* As dg_init, with the state projected on the device from a named problem:
+ * kind 0 isentropic vortex [x0,y0,eps,rho,u,v,p]; 1 four quadrants
+ * [xc,yc,(rho,u,v,p) x 4]; 2 blast [E_total,p_amb,rho,origin_vertex]; 3 two
+ * states [px,py,nx,ny,(rho,u,v,p)_L,(rho,u,v,p)_R].  L2 projection with the
+ * 12-point rule of tab:6th; the blast sets cell averages only. */
+dg_status dg_init_problem(dg_ctx* ctx, const dg_config* cfg, int kind, const double* params,
+                          int n_params);
+
+/* One stage s = 0, 1, 2 of the current step: residual + SSP combination, the
+ * domain reductions, the OE filter, the BP limiter and the max wave speed of
+ * the result.  Stage 2 also advances t and the step count and sets the next
+ * Delta t.  No host synchronisation. */
+dg_status dg_stage(dg_ctx* ctx, int s);
+
+/* One full step (three stages).  If dt_out is not NULL the stream is
+ * synchronised and the step's Delta t is written there. */
+dg_status dg_step(dg_ctx* ctx, double* dt_out);
+
+/* Steps until t reaches t_end (the last step is shortened to land on it) or
+ * max_steps steps were taken.  Synchronises every few steps to poll. */
+dg_status dg_step_to(dg_ctx* ctx, double t_end, int64_t max_steps, int64_t* steps_done);
+
+/* Copies u^n (host, modal, layout above) and the time and step count. */
+dg_status dg_readback(dg_ctx* ctx, double* u_modal, double* t, int64_t* step);
+
+/* Copies an internal state buffer: which = 0 u^n, 1 last stage output,
+ * 2 last pre-filter state (before OE and limiter). */
+dg_status dg_read_state(dg_ctx* ctx, int which, double* u_modal);
+
+typedef struct {
+    double t, dt, alpha;          /* time, current step, LF viscosity of u^n */
+    int64_t step;
+    int64_t n_limited;            /* cell-stages where the limiter scaled modes */
+    int64_t n_bad;                /* cell averages outside the admissible set */
+    int64_t n_cfl_excursions;     /* stages whose alpha exceeded the step's alpha */
+    double ubar[4];               /* domain averages of the last pre-filter state */
+    double nrm[4];                /* ||u - ubar||_inf per variable (eq. normOmg) */
+    double nrm_m;                 /* ||| m - mbar |||_inf (vector norm) */
+    int active;                   /* 0 once t has reached the last t_end */
+} dg_diag_t;
+
+/* Diagnostics of the context (synchronises). */
+dg_status dg_diag(dg_ctx* ctx, dg_diag_t* out);
+
+/* Number of cells, degree and modes of the uploaded mesh. */
+dg_status dg_sizes(dg_ctx* ctx, int32_t* n_cell, int* k, int* n_modes);
+
+/* Last error message of the context (never NULL). */
+const char* dg_last_error(const dg_ctx* ctx);
+
+/* Frees the context and the memory the library allocated. */
+void dg_destroy(dg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OEDG_H */

@@ -51,6 +51,7 @@ def lib():
             "orc_start": (_I, [_P]),
             "orc_stage": (_I, [_P, _I]),
             "orc_step": (_I, [_P]),
+            "orc_finish_step": (_I, [_P]),
             "orc_run": (_I, [_P, _D, _L, _P]),
             "orc_get_state": (_I, [_P, _I, _P]),
             "orc_get_scalars": (_I, [_P, _P]),
@@ -154,6 +155,10 @@ class Oracle:
 
     def step(self):
         return lib().orc_step(self.h)
+
+    def finish_step(self):
+        """Bookkeeping that ends a step run stage by stage (u^n, t, alpha, Delta t)."""
+        return lib().orc_finish_step(self.h)
 
     def run(self, t_end=float("inf"), max_steps=1 << 62):
         done = ctypes.c_long(0)

@@ -807,16 +807,21 @@ int orc_stage(Orc* o, int s) {
     return o->err;
 }
 
-int orc_step(Orc* o) {
-    if (!o->active) return 1;
-    for (int s = 0; s < 3 && !o->err; ++s) orc_stage(o, s);
-    if (o->err) return o->err;
+/* end of a step: u^{n+1} becomes u^n, t advances, alpha and Delta t of the new u^n */
+int orc_finish_step(Orc* o) {
     memcpy(o->u0, o->u, sizeof(double) * (size_t)o->nc * NVAR * o->nm);
     o->t += o->dt;
     o->step += 1;
     o->alpha = max_wave_speed(o, o->u0);
     next_dt(o);
     return 0;
+}
+
+int orc_step(Orc* o) {
+    if (!o->active) return 1;
+    for (int s = 0; s < 3 && !o->err; ++s) orc_stage(o, s);
+    if (o->err) return o->err;
+    return orc_finish_step(o);
 }
 
 int orc_run(Orc* o, double t_end, long max_steps, long* done) {

@@ -1,0 +1,251 @@
+"""ctypes binding of the C ABI in include/oedg.h (argument marshalling only).
+
+Every stage step runs in the HIP library; this module never computes any part
+of the method.  If the library is not built, loading fails loudly.
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_HERE)
+_LIB = os.path.join(_HERE, "_lib", "liboedg.so")
+_HEADER = os.path.join(_ROOT, "include", "oedg.h")
+
+DG_OE_RI = 0
+DG_OE_CW = 1
+STATUS = {0: "DG_OK", -1: "DG_E_ARG", -2: "DG_E_MESH", -3: "DG_E_NOMEM", -4: "DG_E_HIP",
+          -5: "DG_E_BOUNDS", -6: "DG_E_STATE"}
+
+_lib = None
+_c_d, _c_i, _c_p = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
+_c_i32, _c_i64, _c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+
+
+class DgConfig(ctypes.Structure):
+    _fields_ = [("k", _c_i), ("gamma", _c_d), ("c_ssp", _c_d), ("oe_enable", _c_i),
+                ("oe_mode", _c_i), ("bp_enable", _c_i), ("precision", _c_i)]
+
+
+class DgDiag(ctypes.Structure):
+    _fields_ = [("t", _c_d), ("dt", _c_d), ("alpha", _c_d), ("step", _c_i64),
+                ("n_limited", _c_i64), ("n_bad", _c_i64), ("n_cfl_excursions", _c_i64),
+                ("ubar", _c_d * 4), ("nrm", _c_d * 4), ("nrm_m", _c_d), ("active", _c_i)]
+
+
+class DgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib_path():
+    return _LIB
+
+
+def symbols_declared():
+    """Names of the functions declared in include/oedg.h."""
+    text = open(_HEADER).read()
+    return sorted(set(re.findall(r"\b(dg_[a-z_]+)\s*\(", text)))
+
+
+_SIGS = {
+    "dg_config_default": (None, [_c_p]),
+    "dg_create": (_c_i, [_c_p, _c_i, _c_p]),
+    "dg_workspace_bytes": (_c_i, [_c_i32, _c_i, _c_p]),
+    "dg_bind_workspace": (_c_i, [_c_p, _c_p, _c_sz]),
+    "dg_mesh_upload": (_c_i, [_c_p, _c_i, _c_i32, _c_p, _c_i32, _c_p, _c_p, _c_p]),
+    "dg_mesh_tables": (_c_i, [_c_p] * 8),
+    "dg_init": (_c_i, [_c_p, _c_p, _c_p]),
+    "dg_init_problem": (_c_i, [_c_p, _c_p, _c_i, _c_p, _c_i]),
+    "dg_stage": (_c_i, [_c_p, _c_i]),
+    "dg_step": (_c_i, [_c_p, _c_p]),
+    "dg_step_to": (_c_i, [_c_p, _c_d, _c_i64, _c_p]),
+    "dg_readback": (_c_i, [_c_p, _c_p, _c_p, _c_p]),
+    "dg_read_state": (_c_i, [_c_p, _c_i, _c_p]),
+    "dg_diag": (_c_i, [_c_p, _c_p]),
+    "dg_sizes": (_c_i, [_c_p, _c_p, _c_p, _c_p]),
+    "dg_last_error": (ctypes.c_char_p, [_c_p]),
+    "dg_destroy": (None, [_c_p]),
+}
+
+
+def load_library():
+    """Loads the built HIP library (no fallback: raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            raise RuntimeError(f"HIP library {_LIB} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(_LIB)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+class Solver:
+    """One mesh and state on one GPU.
+
+    mesh: object with xy (n_vert,2) float64, tri (n_cell,3) int32 and optional
+    cell_xy (n_cell,6); k: degree 1 or 2.  Device memory comes from a torch
+    tensor bound as the library's workspace, and work runs on torch's current
+    stream of `device`.
+    """
+
+    def __init__(self, mesh, k, device=0, torch_workspace=True):
+        import torch
+        L = load_library()
+        self.k = int(k)
+        self.nm = (self.k + 1) * (self.k + 2) // 2
+        self.nc = int(mesh.tri.shape[0])
+        self.device = int(device)
+        self._torch = torch
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = L.dg_create(ctypes.byref(h), self.device, ctypes.c_void_p(self.stream.cuda_stream))
+        if st != 0:
+            raise DgError(st, "dg_create failed")
+        self.h = h
+        self._ws = None
+        if torch_workspace and self.nc > 0:
+            nbytes = ctypes.c_size_t(0)
+            self._check(L.dg_workspace_bytes(self.nc, self.k, ctypes.byref(nbytes)))
+            self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=f"cuda:{self.device}")
+            base = self._ws.data_ptr()
+            aligned = (base + 255) & ~255
+            self._check(L.dg_bind_workspace(self.h, ctypes.c_void_p(aligned), nbytes.value))
+        xy = np.ascontiguousarray(mesh.xy, dtype=np.float64)
+        tri = np.ascontiguousarray(mesh.tri, dtype=np.int32)
+        cxy = getattr(mesh, "cell_xy", None)
+        cxy = None if cxy is None else np.ascontiguousarray(cxy, dtype=np.float64)
+        self._check(L.dg_mesh_upload(self.h, self.k, int(xy.shape[0]), _ptr(xy), self.nc, _ptr(tri),
+                                     _ptr(cxy), None))
+
+    # ------------------------------------------------------------------ plumbing
+    def _check(self, st):
+        if st != 0:
+            msg = load_library().dg_last_error(self.h)
+            raise DgError(st, msg.decode() if msg else "")
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().dg_destroy(self.h)
+            self.h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def config(self, oe=True, bp=True, oe_mode=DG_OE_RI, gamma=1.4, c_ssp=1.0):
+        cfg = DgConfig()
+        load_library().dg_config_default(ctypes.byref(cfg))
+        cfg.k = self.k
+        cfg.gamma = gamma
+        cfg.c_ssp = c_ssp
+        cfg.oe_enable = int(oe)
+        cfg.bp_enable = int(bp)
+        cfg.oe_mode = int(oe_mode)
+        return cfg
+
+    def shape(self):
+        return (4, self.nm, self.nc)
+
+    # ------------------------------------------------------------------ API
+    def init_problem(self, kind, params, **cfg):
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        c = self.config(**cfg)
+        self._check(load_library().dg_init_problem(self.h, ctypes.byref(c), int(kind), _ptr(p), len(p)))
+
+    def init_modal(self, u, **cfg):
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(self.shape())
+        c = self.config(**cfg)
+        self._check(load_library().dg_init(self.h, ctypes.byref(c), _ptr(u)))
+
+    def stage(self, s):
+        self._check(load_library().dg_stage(self.h, int(s)))
+
+    def step(self, want_dt=False):
+        dt = ctypes.c_double(0)
+        self._check(load_library().dg_step(self.h, ctypes.byref(dt) if want_dt else None))
+        return dt.value if want_dt else None
+
+    def step_to(self, t_end=float("inf"), max_steps=(1 << 62)):
+        n = ctypes.c_int64(0)
+        self._check(load_library().dg_step_to(self.h, float(t_end), int(max_steps), ctypes.byref(n)))
+        return n.value
+
+    def readback(self):
+        u = np.zeros(self.shape())
+        t = ctypes.c_double(0)
+        s = ctypes.c_int64(0)
+        self._check(load_library().dg_readback(self.h, _ptr(u), ctypes.byref(t), ctypes.byref(s)))
+        return u, t.value, s.value
+
+    def read_state(self, which):
+        u = np.zeros(self.shape())
+        self._check(load_library().dg_read_state(self.h, int(which), _ptr(u)))
+        return u
+
+    def diag(self):
+        d = DgDiag()
+        self._check(load_library().dg_diag(self.h, ctypes.byref(d)))
+        out = {k: getattr(d, k) for k, _ in DgDiag._fields_}
+        out["ubar"] = list(d.ubar)
+        out["nrm"] = list(d.nrm)
+        return out
+
+    def mesh_tables(self):
+        nc = self.nc
+        out = dict(tri=np.zeros((nc, 3), np.int32), nbr=np.zeros((nc, 3), np.int32),
+                   nbe=np.zeros((nc, 3), np.int32), perm=np.zeros((nc, 3), np.int32),
+                   node_ref=np.zeros((4, nc)), ck=np.zeros(nc))
+        minck = ctypes.c_double(0)
+        self._check(load_library().dg_mesh_tables(
+            self.h, _ptr(out["tri"]), _ptr(out["nbr"]), _ptr(out["nbe"]), _ptr(out["perm"]),
+            _ptr(out["node_ref"]), _ptr(out["ck"]), ctypes.byref(minck)))
+        out["minck"] = minck.value
+        return out
+
+
+def host_mesh_tables(mesh, k):
+    """Mesh tables built by the library's host precompute, through a host-only
+    context (no device needed)."""
+    L = load_library()
+    h = ctypes.c_void_p()
+    st = L.dg_create(ctypes.byref(h), -1, None)
+    if st != 0:
+        raise DgError(st, "dg_create(DG_HOST_ONLY) failed")
+    try:
+        xy = np.ascontiguousarray(mesh.xy, dtype=np.float64)
+        tri = np.ascontiguousarray(mesh.tri, dtype=np.int32)
+        cxy = getattr(mesh, "cell_xy", None)
+        cxy = None if cxy is None else np.ascontiguousarray(cxy, dtype=np.float64)
+        nc = int(tri.shape[0])
+        st = L.dg_mesh_upload(h, int(k), int(xy.shape[0]), _ptr(xy), nc, _ptr(tri), _ptr(cxy), None)
+        if st != 0:
+            raise DgError(st, L.dg_last_error(h).decode())
+        out = dict(tri=np.zeros((nc, 3), np.int32), nbr=np.zeros((nc, 3), np.int32),
+                   nbe=np.zeros((nc, 3), np.int32), perm=np.zeros((nc, 3), np.int32),
+                   node_ref=np.zeros((4, nc)), ck=np.zeros(nc))
+        minck = ctypes.c_double(0)
+        st = L.dg_mesh_tables(h, _ptr(out["tri"]), _ptr(out["nbr"]), _ptr(out["nbe"]), _ptr(out["perm"]),
+                              _ptr(out["node_ref"]), _ptr(out["ck"]), ctypes.byref(minck))
+        if st != 0:
+            raise DgError(st, L.dg_last_error(h).decode())
+        out["minck"] = minck.value
+        return out
+    finally:
+        L.dg_destroy(h)

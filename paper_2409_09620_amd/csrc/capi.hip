@@ -1,0 +1,495 @@
+// C ABI of the BP RI-OEDG stage library: context, device memory, stage
+// sequencing and polling.  All per-cell arithmetic of a stage runs in the
+// kernels of kernels.hip; this file only moves data and orders launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "oedg.h"
+#include "oedg_internal.h"
+
+using oedg::Glob;
+
+struct dg_ctx {
+    int device = 0;
+    bool host_only = false;
+    hipStream_t stream = nullptr;
+    dg_status status = DG_OK;
+    std::string err;
+
+    void* bound = nullptr;       // caller-owned workspace
+    size_t bound_bytes = 0;
+    void* owned = nullptr;       // library allocation
+    size_t used_bytes = 0;
+
+    oedg::HostMesh mesh;
+    bool have_mesh = false;
+    bool initialised = false;
+    dg_config cfg{};
+    int nm = 0;
+
+    double *jinv = nullptr, *area = nullptr, *len = nullptr, *node = nullptr;
+    int32_t* link = nullptr;
+    double *u0 = nullptr, *u = nullptr, *w = nullptr, *part = nullptr;
+    const double* last_out = nullptr;
+    Glob* g = nullptr;
+};
+
+namespace {
+
+dg_status fail(dg_ctx* c, dg_status s, const std::string& msg) {
+    if (c && c->status == DG_OK) {
+        c->status = s;
+        c->err = msg;
+    }
+    return s;
+}
+
+#define HIP_TRY(ctx, call)                                                                       \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) return fail(ctx, DG_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCH_TRY(ctx, expr)                                                                    \
+    do {                                                                                         \
+        int e_ = (expr);                                                                         \
+        if (e_ != 0) return fail(ctx, DG_E_HIP, std::string(#expr) + ": " + hipGetErrorString((hipError_t)e_)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t jinv, area, len, node, link, u0, u, w, part, glob, total;
+};
+
+Layout layout(size_t nc, int k) {
+    const size_t nm = (size_t)(k + 1) * (k + 2) / 2;
+    const size_t nblk = (nc + oedg::kBlock - 1) / oedg::kBlock;
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+    L.jinv = take(4 * nc * sizeof(double));
+    L.area = take(nc * sizeof(double));
+    L.len = take(3 * nc * sizeof(double));
+    L.node = take(4 * nc * sizeof(double));
+    L.link = take(3 * nc * sizeof(int32_t));
+    L.u0 = take(4 * nm * nc * sizeof(double));
+    L.u = take(4 * nm * nc * sizeof(double));
+    L.w = take(std::max<size_t>(4 * nm, 7) * nc * sizeof(double));
+    L.part = take(nblk * 18 * sizeof(double));
+    L.glob = take(sizeof(Glob));
+    L.total = off;
+    return L;
+}
+
+bool check_ctx(dg_ctx* c) { return c != nullptr; }
+
+dg_status ready(dg_ctx* c, bool need_init) {
+    if (!c) return DG_E_ARG;
+    if (c->status != DG_OK) return c->status;
+    if (c->host_only) return fail(c, DG_E_STATE, "host-only context");
+    if (!c->have_mesh) return fail(c, DG_E_STATE, "no mesh uploaded");
+    if (need_init && !c->initialised) return fail(c, DG_E_STATE, "state not initialised");
+    HIP_TRY(c, hipSetDevice(c->device));
+    return DG_OK;
+}
+
+oedg::StageArgs stage_args(dg_ctx* c, int s) {
+    oedg::StageArgs a{};
+    a.m.n_cell = c->mesh.n_cell;
+    a.m.jinv = c->jinv;
+    a.m.area = c->area;
+    a.m.len = c->len;
+    a.m.node_ref = c->node;
+    a.m.link = c->link;
+    a.uin = s <= 0 ? c->u0 : c->u;
+    a.u0 = c->u0;
+    a.w = c->w;
+    a.uout = s == 2 ? c->u0 : c->u;
+    a.part = c->part;
+    a.g = c->g;
+    a.gamma = c->cfg.gamma;
+    a.stage = s;
+    a.oe_enable = c->cfg.oe_enable;
+    a.oe_mode = c->cfg.oe_mode;
+    a.bp_enable = c->cfg.bp_enable;
+    return a;
+}
+
+dg_status check_cfg(dg_ctx* c, const dg_config* cfg) {
+    if (!cfg) return fail(c, DG_E_ARG, "null config");
+    if (cfg->k != c->mesh.k) return fail(c, DG_E_ARG, "config degree differs from the mesh upload");
+    if (cfg->precision != DG_PREC_FP64) return fail(c, DG_E_ARG, "unsupported precision");
+    if (cfg->oe_mode != DG_OE_RI && cfg->oe_mode != DG_OE_CW) return fail(c, DG_E_ARG, "bad oe_mode");
+    if (!(cfg->gamma > 1.0) || !(cfg->c_ssp > 0.0)) return fail(c, DG_E_ARG, "bad gamma or c_ssp");
+    return DG_OK;
+}
+
+// fresh device scalars for t = 0; alpha and dt follow from the limiter pass
+dg_status reset_glob(dg_ctx* c) {
+    Glob h{};
+    h.t_end = INFINITY;
+    h.minck = c->mesh.minck;
+    h.area_sum = c->mesh.area_sum;
+    h.c_ssp = c->cfg.c_ssp;
+    h.alpha = h.alpha_step = 0.0;
+    h.active = 1;
+    HIP_TRY(c, hipMemcpyAsync(c->g, &h, sizeof(Glob), hipMemcpyHostToDevice, c->stream));
+    return DG_OK;
+}
+
+// limiter (no OE) + alpha^0 + Delta t^0 on u^0, in place
+dg_status start(dg_ctx* c) {
+    oedg::StageArgs a = stage_args(c, -1);
+    a.w = c->u0;
+    a.uout = c->u0;
+    a.oe_enable = 0;
+    LAUNCH_TRY(c, oedg::launch_filter(c->cfg.k, a, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->u, c->u0, 4 * (size_t)c->nm * c->mesh.n_cell * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
+    c->last_out = c->u0;
+    c->initialised = true;
+    Glob h{};
+    HIP_TRY(c, hipMemcpyAsync(&h, c->g, sizeof(Glob), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (h.err) return fail(c, DG_E_BOUNDS, "initial data has an inadmissible cell average");
+    return DG_OK;
+}
+
+dg_status read_glob(dg_ctx* c, Glob* h) {
+    HIP_TRY(c, hipMemcpyAsync(h, c->g, sizeof(Glob), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return DG_OK;
+}
+
+dg_status run_stage(dg_ctx* c, int s) {
+    const oedg::StageArgs a = stage_args(c, s);
+    LAUNCH_TRY(c, oedg::launch_residual(c->cfg.k, a, c->stream));
+    if (c->cfg.oe_enable) LAUNCH_TRY(c, oedg::launch_mnorm(c->cfg.k, a, c->stream));
+    LAUNCH_TRY(c, oedg::launch_filter(c->cfg.k, a, c->stream));
+    c->last_out = a.uout;
+    return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dg_config_default(dg_config* cfg) {
+    if (!cfg) return;
+    cfg->k = 2;
+    cfg->gamma = 1.4;
+    cfg->c_ssp = 1.0;
+    cfg->oe_enable = 1;
+    cfg->oe_mode = DG_OE_RI;
+    cfg->bp_enable = 1;
+    cfg->precision = DG_PREC_FP64;
+}
+
+dg_status dg_create(dg_ctx** out, int hip_device, void* hip_stream) {
+    if (!out) return DG_E_ARG;
+    *out = nullptr;
+    if (hip_device == DG_HOST_ONLY) {
+        dg_ctx* c = new (std::nothrow) dg_ctx();
+        if (!c) return DG_E_NOMEM;
+        c->host_only = true;
+        dg_config_default(&c->cfg);
+        *out = c;
+        return DG_OK;
+    }
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return DG_E_HIP;
+    if (hipSetDevice(hip_device) != hipSuccess) return DG_E_HIP;
+    dg_ctx* c = new (std::nothrow) dg_ctx();
+    if (!c) return DG_E_NOMEM;
+    c->device = hip_device;
+    c->stream = (hipStream_t)hip_stream;
+    dg_config_default(&c->cfg);
+    *out = c;
+    return DG_OK;
+}
+
+dg_status dg_workspace_bytes(int32_t n_cell, int k, size_t* bytes) {
+    if (!bytes || n_cell <= 0 || (k != 1 && k != 2)) return DG_E_ARG;
+    *bytes = layout((size_t)n_cell, k).total;
+    return DG_OK;
+}
+
+dg_status dg_bind_workspace(dg_ctx* c, void* dev_ptr, size_t bytes) {
+    if (!c) return DG_E_ARG;
+    if (c->status != DG_OK) return c->status;
+    if (!dev_ptr || bytes == 0) return fail(c, DG_E_ARG, "null workspace");
+    if (((uintptr_t)dev_ptr & 255) != 0) return fail(c, DG_E_ARG, "workspace must be 256-byte aligned");
+    c->bound = dev_ptr;
+    c->bound_bytes = bytes;
+    return DG_OK;
+}
+
+dg_status dg_mesh_upload(dg_ctx* c, int k, int32_t n_vert, const double* xy, int32_t n_cell, const int32_t* tri,
+                         const double* cell_xy, const int32_t* edge_bc) {
+    if (!c) return DG_E_ARG;
+    if (c->status != DG_OK) return c->status;
+    if (k != 1 && k != 2) return fail(c, DG_E_ARG, "degree must be 1 or 2");
+    if (n_cell <= 0 || n_vert <= 0) return fail(c, DG_E_MESH, "mesh has no cells or no vertices");
+    if (!tri || (!xy && !cell_xy)) return fail(c, DG_E_ARG, "null mesh array");
+    oedg::HostMesh m;
+    std::string err;
+    const int r = oedg::build_mesh(k, n_vert, xy, n_cell, tri, cell_xy, edge_bc, m, err);
+    if (r != 0) return fail(c, r == -1 ? DG_E_ARG : DG_E_MESH, err);
+    if (c->host_only) {
+        c->mesh = std::move(m);
+        c->nm = (k + 1) * (k + 2) / 2;
+        c->cfg.k = k;
+        c->have_mesh = true;
+        return DG_OK;
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+
+    const size_t nc = (size_t)n_cell;
+    const Layout L = layout(nc, k);
+    char* base = nullptr;
+    if (c->bound) {
+        if (c->bound_bytes < L.total) return fail(c, DG_E_NOMEM, "bound workspace too small");
+        if (c->owned) {
+            HIP_TRY(c, hipFree(c->owned));
+            c->owned = nullptr;
+        }
+        base = (char*)c->bound;
+    } else {
+        if (c->owned && c->used_bytes < L.total) {
+            HIP_TRY(c, hipFree(c->owned));
+            c->owned = nullptr;
+        }
+        if (!c->owned) {
+            void* p = nullptr;
+            if (hipMalloc(&p, L.total) != hipSuccess) return fail(c, DG_E_NOMEM, "hipMalloc of the workspace failed");
+            c->owned = p;
+            c->used_bytes = L.total;
+        }
+        base = (char*)c->owned;
+    }
+    c->jinv = (double*)(base + L.jinv);
+    c->area = (double*)(base + L.area);
+    c->len = (double*)(base + L.len);
+    c->node = (double*)(base + L.node);
+    c->link = (int32_t*)(base + L.link);
+    c->u0 = (double*)(base + L.u0);
+    c->u = (double*)(base + L.u);
+    c->w = (double*)(base + L.w);
+    c->part = (double*)(base + L.part);
+    c->g = (Glob*)(base + L.glob);
+    c->mesh = std::move(m);
+    c->nm = (k + 1) * (k + 2) / 2;
+    c->cfg.k = k;
+    const oedg::HostMesh& hm = c->mesh;
+    HIP_TRY(c, hipMemcpyAsync(c->jinv, hm.jinv.data(), 4 * nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->area, hm.area.data(), nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->len, hm.len.data(), 3 * nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->node, hm.node_ref.data(), 4 * nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->link, hm.link.data(), 3 * nc * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    static const Glob zero{};
+    HIP_TRY(c, hipMemcpyAsync(c->g, &zero, sizeof(Glob), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->have_mesh = true;
+    c->initialised = false;
+    return DG_OK;
+}
+
+dg_status dg_mesh_tables(dg_ctx* c, int32_t* tri, int32_t* nbr, int32_t* nbe, int32_t* perm, double* node_ref,
+                         double* ck, double* minck) {
+    if (!c) return DG_E_ARG;
+    if (!c->have_mesh) return fail(c, DG_E_STATE, "no mesh uploaded");
+    const oedg::HostMesh& m = c->mesh;
+    const size_t nc = (size_t)m.n_cell;
+    if (tri) std::memcpy(tri, m.tri.data(), 3 * nc * sizeof(int32_t));
+    if (nbr) std::memcpy(nbr, m.nbr.data(), 3 * nc * sizeof(int32_t));
+    if (nbe) std::memcpy(nbe, m.nbe.data(), 3 * nc * sizeof(int32_t));
+    if (perm) std::memcpy(perm, m.perm.data(), 3 * nc * sizeof(int32_t));
+    if (node_ref) std::memcpy(node_ref, m.node_ref.data(), 4 * nc * sizeof(double));
+    if (ck) std::memcpy(ck, m.ck.data(), nc * sizeof(double));
+    if (minck) *minck = m.minck;
+    return DG_OK;
+}
+
+dg_status dg_init(dg_ctx* c, const dg_config* cfg, const double* u0_modal) {
+    dg_status s = ready(c, false);
+    if (s != DG_OK) return s;
+    if ((s = check_cfg(c, cfg)) != DG_OK) return s;
+    if (!u0_modal) return fail(c, DG_E_ARG, "null initial state");
+    c->cfg = *cfg;
+    HIP_TRY(c, hipMemcpyAsync(c->u0, u0_modal, 4 * (size_t)c->nm * c->mesh.n_cell * sizeof(double),
+                              hipMemcpyHostToDevice, c->stream));
+    if ((s = reset_glob(c)) != DG_OK) return s;
+    return start(c);
+}
+
+dg_status dg_init_problem(dg_ctx* c, const dg_config* cfg, int kind, const double* params, int n_params) {
+    dg_status s = ready(c, false);
+    if (s != DG_OK) return s;
+    if ((s = check_cfg(c, cfg)) != DG_OK) return s;
+    static const int need[4] = {7, 18, 4, 12};
+    if (kind < 0 || kind > 3 || !params || n_params < need[kind] || n_params > 19)
+        return fail(c, DG_E_ARG, "bad problem kind or parameter count");
+    c->cfg = *cfg;
+    const oedg::HostMesh& m = c->mesh;
+    const size_t nc = (size_t)m.n_cell;
+    std::vector<double> P(params, params + n_params);
+    // coordinates (and, for the blast, the flags of the cells owning the origin
+    // vertex) travel in the pre-filter buffer, which is free until the first stage
+    std::vector<double> aux(7 * nc, 0.0);
+    std::memcpy(aux.data(), m.vx.data(), 6 * nc * sizeof(double));
+    if (kind == 2) {
+        const double ov = params[3];
+        if (!(ov >= 0) || ov != std::floor(ov)) return fail(c, DG_E_ARG, "bad origin vertex id");
+        double hit_area = 0.0;
+        for (size_t cc = 0; cc < nc; ++cc) {
+            bool hit = false;
+            for (int q = 0; q < 3; ++q) hit |= (double)m.tri[3 * cc + q] == ov;
+            if (hit) {
+                aux[6 * nc + cc] = 1.0;
+                hit_area += m.area[cc];
+            }
+        }
+        if (!(hit_area > 0)) return fail(c, DG_E_ARG, "origin vertex is in no cell");
+        P.resize(5);
+        P[4] = hit_area;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->w, aux.data(), 7 * nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if ((s = reset_glob(c)) != DG_OK) return s;
+    oedg::StageArgs a = stage_args(c, -1);
+    a.uout = c->u0;
+    LAUNCH_TRY(c, oedg::launch_project(c->cfg.k, a, kind, P.data(), (int)P.size(), c->stream));
+    // the host buffer must outlive the copy
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return start(c);
+}
+
+dg_status dg_stage(dg_ctx* c, int s) {
+    dg_status st = ready(c, true);
+    if (st != DG_OK) return st;
+    if (s < 0 || s > 2) return fail(c, DG_E_ARG, "stage must be 0, 1 or 2");
+    return run_stage(c, s);
+}
+
+dg_status dg_step(dg_ctx* c, double* dt_out) {
+    dg_status st = ready(c, true);
+    if (st != DG_OK) return st;
+    if (dt_out) {
+        Glob h{};
+        if ((st = read_glob(c, &h)) != DG_OK) return st;
+        *dt_out = h.active ? h.dt : 0.0;
+    }
+    for (int s = 0; s < 3; ++s)
+        if ((st = run_stage(c, s)) != DG_OK) return st;
+    return DG_OK;
+}
+
+dg_status dg_step_to(dg_ctx* c, double t_end, int64_t max_steps, int64_t* steps_done) {
+    dg_status st = ready(c, true);
+    if (st != DG_OK) return st;
+    if (max_steps < 0 || std::isnan(t_end)) return fail(c, DG_E_ARG, "bad t_end or max_steps");
+    Glob h{};
+    if ((st = read_glob(c, &h)) != DG_OK) return st;
+    const long long step0 = h.step;
+    LAUNCH_TRY(c, oedg::launch_set_end(c->g, t_end, c->stream));
+    int64_t launched = 0;
+    int chunk = 4;
+    while (launched < max_steps) {
+        const int64_t n = std::min<int64_t>(chunk, max_steps - launched);
+        for (int64_t i = 0; i < n; ++i)
+            for (int s = 0; s < 3; ++s)
+                if ((st = run_stage(c, s)) != DG_OK) return st;
+        launched += n;
+        if ((st = read_glob(c, &h)) != DG_OK) return st;
+        if (!h.active || h.err) break;
+        chunk = std::min(chunk * 2, 64);
+    }
+    if ((st = read_glob(c, &h)) != DG_OK) return st;
+    if (steps_done) *steps_done = h.step - step0;
+    if (h.err) return fail(c, DG_E_BOUNDS, "a cell average left the admissible set");
+    return DG_OK;
+}
+
+dg_status dg_readback(dg_ctx* c, double* u_modal, double* t, int64_t* step) {
+    dg_status st = ready(c, true);
+    if (st != DG_OK && st != DG_E_BOUNDS) return st;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (u_modal)
+        HIP_TRY(c, hipMemcpyAsync(u_modal, c->u0, 4 * (size_t)c->nm * c->mesh.n_cell * sizeof(double),
+                                  hipMemcpyDeviceToHost, c->stream));
+    Glob h{};
+    HIP_TRY(c, hipMemcpyAsync(&h, c->g, sizeof(Glob), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (t) *t = h.t;
+    if (step) *step = h.step;
+    return c->status;
+}
+
+dg_status dg_read_state(dg_ctx* c, int which, double* u_modal) {
+    if (!c) return DG_E_ARG;
+    if (c->host_only) return fail(c, DG_E_STATE, "host-only context");
+    if (!c->have_mesh || !c->initialised) return fail(c, DG_E_STATE, "state not initialised");
+    if (!u_modal || which < 0 || which > 2) return fail(c, DG_E_ARG, "bad buffer selector");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const double* src = which == 0 ? c->u0 : (which == 1 ? c->last_out : c->w);
+    HIP_TRY(c, hipMemcpyAsync(u_modal, src, 4 * (size_t)c->nm * c->mesh.n_cell * sizeof(double),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return DG_OK;
+}
+
+dg_status dg_diag(dg_ctx* c, dg_diag_t* out) {
+    if (!c || !out) return DG_E_ARG;
+    if (c->host_only) return fail(c, DG_E_STATE, "host-only context");
+    if (!c->have_mesh) return fail(c, DG_E_STATE, "no mesh uploaded");
+    HIP_TRY(c, hipSetDevice(c->device));
+    Glob h{};
+    dg_status st = read_glob(c, &h);
+    if (st != DG_OK) return st;
+    out->t = h.t;
+    out->dt = h.dt;
+    out->alpha = h.alpha_step;
+    out->step = h.step;
+    out->n_limited = h.n_limited;
+    out->n_bad = h.n_bad;
+    out->n_cfl_excursions = h.n_cfl_exc;
+    for (int v = 0; v < 4; ++v) {
+        out->ubar[v] = h.ubar[v];
+        out->nrm[v] = h.nrm[v];
+    }
+    out->nrm_m = h.nrm_m;
+    out->active = h.active;
+    return DG_OK;
+}
+
+dg_status dg_sizes(dg_ctx* c, int32_t* n_cell, int* k, int* n_modes) {
+    if (!c) return DG_E_ARG;
+    if (!c->have_mesh) return fail(c, DG_E_STATE, "no mesh uploaded");
+    if (n_cell) *n_cell = c->mesh.n_cell;
+    if (k) *k = c->mesh.k;
+    if (n_modes) *n_modes = c->nm;
+    return DG_OK;
+}
+
+const char* dg_last_error(const dg_ctx* c) {
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+void dg_destroy(dg_ctx* c) {
+    if (!c) return;
+    if (c->owned && !c->host_only) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->owned);
+    }
+    delete c;
+}
+
+}  // extern "C"

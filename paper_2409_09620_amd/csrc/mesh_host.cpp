@@ -1,0 +1,196 @@
+// Per-mesh precompute on the host (once per mesh, outside the stepped path):
+// orientation, edge table, geometry and the optimal convex decomposition.
+//
+//  - Notation of Sec. 2 (Fig. MeshK): vertices counter-clockwise, local edge i is
+//    opposite local vertex i; it runs from vertex i+1 to vertex i+2, so a shared
+//    edge is traversed in opposite directions by its two cells.
+//  - Affine map x - x_1 = J_K (xi, eta) (below eq. basisfunc); J^{-1} is stored.
+//  - Decomposition (Sec. 4.3): edges sorted by decreasing length (stable),
+//    P1 limiter points are the vertices opposite the two longest edges
+//    (eq. 1944), P2 internal nodes have barycentric coordinates beta_{s,i} of
+//    eq. 1139 with lhat of eq. 1703; C^DCW_{K,1} = 2/(3(l1+l2)) (eq. 1692),
+//    C^DCW_{K,2} = 2/(9 lbar + 3 lhat) (eq. 1713).
+//
+// Compiled with -ffp-contract=off so lengths and the stable sort are reproducible.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "oedg_internal.h"
+
+namespace oedg {
+
+namespace {
+
+struct HalfEdge {
+    uint64_t key;   // (min vertex id << 32) | max vertex id
+    int32_t cell;
+    int32_t edge;
+};
+
+// barycentric coordinates of the two P2 internal nodes, in the sorted labelling
+void p2_nodes(double l1, double l2, double l3, double beta[2][3], double* cdcw) {
+    const double s3 = std::sqrt(3.0);
+    const double lb = (l1 + l2 + l3) / 3.0;
+    const double lh = std::sqrt(l1 * l1 + l2 * l2 + l3 * l3 - 2.0 / 3.0 * (l1 * l2 + l2 * l3 + l3 * l1));
+    // M_{s,i} (symmetric) and c_{s,i}, eq. 1139
+    const double M[2][3][6] = {
+        // entries (11, 22, 33, 12, 13, 23)
+        {{6, 2 * s3 + 6, 6, 1, -2, -s3 - 2},
+         {6, 12, 6, -s3 - 2, -2, s3 - 2},
+         {6, 6 - 2 * s3, 6, s3 - 2, -2, 1}},
+        {{6, 6 - 2 * s3, 6, 1, -2, s3 - 2},
+         {6, 12, 6, s3 - 2, -2, -s3 - 2},
+         {6, 2 * s3 + 6, 6, -s3 - 2, -2, 1}}};
+    const double c[2][3] = {{3 * l1 + 3 * l2 + s3 * (l2 - l3), 6 * l2 + s3 * (l3 - l1), 3 * l2 + 3 * l3 + s3 * (l1 - l2)},
+                            {3 * l1 + 3 * l2 + s3 * (l3 - l2), 6 * l2 + s3 * (l1 - l3), 3 * l2 + 3 * l3 + s3 * (l2 - l1)}};
+    const double den = 18.0 * (lb + lh) * (l2 + lh);
+    for (int s = 0; s < 2; ++s)
+        for (int i = 0; i < 3; ++i) {
+            const double* m = M[s][i];
+            const double q = m[0] * l1 * l1 + m[1] * l2 * l2 + m[2] * l3 * l3 +
+                             2.0 * (m[3] * l1 * l2 + m[4] * l1 * l3 + m[5] * l2 * l3);
+            beta[s][i] = (q + 2.0 * c[s][i] * lh) / den;
+        }
+    *cdcw = 2.0 / (9.0 * lb + 3.0 * lh);
+}
+
+}  // namespace
+
+int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const int32_t* tri_in,
+               const double* cell_xy, const int32_t* edge_bc, HostMesh& m, std::string& err) {
+    if (n_cell <= 0 || n_vert <= 0) { err = "mesh has no cells or no vertices"; return -2; }
+    m.n_cell = n_cell;
+    m.k = k;
+    const size_t nc = static_cast<size_t>(n_cell);
+    m.tri.assign(3 * nc, 0);
+    m.nbr.assign(3 * nc, -1);
+    m.nbe.assign(3 * nc, -1);
+    m.perm.assign(3 * nc, 0);
+    m.jinv.assign(4 * nc, 0.0);
+    m.area.assign(nc, 0.0);
+    m.len.assign(3 * nc, 0.0);
+    m.node_ref.assign(4 * nc, 0.0);
+    m.ck.assign(nc, 0.0);
+    m.link.assign(3 * nc, -1);
+    m.vx.assign(6 * nc, 0.0);
+    std::vector<double> vx(6 * nc);
+
+    for (size_t c = 0; c < nc; ++c) {
+        int32_t id[3];
+        double p[6];
+        for (int q = 0; q < 3; ++q) {
+            id[q] = tri_in[3 * c + q];
+            if (id[q] < 0 || id[q] >= n_vert) { err = "vertex id out of range"; return -2; }
+            if (cell_xy) {
+                p[2 * q] = cell_xy[6 * c + 2 * q];
+                p[2 * q + 1] = cell_xy[6 * c + 2 * q + 1];
+            } else {
+                p[2 * q] = xy[2 * static_cast<size_t>(id[q])];
+                p[2 * q + 1] = xy[2 * static_cast<size_t>(id[q]) + 1];
+            }
+        }
+        const double twice_area = (p[2] - p[0]) * (p[5] - p[1]) - (p[4] - p[0]) * (p[3] - p[1]);
+        if (!(twice_area != 0.0) || !std::isfinite(twice_area)) { err = "degenerate cell"; return -2; }
+        if (twice_area < 0) {
+            std::swap(id[1], id[2]);
+            std::swap(p[2], p[4]);
+            std::swap(p[3], p[5]);
+        }
+        for (int q = 0; q < 3; ++q) m.tri[3 * c + q] = id[q];
+        std::memcpy(&vx[6 * c], p, sizeof(p));
+        for (int q = 0; q < 6; ++q) m.vx[q * nc + c] = p[q];
+    }
+
+    // edge table: sort half-edges by their unordered vertex pair
+    std::vector<HalfEdge> he(3 * nc);
+    for (size_t c = 0; c < nc; ++c)
+        for (int i = 0; i < 3; ++i) {
+            const uint32_t a = static_cast<uint32_t>(m.tri[3 * c + (i + 1) % 3]);
+            const uint32_t b = static_cast<uint32_t>(m.tri[3 * c + (i + 2) % 3]);
+            const uint64_t lo = std::min(a, b), hi = std::max(a, b);
+            he[3 * c + i] = HalfEdge{(lo << 32) | hi, static_cast<int32_t>(c), i};
+        }
+    std::sort(he.begin(), he.end(), [](const HalfEdge& x, const HalfEdge& y) {
+        if (x.key != y.key) return x.key < y.key;
+        return x.cell != y.cell ? x.cell < y.cell : x.edge < y.edge;
+    });
+    for (size_t r = 0; r < he.size();) {
+        size_t s = r + 1;
+        while (s < he.size() && he[s].key == he[r].key) ++s;
+        if (s - r > 2) { err = "edge shared by more than two cells"; return -2; }
+        if (s - r == 2) {
+            const HalfEdge& x = he[r];
+            const HalfEdge& y = he[r + 1];
+            if (x.cell == y.cell) { err = "cell adjacent to itself"; return -2; }
+            m.nbr[3 * x.cell + x.edge] = y.cell;
+            m.nbe[3 * x.cell + x.edge] = y.edge;
+            m.nbr[3 * y.cell + y.edge] = x.cell;
+            m.nbe[3 * y.cell + y.edge] = x.edge;
+        } else if (edge_bc && edge_bc[3 * static_cast<size_t>(he[r].cell) + he[r].edge] != 0) {
+            err = "unsupported boundary tag (only 0 = transmissive)";
+            return -1;
+        }
+        r = s;
+    }
+    if (static_cast<uint64_t>(n_cell) * 4 >= (1ull << 31)) { err = "too many cells"; return -1; }
+    for (size_t c = 0; c < nc; ++c)
+        for (int i = 0; i < 3; ++i) {
+            const int32_t nb = m.nbr[3 * c + i];
+            m.link[i * nc + c] = nb >= 0 ? (nb << 2) | m.nbe[3 * c + i] : -1;
+        }
+
+    // geometry and decomposition
+    const double ref[3][2] = {{0, 0}, {1, 0}, {0, 1}};
+    double minck = INFINITY;
+    for (size_t c = 0; c < nc; ++c) {
+        const double* p = &vx[6 * c];
+        const double a = p[2] - p[0], b = p[4] - p[0], cc = p[3] - p[1], d = p[5] - p[1];
+        const double det = a * d - b * cc;
+        m.area[c] = 0.5 * det;
+        m.jinv[0 * nc + c] = d / det;     // d xi / dx
+        m.jinv[1 * nc + c] = -b / det;    // d xi / dy
+        m.jinv[2 * nc + c] = -cc / det;   // d eta / dx
+        m.jinv[3 * nc + c] = a / det;     // d eta / dy
+        double l[3];
+        for (int i = 0; i < 3; ++i) {
+            const double* s = p + 2 * ((i + 1) % 3);
+            const double* e = p + 2 * ((i + 2) % 3);
+            const double dx = e[0] - s[0], dy = e[1] - s[1];
+            l[i] = std::sqrt(dx * dx + dy * dy);
+            m.len[i * nc + c] = l[i];
+        }
+        int o[3] = {0, 1, 2};
+        std::stable_sort(o, o + 3, [&](int x, int y) { return l[x] > l[y]; });
+        for (int i = 0; i < 3; ++i) m.perm[3 * c + i] = o[i];
+        double cd;
+        if (k == 1) {
+            cd = 2.0 / (3.0 * (l[o[0]] + l[o[1]]));
+            for (int s = 0; s < 2; ++s) {
+                m.node_ref[(2 * s) * nc + c] = ref[o[s]][0];
+                m.node_ref[(2 * s + 1) * nc + c] = ref[o[s]][1];
+            }
+        } else {
+            double beta[2][3];
+            p2_nodes(l[o[0]], l[o[1]], l[o[2]], beta, &cd);
+            for (int s = 0; s < 2; ++s) {
+                double xi = 0, eta = 0;
+                for (int i = 0; i < 3; ++i) {   // sorted vertex i is local vertex o[i]
+                    xi += beta[s][i] * ref[o[i]][0];
+                    eta += beta[s][i] * ref[o[i]][1];
+                }
+                m.node_ref[(2 * s) * nc + c] = xi;
+                m.node_ref[(2 * s + 1) * nc + c] = eta;
+            }
+        }
+        m.ck[c] = cd * m.area[c];
+        minck = std::min(minck, m.ck[c]);
+        m.area_sum += m.area[c];
+    }
+    m.minck = minck;
+    return 0;
+}
+
+}  // namespace oedg

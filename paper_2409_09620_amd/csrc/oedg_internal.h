@@ -1,0 +1,89 @@
+// Internal declarations shared by the host code and the kernels of the library.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace oedg {
+
+constexpr int kBlock = 256;       // threads per workgroup of the stage kernels
+constexpr int kNumPartial = 12;   // per-block partials of the residual pass
+
+// Host-side mesh tables built once per mesh (see mesh_host.cpp).  Per-cell arrays
+// that go to the device are structure-of-arrays: component-major, cell fastest.
+struct HostMesh {
+    int32_t n_cell = 0;
+    int k = 0;
+    std::vector<int32_t> tri, nbr, nbe, perm;   // [cell][3]
+    std::vector<int32_t> link;                  // [3][cell]: (nbr << 2) | nbe, or -1
+    std::vector<double> jinv;                   // [4][cell]: xi_x, xi_y, eta_x, eta_y
+    std::vector<double> area;                   // [cell]
+    std::vector<double> len;                    // [3][cell]
+    std::vector<double> node_ref;               // [4][cell]: xi_1, eta_1, xi_2, eta_2
+    std::vector<double> ck;                     // [cell] C^DCW_{K,k} |K|
+    std::vector<double> vx;                     // [6][cell] oriented vertex coordinates
+    double minck = 0.0;
+    double area_sum = 0.0;
+};
+
+int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const int32_t* tri,
+               const double* cell_xy, const int32_t* edge_bc, HostMesh& m, std::string& err);
+
+// Device-resident scalars of one context.  Written only by the last workgroup of a
+// kernel (after all others have published their partials) or by the host between
+// steps.
+struct Glob {
+    double alpha;        // LF viscosity of the current stage input (eq. 1250)
+    double alpha_step;   // alpha of u^n, which sets the step's Delta t
+    double dt;           // Delta t of the current step
+    double t;            // time of u^n
+    double t_end;        // stop time (infinity when unset)
+    double minck;        // min_K C^DCW_{K,k} |K|
+    double area_sum;     // |Omega|
+    double c_ssp;
+    double ubar[4];      // domain averages of the pre-filter state
+    double nrm[4];       // ||u - ubar||_inf per variable
+    double nrm_m;        // ||| m - mbar |||_inf
+    double inv_nrm[4];   // 1/nrm or 0 where the zero branch of eq. OEScalar:Coef2 applies
+    double inv_nrm_m;
+    long long step;
+    long long n_limited;
+    long long n_bad;
+    long long n_cfl_exc;
+    int active;          // 0: t reached t_end, or an error stopped the run
+    int err;             // sticky: 1 once a cell average left the admissible set
+    unsigned int ticket[4];
+};
+
+struct DevMesh {
+    int32_t n_cell;
+    const double* jinv;
+    const double* area;
+    const double* len;
+    const double* node_ref;
+    const int32_t* link;
+};
+
+struct StageArgs {
+    DevMesh m;
+    const double* uin;    // stage input (own + neighbours)
+    const double* u0;     // u^n for the SSP combination
+    double* w;            // pre-filter state (written by the residual pass)
+    double* uout;         // limited stage output
+    double* part;         // per-block partials
+    Glob* g;
+    double gamma;
+    int stage;            // 0, 1, 2; -1 = limiter and alpha only (initial data)
+    int oe_enable, oe_mode, bp_enable;
+};
+
+// kernel launchers (kernels.hip); return a hipError_t as int
+int launch_residual(int k, const StageArgs& a, void* stream);
+int launch_mnorm(int k, const StageArgs& a, void* stream);
+int launch_filter(int k, const StageArgs& a, void* stream);
+int launch_project(int k, const StageArgs& a, int kind, const double* dparams, int n_params,
+                   void* stream);
+int launch_set_end(Glob* g, double t_end, void* stream);
+
+}  // namespace oedg

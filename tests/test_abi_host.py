@@ -1,0 +1,110 @@
+"""CPU checks of the HIP library: it loads, exports every declared symbol, and its
+host-side mesh precompute matches the oracle's (integer tables bit for bit)."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2409_09620_amd as pkg
+from paper_2409_09620_amd import binding
+from synth import mesh as smesh
+from synth import workloads
+
+
+def test_library_exports_every_declared_symbol():
+    L = pkg.load_library()
+    names = pkg.symbols_declared()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_workspace_bytes():
+    L = pkg.load_library()
+    b1, b2 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert L.dg_workspace_bytes(1000, 1, ctypes.byref(b1)) == 0
+    assert L.dg_workspace_bytes(1000, 2, ctypes.byref(b2)) == 0
+    # three state buffers of 4 (L+1) doubles plus geometry per cell
+    assert b2.value > b1.value > 1000 * 8 * (3 * 12)
+    assert L.dg_workspace_bytes(0, 1, ctypes.byref(b1)) == -1
+    assert L.dg_workspace_bytes(10, 3, ctypes.byref(b1)) == -1
+
+
+def _meshes():
+    return [("periodic", smesh.periodic_jittered_grid(n=7, seed=4)),
+            ("delaunay", smesh.poisson_delaunay(900, seed=12)),
+            ("blast", workloads.blast_delaunay(n_cells=700, seed=5)[0])]
+
+
+@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("idx", [0, 1, 2])
+def test_host_mesh_tables_match_oracle(k, idx):
+    name, m = _meshes()[idx]
+    lib = pkg.host_mesh_tables(m, k)
+    o = oracle.Oracle(m, k).mesh_arrays()
+    for key in ("tri", "nbr", "nbe", "perm"):
+        assert np.array_equal(lib[key], o[key]), key
+    # same length formula in both codes: C^DCW |K| agrees to the last bits
+    assert np.abs(lib["ck"] - o["ck"]).max() <= 4e-16 * np.abs(o["ck"]).max()
+    assert abs(lib["minck"] - o["minck"]) <= 4e-16 * o["minck"]
+    # limiter points: P1 the vertices opposite the two longest edges, P2 the oracle's
+    # internal nodes (physical) mapped to reference coordinates of the oriented cell
+    ref_v = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    if k == 1:
+        for s in range(2):
+            want = ref_v[o["limv"][:, s]]
+            assert np.array_equal(lib["node_ref"][2 * s], want[:, 0])
+            assert np.array_equal(lib["node_ref"][2 * s + 1], want[:, 1])
+        return
+    V = m.cell_coords()
+    Vo = np.empty_like(V)
+    for c in range(m.n_cell):
+        for q in range(3):
+            src = int(np.nonzero(m.tri[c] == o["tri"][c, q])[0][0])
+            Vo[c, q] = V[c, src]
+    J = np.stack([Vo[:, 1] - Vo[:, 0], Vo[:, 2] - Vo[:, 0]], axis=2)   # columns
+    for s in range(2):
+        d = o["node"][:, s, :] - Vo[:, 0]
+        ref = np.linalg.solve(J, d[..., None])[..., 0]
+        assert np.abs(lib["node_ref"][2 * s] - ref[:, 0]).max() < 1e-12
+        assert np.abs(lib["node_ref"][2 * s + 1] - ref[:, 1]).max() < 1e-12
+
+
+def test_host_mesh_errors():
+    L = pkg.load_library()
+    good = smesh.poisson_delaunay(60, seed=1)
+
+    def upload(xy, tri, k=1):
+        h = ctypes.c_void_p()
+        assert L.dg_create(ctypes.byref(h), -1, None) == 0
+        xy = np.ascontiguousarray(xy, np.float64)
+        tri = np.ascontiguousarray(tri, np.int32)
+        st = L.dg_mesh_upload(h, k, len(xy), binding._ptr(xy), len(tri), binding._ptr(tri), None, None)
+        msg = L.dg_last_error(h)
+        # device calls on a host-only context are refused
+        st2 = L.dg_stage(h, 0)
+        L.dg_destroy(h)
+        return st, msg, st2
+
+    assert upload(good.xy, good.tri)[0] == 0
+    assert upload(good.xy, good.tri)[2] == -6
+    bad = good.tri.copy()
+    bad[3, 1] = len(good.xy) + 5
+    assert upload(good.xy, bad)[0] == -2                      # vertex id out of range
+    deg = good.tri.copy()
+    deg[0, 2] = deg[0, 1]
+    assert upload(good.xy, deg)[0] == -2                      # zero-area cell
+    assert upload(good.xy, good.tri, k=3)[0] == -1            # bad degree
+    assert upload(good.xy, np.zeros((0, 3)))[0] == -2         # no cells
+    nm = np.concatenate([good.tri, good.tri[:1]])             # duplicated cell: non-manifold edges
+    assert upload(good.xy, nm)[0] == -2
+
+
+def test_product_path_has_no_fallback():
+    """The binding loads only the built HIP library and never the oracle."""
+    import inspect
+    src = inspect.getsource(binding)
+    assert "oracle" not in src.replace("never the oracle", "")
+    assert "import torch" in src
