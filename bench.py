@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Throughput of the BP RI-OEDG stage on one MI355X.
+
+Metric: DOF-stage updates per second, DOF = 4 variables x (L_k + 1) modes per cell,
+one SSP-RK3 step = 3 stages.  A benchmark step is one SSP-RK3 step of the whole
+stage path (residual + SSP combination, domain reductions, RIOE, BP limiter,
+max wave speed, device-side Delta t) over the resident mesh and state.
+
+Default workload: P2, about 200k cells of a seeded Poisson-disk Delaunay mesh of
+the unit square, four-quadrant Riemann data (rho in [0.14, 1.5], p in [0.03, 1.5]),
+FP64, transmissive boundaries.  With --extra the near-vacuum blast on a ~1M-cell
+mesh is measured as well (reported under "extra").
+
+Prints one JSON line.  Only one GPU is supported: --gpus N with N > 1 exits.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, vendor figure
+KERNEL_SRC = os.path.join(ROOT, "paper_2409_09620_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+
+
+def algorithmic_bytes_per_cell(k):
+    """Bytes each kernel must move per cell and launch (FP64).  Neighbour re-reads
+    are cache hits and not counted.  S = state per cell, geometry as stored."""
+    nm = (k + 1) * (k + 2) // 2
+    S = 4 * nm * 8
+    g_res = 4 * 8 + 8 + 3 * 8 + 3 * 4          # J^-1, |K|, edge lengths, edge links
+    g_fil = g_res + 4 * 8                      # + reference coordinates of 2 limiter points
+    return {
+        # stage input + pre-filter write, plus u^n in 2 of 3 stages
+        "residual": S + g_res + S + (2.0 / 3.0) * S,
+        "mnorm": 2 * nm * 8,                   # momentum modes of the pre-filter state
+        "filter": S + g_fil + S,               # pre-filter state in, limited state out
+    }
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(kernel, workload):
+    try:
+        with open(TRAFFIC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    rec = d.get("kernels", {}).get(kernel)
+    if not rec or d.get("workload") != workload:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def run_gpu(mesh, kind, params, k, steps, warmup):
+    import torch
+    from paper_2409_09620_amd import Solver
+
+    s = Solver(mesh, k, device=0)
+    s.init_problem(kind, params)
+    for _ in range(warmup):
+        s.step()
+    torch.cuda.synchronize()
+    s.profile(True)
+    s.profile_read()                       # reset the accumulators
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile_read()
+    s.profile(False)
+    d = s.diag()
+    s.close()
+    return t1 - t0, prof, d
+
+
+def roofline(prof, k, n_cell, workload):
+    per_cell = algorithmic_bytes_per_cell(k)
+    kernels = {}
+    for name, (ms, n) in prof.items():
+        if n == 0:
+            continue
+        avg_s = ms / n / 1e3
+        alg = per_cell[name] * n_cell
+        kernels[name] = {"avg_us": avg_s * 1e6, "launches": n, "alg_bytes": alg,
+                         "gbs": alg / avg_s / 1e9}
+    dom = max(kernels, key=lambda x: kernels[x]["avg_us"] * kernels[x]["launches"])
+    kd = kernels[dom]
+    traffic = load_traffic(dom, workload)
+    return {
+        "bound": "hbm",
+        "kernel": dom,
+        "achieved": round(kd["gbs"], 1),
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": round(kd["gbs"] / PEAK_HBM_GBS, 4),
+        "traffic": traffic,
+        "alg_bytes_per_launch": int(kd["alg_bytes"]),
+        "avg_launch_us": round(kd["avg_us"], 2),
+    }, {n: {kk: (round(v, 2) if isinstance(v, float) else v) for kk, v in kd_.items()}
+        for n, kd_ in kernels.items()}
+
+
+def cpu_baseline(mesh, kind, params, k):
+    """The oracle as it stands (single thread, FP64) on one SSP-RK3 step of the
+    same workload."""
+    import oracle
+    o = oracle.Oracle(mesh, k)
+    o.init_problem(kind, params)
+    t0 = time.perf_counter()
+    r = o.step()
+    t1 = time.perf_counter()
+    assert r == 0
+    nm = (k + 1) * (k + 2) // 2
+    dof_stages = mesh.n_cell * 4 * nm * 3
+    return {"value": dof_stages / (t1 - t0), "unit": "DOF-stage updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"1 SSP-RK3 step (3 stages) of the same {mesh.n_cell}-cell P{k} workload, "
+                      f"single-threaded C oracle ({t1 - t0:.1f} s)",
+            "host_cpu": platform.processor() or platform.machine(), "host_threads": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cells", type=int, default=200_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extra", action="store_true", help="also run the ~1M-cell blast")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized buffer 5 times (reference kernel for HBM counters)")
+    args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 8, "copies": 5}), flush=True)
+        return
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the stage is not sharded across GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2409_09620_amd import binding
+    if not os.path.exists(binding.lib_path()):
+        import __graft_entry__
+        __graft_entry__.build()
+    from synth import workloads
+
+    torch.cuda.set_device(0)
+    k = 2
+    mesh, kind, params = workloads.quadrant_delaunay(n_cells=args.cells)
+    workload = f"p2_quadrant_delaunay_{args.cells // 1000}k_fp64"
+    elapsed, prof, d = run_gpu(mesh, kind, params, k, args.steps, args.warmup)
+    nm = (k + 1) * (k + 2) // 2
+    dof = mesh.n_cell * 4 * nm
+    value = dof * 3 * args.steps / elapsed
+    roof, per_kernel = roofline(prof, k, mesh.n_cell, workload)
+
+    out = {
+        "metric": "P2 Euler DOF-stage updates/s",
+        "value": value,
+        "unit": "DOF-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "cells": mesh.n_cell, "degree": k, "dof_per_cell": 4 * nm,
+                   "stages_per_step": 3, "precision": "fp64", "mesh": "poisson-disk delaunay",
+                   "problem": "four-quadrant riemann", "parallelism": "single-gpu"},
+        "roofline": roof,
+        "kernels": per_kernel,
+        "run": {"t": d["t"], "step": d["step"], "alpha": d["alpha"], "n_limited": d["n_limited"],
+                "device": torch.cuda.get_device_name(0)},
+    }
+    if args.extra:
+        bm, bk, bp = workloads.blast_delaunay()
+        be, bprof, bd = run_gpu(bm, bk, bp, 2, max(5, args.steps // 3), 2)
+        bsteps = max(5, args.steps // 3)
+        broof, bker = roofline(bprof, 2, bm.n_cell, f"p2_blast_delaunay_{bm.n_cell // 1000}k_fp64")
+        out["extra"] = {"p2_blast_1m_fp64": {
+            "value": bm.n_cell * 4 * nm * 3 * bsteps / be, "cells": bm.n_cell, "steps": bsteps,
+            "ms_per_step": be / bsteps * 1e3, "roofline": broof, "kernels": bker,
+            "n_limited": bd["n_limited"]}}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mesh, kind, params, k)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -152,6 +152,16 @@ typedef struct {
 /* Diagnostics of the context (synchronises). */
 dg_status dg_diag(dg_ctx* ctx, dg_diag_t* out);
 
+/* Kernel timing with HIP events recorded on the context's stream around every
+ * stage kernel launch (a few microseconds of overhead per launch).
+ * dg_profile_enable(ctx, 1) starts recording; dg_profile_read synchronises, adds
+ * the elapsed times since the last read into ms[k] and the launch counts into
+ * launches[k] for k = 0 residual pass, 1 momentum-norm pass, 2 filter pass, and
+ * restarts the accumulation.  Both arrays have DG_PROFILE_KERNELS entries. */
+#define DG_PROFILE_KERNELS 3
+dg_status dg_profile_enable(dg_ctx* ctx, int enable);
+dg_status dg_profile_read(dg_ctx* ctx, double* ms, int64_t* launches);
+
 /* Number of cells, degree and modes of the uploaded mesh. */
 dg_status dg_sizes(dg_ctx* ctx, int32_t* n_cell, int* k, int* n_modes);
 

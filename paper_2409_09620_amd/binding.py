@@ -68,6 +68,8 @@ _SIGS = {
     "dg_read_state": (_c_i, [_c_p, _c_i, _c_p]),
     "dg_diag": (_c_i, [_c_p, _c_p]),
     "dg_sizes": (_c_i, [_c_p, _c_p, _c_p, _c_p]),
+    "dg_profile_enable": (_c_i, [_c_p, _c_i]),
+    "dg_profile_read": (_c_i, [_c_p, _c_p, _c_p]),
     "dg_last_error": (ctypes.c_char_p, [_c_p]),
     "dg_destroy": (None, [_c_p]),
 }
@@ -206,6 +208,18 @@ class Solver:
         out["ubar"] = list(d.ubar)
         out["nrm"] = list(d.nrm)
         return out
+
+    KERNELS = ("residual", "mnorm", "filter")
+
+    def profile(self, enable=True):
+        self._check(load_library().dg_profile_enable(self.h, int(enable)))
+
+    def profile_read(self):
+        """{kernel: (total_ms, launches)} since the last read (synchronises)."""
+        ms = np.zeros(3)
+        n = np.zeros(3, np.int64)
+        self._check(load_library().dg_profile_read(self.h, _ptr(ms), _ptr(n)))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.KERNELS)}
 
     def mesh_tables(self):
         nc = self.nc

@@ -38,6 +38,12 @@ struct dg_ctx {
     double *u0 = nullptr, *u = nullptr, *w = nullptr, *part = nullptr;
     const double* last_out = nullptr;
     Glob* g = nullptr;
+
+    // kernel timing (dg_profile_enable)
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;    // pairs: start, stop
+    std::vector<int> prof_kind;         // kernel id of each pair
+    size_t prof_used = 0;               // pairs recorded since the last read
 };
 
 namespace {
@@ -168,11 +174,43 @@ dg_status read_glob(dg_ctx* c, Glob* h) {
     return DG_OK;
 }
 
+// records the start event of a timed launch; returns the pair index or -1
+dg_status prof_begin(dg_ctx* c, int kind, long* pair) {
+    *pair = -1;
+    if (!c->prof_on) return DG_OK;
+    if (c->prof_used == c->prof_kind.size()) {
+        hipEvent_t a, b;
+        HIP_TRY(c, hipEventCreate(&a));
+        HIP_TRY(c, hipEventCreate(&b));
+        c->prof_ev.push_back(a);
+        c->prof_ev.push_back(b);
+        c->prof_kind.push_back(kind);
+    }
+    c->prof_kind[c->prof_used] = kind;
+    HIP_TRY(c, hipEventRecord(c->prof_ev[2 * c->prof_used], c->stream));
+    *pair = (long)c->prof_used++;
+    return DG_OK;
+}
+
+dg_status prof_end(dg_ctx* c, long pair) {
+    if (pair >= 0) HIP_TRY(c, hipEventRecord(c->prof_ev[2 * pair + 1], c->stream));
+    return DG_OK;
+}
+
+#define TIMED_LAUNCH(ctx, kind, expr)                 \
+    do {                                              \
+        long pair_;                                   \
+        dg_status ps_ = prof_begin(ctx, kind, &pair_); \
+        if (ps_ != DG_OK) return ps_;                 \
+        LAUNCH_TRY(ctx, expr);                        \
+        if ((ps_ = prof_end(ctx, pair_)) != DG_OK) return ps_; \
+    } while (0)
+
 dg_status run_stage(dg_ctx* c, int s) {
     const oedg::StageArgs a = stage_args(c, s);
-    LAUNCH_TRY(c, oedg::launch_residual(c->cfg.k, a, c->stream));
-    if (c->cfg.oe_enable) LAUNCH_TRY(c, oedg::launch_mnorm(c->cfg.k, a, c->stream));
-    LAUNCH_TRY(c, oedg::launch_filter(c->cfg.k, a, c->stream));
+    TIMED_LAUNCH(c, 0, oedg::launch_residual(c->cfg.k, a, c->stream));
+    if (c->cfg.oe_enable) TIMED_LAUNCH(c, 1, oedg::launch_mnorm(c->cfg.k, a, c->stream));
+    TIMED_LAUNCH(c, 2, oedg::launch_filter(c->cfg.k, a, c->stream));
     c->last_out = a.uout;
     return DG_OK;
 }
@@ -468,6 +506,32 @@ dg_status dg_diag(dg_ctx* c, dg_diag_t* out) {
     return DG_OK;
 }
 
+dg_status dg_profile_enable(dg_ctx* c, int enable) {
+    if (!c) return DG_E_ARG;
+    if (c->host_only) return fail(c, DG_E_STATE, "host-only context");
+    c->prof_on = enable != 0;
+    return DG_OK;
+}
+
+dg_status dg_profile_read(dg_ctx* c, double* ms, int64_t* launches) {
+    if (!c || !ms || !launches) return DG_E_ARG;
+    if (c->host_only) return fail(c, DG_E_STATE, "host-only context");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < DG_PROFILE_KERNELS; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (size_t i = 0; i < c->prof_used; ++i) {
+        float t = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&t, c->prof_ev[2 * i], c->prof_ev[2 * i + 1]));
+        ms[c->prof_kind[i]] += t;
+        launches[c->prof_kind[i]] += 1;
+    }
+    c->prof_used = 0;
+    return DG_OK;
+}
+
 dg_status dg_sizes(dg_ctx* c, int32_t* n_cell, int* k, int* n_modes) {
     if (!c) return DG_E_ARG;
     if (!c->have_mesh) return fail(c, DG_E_STATE, "no mesh uploaded");
@@ -484,6 +548,11 @@ const char* dg_last_error(const dg_ctx* c) {
 
 void dg_destroy(dg_ctx* c) {
     if (!c) return;
+    if (!c->host_only) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+    }
     if (c->owned && !c->host_only) {
         (void)hipSetDevice(c->device);
         (void)hipStreamSynchronize(c->stream);
