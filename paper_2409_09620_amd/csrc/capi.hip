@@ -76,7 +76,6 @@ struct Layout {
 
 Layout layout(size_t nc, int k) {
     const size_t nm = (size_t)(k + 1) * (k + 2) / 2;
-    const size_t nblk = (nc + oedg::kBlock - 1) / oedg::kBlock;
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
@@ -88,7 +87,7 @@ Layout layout(size_t nc, int k) {
     L.u0 = take(4 * nm * nc * sizeof(double));
     L.u = take(4 * nm * nc * sizeof(double));
     L.w = take(std::max<size_t>(4 * nm, 7) * nc * sizeof(double));
-    L.part = take(nblk * 18 * sizeof(double));
+    L.part = take((size_t)16 * oedg::kMaxBlocks * sizeof(double));
     L.glob = take(sizeof(Glob));
     L.total = off;
     return L;
@@ -157,6 +156,7 @@ dg_status start(dg_ctx* c) {
     a.uout = c->u0;
     a.oe_enable = 0;
     LAUNCH_TRY(c, oedg::launch_filter(c->cfg.k, a, c->stream));
+    LAUNCH_TRY(c, oedg::launch_finalize(2, a, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->u, c->u0, 4 * (size_t)c->nm * c->mesh.n_cell * sizeof(double),
                               hipMemcpyDeviceToDevice, c->stream));
     c->last_out = c->u0;
@@ -209,8 +209,13 @@ dg_status prof_end(dg_ctx* c, long pair) {
 dg_status run_stage(dg_ctx* c, int s) {
     const oedg::StageArgs a = stage_args(c, s);
     TIMED_LAUNCH(c, 0, oedg::launch_residual(c->cfg.k, a, c->stream));
-    if (c->cfg.oe_enable) TIMED_LAUNCH(c, 1, oedg::launch_mnorm(c->cfg.k, a, c->stream));
+    LAUNCH_TRY(c, oedg::launch_finalize(0, a, c->stream));
+    if (c->cfg.oe_enable) {
+        TIMED_LAUNCH(c, 1, oedg::launch_mnorm(c->cfg.k, a, c->stream));
+        LAUNCH_TRY(c, oedg::launch_finalize(1, a, c->stream));
+    }
     TIMED_LAUNCH(c, 2, oedg::launch_filter(c->cfg.k, a, c->stream));
+    LAUNCH_TRY(c, oedg::launch_finalize(2, a, c->stream));
     c->last_out = a.uout;
     return DG_OK;
 }

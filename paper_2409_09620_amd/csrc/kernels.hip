@@ -1,20 +1,25 @@
 // gfx950 kernels of one BP RI-OEDG stage (2D Euler, P1/P2 modal DG on triangles).
 //
-// Three passes per stage, one thread per cell, state in structure-of-arrays
-// [var][mode][cell] so every own-cell load and store is coalesced:
+// Three passes per stage over a state stored as structure-of-arrays
+// [var][mode][cell] (cell fastest):
 //   k_residual  volume + edge quadrature of eq. DGSystem:Dis with the LF flux
-//               (eq. fluxLF), the diagonal mass, the SSP-RK3 combination (eq.
-//               RKTime); writes the pre-filter state and per-block partials of
+//               (eq. fluxLF), the diagonal mass and the SSP-RK3 combination (eq.
+//               RKTime); writes the pre-filter state and per-workgroup partials of
 //               sum |K| ubar_K and of min/max at the volume points (eq. normOmg).
 //   k_mnorm     ||| m - mbar |||_inf at the volume points (needs mbar first).
-//   k_filter    RIOE damping (eq. oe:sys, coefficients of eqs. OEScalar:beta,
-//               OEScalar:Coef2, oe:sysdelta2, RIOESys:CoefM), the BP limiter at
-//               the decomposition nodes (Sec. 4.4), and the max wave speed of the
-//               result (eq. 1250) that sets the next stage's LF viscosity and,
-//               after the third stage, Delta t (Sec. 5 with eq. 1692 / eq. 1713).
-// Each pass publishes per-workgroup partials; the last workgroup to finish (an
-// atomic ticket) reduces them in a fixed order, so results do not depend on
-// scheduling.  Neighbour data is gathered through the edge table (link).
+//   k_filter    RIOE damping (eq. oe:sys with eqs. OEScalar:beta, OEScalar:Coef2,
+//               oe:sysdelta2, RIOESys:CoefM), the BP limiter at the decomposition
+//               nodes (Sec. 4.4) and the max wave speed of the result (eq. 1250).
+// Each pass is followed by a one-workgroup finalize kernel that reduces the
+// partials in a fixed order, so results do not depend on scheduling and no
+// workgroup needs a device-scope fence.
+//
+// Lane layout of the residual and filter passes: the 4 lanes of a DPP quad own
+// one cell, lane v holding conservative variable v (rho, m1, m2, E).  A lane
+// keeps only its variable's modes in registers; values at a quadrature point are
+// exchanged inside the quad with DPP quad_perm moves.  Workgroups are spread so
+// that each XCD walks a contiguous range of the (Hilbert-ordered) cells, which
+// keeps neighbour gathers inside that XCD's L2.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -35,8 +40,8 @@ struct Rule<1> {
     static constexpr double xi[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
     static constexpr double eta[3] = {2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0};
     static constexpr double w[3] = {1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0};
-    static constexpr double s[2] = {0.2113248654051871, 0.7886751345948129};
-    static constexpr double ws[2] = {0.5, 0.5};
+    static constexpr double s[3] = {0.2113248654051871, 0.7886751345948129, 0.0};
+    static constexpr double ws[3] = {0.5, 0.5, 0.0};
 };
 template <>
 struct Rule<2> {
@@ -102,45 +107,172 @@ __device__ __forceinline__ void vertex_point(int v, double& x, double& e) {
     e = v == 2 ? 1.0 : 0.0;
 }
 
-template <int NM>
-__device__ __forceinline__ void eval4(const double (&u)[4][NM], const double* p, double* q) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        double s = u[v][0] * p[0];
-#pragma unroll
-        for (int l = 1; l < NM; ++l) s = fma(u[v][l], p[l], s);
-        q[v] = s;
+// Basis values at the fixed points of a stage, in constant memory: the point loops
+// run with a wave-uniform index, so these become scalar loads instead of registers.
+template <int K>
+struct Tab {
+    static constexpr int NM = Rule<K>::NM, NQ = Rule<K>::NQ, NE = Rule<K>::NE;
+    double vp[NQ][NM], vdx[NQ][NM], vde[NQ][NM];   // volume points: Psi, dPsi/dxi, dPsi/deta
+    double vw[NQ];                                 // volume weights
+    double ep[3 * NE][NM];                         // own edge Gauss points (edge i, node nu)
+    double vtp[3][NM], vtdx[3][NM], vtde[3][NM];   // reference vertices
+};
+
+constexpr void basis_at(int nm, double x, double e, double* p, double* dx, double* de) {
+    const double P[6] = {1.0, 4.0 * x + 2.0 * e - 2.0, 3.0 * e - 1.0,
+                         24.0 * x * x + 24.0 * x * e + 4.0 * e * e - 24.0 * x - 8.0 * e + 4.0,
+                         20.0 * x * e + 10.0 * e * e - 4.0 * x - 12.0 * e + 2.0, 10.0 * e * e - 8.0 * e + 1.0};
+    const double X[6] = {0.0, 4.0, 0.0, 48.0 * x + 24.0 * e - 24.0, 20.0 * e - 4.0, 0.0};
+    const double E[6] = {0.0, 2.0, 3.0, 24.0 * x + 8.0 * e - 8.0, 20.0 * x + 20.0 * e - 12.0, 20.0 * e - 8.0};
+    for (int l = 0; l < nm; ++l) {
+        p[l] = P[l];
+        dx[l] = X[l];
+        de[l] = E[l];
     }
+}
+
+template <int K>
+constexpr Tab<K> make_tab() {
+    using R = Rule<K>;
+    Tab<K> t{};
+    double scratch[6] = {}, scratch2[6] = {};
+    for (int m = 0; m < R::NQ; ++m) {
+        basis_at(R::NM, R::xi[m], R::eta[m], t.vp[m], t.vdx[m], t.vde[m]);
+        t.vw[m] = R::w[m];
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int nu = 0; nu < R::NE; ++nu) {
+            const double s = R::s[nu];
+            const double x = i == 0 ? 1.0 - s : (i == 1 ? 0.0 : s);
+            const double e = i == 0 ? s : (i == 1 ? 1.0 - s : 0.0);
+            basis_at(R::NM, x, e, t.ep[i * R::NE + nu], scratch, scratch2);
+        }
+    for (int vtx = 0; vtx < 3; ++vtx)
+        basis_at(R::NM, vtx == 1 ? 1.0 : 0.0, vtx == 2 ? 1.0 : 0.0, t.vtp[vtx], t.vtdx[vtx], t.vtde[vtx]);
+    return t;
+}
+
+__constant__ Tab<1> kTab1 = make_tab<1>();
+__constant__ Tab<2> kTab2 = make_tab<2>();
+template <int K>
+__device__ __forceinline__ const Tab<K>& tab();
+template <>
+__device__ __forceinline__ const Tab<1>& tab<1>() { return kTab1; }
+template <>
+__device__ __forceinline__ const Tab<2>& tab<2>() { return kTab2; }
+
+template <int NM>
+__device__ __forceinline__ double dot(const double* u, const double* p) {
+    double s = u[0] * p[0];
+#pragma unroll
+    for (int l = 1; l < NM; ++l) s = fma(u[l], p[l], s);
+    return s;
+}
+
+// ------------------------------------------------------------------------- fast FP64 helpers
+
+// 1/x from v_rcp_f64 and two Newton steps (about 1 ulp; not correctly rounded)
+__device__ __forceinline__ double frcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// sqrt(x) for x >= 0 from v_rsq_f64 and Goldschmidt/Newton corrections (about 1 ulp)
+__device__ __forceinline__ double fsqrt(double x) {
+    const double xs = x > 0.0 ? x : 1.0;
+    const double y = __builtin_amdgcn_rsq(xs);
+    double g = xs * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, xs);
+    g = fma(d, h, g);
+    d = fma(-g, g, xs);
+    g = fma(d, h, g);
+    return x > 0.0 ? g : 0.0;
+}
+
+// ------------------------------------------------------------------------- quad exchanges
+
+// DPP quad_perm move of a double: lane q of every quad receives lane perm[q]'s value
+template <int CTRL>
+__device__ __forceinline__ double qperm(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+template <int L>
+__device__ __forceinline__ double qget(double x) { return qperm<L * 0x55>(x); }   // broadcast lane L
+__device__ __forceinline__ double qswap12(double x) { return qperm<0xD8>(x); }   // [0,2,1,3]
+__device__ __forceinline__ double qxor1(double x) { return qperm<0xB1>(x); }     // [1,0,3,2]
+__device__ __forceinline__ double qxor2(double x) { return qperm<0x4E>(x); }     // [2,3,0,1]
+__device__ __forceinline__ double qmax(double x) {
+    x = fmax(x, qxor1(x));
+    return fmax(x, qxor2(x));
+}
+__device__ __forceinline__ double sel4(int v, double a0, double a1, double a2, double a3) {
+    return v == 0 ? a0 : (v == 1 ? a1 : (v == 2 ? a2 : a3));
+}
+// 4x4 transpose inside a quad: lane w holds x[c] = (its variable w at state c);
+// on return q[w] = variable w at state v, where v is the calling lane
+__device__ __forceinline__ void quad_transpose(int v, const double (&x)[4], double (&q)[4]) {
+    // round k: lane v reads lane (v+k)&3, which offers its entry (owner - k)&3 = v
+    const double r0 = sel4(v, x[0], x[1], x[2], x[3]);
+    const double r1 = qperm<0x39>(sel4(v, x[3], x[0], x[1], x[2]));   // rotate by 1: [1,2,3,0]
+    const double r2 = qperm<0x4E>(sel4(v, x[2], x[3], x[0], x[1]));   // rotate by 2: [2,3,0,1]
+    const double r3 = qperm<0x93>(sel4(v, x[1], x[2], x[3], x[0]));   // rotate by 3: [3,0,1,2]
+    // r_k is variable (v+k)&3
+    q[0] = sel4(v, r0, r3, r2, r1);
+    q[1] = sel4(v, r1, r0, r3, r2);
+    q[2] = sel4(v, r2, r1, r0, r3);
+    q[3] = sel4(v, r3, r2, r1, r0);
+}
+__device__ __forceinline__ double qmin(double x) {
+    x = fmin(x, qxor1(x));
+    return fmin(x, qxor2(x));
 }
 
 // ------------------------------------------------------------------------- Euler
 
-// normal flux F(q).n for a (possibly scaled) normal (nx, ny)
-__device__ __forceinline__ void normal_flux(const double* q, double nx, double ny, double gm1, double* f) {
-    const double ir = 1.0 / q[0];
-    const double mn = q[1] * nx + q[2] * ny;
-    const double p = gm1 * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) * ir);
+// component v of F(q).n for the lane's variable (s1, s2, s3 = [v==1], [v==2], [v==3]);
+// (nx, ny) may be a scaled normal
+__device__ __forceinline__ double lane_flux(double qv, double q0, double q1, double q2, double q3, double nx,
+                                            double ny, double gm1, double s1, double s2, double s3) {
+    const double ir = frcp(q0);
+    const double mn = q1 * nx + q2 * ny;
     const double vn = mn * ir;
-    f[0] = mn;
-    f[1] = q[1] * vn + p * nx;
-    f[2] = q[2] * vn + p * ny;
-    f[3] = (q[3] + p) * vn;
+    const double p = gm1 * (q3 - 0.5 * (q1 * q1 + q2 * q2) * ir);
+    return qv * vn + p * (s1 * nx + s2 * ny + s3 * vn);
 }
 
 // spectral radius |v.n| + c of F'(u).n (Example ex:euler); guarded so that a
 // pre-limiter state with rho <= 0 or p < 0 still gives a finite value
-__device__ __forceinline__ double spectral_radius(const double* q, double nx, double ny, double gamma) {
-    const double rs = fmax(q[0], kEpsBP);
-    const double ir = 1.0 / rs;
-    const double p = (gamma - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) * ir);
-    return fabs(q[1] * nx + q[2] * ny) * ir + sqrt(gamma * fmax(p, 0.0) * ir);
+__device__ __forceinline__ double spectral_radius(double q0, double q1, double q2, double q3, double nx, double ny,
+                                                  double gamma) {
+    const double ir = frcp(fmax(q0, kEpsBP));
+    const double p = (gamma - 1.0) * (q3 - 0.5 * (q1 * q1 + q2 * q2) * ir);
+    return fabs(q1 * nx + q2 * ny) * ir + fsqrt(gamma * fmax(p, 0.0) * ir);
 }
 
-__device__ __forceinline__ double internal_energy(const double* q) {
-    return q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / q[0];
-}
+// ------------------------------------------------------------------------- work distribution
 
-// ------------------------------------------------------------------------- reductions
+// Workgroup b of a pass with G workgroups (G a multiple of 8) runs on XCD b % 8;
+// XCD x owns the contiguous tile range [x T, (x+1) T), T = ceil(n_tiles / 8), which
+// its G/8 workgroups walk in dispatch order.
+struct TileWalk {
+    int first, end, stride;
+};
+__device__ __forceinline__ TileWalk tile_walk(int n_tiles) {
+    const int per_x = gridDim.x >> 3;
+    const int x = blockIdx.x & 7, r = blockIdx.x >> 3;
+    const int T = (n_tiles + 7) >> 3;
+    const int lo = x * T;
+    return {lo + r, min(lo + T, n_tiles), per_x};
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -152,68 +284,6 @@ __device__ __forceinline__ double wave_max(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;
 }
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// op: 0 sum, 1 min, 2 max.  Result valid in thread 0.  Fixed reduction order.
-template <int N>
-__device__ __forceinline__ void block_reduce(double* vals, const int* ops, double (*lds)[N]) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        double v = vals[k];
-        v = ops[k] == 0 ? wave_sum(v) : (ops[k] == 1 ? wave_min(v) : wave_max(v));
-        if (lane == 0) lds[wid][k] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            double v = lds[0][k];
-            for (int w = 1; w < kBlock / 64; ++w)
-                v = ops[k] == 0 ? v + lds[w][k] : (ops[k] == 1 ? fmin(v, lds[w][k]) : fmax(v, lds[w][k]));
-            vals[k] = v;
-        }
-    }
-    __syncthreads();
-}
-
-// Publishes this block's partials (thread 0 wrote them) and tells whether this
-// block is the last one of the grid to arrive.
-__device__ __forceinline__ bool arrive_last(unsigned int* ticket) {
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned int t = atomicAdd(ticket, 1u);
-        last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last;
-}
-
-// Reduces part[b * stride + k] over all blocks b in a fixed order.
-template <int N>
-__device__ __forceinline__ void reduce_partials(const double* part, int stride, int nblk, const int* ops,
-                                                double* out, double (*lds)[N]) {
-    double acc[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) acc[k] = ops[k] == 0 ? 0.0 : (ops[k] == 1 ? INFINITY : -INFINITY);
-    for (int b = threadIdx.x; b < nblk; b += kBlock) {
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const double v = __hip_atomic_load(part + (size_t)b * stride + k, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-            acc[k] = ops[k] == 0 ? acc[k] + v : (ops[k] == 1 ? fmin(acc[k], v) : fmax(acc[k], v));
-        }
-    }
-    block_reduce<N>(acc, ops, lds);
-    if (threadIdx.x == 0)
-        for (int k = 0; k < N; ++k) out[k] = acc[k];
-}
 
 // ------------------------------------------------------------------------- pass 1: residual
 
@@ -221,155 +291,132 @@ template <int K>
 __global__ __launch_bounds__(kBlock) void k_residual(StageArgs a) {
     using R = Rule<K>;
     constexpr int NM = R::NM;
-    Glob* g = a.g;
+    const Glob* g = a.g;
     if (!g->active) return;
     const int nc = a.m.n_cell;
-    const int c = blockIdx.x * kBlock + threadIdx.x;
     const size_t snc = (size_t)nc;
+    const int v = threadIdx.x & 3;
+    const double s1 = v == 1 ? 1.0 : 0.0, s2 = v == 2 ? 1.0 : 0.0, s3 = v == 3 ? 1.0 : 0.0;
+    const double alpha = g->alpha, dt = g->dt, gm1 = a.gamma - 1.0;
+    const double sa = a.stage == 0 ? 0.0 : (a.stage == 1 ? 0.75 : 1.0 / 3.0);
+    const double sb = a.stage == 0 ? 1.0 : (a.stage == 1 ? 0.25 : 2.0 / 3.0);
+    const double* uv = a.uin + (size_t)v * NM * snc;   // this lane's variable
+    double* wv = a.w + (size_t)v * NM * snc;
+    const double* u0v = a.u0 + (size_t)v * NM * snc;
+    const Tab<K>& T = tab<K>();
 
-    double red[kNumPartial];
+    double psum = 0.0, pmin = INFINITY, pmax = -INFINITY;
+    const TileWalk tw = tile_walk((nc + kCellsPerTile - 1) / kCellsPerTile);
+    for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
+        const int c = tile * kCellsPerTile + (threadIdx.x >> 2);
+        if (c >= nc) continue;   // whole quad
+        double u[NM];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        red[v] = 0.0;
-        red[4 + v] = INFINITY;
-        red[8 + v] = -INFINITY;
-    }
-
-    if (c < nc) {
-        const double alpha = g->alpha, dt = g->dt, gm1 = a.gamma - 1.0;
-        double u[4][NM];
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-            for (int l = 0; l < NM; ++l) u[v][l] = a.uin[(v * NM + l) * snc + c];
+        for (int l = 0; l < NM; ++l) u[l] = uv[l * snc + c];
         const double xx = a.m.jinv[c], xy = a.m.jinv[snc + c];
         const double ex = a.m.jinv[2 * snc + c], ey = a.m.jinv[3 * snc + c];
         const double area = a.m.area[c];
 
-        double r[4][NM];
+        double r[NM];
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-            for (int l = 0; l < NM; ++l) r[v][l] = 0.0;
+        for (int l = 0; l < NM; ++l) r[l] = 0.0;
 
-        // volume term: |K| sum_mu w_mu F(u) . grad Psi_l, with grad Psi = J^{-T} grad_ref Psi
-        // written as dPsi/dxi (F . grad xi) + dPsi/deta (F . grad eta)
-#pragma unroll
+        // volume term |K| sum_mu w_mu F(u).grad Psi_l with grad Psi = J^{-T} grad_ref Psi,
+        // i.e. dPsi/dxi (F.grad xi) + dPsi/deta (F.grad eta)
+#pragma unroll 1
         for (int m = 0; m < R::NQ; ++m) {
-            double p[NM], dx[NM], de[NM], q[4], g1[4], g2[4];
-            psi<K>(R::xi[m], R::eta[m], p);
-            dpsi<K>(R::xi[m], R::eta[m], dx, de);
-            eval4<NM>(u, p, q);
-            normal_flux(q, xx, xy, gm1, g1);
-            normal_flux(q, ex, ey, gm1, g2);
-            const double wa = R::w[m] * area;
+            const double* p = T.vp[m];
+            const double* dx = T.vdx[m];
+            const double* de = T.vde[m];
+            const double qv = dot<NM>(u, p);
+            const double q0 = qget<0>(qv), q1 = qget<1>(qv), q2 = qget<2>(qv), q3 = qget<3>(qv);
+            const double wa = T.vw[m] * area;
+            const double g1 = wa * lane_flux(qv, q0, q1, q2, q3, xx, xy, gm1, s1, s2, s3);
+            const double g2 = wa * lane_flux(qv, q0, q1, q2, q3, ex, ey, gm1, s1, s2, s3);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const double a1 = wa * g1[v], a2 = wa * g2[v];
-#pragma unroll
-                for (int l = 1; l < NM; ++l) r[v][l] = fma(dx[l], a1, fma(de[l], a2, r[v][l]));
-            }
+            for (int l = 1; l < NM; ++l) r[l] = fma(dx[l], g1, fma(de[l], g2, r[l]));
         }
 
-        // surface term: - sum_i l_i sum_nu w_nu Fhat(u_int, u_ext, n_i) Psi_l; the scaled
+        // surface term - sum_i l_i sum_nu w_nu Fhat(u_int, u_ext, n_i) Psi_l; the scaled
         // normal l_i n_i equals -2|K| grad(lambda_i) of the barycentric coordinate
-#pragma unroll
+#pragma unroll 1
         for (int i = 0; i < 3; ++i) {
             const double gx = i == 0 ? -(xx + ex) : (i == 1 ? xx : ex);
             const double gy = i == 0 ? -(xy + ey) : (i == 1 ? xy : ey);
             const double lnx = -2.0 * area * gx, lny = -2.0 * area * gy;
-            const double li = a.m.len[i * snc + c];
+            const double al = alpha * a.m.len[i * snc + c];
             const int link = a.m.link[i * snc + c];
             const bool has = link >= 0;
             const int nb = has ? (link >> 2) : c;
             const int j = link & 3;
-            double un[4][NM];
+            double un[NM];
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-#pragma unroll
-                for (int l = 0; l < NM; ++l) un[v][l] = a.uin[(v * NM + l) * snc + nb];
-#pragma unroll
+            for (int l = 0; l < NM; ++l) un[l] = uv[l * snc + nb];
+#pragma unroll 1
             for (int nu = 0; nu < R::NE; ++nu) {
-                double x, e, p[NM], qi[4], qe[4], fi[4], fe[4];
-                edge_point(i, R::s[nu], x, e);
-                psi<K>(x, e, p);
-                eval4<NM>(u, p, qi);
+                const double* p = T.ep[i * R::NE + nu];
+                const double sn = nu == 0 ? R::s[0] : (nu == 1 ? R::s[1] : R::s[2]);
+                const double wsn = nu == 0 ? R::ws[0] : (nu == 1 ? R::ws[1] : R::ws[2]);
+                const double qi = dot<NM>(u, p);
+                double qe = qi;
                 if (has) {
                     // the neighbour runs the shared edge the other way: parameter 1 - s
                     double xn, en, pn[NM];
-                    edge_point(j, 1.0 - R::s[nu], xn, en);
+                    edge_point(j, 1.0 - sn, xn, en);
                     psi<K>(xn, en, pn);
-                    eval4<NM>(un, pn, qe);
-                } else {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) qe[v] = qi[v];
+                    qe = dot<NM>(un, pn);
                 }
-                normal_flux(qi, lnx, lny, gm1, fi);
-                normal_flux(qe, lnx, lny, gm1, fe);
-                const double al = alpha * li;
+                const double fi = lane_flux(qi, qget<0>(qi), qget<1>(qi), qget<2>(qi), qget<3>(qi), lnx, lny, gm1,
+                                            s1, s2, s3);
+                const double fe = lane_flux(qe, qget<0>(qe), qget<1>(qe), qget<2>(qe), qget<3>(qe), lnx, lny, gm1,
+                                            s1, s2, s3);
+                const double fh = wsn * 0.5 * (fi + fe - al * (qe - qi));
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const double fh = R::ws[nu] * 0.5 * (fi[v] + fe[v] - al * (qe[v] - qi[v]));
-#pragma unroll
-                    for (int l = 0; l < NM; ++l) r[v][l] = fma(-fh, p[l], r[v][l]);
-                }
+                for (int l = 0; l < NM; ++l) r[l] = fma(-fh, p[l], r[l]);
             }
         }
 
         // diagonal mass a_K^(l) = |K| (a_l/|K|), then the SSP-RK3 combination
-        const double ia = 1.0 / area;
-        const double sa = a.stage == 0 ? 0.0 : (a.stage == 1 ? 0.75 : 1.0 / 3.0);
-        const double sb = a.stage == 0 ? 1.0 : (a.stage == 1 ? 0.25 : 2.0 / 3.0);
-        double w[4][NM];
+        const double ia = frcp(area);
+        double w[NM];
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-            for (int l = 0; l < NM; ++l) {
-                const double du = r[v][l] * ia * kInvMass[l];
-                const double adv = u[v][l] + dt * du;
-                double val;
-                if (a.stage == 0) {
-                    val = adv;
-                } else {
-                    val = sa * a.u0[(v * NM + l) * snc + c] + sb * adv;
-                }
-                w[v][l] = val;
-                a.w[(v * NM + l) * snc + c] = val;
-            }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) red[v] = area * w[v][0];
-#pragma unroll
+        for (int l = 0; l < NM; ++l) {
+            const double adv = u[l] + dt * (r[l] * ia * kInvMass[l]);
+            w[l] = a.stage == 0 ? adv : sa * u0v[l * snc + c] + sb * adv;
+            wv[l * snc + c] = w[l];
+        }
+        psum += area * w[0];
+#pragma unroll 1
         for (int m = 0; m < R::NQ; ++m) {
-            double p[NM], q[4];
-            psi<K>(R::xi[m], R::eta[m], p);
-            eval4<NM>(w, p, q);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                red[4 + v] = fmin(red[4 + v], q[v]);
-                red[8 + v] = fmax(red[8 + v], q[v]);
-            }
+            const double q = dot<NM>(w, T.vp[m]);
+            pmin = fmin(pmin, q);
+            pmax = fmax(pmax, q);
         }
     }
 
-    __shared__ double lds[kBlock / 64][kNumPartial];
-    const int ops[kNumPartial] = {0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 2};
-    block_reduce<kNumPartial>(red, ops, lds);
-    if (threadIdx.x == 0)
-        for (int k = 0; k < kNumPartial; ++k) a.part[(size_t)blockIdx.x * 16 + k] = red[k];
-    if (!arrive_last(&g->ticket[0])) return;
-
-    double tot[kNumPartial];
-    reduce_partials<kNumPartial>(a.part, 16, gridDim.x, ops, tot, lds);
-    if (threadIdx.x == 0) {
-        // eq. normOmg: ||u - ubar||_inf = max(max u - ubar, ubar - min u) over the volume points
-        for (int v = 0; v < 4; ++v) {
-            const double ub = tot[v] / g->area_sum;
-            const double n = fmax(tot[8 + v] - ub, ub - tot[4 + v]);
-            g->ubar[v] = ub;
-            g->nrm[v] = n;
-            g->inv_nrm[v] = n <= kEpsOE * fmax(1.0, fabs(ub)) ? 0.0 : 1.0 / n;
+    // reduce over the lanes holding the same variable (xor of lane ids >= 4), then waves
+#pragma unroll
+    for (int o = 4; o < 64; o <<= 1) {
+        psum += __shfl_xor(psum, o, 64);
+        pmin = fmin(pmin, __shfl_xor(pmin, o, 64));
+        pmax = fmax(pmax, __shfl_xor(pmax, o, 64));
+    }
+    __shared__ double lds[kBlock / 64][3][4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane < 4) {
+        lds[wid][0][lane] = psum;
+        lds[wid][1][lane] = pmin;
+        lds[wid][2][lane] = pmax;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumPartial) {
+        const int k = threadIdx.x >> 2, vv = threadIdx.x & 3;
+        double acc = lds[0][k][vv];
+        for (int w2 = 1; w2 < kBlock / 64; ++w2) {
+            const double x = lds[w2][k][vv];
+            acc = k == 0 ? acc + x : (k == 1 ? fmin(acc, x) : fmax(acc, x));
         }
-        g->ticket[0] = 0;
+        a.part[(size_t)threadIdx.x * kMaxBlocks + blockIdx.x] = acc;   // index k*4 + v
     }
 }
 
@@ -379,76 +426,43 @@ template <int K>
 __global__ __launch_bounds__(kBlock) void k_mnorm(StageArgs a) {
     using R = Rule<K>;
     constexpr int NM = R::NM;
-    Glob* g = a.g;
+    const Glob* g = a.g;
     if (!g->active) return;
     const int nc = a.m.n_cell;
-    const int c = blockIdx.x * kBlock + threadIdx.x;
     const size_t snc = (size_t)nc;
-    double best[1] = {0.0};
-    if (c < nc) {
-        const double mb1 = g->ubar[1], mb2 = g->ubar[2];
+    const double mb1 = g->ubar[1], mb2 = g->ubar[2];
+    double best = 0.0;
+    const TileWalk tw = tile_walk((nc + kCellsPerTileScalar - 1) / kCellsPerTileScalar);
+    for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
+        const int c = tile * kCellsPerTileScalar + threadIdx.x;
+        if (c >= nc) continue;
         double m1[NM], m2[NM];
 #pragma unroll
         for (int l = 0; l < NM; ++l) {
             m1[l] = a.w[(1 * NM + l) * snc + c];
             m2[l] = a.w[(2 * NM + l) * snc + c];
         }
-#pragma unroll
+#pragma unroll 1
         for (int m = 0; m < R::NQ; ++m) {
-            double p[NM];
-            psi<K>(R::xi[m], R::eta[m], p);
-            double s1 = m1[0] * p[0], s2 = m2[0] * p[0];
-#pragma unroll
-            for (int l = 1; l < NM; ++l) {
-                s1 = fma(m1[l], p[l], s1);
-                s2 = fma(m2[l], p[l], s2);
-            }
-            const double d1 = s1 - mb1, d2 = s2 - mb2;
-            best[0] = fmax(best[0], d1 * d1 + d2 * d2);
+            const double* p = tab<K>().vp[m];
+            const double d1 = dot<NM>(m1, p) - mb1, d2 = dot<NM>(m2, p) - mb2;
+            best = fmax(best, d1 * d1 + d2 * d2);
         }
     }
-    __shared__ double lds[kBlock / 64][1];
-    const int ops[1] = {2};
-    block_reduce<1>(best, ops, lds);
-    double* part = a.part + (size_t)gridDim.x * 16;
-    if (threadIdx.x == 0) part[blockIdx.x] = best[0];
-    if (!arrive_last(&g->ticket[1])) return;
-    double tot[1];
-    reduce_partials<1>(part, 1, gridDim.x, ops, tot, lds);
+    best = wave_max(best);
+    __shared__ double lds[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = best;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        const double n = sqrt(tot[0]);
-        const double mb = sqrt(g->ubar[1] * g->ubar[1] + g->ubar[2] * g->ubar[2]);
-        g->nrm_m = n;
-        g->inv_nrm_m = n <= kEpsOE * fmax(1.0, mb) ? 0.0 : 1.0 / n;
-        g->ticket[1] = 0;
+        double acc = lds[0];
+        for (int w2 = 1; w2 < kBlock / 64; ++w2) acc = fmax(acc, lds[w2]);
+        a.part[(size_t)kNumPartial * kMaxBlocks + blockIdx.x] = acc;
     }
 }
 
 // ------------------------------------------------------------------------- pass 3: OE, limiter, alpha
 
-// value and physical gradient of all variables at reference point (x, e)
-template <int K, int NM>
-__device__ __forceinline__ void eval_grad(const double (&u)[4][NM], double x, double e, double xx, double xy,
-                                          double ex, double ey, double* q, double* qx, double* qy) {
-    double p[NM], dx[NM], de[NM];
-    psi<K>(x, e, p);
-    dpsi<K>(x, e, dx, de);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        double s = 0.0, sx = 0.0, se = 0.0;
-#pragma unroll
-        for (int l = 0; l < NM; ++l) {
-            s = fma(u[v][l], p[l], s);
-            sx = fma(u[v][l], dx[l], sx);
-            se = fma(u[v][l], de[l], se);
-        }
-        q[v] = s;
-        qx[v] = sx * xx + se * ex;
-        qy[v] = sx * xy + se * ey;
-    }
-}
-
-// constant physical Hessian (xx, xy, yy) of a P2 field with modes u[0..5]
+// P2 physical Hessian (xx, xy, yy) of one variable with modes u[0..5] (constant per cell)
 __device__ __forceinline__ void hessian(const double* u, double xx, double xy, double ex, double ey, double* h) {
     const double hxx = 48.0 * u[3];
     const double hxe = 24.0 * u[3] + 20.0 * u[4];
@@ -458,273 +472,379 @@ __device__ __forceinline__ void hessian(const double* u, double xx, double xy, d
     h[2] = hxx * xy * xy + 2.0 * hxe * xy * ey + hee * ey * ey;
 }
 
+// value and physical gradient of one variable at reference point (x, e)
+template <int K, int NM>
+__device__ __forceinline__ void value_grad(const double* u, double x, double e, double xx, double xy, double ex,
+                                           double ey, double& q, double& qx, double& qy) {
+    double p[NM], dx[NM], de[NM];
+    psi<K>(x, e, p);
+    dpsi<K>(x, e, dx, de);
+    q = dot<NM>(u, p);
+    const double sx = dot<NM>(u, dx), se = dot<NM>(u, de);
+    qx = sx * xx + se * ex;
+    qy = sx * xy + se * ey;
+}
+
+// point t of the limiter's node set: 3 NE edge Gauss points, then the two extra points
+template <int K>
+__device__ __forceinline__ void node_point(int t, double n0x, double n0e, double n1x, double n1e, double& x,
+                                           double& e) {
+    using R = Rule<K>;
+    const int i = t / R::NE, nu = t - (t / R::NE) * R::NE;
+    const double s = nu == 0 ? R::s[0] : (nu == 1 ? R::s[1] : R::s[2]);
+    edge_point(i, s, x, e);
+    if (t == 3 * R::NE) {
+        x = n0x;
+        e = n0e;
+    } else if (t == 3 * R::NE + 1) {
+        x = n1x;
+        e = n1e;
+    }
+}
+
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_filter(StageArgs a) {
     using R = Rule<K>;
     constexpr int NM = R::NM;
-    Glob* g = a.g;
+    constexpr int NE = R::NE;
+    constexpr int NP = 3 * NE + 2;   // limiter node set size
+    const Glob* g = a.g;
     if (!g->active) return;
     const int nc = a.m.n_cell;
-    const int c = blockIdx.x * kBlock + threadIdx.x;
     const size_t snc = (size_t)nc;
     const double gamma = a.gamma;
-    double amax = 0.0;
-    int n_lim = 0, n_bad = 0;
+    const int v = threadIdx.x & 3;
+    const bool oe = a.oe_enable && a.stage >= 0;
+    const bool ri = a.oe_mode == 0;
+    const double dt = g->dt;
+    // inverse L-infinity norm of this lane's quantity (0 in the zero branch)
+    const double inv_my = v == 0 ? g->inv_nrm[0] : (v == 3 ? g->inv_nrm[3] : (ri ? g->inv_nrm_m : g->inv_nrm[v]));
+    const double* wsrc = a.w + (size_t)v * NM * snc;
+    double* wdst = a.uout + (size_t)v * NM * snc;
+    const Tab<K>& T = tab<K>();
 
-    if (c < nc) {
-        double w[4][NM];
+    double amax = 0.0, n_lim = 0.0, n_bad = 0.0;
+    const TileWalk tw = tile_walk((nc + kCellsPerTile - 1) / kCellsPerTile);
+    for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
+        const int c = tile * kCellsPerTile + (threadIdx.x >> 2);
+        if (c >= nc) continue;   // whole quad
+        double w[NM];
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-            for (int l = 0; l < NM; ++l) w[v][l] = a.w[(v * NM + l) * snc + c];
+        for (int l = 0; l < NM; ++l) w[l] = wsrc[l * snc + c];
         const double xx = a.m.jinv[c], xy = a.m.jinv[snc + c];
         const double ex = a.m.jinv[2 * snc + c], ey = a.m.jinv[3 * snc + c];
         const double area = a.m.area[c];
+        // unit outward normals n_i = l_i n_i / l_i with l_i n_i = -2|K| grad(lambda_i)
+        double nxs[3], nys[3], ils[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double gx = i == 0 ? -(xx + ex) : (i == 1 ? xx : ex);
+            const double gy = i == 0 ? -(xy + ey) : (i == 1 ? xy : ey);
+            ils[i] = frcp(a.m.len[i * snc + c]);
+            nxs[i] = -2.0 * area * gx * ils[i];
+            nys[i] = -2.0 * area * gy * ils[i];
+        }
 
-        if (a.oe_enable && a.stage >= 0) {
-            const double dt = g->dt;
-            const double inv_r = g->inv_nrm[0], inv_e = g->inv_nrm[3];
-            const double inv_m = g->inv_nrm_m, inv_1 = g->inv_nrm[1], inv_2 = g->inv_nrm[2];
-            const bool ri = a.oe_mode == 0;
-            double ho[4][3];
-            if constexpr (K == 2) {
+        if (oe) {
+            double sig[K + 1];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) hessian(w[v], xx, xy, ex, ey, ho[v]);
-            }
-            double sig[4][K + 1];
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-#pragma unroll
-                for (int j = 0; j <= K; ++j) sig[v][j] = 0.0;
-
-#pragma unroll
+            for (int jj = 0; jj <= K; ++jj) sig[jj] = 0.0;
+            double ho[3] = {0.0, 0.0, 0.0};
+            if constexpr (K == 2) hessian(w, xx, xy, ex, ey, ho);
+#pragma unroll 1
             for (int i = 0; i < 3; ++i) {
                 const int link = a.m.link[i * snc + c];
-                if (link < 0) continue;   // transmissive boundary: zero jump
+                if (link < 0) continue;   // transmissive boundary: zero jump (whole quad)
                 const int nb = link >> 2, j = link & 3;
-                double wn[4][NM];
+                double wn[NM];
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-#pragma unroll
-                    for (int l = 0; l < NM; ++l) wn[v][l] = a.w[(v * NM + l) * snc + nb];
+                for (int l = 0; l < NM; ++l) wn[l] = wsrc[l * snc + nb];
                 const double nxx = a.m.jinv[nb], nxy = a.m.jinv[snc + nb];
                 const double nex = a.m.jinv[2 * snc + nb], ney = a.m.jinv[3 * snc + nb];
-                const double li = a.m.len[i * snc + c];
-                const double gx = i == 0 ? -(xx + ex) : (i == 1 ? xx : ex);
-                const double gy = i == 0 ? -(xy + ey) : (i == 1 ? xy : ey);
-                const double il = 1.0 / li;
-                const double nx = -2.0 * area * gx * il, ny = -2.0 * area * gy * il;
-                const double h = 2.0 * area * il;
-
-                // S[q][j]: sum over the two endpoints of squared jumps of order j for
-                // q = rho, m_n (or m1), m_t (or m2), E
-                double S[4][K + 1];
+                const double nx = i == 0 ? nxs[0] : (i == 1 ? nxs[1] : nxs[2]);
+                const double ny = i == 0 ? nys[0] : (i == 1 ? nys[1] : nys[2]);
+                const double h = 2.0 * area * (i == 0 ? ils[0] : (i == 1 ? ils[1] : ils[2]));
+                // momentum lanes see m_n = m.n (lane 1) and m_t = m.(-n_y, n_x) (lane 2)
+                const double ca = (ri && (v == 1 || v == 2)) ? nx : 1.0;
+                const double cb = ri ? (v == 1 ? ny : (v == 2 ? -ny : 0.0)) : 0.0;
+                double S[K + 1];
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int jj = 0; jj <= K; ++jj) S[q][jj] = 0.0;
-                double beta = 0.0;
+                for (int jj = 0; jj <= K; ++jj) S[jj] = 0.0;
+                double xs[4];   // own variable at: own end 0, neighbour end 0, own end 1, neighbour end 1
 #pragma unroll
                 for (int end = 0; end < 2; ++end) {
                     // own vertex i+1 (then i+2) meets the neighbour's vertex j+2 (then j+1)
                     const int ov = (i + 1 + end) % 3;
-                    const int nv = (j + 2 - end) % 3;
-                    double ox, oe, px, pe;
-                    vertex_point(ov, ox, oe);
-                    vertex_point(nv, px, pe);
-                    double q[4], qx[4], qy[4], r[4], rx[4], ry[4];
-                    eval_grad<K, NM>(w, ox, oe, xx, xy, ex, ey, q, qx, qy);
-                    eval_grad<K, NM>(wn, px, pe, nxx, nxy, nex, ney, r, rx, ry);
-                    beta = fmax(beta, fmax(spectral_radius(q, nx, ny, gamma), spectral_radius(r, nx, ny, gamma)));
-                    double jv[4], jx[4], jy[4];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        jv[v] = r[v] - q[v];
-                        jx[v] = rx[v] - qx[v];
-                        jy[v] = ry[v] - qy[v];
+                    double px, pe;
+                    vertex_point((j + 2 - end) % 3, px, pe);
+                    double q, qx, qy, r, rx, ry;
+                    {
+                        q = dot<NM>(w, T.vtp[ov]);
+                        const double sx = dot<NM>(w, T.vtdx[ov]), se = dot<NM>(w, T.vtde[ov]);
+                        qx = sx * xx + se * ex;
+                        qy = sx * xy + se * ey;
                     }
-                    if (ri) {   // m_n = m . n, m_t = m . (-n_y, n_x)
-                        const double a0 = jv[1] * nx + jv[2] * ny, b0 = -jv[1] * ny + jv[2] * nx;
-                        const double a1 = jx[1] * nx + jx[2] * ny, b1 = -jx[1] * ny + jx[2] * nx;
-                        const double a2 = jy[1] * nx + jy[2] * ny, b2 = -jy[1] * ny + jy[2] * nx;
-                        jv[1] = a0; jv[2] = b0; jx[1] = a1; jx[2] = b1; jy[1] = a2; jy[2] = b2;
+                    value_grad<K, NM>(wn, px, pe, nxx, nxy, nex, ney, r, rx, ry);
+                    xs[2 * end] = q;
+                    xs[2 * end + 1] = r;
+                    double jv = r - q, jx = rx - qx, jy = ry - qy;
+                    if (ri) {
+                        jv = ca * jv + cb * qswap12(jv);
+                        jx = ca * jx + cb * qswap12(jx);
+                        jy = ca * jy + cb * qswap12(jy);
                     }
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        S[v][0] = fma(jv[v], jv[v], S[v][0]);
-                        S[v][1] = fma(jx[v], jx[v], fma(jy[v], jy[v], S[v][1]));
-                    }
+                    S[0] = fma(jv, jv, S[0]);
+                    S[1] = fma(jx, jx, fma(jy, jy, S[1]));
                 }
                 if constexpr (K == 2) {
-                    // second derivatives are constant per cell, so both endpoints carry
-                    // the same jump: 2 (jxx^2 + 2 jxy^2 + jyy^2)
-                    double hn[4][3];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        hessian(wn[v], nxx, nxy, nex, ney, hn[v]);
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) hn[v][d] -= ho[v][d];
-                    }
+                    // second derivatives are constant per cell: both endpoints carry the
+                    // same jump, 2 (jxx^2 + 2 jxy^2 + jyy^2)
+                    double hn[3];
+                    hessian(wn, nxx, nxy, nex, ney, hn);
+                    double d0 = hn[0] - ho[0], d1 = hn[1] - ho[1], d2 = hn[2] - ho[2];
                     if (ri) {
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            const double a0 = hn[1][d] * nx + hn[2][d] * ny, b0 = -hn[1][d] * ny + hn[2][d] * nx;
-                            hn[1][d] = a0;
-                            hn[2][d] = b0;
-                        }
+                        d0 = ca * d0 + cb * qswap12(d0);
+                        d1 = ca * d1 + cb * qswap12(d1);
+                        d2 = ca * d2 + cb * qswap12(d2);
                     }
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        S[v][2] = 2.0 * (hn[v][0] * hn[v][0] + 2.0 * hn[v][1] * hn[v][1] + hn[v][2] * hn[v][2]);
+                    S[2] = 2.0 * (d0 * d0 + 2.0 * d1 * d1 + d2 * d2);
                 }
+                // beta^(i): max spectral radius over both endpoints and both sides; lane v
+                // evaluates state v of the four
+                double st[4];
+                quad_transpose(v, xs, st);
+                const double beta = qmax(spectral_radius(st[0], st[1], st[2], st[3], nx, ny, gamma));
                 const double bh = beta / h;
                 double hj = 1.0;
 #pragma unroll
                 for (int jj = 0; jj <= K; ++jj) {
-                    const double f = kA[K][jj] * hj;
-                    const double dr = f * inv_r * sqrt(0.5 * S[0][jj]);
-                    const double de = f * inv_e * sqrt(0.5 * S[3][jj]);
-                    double d1, d2;
-                    if (ri) {
-                        d1 = d2 = f * inv_m * fmax(sqrt(0.5 * S[1][jj]), sqrt(0.5 * S[2][jj]));
-                    } else {
-                        d1 = f * inv_1 * sqrt(0.5 * S[1][jj]);
-                        d2 = f * inv_2 * sqrt(0.5 * S[2][jj]);
-                    }
-                    sig[0][jj] = fma(bh, dr, sig[0][jj]);
-                    sig[1][jj] = fma(bh, d1, sig[1][jj]);
-                    sig[2][jj] = fma(bh, d2, sig[2][jj]);
-                    sig[3][jj] = fma(bh, de, sig[3][jj]);
+                    double d = kA[K][jj] * hj * inv_my * fsqrt(0.5 * S[jj]);
+                    if (ri) d = fmax(d, qswap12(d));   // delta(m) = max(delta(m_n), delta(m_t))
+                    sig[jj] = fma(bh, d, sig[jj]);
                     hj *= h;
                 }
             }
             // exact solution of the damping ODE: degree-m modes scaled by
             // exp(-dt sum_{j<=m} sigma^j); the cell average is untouched (eq. OE:m0)
+            double acc = sig[0];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                double acc = sig[v][0];
+            for (int m = 1; m <= K; ++m) {
+                acc += sig[m];
+                const double f = exp(-dt * acc);
 #pragma unroll
-                for (int m = 1; m <= K; ++m) {
-                    acc += sig[v][m];
-                    const double f = exp(-dt * acc);
-#pragma unroll
-                    for (int l = m * (m + 1) / 2; l < (m + 1) * (m + 2) / 2; ++l) w[v][l] *= f;
-                }
+                for (int l = m * (m + 1) / 2; l < (m + 1) * (m + 2) / 2; ++l) w[l] *= f;
             }
         }
 
+        // every lane of the quad gets all coefficients of the cell; lane v then
+        // evaluates the full state at its share of points t = v, v+4, v+8
+        double W[4][NM];
+#pragma unroll
+        for (int l = 0; l < NM; ++l) {
+            W[0][l] = qget<0>(w[l]);
+            W[1][l] = qget<1>(w[l]);
+            W[2][l] = qget<2>(w[l]);
+            W[3][l] = qget<3>(w[l]);
+        }
+        const double n0x = a.m.node_ref[c], n0e = a.m.node_ref[snc + c];
+        const double n1x = a.m.node_ref[2 * snc + c], n1e = a.m.node_ref[3 * snc + c];
+
         if (a.bp_enable) {
-            // node set: 3 x NE edge Gauss points and two extra points (P1 vertices v1,
-            // v2 of eq. 1944; P2 internal nodes of eq. 1139)
-            const double n0x = a.m.node_ref[c], n0e = a.m.node_ref[snc + c];
-            const double n1x = a.m.node_ref[2 * snc + c], n1e = a.m.node_ref[3 * snc + c];
-            // step 1: density
-            const double rb = w[0][0];
-            double rmin = INFINITY;
-#pragma unroll
-            for (int t = 0; t < 3 * R::NE + 2; ++t) {
-                double x, e, p[NM];
-                if (t < 3 * R::NE) edge_point(t / R::NE, R::s[t % R::NE], x, e);
-                else if (t == 3 * R::NE) { x = n0x; e = n0e; }
-                else { x = n1x; e = n1e; }
-                psi<K>(x, e, p);
-                double s = w[0][0];
-#pragma unroll
-                for (int l = 1; l < NM; ++l) s = fma(w[0][l], p[l], s);
-                rmin = fmin(rmin, s);
+            // step 1: density (Sec. 4.4, eq. 1944)
+            const double rb = W[0][0];
+            double rloc = INFINITY;
+#pragma unroll 1
+            for (int kk = 0; kk < 3; ++kk) {
+                const int t = v + 4 * kk;
+                if (t < NP) {
+                    double x, e, p[NM];
+                    node_point<K>(t, n0x, n0e, n1x, n1e, x, e);
+                    psi<K>(x, e, p);
+                    rloc = fmin(rloc, dot<NM>(W[0], p));
+                }
             }
+            const double rmin = qmin(rloc);
             const double e1 = fmin(rb, kEpsBP);
             const double th1 = rmin >= e1 ? 1.0 : fmin((rb - e1) / (rb - rmin), 1.0);
 #pragma unroll
-            for (int l = 1; l < NM; ++l) w[0][l] *= th1;
-            // step 2: internal energy E - |m|^2 / (2 rho)
-            const double ub[4] = {w[0][0], w[1][0], w[2][0], w[3][0]};
-            const double eb = internal_energy(ub);
+            for (int l = 1; l < NM; ++l) W[0][l] *= th1;
+            // step 2: internal energy E - |m|^2 / (2 rho) (eq. 1981)
+            const double eb = W[3][0] - 0.5 * (W[1][0] * W[1][0] + W[2][0] * W[2][0]) / W[0][0];
             const double e2 = fmin(eb, kEpsBP);
-            double emin = INFINITY;
-#pragma unroll
-            for (int t = 0; t < 3 * R::NE + 2; ++t) {
-                double x, e, p[NM], q[4];
-                if (t < 3 * R::NE) edge_point(t / R::NE, R::s[t % R::NE], x, e);
-                else if (t == 3 * R::NE) { x = n0x; e = n0e; }
-                else { x = n1x; e = n1e; }
-                psi<K>(x, e, p);
-                eval4<NM>(w, p, q);
-                emin = fmin(emin, internal_energy(q));
+            double eloc = INFINITY;
+#pragma unroll 1
+            for (int kk = 0; kk < 3; ++kk) {
+                const int t = v + 4 * kk;
+                if (t < NP) {
+                    double x, e, p[NM];
+                    node_point<K>(t, n0x, n0e, n1x, n1e, x, e);
+                    psi<K>(x, e, p);
+                    const double q0 = dot<NM>(W[0], p), q1 = dot<NM>(W[1], p);
+                    const double q2 = dot<NM>(W[2], p), q3 = dot<NM>(W[3], p);
+                    eloc = fmin(eloc, q3 - 0.5 * (q1 * q1 + q2 * q2) * frcp(q0));
+                }
             }
+            const double emin = qmin(eloc);
             const double th2 = emin >= e2 ? 1.0 : fmin((eb - e2) / (eb - emin), 1.0);
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int l = 1; l < NM; ++l) w[v][l] *= th2;
-            n_lim = (th1 < 1.0 || th2 < 1.0) ? 1 : 0;
-            n_bad = (rb > 0.0 && eb > 0.0) ? 0 : 1;
+                for (int l = 1; l < NM; ++l) W[q][l] *= th2;
+#pragma unroll
+            for (int l = 1; l < NM; ++l) {
+                if (v == 0) w[l] *= th1;
+                w[l] *= th2;
+            }
+            if (v == 0) {
+                n_lim += (th1 < 1.0 || th2 < 1.0) ? 1.0 : 0.0;
+                n_bad += (rb > 0.0 && eb > 0.0) ? 0.0 : 1.0;
+            }
         }
 
         // max wave speed over the edge Gauss points of the limited state (eq. 1250)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const double gx = i == 0 ? -(xx + ex) : (i == 1 ? xx : ex);
-            const double gy = i == 0 ? -(xy + ey) : (i == 1 ? xy : ey);
-            const double il = 1.0 / a.m.len[i * snc + c];
-            const double nx = -2.0 * area * gx * il, ny = -2.0 * area * gy * il;
-#pragma unroll
-            for (int nu = 0; nu < R::NE; ++nu) {
-                double x, e, p[NM], q[4];
-                edge_point(i, R::s[nu], x, e);
+#pragma unroll 1
+        for (int kk = 0; kk < 3; ++kk) {
+            const int t = v + 4 * kk;
+            if (t < 3 * NE) {
+                double x, e, p[NM];
+                node_point<K>(t, n0x, n0e, n1x, n1e, x, e);
                 psi<K>(x, e, p);
-                eval4<NM>(w, p, q);
-                const double rr = spectral_radius(q, nx, ny, gamma);
+                const int i = t / NE;
+                const double nx = i == 0 ? nxs[0] : (i == 1 ? nxs[1] : nxs[2]);
+                const double ny = i == 0 ? nys[0] : (i == 1 ? nys[1] : nys[2]);
+                const double rr = spectral_radius(dot<NM>(W[0], p), dot<NM>(W[1], p), dot<NM>(W[2], p),
+                                                  dot<NM>(W[3], p), nx, ny, gamma);
                 amax = (rr > amax || rr != rr) ? rr : amax;
             }
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-            for (int l = 0; l < NM; ++l) a.uout[(v * NM + l) * snc + c] = w[v][l];
+        for (int l = 0; l < NM; ++l) wdst[l * snc + c] = w[l];
     }
 
+    amax = wave_max(amax);
+    n_lim = wave_sum(n_lim);
+    n_bad = wave_sum(n_bad);
     __shared__ double lds[kBlock / 64][3];
-    double red[3] = {amax, (double)n_lim, (double)n_bad};
-    const int ops[3] = {2, 0, 0};
-    block_reduce<3>(red, ops, lds);
-    double* part = a.part + (size_t)gridDim.x * 17;
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = red[0];
-        if (red[1] > 0) atomicAdd((unsigned long long*)&g->n_limited, (unsigned long long)red[1]);
-        if (red[2] > 0) atomicAdd((unsigned long long*)&g->n_bad, (unsigned long long)red[2]);
+    if ((threadIdx.x & 63) == 0) {
+        lds[threadIdx.x >> 6][0] = amax;
+        lds[threadIdx.x >> 6][1] = n_lim;
+        lds[threadIdx.x >> 6][2] = n_bad;
     }
-    if (!arrive_last(&g->ticket[2])) return;
-    const int opm[1] = {2};
-    double tot[1];
-    __shared__ double lds1[kBlock / 64][1];
-    reduce_partials<1>(part, 1, gridDim.x, opm, tot, lds1);
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        double acc = lds[0][k];
+        for (int w2 = 1; w2 < kBlock / 64; ++w2) acc = k == 0 ? fmax(acc, lds[w2][k]) : acc + lds[w2][k];
+        a.part[(size_t)(kNumPartial + 1 + k) * kMaxBlocks + blockIdx.x] = acc;
+    }
+}
+
+// ------------------------------------------------------------------------- finalize (one workgroup)
+
+constexpr int kFinThreads = 1024;
+
+// Reduces NC columns part[col[k] * kMaxBlocks + b], b < G, with op[k] (0 sum,
+// 1 min, 2 max) in a fixed order; the result is valid in thread 0.
+template <int NC>
+__device__ __forceinline__ void reduce_columns(const double* part, int G, const int (&col)[NC], const int (&op)[NC],
+                                               double (&out)[NC]) {
+    double acc[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) acc[k] = op[k] == 0 ? 0.0 : (op[k] == 1 ? INFINITY : -INFINITY);
+    for (int b = threadIdx.x; b < G; b += kFinThreads) {
+        double x[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) x[k] = part[(size_t)col[k] * kMaxBlocks + b];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) acc[k] = op[k] == 0 ? acc[k] + x[k] : (op[k] == 1 ? fmin(acc[k], x[k]) : fmax(acc[k], x[k]));
+    }
+    __shared__ double lds[kFinThreads / 64][NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        double v = acc[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double y = __shfl_xor(v, o, 64);
+            v = op[k] == 0 ? v + y : (op[k] == 1 ? fmin(v, y) : fmax(v, y));
+        }
+        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6][k] = v;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        const double alpha = tot[0];
-        g->ticket[2] = 0;
-        if (__hip_atomic_load(&g->n_bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0) {
-            g->err = 1;
-            g->active = 0;
-        }
-        if (a.stage < 2) {
-            g->alpha = alpha;
-            if (a.stage < 0) g->alpha_step = alpha;
-            else if (alpha > g->alpha_step * (1.0 + 1e-12)) g->n_cfl_exc += 1;
-        } else {
-            g->t += g->dt;
-            g->step += 1;
-            g->alpha = alpha;
-            g->alpha_step = alpha;
-        }
-        if (a.stage < 0 || a.stage == 2) {
-            double dt = g->c_ssp * g->minck / alpha;
-            const double rem = g->t_end - g->t;
-            if (rem < dt) dt = rem;
-            g->dt = dt;
-            if (!(isinf(g->t_end) || rem > 1e-12 * fmax(1.0, fabs(g->t_end)))) g->active = 0;
-            if (g->err) g->active = 0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            double v = lds[0][k];
+            for (int w2 = 1; w2 < kFinThreads / 64; ++w2)
+                v = op[k] == 0 ? v + lds[w2][k] : (op[k] == 1 ? fmin(v, lds[w2][k]) : fmax(v, lds[w2][k]));
+            out[k] = v;
         }
     }
+}
+
+// domain averages and L-infinity norms (eq. normOmg): ||u - ubar|| = max(max u - ubar, ubar - min u)
+__global__ __launch_bounds__(kFinThreads) void k_fin_residual(const double* part, int G, Glob* g) {
+    if (!g->active) return;
+    const int col[kNumPartial] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11};
+    const int op[kNumPartial] = {0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 2};
+    double tot[kNumPartial];
+    reduce_columns<kNumPartial>(part, G, col, op, tot);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double ub = tot[v] / g->area_sum;
+            const double n = fmax(tot[8 + v] - ub, ub - tot[4 + v]);
+            g->ubar[v] = ub;
+            g->nrm[v] = n;
+            g->inv_nrm[v] = n <= kEpsOE * fmax(1.0, fabs(ub)) ? 0.0 : 1.0 / n;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_fin_mnorm(const double* part, int G, Glob* g) {
+    if (!g->active) return;
+    const int col[1] = {kNumPartial};
+    const int op[1] = {2};
+    double best[1];
+    reduce_columns<1>(part, G, col, op, best);
+    if (threadIdx.x == 0) {
+        const double n = sqrt(best[0]);
+        const double mb = sqrt(g->ubar[1] * g->ubar[1] + g->ubar[2] * g->ubar[2]);
+        g->nrm_m = n;
+        g->inv_nrm_m = n <= kEpsOE * fmax(1.0, mb) ? 0.0 : 1.0 / n;
+    }
+}
+
+// alpha of the stage output; after the third stage (or the initial limiter pass)
+// t, the step count and Delta t = C_SSP/alpha min_K C^DCW_{K,k}|K|, clamped to t_end
+__global__ __launch_bounds__(kFinThreads) void k_fin_filter(const double* part, int G, Glob* g, int stage) {
+    if (!g->active) return;
+    const int col[3] = {kNumPartial + 1, kNumPartial + 2, kNumPartial + 3};
+    const int op[3] = {2, 0, 0};
+    double r[3];
+    reduce_columns<3>(part, G, col, op, r);
+    if (threadIdx.x != 0) return;
+    const double alpha = r[0], lim = r[1], bad = r[2];
+    g->n_limited += (long long)lim;
+    g->n_bad += (long long)bad;
+    if (bad > 0) g->err = 1;
+    if (stage < 2) {
+        g->alpha = alpha;
+        if (stage < 0) g->alpha_step = alpha;
+        else if (alpha > g->alpha_step * (1.0 + 1e-12)) g->n_cfl_exc += 1;
+    } else {
+        g->t += g->dt;
+        g->step += 1;
+        g->alpha = alpha;
+        g->alpha_step = alpha;
+    }
+    if (stage < 0 || stage == 2) {
+        double dt = g->c_ssp * g->minck / alpha;
+        const double rem = g->t_end - g->t;
+        if (rem < dt) dt = rem;
+        g->dt = dt;
+        if (!(isinf(g->t_end) || rem > 1e-12 * fmax(1.0, fabs(g->t_end)))) g->active = 0;
+    }
+    if (g->err) g->active = 0;
 }
 
 // ------------------------------------------------------------------------- initial data
@@ -842,24 +962,47 @@ inline unsigned grid_for(int nc) { return (unsigned)((nc + kBlock - 1) / kBlock)
 
 }  // namespace
 
+int pass_blocks(int n_cell, int per_tile) {
+    const int tiles = (n_cell + per_tile - 1) / per_tile;
+    const int g = ((tiles + 7) / 8) * 8;
+    return g < kMaxBlocks ? (g > 0 ? g : 8) : kMaxBlocks;
+}
+
 int launch_residual(int k, const StageArgs& a, void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    if (k == 1) hipLaunchKernelGGL(k_residual<1>, dim3(grid_for(a.m.n_cell)), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL(k_residual<2>, dim3(grid_for(a.m.n_cell)), dim3(kBlock), 0, s, a);
+    const dim3 grid(pass_blocks(a.m.n_cell, kCellsPerTile));
+    if (k == 1) hipLaunchKernelGGL(k_residual<1>, grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_residual<2>, grid, dim3(kBlock), 0, s, a);
     return (int)hipGetLastError();
 }
 
 int launch_mnorm(int k, const StageArgs& a, void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    if (k == 1) hipLaunchKernelGGL(k_mnorm<1>, dim3(grid_for(a.m.n_cell)), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL(k_mnorm<2>, dim3(grid_for(a.m.n_cell)), dim3(kBlock), 0, s, a);
+    const dim3 grid(pass_blocks(a.m.n_cell, kCellsPerTileScalar));
+    if (k == 1) hipLaunchKernelGGL(k_mnorm<1>, grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_mnorm<2>, grid, dim3(kBlock), 0, s, a);
     return (int)hipGetLastError();
 }
 
 int launch_filter(int k, const StageArgs& a, void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    if (k == 1) hipLaunchKernelGGL(k_filter<1>, dim3(grid_for(a.m.n_cell)), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL(k_filter<2>, dim3(grid_for(a.m.n_cell)), dim3(kBlock), 0, s, a);
+    const dim3 grid(pass_blocks(a.m.n_cell, kCellsPerTile));
+    if (k == 1) hipLaunchKernelGGL(k_filter<1>, grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_filter<2>, grid, dim3(kBlock), 0, s, a);
+    return (int)hipGetLastError();
+}
+
+int launch_finalize(int which, const StageArgs& a, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (which == 0)
+        hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(kFinThreads), 0, s, a.part,
+                           pass_blocks(a.m.n_cell, kCellsPerTile), a.g);
+    else if (which == 1)
+        hipLaunchKernelGGL(k_fin_mnorm, dim3(1), dim3(kFinThreads), 0, s, a.part,
+                           pass_blocks(a.m.n_cell, kCellsPerTileScalar), a.g);
+    else
+        hipLaunchKernelGGL(k_fin_filter, dim3(1), dim3(kFinThreads), 0, s, a.part,
+                           pass_blocks(a.m.n_cell, kCellsPerTile), a.g, a.stage);
     return (int)hipGetLastError();
 }
 

@@ -7,8 +7,11 @@
 
 namespace oedg {
 
-constexpr int kBlock = 256;       // threads per workgroup of the stage kernels
-constexpr int kNumPartial = 12;   // per-block partials of the residual pass
+constexpr int kBlock = 256;            // threads per workgroup of the stage kernels
+constexpr int kCellsPerTile = 64;      // a quad of 4 lanes per cell in the residual/filter passes
+constexpr int kCellsPerTileScalar = 256;   // one lane per cell in the momentum-norm pass
+constexpr int kMaxBlocks = 4096;       // upper bound of a pass's grid (= number of partials)
+constexpr int kNumPartial = 12;        // per-block partials of the residual pass
 
 // Host-side mesh tables built once per mesh (see mesh_host.cpp).  Per-cell arrays
 // that go to the device are structure-of-arrays: component-major, cell fastest.
@@ -53,7 +56,6 @@ struct Glob {
     long long n_cfl_exc;
     int active;          // 0: t reached t_end, or an error stopped the run
     int err;             // sticky: 1 once a cell average left the admissible set
-    unsigned int ticket[4];
 };
 
 struct DevMesh {
@@ -71,17 +73,25 @@ struct StageArgs {
     const double* u0;     // u^n for the SSP combination
     double* w;            // pre-filter state (written by the residual pass)
     double* uout;         // limited stage output
-    double* part;         // per-block partials
+    double* part;         // per-block partials: [12][kMaxBlocks] residual, [kMaxBlocks] momentum
+                          // norm, [3][kMaxBlocks] filter
     Glob* g;
     double gamma;
     int stage;            // 0, 1, 2; -1 = limiter and alpha only (initial data)
     int oe_enable, oe_mode, bp_enable;
 };
 
-// kernel launchers (kernels.hip); return a hipError_t as int
+// Grid of a pass over n_cell cells with `per_tile` cells per tile: a multiple of 8
+// (one share per XCD), at most kMaxBlocks; workgroups stride over their XCD's tiles.
+int pass_blocks(int n_cell, int per_tile);
+
+// kernel launchers (kernels.hip); return a hipError_t as int.  Each pass kernel
+// writes per-workgroup partials; the matching finalize kernel (one workgroup)
+// reduces them in a fixed order into Glob.
 int launch_residual(int k, const StageArgs& a, void* stream);
 int launch_mnorm(int k, const StageArgs& a, void* stream);
 int launch_filter(int k, const StageArgs& a, void* stream);
+int launch_finalize(int which, const StageArgs& a, void* stream);   // 0 residual, 1 mnorm, 2 filter
 int launch_project(int k, const StageArgs& a, int kind, const double* dparams, int n_params,
                    void* stream);
 int launch_set_end(Glob* g, double t_end, void* stream);
