@@ -355,16 +355,13 @@ __global__ __launch_bounds__(kBlock) void k_residual(StageArgs a) {
 #pragma unroll 1
             for (int nu = 0; nu < R::NE; ++nu) {
                 const double* p = T.ep[i * R::NE + nu];
-                const double sn = nu == 0 ? R::s[0] : (nu == 1 ? R::s[1] : R::s[2]);
                 const double wsn = nu == 0 ? R::ws[0] : (nu == 1 ? R::ws[1] : R::ws[2]);
                 const double qi = dot<NM>(u, p);
                 double qe = qi;
                 if (has) {
-                    // the neighbour runs the shared edge the other way: parameter 1 - s
-                    double xn, en, pn[NM];
-                    edge_point(j, 1.0 - sn, xn, en);
-                    psi<K>(xn, en, pn);
-                    qe = dot<NM>(un, pn);
+                    // the neighbour runs the shared edge the other way: its parameter is
+                    // 1 - s_nu = s_{NE-1-nu} (symmetric Gauss nodes)
+                    qe = dot<NM>(un, T.ep[j * R::NE + (R::NE - 1 - nu)]);
                 }
                 const double fi = lane_flux(qi, qget<0>(qi), qget<1>(qi), qget<2>(qi), qget<3>(qi), lnx, lny, gm1,
                                             s1, s2, s3);
@@ -574,17 +571,18 @@ __global__ __launch_bounds__(kBlock) void k_filter(StageArgs a) {
 #pragma unroll
                 for (int end = 0; end < 2; ++end) {
                     // own vertex i+1 (then i+2) meets the neighbour's vertex j+2 (then j+1)
-                    const int ov = (i + 1 + end) % 3;
-                    double px, pe;
-                    vertex_point((j + 2 - end) % 3, px, pe);
+                    const int ov = (i + 1 + end) % 3, nv = (j + 2 - end) % 3;
                     double q, qx, qy, r, rx, ry;
                     {
                         q = dot<NM>(w, T.vtp[ov]);
                         const double sx = dot<NM>(w, T.vtdx[ov]), se = dot<NM>(w, T.vtde[ov]);
                         qx = sx * xx + se * ex;
                         qy = sx * xy + se * ey;
+                        r = dot<NM>(wn, T.vtp[nv]);
+                        const double tx = dot<NM>(wn, T.vtdx[nv]), te = dot<NM>(wn, T.vtde[nv]);
+                        rx = tx * nxx + te * nex;
+                        ry = tx * nxy + te * ney;
                     }
-                    value_grad<K, NM>(wn, px, pe, nxx, nxy, nex, ney, r, rx, ry);
                     xs[2 * end] = q;
                     xs[2 * end + 1] = r;
                     double jv = r - q, jx = rx - qx, jy = ry - qy;
@@ -649,47 +647,43 @@ __global__ __launch_bounds__(kBlock) void k_filter(StageArgs a) {
         const double n0x = a.m.node_ref[c], n0e = a.m.node_ref[snc + c];
         const double n1x = a.m.node_ref[2 * snc + c], n1e = a.m.node_ref[3 * snc + c];
 
+        // the full state at this lane's points t = v, v+4, v+8 of the node set
+        double pv[3][4];
+        bool pin[3];
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+            const int t = v + 4 * kk;
+            pin[kk] = t < NP;
+            double x, e, p[NM];
+            node_point<K>(t < NP ? t : v, n0x, n0e, n1x, n1e, x, e);
+            psi<K>(x, e, p);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pv[kk][q] = dot<NM>(W[q], p);
+        }
+        const double ub0 = W[0][0], ub1 = W[1][0], ub2 = W[2][0], ub3 = W[3][0];
+        double th1 = 1.0, th2 = 1.0;
         if (a.bp_enable) {
             // step 1: density (Sec. 4.4, eq. 1944)
-            const double rb = W[0][0];
             double rloc = INFINITY;
-#pragma unroll 1
-            for (int kk = 0; kk < 3; ++kk) {
-                const int t = v + 4 * kk;
-                if (t < NP) {
-                    double x, e, p[NM];
-                    node_point<K>(t, n0x, n0e, n1x, n1e, x, e);
-                    psi<K>(x, e, p);
-                    rloc = fmin(rloc, dot<NM>(W[0], p));
-                }
-            }
-            const double rmin = qmin(rloc);
-            const double e1 = fmin(rb, kEpsBP);
-            const double th1 = rmin >= e1 ? 1.0 : fmin((rb - e1) / (rb - rmin), 1.0);
 #pragma unroll
-            for (int l = 1; l < NM; ++l) W[0][l] *= th1;
-            // step 2: internal energy E - |m|^2 / (2 rho) (eq. 1981)
-            const double eb = W[3][0] - 0.5 * (W[1][0] * W[1][0] + W[2][0] * W[2][0]) / W[0][0];
+            for (int kk = 0; kk < 3; ++kk)
+                if (pin[kk]) rloc = fmin(rloc, pv[kk][0]);
+            const double rmin = qmin(rloc);
+            const double e1 = fmin(ub0, kEpsBP);
+            th1 = rmin >= e1 ? 1.0 : fmin((ub0 - e1) / (ub0 - rmin), 1.0);
+            // step 2: internal energy E - |m|^2 / (2 rho) of the density-scaled state (eq. 1981)
+            const double eb = ub3 - 0.5 * (ub1 * ub1 + ub2 * ub2) / ub0;
             const double e2 = fmin(eb, kEpsBP);
             double eloc = INFINITY;
-#pragma unroll 1
+#pragma unroll
             for (int kk = 0; kk < 3; ++kk) {
-                const int t = v + 4 * kk;
-                if (t < NP) {
-                    double x, e, p[NM];
-                    node_point<K>(t, n0x, n0e, n1x, n1e, x, e);
-                    psi<K>(x, e, p);
-                    const double q0 = dot<NM>(W[0], p), q1 = dot<NM>(W[1], p);
-                    const double q2 = dot<NM>(W[2], p), q3 = dot<NM>(W[3], p);
-                    eloc = fmin(eloc, q3 - 0.5 * (q1 * q1 + q2 * q2) * frcp(q0));
-                }
+                pv[kk][0] = ub0 + th1 * (pv[kk][0] - ub0);
+                if (pin[kk])
+                    eloc = fmin(eloc, pv[kk][3] - 0.5 * (pv[kk][1] * pv[kk][1] + pv[kk][2] * pv[kk][2]) *
+                                                      frcp(pv[kk][0]));
             }
             const double emin = qmin(eloc);
-            const double th2 = emin >= e2 ? 1.0 : fmin((eb - e2) / (eb - emin), 1.0);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int l = 1; l < NM; ++l) W[q][l] *= th2;
+            th2 = emin >= e2 ? 1.0 : fmin((eb - e2) / (eb - emin), 1.0);
 #pragma unroll
             for (int l = 1; l < NM; ++l) {
                 if (v == 0) w[l] *= th1;
@@ -697,23 +691,21 @@ __global__ __launch_bounds__(kBlock) void k_filter(StageArgs a) {
             }
             if (v == 0) {
                 n_lim += (th1 < 1.0 || th2 < 1.0) ? 1.0 : 0.0;
-                n_bad += (rb > 0.0 && eb > 0.0) ? 0.0 : 1.0;
+                n_bad += (ub0 > 0.0 && eb > 0.0) ? 0.0 : 1.0;
             }
         }
 
         // max wave speed over the edge Gauss points of the limited state (eq. 1250)
-#pragma unroll 1
+#pragma unroll
         for (int kk = 0; kk < 3; ++kk) {
             const int t = v + 4 * kk;
             if (t < 3 * NE) {
-                double x, e, p[NM];
-                node_point<K>(t, n0x, n0e, n1x, n1e, x, e);
-                psi<K>(x, e, p);
                 const int i = t / NE;
                 const double nx = i == 0 ? nxs[0] : (i == 1 ? nxs[1] : nxs[2]);
                 const double ny = i == 0 ? nys[0] : (i == 1 ? nys[1] : nys[2]);
-                const double rr = spectral_radius(dot<NM>(W[0], p), dot<NM>(W[1], p), dot<NM>(W[2], p),
-                                                  dot<NM>(W[3], p), nx, ny, gamma);
+                const double rr = spectral_radius(ub0 + th2 * (pv[kk][0] - ub0), ub1 + th2 * (pv[kk][1] - ub1),
+                                                  ub2 + th2 * (pv[kk][2] - ub2), ub3 + th2 * (pv[kk][3] - ub3), nx,
+                                                  ny, gamma);
                 amax = (rr > amax || rr != rr) ? rr : amax;
             }
         }

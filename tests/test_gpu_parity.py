@@ -63,6 +63,19 @@ def make(case, **cfg):
     return s, o, m
 
 
+def alpha_tolerance(o, limited, floor=1e-13):
+    """Relative bound for the max wave speed of a limited state.
+
+    The density at an edge Gauss point is a sum of O(rho_bar) terms; where the
+    limiter pinned it near its 1e-13 floor two FP64 evaluation orders differ by
+    about 1e-16 rho_bar absolutely, and the sound speed (~ rho^-1/2) inherits
+    half that relative error.  Bound: 1e-15 * max_K rho_bar_K / rho_min_K."""
+    npt = 3 * (o.k + 1)
+    vals = o.limiter_node_values(limited)[:, :npt, 0]
+    ratio = (np.abs(limited[0, 0, :]) / np.maximum(vals.min(axis=1), 1e-13)).max()
+    return max(floor, 1e-15 * ratio)
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_initial_state_parity(case):
     s, o, m = make(case)
@@ -72,8 +85,9 @@ def test_initial_state_parity(case):
     assert rel_err(u, ref) < 1e-13
     d = s.diag()
     so = o.scalars()
-    assert abs(d["alpha"] - so["alpha"]) <= 1e-13 * so["alpha"]
-    assert abs(d["dt"] - so["dt"]) <= 1e-13 * so["dt"]
+    a_tol = alpha_tolerance(o, ref)
+    assert abs(d["alpha"] - so["alpha"]) <= a_tol * so["alpha"], (d["alpha"], so["alpha"], a_tol)
+    assert abs(d["dt"] - so["dt"]) <= a_tol * so["dt"]
 
 
 def oracle_sensitivity(m, k, u, seed=0):
@@ -96,9 +110,11 @@ def test_stage_by_stage_parity(case):
     s, o, m = make(case)
     k = s.k
     for step in range(2):
-        dt_step = o.scalars()["dt"]
         for st in range(3):
-            tol = max(1e-12, 100.0 * oracle_sensitivity(m, k, o.state(0 if st == 0 else 1)))
+            u_in = o.state(0 if st == 0 else 1)
+            # the stage's LF viscosity is alpha of its input: its conditioning bounds
+            # the state agreement too (relative alpha error enters the dissipation)
+            tol = max(1e-12, 100.0 * oracle_sensitivity(m, k, u_in), 10.0 * alpha_tolerance(o, u_in))
             s.stage(st)
             o.stage(st)
             pre, out = s.read_state(2), s.read_state(1)
@@ -110,12 +126,7 @@ def test_stage_by_stage_parity(case):
         assert abs(d["t"] - so["t"]) <= 1e-14 * max(1.0, so["t"])
         # alpha at a node whose density the limiter pinned to its floor is the
         # difference of O(1) terms: bound it by the oracle's own round-off response
-        f = o.oe(o.state(2), dt_step)
-        rng = np.random.default_rng(1)
-        l0, _ = o.limit(f)
-        lp, _ = o.limit(f * (1.0 + 1e-15 * rng.standard_normal(f.shape)))
-        a0 = o.alpha_of(l0)
-        a_tol = max(1e-12, 100.0 * abs(o.alpha_of(lp) - a0) / a0)
+        a_tol = alpha_tolerance(o, o.state(0), floor=1e-12)
         assert abs(d["alpha"] - so["alpha"]) <= a_tol * so["alpha"], (d["alpha"], so["alpha"], a_tol)
         assert abs(d["dt"] - so["dt"]) <= a_tol * so["dt"]
         assert d["step"] == so["step"]
