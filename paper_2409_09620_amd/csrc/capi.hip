@@ -44,6 +44,12 @@ struct dg_ctx {
     std::vector<hipEvent_t> prof_ev;    // pairs: start, stop
     std::vector<int> prof_kind;         // kernel id of each pair
     size_t prof_used = 0;               // pairs recorded since the last read
+
+    // one captured SSP-RK3 step, replayed on `stream` (rebuilt after set-up changes)
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t step_graph = nullptr;
+    hipGraphExec_t step_exec = nullptr;
+    bool graph_failed = false;
 };
 
 namespace {
@@ -156,7 +162,7 @@ dg_status start(dg_ctx* c) {
     a.uout = c->u0;
     a.oe_enable = 0;
     LAUNCH_TRY(c, oedg::launch_filter(c->cfg.k, a, c->stream));
-    LAUNCH_TRY(c, oedg::launch_finalize(2, a, c->stream));
+    LAUNCH_TRY(c, oedg::launch_finalize(2, c->cfg.k, a, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->u, c->u0, 4 * (size_t)c->nm * c->mesh.n_cell * sizeof(double),
                               hipMemcpyDeviceToDevice, c->stream));
     c->last_out = c->u0;
@@ -209,14 +215,65 @@ dg_status prof_end(dg_ctx* c, long pair) {
 dg_status run_stage(dg_ctx* c, int s) {
     const oedg::StageArgs a = stage_args(c, s);
     TIMED_LAUNCH(c, 0, oedg::launch_residual(c->cfg.k, a, c->stream));
-    LAUNCH_TRY(c, oedg::launch_finalize(0, a, c->stream));
+    LAUNCH_TRY(c, oedg::launch_finalize(0, c->cfg.k, a, c->stream));
     if (c->cfg.oe_enable) {
         TIMED_LAUNCH(c, 1, oedg::launch_mnorm(c->cfg.k, a, c->stream));
-        LAUNCH_TRY(c, oedg::launch_finalize(1, a, c->stream));
+        LAUNCH_TRY(c, oedg::launch_finalize(1, c->cfg.k, a, c->stream));
     }
     TIMED_LAUNCH(c, 2, oedg::launch_filter(c->cfg.k, a, c->stream));
-    LAUNCH_TRY(c, oedg::launch_finalize(2, a, c->stream));
+    LAUNCH_TRY(c, oedg::launch_finalize(2, c->cfg.k, a, c->stream));
     c->last_out = a.uout;
+    return DG_OK;
+}
+
+void drop_graph(dg_ctx* c) {
+    if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
+    if (c->step_graph) (void)hipGraphDestroy(c->step_graph);
+    c->step_exec = nullptr;
+    c->step_graph = nullptr;
+}
+
+// Runs one step.  Without kernel timing the three stages are captured once into a
+// HIP graph (on a library-owned stream, since the null stream cannot be captured)
+// and replayed on the context's stream; every kernel reads its scalars (alpha,
+// Delta t, t) from device memory, so a replay is the same as launching them anew.
+dg_status run_step(dg_ctx* c) {
+    dg_status st;
+    if (c->prof_on || c->graph_failed) {
+        for (int s = 0; s < 3; ++s)
+            if ((st = run_stage(c, s)) != DG_OK) return st;
+        return DG_OK;
+    }
+    if (!c->step_exec) {
+        if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipStream_t user = c->stream;
+        c->stream = c->cap_stream;
+        hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+        st = DG_OK;
+        if (e == hipSuccess) {
+            for (int s = 0; s < 3 && st == DG_OK; ++s) st = run_stage(c, s);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+            if (st == DG_OK && e2 == hipSuccess && g) {
+                c->step_graph = g;
+                if (hipGraphInstantiate(&c->step_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+                    drop_graph(c);
+                    c->graph_failed = true;
+                }
+            } else {
+                if (g) (void)hipGraphDestroy(g);
+                c->graph_failed = true;
+            }
+        } else {
+            c->graph_failed = true;
+        }
+        c->stream = user;
+        if (st != DG_OK) return st;
+        (void)hipGetLastError();
+        if (c->graph_failed) return run_step(c);
+    }
+    HIP_TRY(c, hipGraphLaunch(c->step_exec, c->stream));
+    c->last_out = c->u0;
     return DG_OK;
 }
 
@@ -341,6 +398,7 @@ dg_status dg_mesh_upload(dg_ctx* c, int k, int32_t n_vert, const double* xy, int
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->have_mesh = true;
     c->initialised = false;
+    drop_graph(c);
     return DG_OK;
 }
 
@@ -366,6 +424,7 @@ dg_status dg_init(dg_ctx* c, const dg_config* cfg, const double* u0_modal) {
     if ((s = check_cfg(c, cfg)) != DG_OK) return s;
     if (!u0_modal) return fail(c, DG_E_ARG, "null initial state");
     c->cfg = *cfg;
+    drop_graph(c);
     HIP_TRY(c, hipMemcpyAsync(c->u0, u0_modal, 4 * (size_t)c->nm * c->mesh.n_cell * sizeof(double),
                               hipMemcpyHostToDevice, c->stream));
     if ((s = reset_glob(c)) != DG_OK) return s;
@@ -380,6 +439,7 @@ dg_status dg_init_problem(dg_ctx* c, const dg_config* cfg, int kind, const doubl
     if (kind < 0 || kind > 3 || !params || n_params < need[kind] || n_params > 19)
         return fail(c, DG_E_ARG, "bad problem kind or parameter count");
     c->cfg = *cfg;
+    drop_graph(c);
     const oedg::HostMesh& m = c->mesh;
     const size_t nc = (size_t)m.n_cell;
     std::vector<double> P(params, params + n_params);
@@ -428,9 +488,7 @@ dg_status dg_step(dg_ctx* c, double* dt_out) {
         if ((st = read_glob(c, &h)) != DG_OK) return st;
         *dt_out = h.active ? h.dt : 0.0;
     }
-    for (int s = 0; s < 3; ++s)
-        if ((st = run_stage(c, s)) != DG_OK) return st;
-    return DG_OK;
+    return run_step(c);
 }
 
 dg_status dg_step_to(dg_ctx* c, double t_end, int64_t max_steps, int64_t* steps_done) {
@@ -446,8 +504,7 @@ dg_status dg_step_to(dg_ctx* c, double t_end, int64_t max_steps, int64_t* steps_
     while (launched < max_steps) {
         const int64_t n = std::min<int64_t>(chunk, max_steps - launched);
         for (int64_t i = 0; i < n; ++i)
-            for (int s = 0; s < 3; ++s)
-                if ((st = run_stage(c, s)) != DG_OK) return st;
+            if ((st = run_step(c)) != DG_OK) return st;
         launched += n;
         if ((st = read_glob(c, &h)) != DG_OK) return st;
         if (!h.active || h.err) break;
@@ -557,6 +614,8 @@ void dg_destroy(dg_ctx* c) {
         (void)hipSetDevice(c->device);
         (void)hipStreamSynchronize(c->stream);
         for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+        drop_graph(c);
+        if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     }
     if (c->owned && !c->host_only) {
         (void)hipSetDevice(c->device);

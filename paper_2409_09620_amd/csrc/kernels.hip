@@ -22,7 +22,10 @@
 // keeps neighbour gathers inside that XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <unordered_map>
 
 #include "oedg_internal.h"
 
@@ -954,15 +957,42 @@ inline unsigned grid_for(int nc) { return (unsigned)((nc + kBlock - 1) / kBlock)
 
 }  // namespace
 
-int pass_blocks(int n_cell, int per_tile) {
+// Grid of a pass: one workgroup per tile while the tiles fit on the GPU at once,
+// otherwise as many workgroups as can be resident (occupancy x compute units),
+// rounded down to a multiple of 8 so every XCD gets the same share; workgroups
+// then stride over their XCD's tiles.  Bounded by kMaxBlocks (the partials).
+template <typename Kern>
+int resident_blocks(Kern kernel) {
+    static std::mutex mu;
+    static std::unordered_map<const void*, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    const void* key = reinterpret_cast<const void*>(kernel);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1, cus = cus > 0 ? cus : 256;
+    const int g = std::min(kMaxBlocks, std::max(8, (cus * per_cu) / 8 * 8));
+    cache[key] = g;
+    return g;
+}
+
+int grid_for_pass(int which, int k, int n_cell) {
+    const int per_tile = which == 1 ? kCellsPerTileScalar : kCellsPerTile;
     const int tiles = (n_cell + per_tile - 1) / per_tile;
-    const int g = ((tiles + 7) / 8) * 8;
-    return g < kMaxBlocks ? (g > 0 ? g : 8) : kMaxBlocks;
+    const int want = std::max(8, ((tiles + 7) / 8) * 8);
+    int cap;
+    if (which == 0) cap = k == 1 ? resident_blocks(k_residual<1>) : resident_blocks(k_residual<2>);
+    else if (which == 1) cap = k == 1 ? resident_blocks(k_mnorm<1>) : resident_blocks(k_mnorm<2>);
+    else cap = k == 1 ? resident_blocks(k_filter<1>) : resident_blocks(k_filter<2>);
+    return std::min(want, cap);
 }
 
 int launch_residual(int k, const StageArgs& a, void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    const dim3 grid(pass_blocks(a.m.n_cell, kCellsPerTile));
+    const dim3 grid(grid_for_pass(0, k, a.m.n_cell));
     if (k == 1) hipLaunchKernelGGL(k_residual<1>, grid, dim3(kBlock), 0, s, a);
     else hipLaunchKernelGGL(k_residual<2>, grid, dim3(kBlock), 0, s, a);
     return (int)hipGetLastError();
@@ -970,7 +1000,7 @@ int launch_residual(int k, const StageArgs& a, void* stream) {
 
 int launch_mnorm(int k, const StageArgs& a, void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    const dim3 grid(pass_blocks(a.m.n_cell, kCellsPerTileScalar));
+    const dim3 grid(grid_for_pass(1, k, a.m.n_cell));
     if (k == 1) hipLaunchKernelGGL(k_mnorm<1>, grid, dim3(kBlock), 0, s, a);
     else hipLaunchKernelGGL(k_mnorm<2>, grid, dim3(kBlock), 0, s, a);
     return (int)hipGetLastError();
@@ -978,23 +1008,21 @@ int launch_mnorm(int k, const StageArgs& a, void* stream) {
 
 int launch_filter(int k, const StageArgs& a, void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    const dim3 grid(pass_blocks(a.m.n_cell, kCellsPerTile));
+    const dim3 grid(grid_for_pass(2, k, a.m.n_cell));
     if (k == 1) hipLaunchKernelGGL(k_filter<1>, grid, dim3(kBlock), 0, s, a);
     else hipLaunchKernelGGL(k_filter<2>, grid, dim3(kBlock), 0, s, a);
     return (int)hipGetLastError();
 }
 
-int launch_finalize(int which, const StageArgs& a, void* stream) {
+int launch_finalize(int which, int k, const StageArgs& a, void* stream) {
     hipStream_t s = (hipStream_t)stream;
+    const int G = grid_for_pass(which, k, a.m.n_cell);
     if (which == 0)
-        hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(kFinThreads), 0, s, a.part,
-                           pass_blocks(a.m.n_cell, kCellsPerTile), a.g);
+        hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(kFinThreads), 0, s, a.part, G, a.g);
     else if (which == 1)
-        hipLaunchKernelGGL(k_fin_mnorm, dim3(1), dim3(kFinThreads), 0, s, a.part,
-                           pass_blocks(a.m.n_cell, kCellsPerTileScalar), a.g);
+        hipLaunchKernelGGL(k_fin_mnorm, dim3(1), dim3(kFinThreads), 0, s, a.part, G, a.g);
     else
-        hipLaunchKernelGGL(k_fin_filter, dim3(1), dim3(kFinThreads), 0, s, a.part,
-                           pass_blocks(a.m.n_cell, kCellsPerTile), a.g, a.stage);
+        hipLaunchKernelGGL(k_fin_filter, dim3(1), dim3(kFinThreads), 0, s, a.part, G, a.g, a.stage);
     return (int)hipGetLastError();
 }
 

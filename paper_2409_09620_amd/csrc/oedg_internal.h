@@ -81,9 +81,10 @@ struct StageArgs {
     int oe_enable, oe_mode, bp_enable;
 };
 
-// Grid of a pass over n_cell cells with `per_tile` cells per tile: a multiple of 8
-// (one share per XCD), at most kMaxBlocks; workgroups stride over their XCD's tiles.
-int pass_blocks(int n_cell, int per_tile);
+// Grid of pass `which` (0 residual, 1 momentum norm, 2 filter) at degree k: a
+// multiple of 8 (one share per XCD), at most kMaxBlocks and at most what is
+// resident at once; workgroups stride over their XCD's tiles.
+int grid_for_pass(int which, int k, int n_cell);
 
 // kernel launchers (kernels.hip); return a hipError_t as int.  Each pass kernel
 // writes per-workgroup partials; the matching finalize kernel (one workgroup)
@@ -91,7 +92,7 @@ int pass_blocks(int n_cell, int per_tile);
 int launch_residual(int k, const StageArgs& a, void* stream);
 int launch_mnorm(int k, const StageArgs& a, void* stream);
 int launch_filter(int k, const StageArgs& a, void* stream);
-int launch_finalize(int which, const StageArgs& a, void* stream);   // 0 residual, 1 mnorm, 2 filter
+int launch_finalize(int which, int k, const StageArgs& a, void* stream);   // 0 residual, 1 mnorm, 2 filter
 int launch_project(int k, const StageArgs& a, int kind, const double* dparams, int n_params,
                    void* stream);
 int launch_set_end(Glob* g, double t_end, void* stream);
