@@ -49,7 +49,19 @@ typedef enum {
 } dg_status;
 
 enum { DG_OE_RI = 0, DG_OE_CW = 1 };           /* rotation-invariant (Sec. 3.3) or component-wise (Sec. 3.2) */
-enum { DG_PREC_FP64 = 0 };
+/* Arithmetic of the stage (Sec. 6 runs everything in FP64; the mixed form is this
+ * library's option).  DG_PREC_FP64: all of it in FP64.  DG_PREC_MIXED: cell
+ * averages stored, updated and reduced in FP64; modes >= 1 stored in FP32 and the
+ * volume/surface quadrature and OE filter in FP32; the BP limiter (point values,
+ * theta, internal energy) and the max wave speed in FP64.  In the mixed form the
+ * limiter's theta targets the floors plus a bound of the FP32 rounding of the
+ * scaled modes, and the stored coefficients are re-checked: a cell whose stored
+ * state would fall below half a floor at a node keeps only its average
+ * (counted in dg_diag_t.n_flat).  Every limiter node of every stored state then
+ * has rho >= eps_1/2 > 0 and rho e >= eps_2/2 > 0, evaluated in FP64.  The host
+ * arrays of dg_init/dg_readback/dg_read_state stay FP64 in both forms (modes >= 1
+ * are rounded to nearest FP32 on input). */
+enum { DG_PREC_FP64 = 0, DG_PREC_MIXED = 1 };
 
 typedef struct {
     int k;             /* polynomial degree, 1 or 2 */
@@ -58,7 +70,7 @@ typedef struct {
     int oe_enable;     /* 1: apply the OE filter after every stage */
     int oe_mode;       /* DG_OE_RI or DG_OE_CW */
     int bp_enable;     /* 1: apply the BP limiter after every stage and at init */
-    int precision;     /* DG_PREC_FP64 */
+    int precision;     /* DG_PREC_FP64 or DG_PREC_MIXED */
 } dg_config;
 
 /* Fills *cfg with the defaults: k = 2, gamma = 1.4, c_ssp = 1, OE on (RI), BP on, FP64. */
@@ -71,7 +83,8 @@ void dg_config_default(dg_config* cfg);
 #define DG_HOST_ONLY (-1)
 dg_status dg_create(dg_ctx** out, int hip_device, void* hip_stream);
 
-/* Device bytes the library needs for a mesh of n_cell cells at degree k. */
+/* Device bytes the library needs for a mesh of n_cell cells at degree k (enough
+ * for either precision). */
 dg_status dg_workspace_bytes(int32_t n_cell, int k, size_t* bytes);
 
 /* Hands the library caller-owned device memory (at least dg_workspace_bytes),
@@ -147,6 +160,8 @@ typedef struct {
     double nrm[4];                /* ||u - ubar||_inf per variable (eq. normOmg) */
     double nrm_m;                 /* ||| m - mbar |||_inf (vector norm) */
     int active;                   /* 0 once t has reached the last t_end */
+    int64_t n_flat;               /* DG_PREC_MIXED: cell-stages reset to their average by the
+                                     check of the stored (FP32-rounded) coefficients */
 } dg_diag_t;
 
 /* Diagnostics of the context (synchronises). */

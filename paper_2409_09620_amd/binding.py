@@ -17,6 +17,9 @@ _HEADER = os.path.join(_ROOT, "include", "oedg.h")
 
 DG_OE_RI = 0
 DG_OE_CW = 1
+DG_PREC_FP64 = 0
+DG_PREC_MIXED = 1
+PRECISION = {"fp64": DG_PREC_FP64, "mixed": DG_PREC_MIXED}
 STATUS = {0: "DG_OK", -1: "DG_E_ARG", -2: "DG_E_MESH", -3: "DG_E_NOMEM", -4: "DG_E_HIP",
           -5: "DG_E_BOUNDS", -6: "DG_E_STATE"}
 
@@ -33,7 +36,8 @@ class DgConfig(ctypes.Structure):
 class DgDiag(ctypes.Structure):
     _fields_ = [("t", _c_d), ("dt", _c_d), ("alpha", _c_d), ("step", _c_i64),
                 ("n_limited", _c_i64), ("n_bad", _c_i64), ("n_cfl_excursions", _c_i64),
-                ("ubar", _c_d * 4), ("nrm", _c_d * 4), ("nrm_m", _c_d), ("active", _c_i)]
+                ("ubar", _c_d * 4), ("nrm", _c_d * 4), ("nrm_m", _c_d), ("active", _c_i),
+                ("n_flat", _c_i64)]
 
 
 class DgError(RuntimeError):
@@ -151,7 +155,8 @@ class Solver:
         except Exception:
             pass
 
-    def config(self, oe=True, bp=True, oe_mode=DG_OE_RI, gamma=1.4, c_ssp=1.0):
+    def config(self, oe=True, bp=True, oe_mode=DG_OE_RI, gamma=1.4, c_ssp=1.0, precision="fp64"):
+        """precision: "fp64" or "mixed" (FP32 bulk, FP64 averages and limiter)."""
         cfg = DgConfig()
         load_library().dg_config_default(ctypes.byref(cfg))
         cfg.k = self.k
@@ -160,6 +165,9 @@ class Solver:
         cfg.oe_enable = int(oe)
         cfg.bp_enable = int(bp)
         cfg.oe_mode = int(oe_mode)
+        if precision not in PRECISION:
+            raise ValueError(f"precision must be one of {sorted(PRECISION)}")
+        cfg.precision = PRECISION[precision]
         return cfg
 
     def shape(self):

@@ -3,6 +3,7 @@
 // kernels of kernels.hip; this file only moves data and orders launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -76,12 +77,20 @@ dg_status fail(dg_ctx* c, dg_status s, const std::string& msg) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Mixed-precision state: FP64 averages [4][cell], then (at a 256-byte boundary)
+// the float higher modes [4][mode-1][cell].
+size_t mixed_hi_offset(size_t nc) { return align256(4 * nc * sizeof(double)); }
+size_t mixed_state_bytes(size_t nc, size_t nm) { return mixed_hi_offset(nc) + 4 * (nm - 1) * nc * sizeof(float); }
+size_t fp64_state_bytes(size_t nc, size_t nm) { return 4 * nm * nc * sizeof(double); }
+
 struct Layout {
     size_t jinv, area, len, node, link, u0, u, w, part, glob, total;
 };
 
+// One layout for both precisions: each state buffer holds either form.
 Layout layout(size_t nc, int k) {
     const size_t nm = (size_t)(k + 1) * (k + 2) / 2;
+    const size_t state = std::max(fp64_state_bytes(nc, nm), mixed_state_bytes(nc, nm));
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
@@ -90,10 +99,10 @@ Layout layout(size_t nc, int k) {
     L.len = take(3 * nc * sizeof(double));
     L.node = take(4 * nc * sizeof(double));
     L.link = take(3 * nc * sizeof(int32_t));
-    L.u0 = take(4 * nm * nc * sizeof(double));
-    L.u = take(4 * nm * nc * sizeof(double));
-    L.w = take(std::max<size_t>(4 * nm, 7) * nc * sizeof(double));
-    L.part = take((size_t)16 * oedg::kMaxBlocks * sizeof(double));
+    L.u0 = take(state);
+    L.u = take(state);
+    L.w = take(std::max(state, 7 * nc * sizeof(double)));   // also carries the coordinates at set-up
+    L.part = take((size_t)oedg::kPartCols * oedg::kMaxBlocks * sizeof(double));
     L.glob = take(sizeof(Glob));
     L.total = off;
     return L;
@@ -111,6 +120,45 @@ dg_status ready(dg_ctx* c, bool need_init) {
     return DG_OK;
 }
 
+bool is_mixed(const dg_ctx* c) { return c->cfg.precision == DG_PREC_MIXED; }
+
+size_t state_bytes(const dg_ctx* c) {
+    const size_t nc = (size_t)c->mesh.n_cell;
+    return is_mixed(c) ? mixed_state_bytes(nc, (size_t)c->nm) : fp64_state_bytes(nc, (size_t)c->nm);
+}
+
+// the kernels' view of a state buffer in the configured precision
+oedg::StateView view_of(const dg_ctx* c, const double* base) {
+    double* b = const_cast<double*>(base);
+    const size_t nc = (size_t)c->mesh.n_cell;
+    if (is_mixed(c)) return {b, (char*)b + mixed_hi_offset(nc)};
+    return {b, b + nc};
+}
+
+// host [4][nm][nc] FP64 <-> mixed storage (higher modes rounded to nearest float)
+void pack_mixed(const double* u, size_t nc, size_t nm, std::vector<char>& out) {
+    out.assign(mixed_state_bytes(nc, nm), 0);
+    double* avg = (double*)out.data();
+    float* hi = (float*)(out.data() + mixed_hi_offset(nc));
+    for (size_t v = 0; v < 4; ++v) {
+        for (size_t cc = 0; cc < nc; ++cc) avg[v * nc + cc] = u[v * nm * nc + cc];
+        for (size_t l = 1; l < nm; ++l)
+            for (size_t cc = 0; cc < nc; ++cc) hi[(v * (nm - 1) + l - 1) * nc + cc] = (float)u[(v * nm + l) * nc + cc];
+    }
+}
+void unpack_mixed(const std::vector<char>& in, size_t nc, size_t nm, double* u) {
+    const double* avg = (const double*)in.data();
+    const float* hi = (const float*)(in.data() + mixed_hi_offset(nc));
+    for (size_t v = 0; v < 4; ++v) {
+        for (size_t cc = 0; cc < nc; ++cc) u[v * nm * nc + cc] = avg[v * nc + cc];
+        for (size_t l = 1; l < nm; ++l)
+            for (size_t cc = 0; cc < nc; ++cc) u[(v * nm + l) * nc + cc] = (double)hi[(v * (nm - 1) + l - 1) * nc + cc];
+    }
+}
+
+// copies a device state buffer to host [4][nm][nc] FP64 (synchronises)
+dg_status download_state(dg_ctx* c, const double* src, double* u_modal);
+
 oedg::StageArgs stage_args(dg_ctx* c, int s) {
     oedg::StageArgs a{};
     a.m.n_cell = c->mesh.n_cell;
@@ -119,10 +167,14 @@ oedg::StageArgs stage_args(dg_ctx* c, int s) {
     a.m.len = c->len;
     a.m.node_ref = c->node;
     a.m.link = c->link;
-    a.uin = s <= 0 ? c->u0 : c->u;
-    a.u0 = c->u0;
-    a.w = c->w;
-    a.uout = s == 2 ? c->u0 : c->u;
+    a.uin = view_of(c, s <= 0 ? c->u0 : c->u);
+    a.u0 = view_of(c, c->u0);
+    a.w = view_of(c, c->w);
+    a.uout = view_of(c, s == 2 ? c->u0 : c->u);
+    const size_t nc = (size_t)c->mesh.n_cell, nm = (size_t)c->nm;
+    a.mixed = is_mixed(c) ? 1 : 0;
+    a.avs = a.mixed ? nc : nm * nc;
+    a.hvs = a.mixed ? (nm - 1) * nc : nm * nc;
     a.part = c->part;
     a.g = c->g;
     a.gamma = c->cfg.gamma;
@@ -136,7 +188,8 @@ oedg::StageArgs stage_args(dg_ctx* c, int s) {
 dg_status check_cfg(dg_ctx* c, const dg_config* cfg) {
     if (!cfg) return fail(c, DG_E_ARG, "null config");
     if (cfg->k != c->mesh.k) return fail(c, DG_E_ARG, "config degree differs from the mesh upload");
-    if (cfg->precision != DG_PREC_FP64) return fail(c, DG_E_ARG, "unsupported precision");
+    if (cfg->precision != DG_PREC_FP64 && cfg->precision != DG_PREC_MIXED)
+        return fail(c, DG_E_ARG, "unsupported precision");
     if (cfg->oe_mode != DG_OE_RI && cfg->oe_mode != DG_OE_CW) return fail(c, DG_E_ARG, "bad oe_mode");
     if (!(cfg->gamma > 1.0) || !(cfg->c_ssp > 0.0)) return fail(c, DG_E_ARG, "bad gamma or c_ssp");
     return DG_OK;
@@ -158,13 +211,12 @@ dg_status reset_glob(dg_ctx* c) {
 // limiter (no OE) + alpha^0 + Delta t^0 on u^0, in place
 dg_status start(dg_ctx* c) {
     oedg::StageArgs a = stage_args(c, -1);
-    a.w = c->u0;
-    a.uout = c->u0;
+    a.w = view_of(c, c->u0);
+    a.uout = a.w;
     a.oe_enable = 0;
     LAUNCH_TRY(c, oedg::launch_filter(c->cfg.k, a, c->stream));
     LAUNCH_TRY(c, oedg::launch_finalize(2, c->cfg.k, a, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->u, c->u0, 4 * (size_t)c->nm * c->mesh.n_cell * sizeof(double),
-                              hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->u, c->u0, state_bytes(c), hipMemcpyDeviceToDevice, c->stream));
     c->last_out = c->u0;
     c->initialised = true;
     Glob h{};
@@ -222,7 +274,7 @@ dg_status run_stage(dg_ctx* c, int s) {
     }
     TIMED_LAUNCH(c, 2, oedg::launch_filter(c->cfg.k, a, c->stream));
     LAUNCH_TRY(c, oedg::launch_finalize(2, c->cfg.k, a, c->stream));
-    c->last_out = a.uout;
+    c->last_out = s == 2 ? c->u0 : c->u;
     return DG_OK;
 }
 
@@ -274,6 +326,19 @@ dg_status run_step(dg_ctx* c) {
     }
     HIP_TRY(c, hipGraphLaunch(c->step_exec, c->stream));
     c->last_out = c->u0;
+    return DG_OK;
+}
+
+dg_status download_state(dg_ctx* c, const double* src, double* u_modal) {
+    if (is_mixed(c)) {
+        std::vector<char> packed(state_bytes(c));
+        HIP_TRY(c, hipMemcpyAsync(packed.data(), src, packed.size(), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        unpack_mixed(packed, (size_t)c->mesh.n_cell, (size_t)c->nm, u_modal);
+        return DG_OK;
+    }
+    HIP_TRY(c, hipMemcpyAsync(u_modal, src, state_bytes(c), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     return DG_OK;
 }
 
@@ -425,8 +490,13 @@ dg_status dg_init(dg_ctx* c, const dg_config* cfg, const double* u0_modal) {
     if (!u0_modal) return fail(c, DG_E_ARG, "null initial state");
     c->cfg = *cfg;
     drop_graph(c);
-    HIP_TRY(c, hipMemcpyAsync(c->u0, u0_modal, 4 * (size_t)c->nm * c->mesh.n_cell * sizeof(double),
-                              hipMemcpyHostToDevice, c->stream));
+    std::vector<char> packed;   // must outlive the copy: start() synchronises
+    if (is_mixed(c)) {
+        pack_mixed(u0_modal, (size_t)c->mesh.n_cell, (size_t)c->nm, packed);
+        HIP_TRY(c, hipMemcpyAsync(c->u0, packed.data(), packed.size(), hipMemcpyHostToDevice, c->stream));
+    } else {
+        HIP_TRY(c, hipMemcpyAsync(c->u0, u0_modal, state_bytes(c), hipMemcpyHostToDevice, c->stream));
+    }
     if ((s = reset_glob(c)) != DG_OK) return s;
     return start(c);
 }
@@ -466,8 +536,8 @@ dg_status dg_init_problem(dg_ctx* c, const dg_config* cfg, int kind, const doubl
     HIP_TRY(c, hipMemcpyAsync(c->w, aux.data(), 7 * nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
     if ((s = reset_glob(c)) != DG_OK) return s;
     oedg::StageArgs a = stage_args(c, -1);
-    a.uout = c->u0;
-    LAUNCH_TRY(c, oedg::launch_project(c->cfg.k, a, kind, P.data(), (int)P.size(), c->stream));
+    a.uout = view_of(c, c->u0);
+    LAUNCH_TRY(c, oedg::launch_project(c->cfg.k, a, kind, P.data(), (int)P.size(), c->w, c->stream));
     // the host buffer must outlive the copy
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return start(c);
@@ -520,9 +590,7 @@ dg_status dg_readback(dg_ctx* c, double* u_modal, double* t, int64_t* step) {
     dg_status st = ready(c, true);
     if (st != DG_OK && st != DG_E_BOUNDS) return st;
     HIP_TRY(c, hipSetDevice(c->device));
-    if (u_modal)
-        HIP_TRY(c, hipMemcpyAsync(u_modal, c->u0, 4 * (size_t)c->nm * c->mesh.n_cell * sizeof(double),
-                                  hipMemcpyDeviceToHost, c->stream));
+    if (u_modal && (st = download_state(c, c->u0, u_modal)) != DG_OK) return st;
     Glob h{};
     HIP_TRY(c, hipMemcpyAsync(&h, c->g, sizeof(Glob), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -538,10 +606,7 @@ dg_status dg_read_state(dg_ctx* c, int which, double* u_modal) {
     if (!u_modal || which < 0 || which > 2) return fail(c, DG_E_ARG, "bad buffer selector");
     HIP_TRY(c, hipSetDevice(c->device));
     const double* src = which == 0 ? c->u0 : (which == 1 ? c->last_out : c->w);
-    HIP_TRY(c, hipMemcpyAsync(u_modal, src, 4 * (size_t)c->nm * c->mesh.n_cell * sizeof(double),
-                              hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    return DG_OK;
+    return download_state(c, src, u_modal);
 }
 
 dg_status dg_diag(dg_ctx* c, dg_diag_t* out) {
@@ -559,6 +624,7 @@ dg_status dg_diag(dg_ctx* c, dg_diag_t* out) {
     out->n_limited = h.n_limited;
     out->n_bad = h.n_bad;
     out->n_cfl_excursions = h.n_cfl_exc;
+    out->n_flat = h.n_flat;
     for (int v = 0; v < 4; ++v) {
         out->ubar[v] = h.ubar[v];
         out->nrm[v] = h.nrm[v];

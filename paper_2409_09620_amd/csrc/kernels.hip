@@ -1,7 +1,7 @@
 // gfx950 kernels of one BP RI-OEDG stage (2D Euler, P1/P2 modal DG on triangles).
 //
-// Three passes per stage over a state stored as structure-of-arrays
-// [var][mode][cell] (cell fastest):
+// Three passes per stage over a state stored as structure-of-arrays, cell
+// fastest: cell averages [var][cell] and higher modes [var][mode][cell]:
 //   k_residual  volume + edge quadrature of eq. DGSystem:Dis with the LF flux
 //               (eq. fluxLF), the diagonal mass and the SSP-RK3 combination (eq.
 //               RKTime); writes the pre-filter state and per-workgroup partials of
@@ -20,17 +20,29 @@
 // exchanged inside the quad with DPP quad_perm moves.  Workgroups are spread so
 // that each XCD walks a contiguous range of the (Hilbert-ordered) cells, which
 // keeps neighbour gathers inside that XCD's L2.
+//
+// Precision: every pass is instantiated for a bulk type T, double (FP64) or
+// float (mixed).  Cell averages are stored, updated and reduced in FP64 in both
+// forms; modes >= 1, the volume and surface quadrature and the OE filter run in
+// T.  The BP limiter's point values, theta, the internal energy and the max wave
+// speed always run in FP64.  In the mixed form the limited modes are rounded to
+// float, so theta aims above the floors by a bound of that rounding, and the
+// stored coefficients are checked again: a cell whose stored state still dips
+// below half a floor at a node keeps only its average.  The stored state thus
+// has rho > 0 and rho e > 0 at every limiter node, evaluated in FP64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 #include <unordered_map>
 
 #include "oedg_internal.h"
 
 namespace oedg {
 namespace {
+
 
 template <int K>
 struct Rule;
@@ -68,6 +80,12 @@ __device__ constexpr double kA[3][3] = {{0, 0, 0}, {1.0, 3.0, 0.0}, {1.0 / 3.0, 
 constexpr double kEpsOE = 1e-12;
 constexpr double kEpsBP = 1e-13;
 
+// Mixed form: rounding theta * c_l to float moves it by at most 2^-24 theta |c_l|,
+// and |Psi_l| <= 4 on the reference triangle for every l <= 5, so a point value
+// moves by at most 4 * 2^-24 * theta * sum_{l>=1} |c_l|; the limiter aims twice that
+// above the floor.
+constexpr double kMixMargin = 8.0 * 0x1p-24;
+
 // ------------------------------------------------------------------------- basis
 
 template <int K>
@@ -82,97 +100,97 @@ __device__ __forceinline__ void psi(double x, double e, double* p) {
     }
 }
 
-template <int K>
-__device__ __forceinline__ void dpsi(double x, double e, double* dx, double* de) {
-    dx[0] = 0.0;
-    de[0] = 0.0;
-    dx[1] = 4.0;
-    de[1] = 2.0;
-    dx[2] = 0.0;
-    de[2] = 3.0;
-    if constexpr (K == 2) {
-        dx[3] = 48.0 * x + 24.0 * e - 24.0;
-        de[3] = 24.0 * x + 8.0 * e - 8.0;
-        dx[4] = 20.0 * e - 4.0;
-        de[4] = 20.0 * x + 20.0 * e - 12.0;
-        dx[5] = 0.0;
-        de[5] = 20.0 * e - 8.0;
-    }
-}
-
 // reference point of local edge i at parameter s (edge i runs from vertex i+1 to i+2)
 __device__ __forceinline__ void edge_point(int i, double s, double& x, double& e) {
     x = i == 0 ? 1.0 - s : (i == 1 ? 0.0 : s);
     e = i == 0 ? s : (i == 1 ? 1.0 - s : 0.0);
 }
-__device__ __forceinline__ void vertex_point(int v, double& x, double& e) {
-    x = v == 1 ? 1.0 : 0.0;
-    e = v == 2 ? 1.0 : 0.0;
-}
 
 // Basis values at the fixed points of a stage, in constant memory: the point loops
 // run with a wave-uniform index, so these become scalar loads instead of registers.
-template <int K>
+template <int K, typename T>
 struct Tab {
     static constexpr int NM = Rule<K>::NM, NQ = Rule<K>::NQ, NE = Rule<K>::NE;
-    double vp[NQ][NM], vdx[NQ][NM], vde[NQ][NM];   // volume points: Psi, dPsi/dxi, dPsi/deta
-    double vw[NQ];                                 // volume weights
-    double ep[3 * NE][NM];                         // own edge Gauss points (edge i, node nu)
-    double vtp[3][NM], vtdx[3][NM], vtde[3][NM];   // reference vertices
+    T vp[NQ][NM], vdx[NQ][NM], vde[NQ][NM];   // volume points: Psi, dPsi/dxi, dPsi/deta
+    T vw[NQ];                                 // volume weights
+    T ep[3 * NE][NM];                         // own edge Gauss points (edge i, node nu)
+    T vtp[3][NM], vtdx[3][NM], vtde[3][NM];   // reference vertices
 };
 
-constexpr void basis_at(int nm, double x, double e, double* p, double* dx, double* de) {
+template <typename T>
+constexpr void basis_at(int nm, double x, double e, T* p, T* dx, T* de) {
     const double P[6] = {1.0, 4.0 * x + 2.0 * e - 2.0, 3.0 * e - 1.0,
                          24.0 * x * x + 24.0 * x * e + 4.0 * e * e - 24.0 * x - 8.0 * e + 4.0,
                          20.0 * x * e + 10.0 * e * e - 4.0 * x - 12.0 * e + 2.0, 10.0 * e * e - 8.0 * e + 1.0};
     const double X[6] = {0.0, 4.0, 0.0, 48.0 * x + 24.0 * e - 24.0, 20.0 * e - 4.0, 0.0};
     const double E[6] = {0.0, 2.0, 3.0, 24.0 * x + 8.0 * e - 8.0, 20.0 * x + 20.0 * e - 12.0, 20.0 * e - 8.0};
     for (int l = 0; l < nm; ++l) {
-        p[l] = P[l];
-        dx[l] = X[l];
-        de[l] = E[l];
+        p[l] = (T)P[l];
+        dx[l] = (T)X[l];
+        de[l] = (T)E[l];
     }
 }
 
-template <int K>
-constexpr Tab<K> make_tab() {
+template <int K, typename T>
+constexpr Tab<K, T> make_tab() {
     using R = Rule<K>;
-    Tab<K> t{};
-    double scratch[6] = {}, scratch2[6] = {};
+    Tab<K, T> t{};
+    T scratch[6] = {}, scratch2[6] = {};
     for (int m = 0; m < R::NQ; ++m) {
-        basis_at(R::NM, R::xi[m], R::eta[m], t.vp[m], t.vdx[m], t.vde[m]);
-        t.vw[m] = R::w[m];
+        basis_at<T>(R::NM, R::xi[m], R::eta[m], t.vp[m], t.vdx[m], t.vde[m]);
+        t.vw[m] = (T)R::w[m];
     }
     for (int i = 0; i < 3; ++i)
         for (int nu = 0; nu < R::NE; ++nu) {
             const double s = R::s[nu];
             const double x = i == 0 ? 1.0 - s : (i == 1 ? 0.0 : s);
             const double e = i == 0 ? s : (i == 1 ? 1.0 - s : 0.0);
-            basis_at(R::NM, x, e, t.ep[i * R::NE + nu], scratch, scratch2);
+            basis_at<T>(R::NM, x, e, t.ep[i * R::NE + nu], scratch, scratch2);
         }
     for (int vtx = 0; vtx < 3; ++vtx)
-        basis_at(R::NM, vtx == 1 ? 1.0 : 0.0, vtx == 2 ? 1.0 : 0.0, t.vtp[vtx], t.vtdx[vtx], t.vtde[vtx]);
+        basis_at<T>(R::NM, vtx == 1 ? 1.0 : 0.0, vtx == 2 ? 1.0 : 0.0, t.vtp[vtx], t.vtdx[vtx], t.vtde[vtx]);
     return t;
 }
 
-__constant__ Tab<1> kTab1 = make_tab<1>();
-__constant__ Tab<2> kTab2 = make_tab<2>();
-template <int K>
-__device__ __forceinline__ const Tab<K>& tab();
-template <>
-__device__ __forceinline__ const Tab<1>& tab<1>() { return kTab1; }
-template <>
-__device__ __forceinline__ const Tab<2>& tab<2>() { return kTab2; }
+__constant__ Tab<1, double> kTab1d = make_tab<1, double>();
+__constant__ Tab<2, double> kTab2d = make_tab<2, double>();
+__constant__ Tab<1, float> kTab1f = make_tab<1, float>();
+__constant__ Tab<2, float> kTab2f = make_tab<2, float>();
+template <int K, typename T>
+__device__ __forceinline__ const Tab<K, T>& tab() {
+    if constexpr (std::is_same<T, float>::value) {
+        if constexpr (K == 1) return kTab1f;
+        else return kTab2f;
+    } else {
+        if constexpr (K == 1) return kTab1d;
+        else return kTab2d;
+    }
+}
 
-template <int NM>
-__device__ __forceinline__ double dot(const double* u, const double* p) {
-    double s = u[0] * p[0];
+template <int NM, typename T>
+__device__ __forceinline__ T dot(const T* u, const T* p) {
+    T s = u[0] * p[0];
 #pragma unroll
     for (int l = 1; l < NM; ++l) s = fma(u[l], p[l], s);
     return s;
 }
+// sum over the modes l >= 1 only
+template <int NM, typename T>
+__device__ __forceinline__ T dot_hi(const T* u, const T* p) {
+    T s = u[1] * p[1];
+#pragma unroll
+    for (int l = 2; l < NM; ++l) s = fma(u[l], p[l], s);
+    return s;
+}
+template <int NM>
+__device__ __forceinline__ double abs_sum_hi(const double* u) {
+    double s = fabs(u[1]);
+#pragma unroll
+    for (int l = 2; l < NM; ++l) s += fabs(u[l]);
+    return s;
+}
 
-// ------------------------------------------------------------------------- fast FP64 helpers
+// ------------------------------------------------------------------------- fast arithmetic
 
 // 1/x from v_rcp_f64 and two Newton steps (about 1 ulp; not correctly rounded)
 __device__ __forceinline__ double frcp(double x) {
@@ -198,9 +216,25 @@ __device__ __forceinline__ double fsqrt(double x) {
     return x > 0.0 ? g : 0.0;
 }
 
+// reciprocal, square root (0 for x <= 0) and exponential in the bulk type
+template <typename T>
+struct Fp;
+template <>
+struct Fp<double> {
+    static __device__ __forceinline__ double rcp(double x) { return frcp(x); }
+    static __device__ __forceinline__ double sqrt(double x) { return fsqrt(x); }
+    static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
+};
+template <>
+struct Fp<float> {
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }   // 1 ulp
+    static __device__ __forceinline__ float sqrt(float x) { return x > 0.0f ? __builtin_sqrtf(x) : 0.0f; }
+    static __device__ __forceinline__ float exp(float x) { return expf(x); }
+};
+
 // ------------------------------------------------------------------------- quad exchanges
 
-// DPP quad_perm move of a double: lane q of every quad receives lane perm[q]'s value
+// DPP quad_perm move: lane q of every quad receives lane perm[q]'s value
 template <int CTRL>
 __device__ __forceinline__ double qperm(double x) {
     const long long b = __builtin_bit_cast(long long, x);
@@ -208,57 +242,68 @@ __device__ __forceinline__ double qperm(double x) {
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
 }
-template <int L>
-__device__ __forceinline__ double qget(double x) { return qperm<L * 0x55>(x); }   // broadcast lane L
-__device__ __forceinline__ double qswap12(double x) { return qperm<0xD8>(x); }   // [0,2,1,3]
-__device__ __forceinline__ double qxor1(double x) { return qperm<0xB1>(x); }     // [1,0,3,2]
-__device__ __forceinline__ double qxor2(double x) { return qperm<0x4E>(x); }     // [2,3,0,1]
-__device__ __forceinline__ double qmax(double x) {
+template <int CTRL>
+__device__ __forceinline__ float qperm(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+template <int L, typename T>
+__device__ __forceinline__ T qget(T x) { return qperm<L * 0x55>(x); }   // broadcast lane L
+template <typename T>
+__device__ __forceinline__ T qswap12(T x) { return qperm<0xD8>(x); }   // [0,2,1,3]
+template <typename T>
+__device__ __forceinline__ T qxor1(T x) { return qperm<0xB1>(x); }     // [1,0,3,2]
+template <typename T>
+__device__ __forceinline__ T qxor2(T x) { return qperm<0x4E>(x); }     // [2,3,0,1]
+template <typename T>
+__device__ __forceinline__ T qmax(T x) {
     x = fmax(x, qxor1(x));
     return fmax(x, qxor2(x));
 }
-__device__ __forceinline__ double sel4(int v, double a0, double a1, double a2, double a3) {
+template <typename T>
+__device__ __forceinline__ T qmin(T x) {
+    x = fmin(x, qxor1(x));
+    return fmin(x, qxor2(x));
+}
+template <typename T>
+__device__ __forceinline__ T sel4(int v, T a0, T a1, T a2, T a3) {
     return v == 0 ? a0 : (v == 1 ? a1 : (v == 2 ? a2 : a3));
 }
 // 4x4 transpose inside a quad: lane w holds x[c] = (its variable w at state c);
 // on return q[w] = variable w at state v, where v is the calling lane
-__device__ __forceinline__ void quad_transpose(int v, const double (&x)[4], double (&q)[4]) {
+template <typename T>
+__device__ __forceinline__ void quad_transpose(int v, const T (&x)[4], T (&q)[4]) {
     // round k: lane v reads lane (v+k)&3, which offers its entry (owner - k)&3 = v
-    const double r0 = sel4(v, x[0], x[1], x[2], x[3]);
-    const double r1 = qperm<0x39>(sel4(v, x[3], x[0], x[1], x[2]));   // rotate by 1: [1,2,3,0]
-    const double r2 = qperm<0x4E>(sel4(v, x[2], x[3], x[0], x[1]));   // rotate by 2: [2,3,0,1]
-    const double r3 = qperm<0x93>(sel4(v, x[1], x[2], x[3], x[0]));   // rotate by 3: [3,0,1,2]
+    const T r0 = sel4(v, x[0], x[1], x[2], x[3]);
+    const T r1 = qperm<0x39>(sel4(v, x[3], x[0], x[1], x[2]));   // rotate by 1: [1,2,3,0]
+    const T r2 = qperm<0x4E>(sel4(v, x[2], x[3], x[0], x[1]));   // rotate by 2: [2,3,0,1]
+    const T r3 = qperm<0x93>(sel4(v, x[1], x[2], x[3], x[0]));   // rotate by 3: [3,0,1,2]
     // r_k is variable (v+k)&3
     q[0] = sel4(v, r0, r3, r2, r1);
     q[1] = sel4(v, r1, r0, r3, r2);
     q[2] = sel4(v, r2, r1, r0, r3);
     q[3] = sel4(v, r3, r2, r1, r0);
 }
-__device__ __forceinline__ double qmin(double x) {
-    x = fmin(x, qxor1(x));
-    return fmin(x, qxor2(x));
-}
 
 // ------------------------------------------------------------------------- Euler
 
 // component v of F(q).n for the lane's variable (s1, s2, s3 = [v==1], [v==2], [v==3]);
 // (nx, ny) may be a scaled normal
-__device__ __forceinline__ double lane_flux(double qv, double q0, double q1, double q2, double q3, double nx,
-                                            double ny, double gm1, double s1, double s2, double s3) {
-    const double ir = frcp(q0);
-    const double mn = q1 * nx + q2 * ny;
-    const double vn = mn * ir;
-    const double p = gm1 * (q3 - 0.5 * (q1 * q1 + q2 * q2) * ir);
+template <typename T>
+__device__ __forceinline__ T lane_flux(T qv, T q0, T q1, T q2, T q3, T nx, T ny, T gm1, T s1, T s2, T s3) {
+    const T ir = Fp<T>::rcp(q0);
+    const T mn = q1 * nx + q2 * ny;
+    const T vn = mn * ir;
+    const T p = gm1 * (q3 - (T)0.5 * (q1 * q1 + q2 * q2) * ir);
     return qv * vn + p * (s1 * nx + s2 * ny + s3 * vn);
 }
 
 // spectral radius |v.n| + c of F'(u).n (Example ex:euler); guarded so that a
 // pre-limiter state with rho <= 0 or p < 0 still gives a finite value
-__device__ __forceinline__ double spectral_radius(double q0, double q1, double q2, double q3, double nx, double ny,
-                                                  double gamma) {
-    const double ir = frcp(fmax(q0, kEpsBP));
-    const double p = (gamma - 1.0) * (q3 - 0.5 * (q1 * q1 + q2 * q2) * ir);
-    return fabs(q1 * nx + q2 * ny) * ir + fsqrt(gamma * fmax(p, 0.0) * ir);
+template <typename T>
+__device__ __forceinline__ T spectral_radius(T q0, T q1, T q2, T q3, T nx, T ny, T gamma) {
+    const T ir = Fp<T>::rcp(fmax(q0, (T)kEpsBP));
+    const T p = (gamma - (T)1.0) * (q3 - (T)0.5 * (q1 * q1 + q2 * q2) * ir);
+    return fabs(q1 * nx + q2 * ny) * ir + Fp<T>::sqrt(gamma * fmax(p, (T)0.0) * ir);
 }
 
 // ------------------------------------------------------------------------- work distribution
@@ -288,9 +333,27 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// Addresses of variable v in a state view: its FP64 average and its higher modes
+// (mode l at hi[(l - 1) * n_cell]).  The FP64 form is the plain [var][mode][cell]
+// array, so its higher modes follow the average at a fixed offset.
+template <int NM, typename T>
+struct VarPtr {
+    double* avg;
+    T* hi;
+};
+template <int NM, typename T>
+__device__ __forceinline__ VarPtr<NM, T> var_ptr(const StateView& sv, const StageArgs& a, int v, size_t snc) {
+    if constexpr (std::is_same<T, double>::value) {
+        double* av = sv.avg + (size_t)v * NM * snc;
+        return {av, av + snc};
+    } else {
+        return {sv.avg + v * a.avs, (T*)sv.hi + v * a.hvs};
+    }
+}
+
 // ------------------------------------------------------------------------- pass 1: residual
 
-template <int K>
+template <int K, typename T>
 __global__ __launch_bounds__(kBlock) void k_residual(StageArgs a) {
     using R = Rule<K>;
     constexpr int NM = R::NM;
@@ -299,43 +362,56 @@ __global__ __launch_bounds__(kBlock) void k_residual(StageArgs a) {
     const int nc = a.m.n_cell;
     const size_t snc = (size_t)nc;
     const int v = threadIdx.x & 3;
-    const double s1 = v == 1 ? 1.0 : 0.0, s2 = v == 2 ? 1.0 : 0.0, s3 = v == 3 ? 1.0 : 0.0;
-    const double alpha = g->alpha, dt = g->dt, gm1 = a.gamma - 1.0;
+    const T s1 = v == 1 ? 1.0 : 0.0, s2 = v == 2 ? 1.0 : 0.0, s3 = v == 3 ? 1.0 : 0.0;
+    const T gm1 = (T)(a.gamma - 1.0);
+    const double alpha = g->alpha, dt = g->dt;
     const double sa = a.stage == 0 ? 0.0 : (a.stage == 1 ? 0.75 : 1.0 / 3.0);
     const double sb = a.stage == 0 ? 1.0 : (a.stage == 1 ? 0.25 : 2.0 / 3.0);
-    const double* uv = a.uin + (size_t)v * NM * snc;   // this lane's variable
-    double* wv = a.w + (size_t)v * NM * snc;
-    const double* u0v = a.u0 + (size_t)v * NM * snc;
-    const Tab<K>& T = tab<K>();
+    // this lane's variable: FP64 average and bulk-type higher modes
+    const VarPtr<NM, T> up = var_ptr<NM, T>(a.uin, a, v, snc);
+    const VarPtr<NM, T> u0p = var_ptr<NM, T>(a.u0, a, v, snc);
+    const VarPtr<NM, T> wp = var_ptr<NM, T>(a.w, a, v, snc);
+    const double* ua_p = up.avg;
+    const T* uh_p = up.hi;
+    const double* u0a_p = u0p.avg;
+    const T* u0h_p = u0p.hi;
+    double* wa_p = wp.avg;
+    T* wh_p = wp.hi;
+    const Tab<K, T>& TB = tab<K, T>();
 
     double psum = 0.0, pmin = INFINITY, pmax = -INFINITY;
     const TileWalk tw = tile_walk((nc + kCellsPerTile - 1) / kCellsPerTile);
     for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
         const int c = tile * kCellsPerTile + (threadIdx.x >> 2);
         if (c >= nc) continue;   // whole quad
-        double u[NM];
+        const double ua = ua_p[c];
+        T u[NM];
+        u[0] = (T)ua;
 #pragma unroll
-        for (int l = 0; l < NM; ++l) u[l] = uv[l * snc + c];
-        const double xx = a.m.jinv[c], xy = a.m.jinv[snc + c];
-        const double ex = a.m.jinv[2 * snc + c], ey = a.m.jinv[3 * snc + c];
+        for (int l = 1; l < NM; ++l) u[l] = uh_p[(l - 1) * snc + c];
+        const T xx = (T)a.m.jinv[c], xy = (T)a.m.jinv[snc + c];
+        const T ex = (T)a.m.jinv[2 * snc + c], ey = (T)a.m.jinv[3 * snc + c];
         const double area = a.m.area[c];
+        const T areaT = (T)area;
 
-        double r[NM];
+        // mode 0 accumulates in FP64 in both forms (its volume term is zero)
+        double r0 = 0.0;
+        T r[NM];
 #pragma unroll
-        for (int l = 0; l < NM; ++l) r[l] = 0.0;
+        for (int l = 0; l < NM; ++l) r[l] = (T)0.0;
 
         // volume term |K| sum_mu w_mu F(u).grad Psi_l with grad Psi = J^{-T} grad_ref Psi,
         // i.e. dPsi/dxi (F.grad xi) + dPsi/deta (F.grad eta)
 #pragma unroll 1
         for (int m = 0; m < R::NQ; ++m) {
-            const double* p = T.vp[m];
-            const double* dx = T.vdx[m];
-            const double* de = T.vde[m];
-            const double qv = dot<NM>(u, p);
-            const double q0 = qget<0>(qv), q1 = qget<1>(qv), q2 = qget<2>(qv), q3 = qget<3>(qv);
-            const double wa = T.vw[m] * area;
-            const double g1 = wa * lane_flux(qv, q0, q1, q2, q3, xx, xy, gm1, s1, s2, s3);
-            const double g2 = wa * lane_flux(qv, q0, q1, q2, q3, ex, ey, gm1, s1, s2, s3);
+            const T* p = TB.vp[m];
+            const T* dx = TB.vdx[m];
+            const T* de = TB.vde[m];
+            const T qv = dot<NM>(u, p);
+            const T q0 = qget<0>(qv), q1 = qget<1>(qv), q2 = qget<2>(qv), q3 = qget<3>(qv);
+            const T wa = TB.vw[m] * areaT;
+            const T g1 = wa * lane_flux(qv, q0, q1, q2, q3, xx, xy, gm1, s1, s2, s3);
+            const T g2 = wa * lane_flux(qv, q0, q1, q2, q3, ex, ey, gm1, s1, s2, s3);
 #pragma unroll
             for (int l = 1; l < NM; ++l) r[l] = fma(dx[l], g1, fma(de[l], g2, r[l]));
         }
@@ -344,51 +420,59 @@ __global__ __launch_bounds__(kBlock) void k_residual(StageArgs a) {
         // normal l_i n_i equals -2|K| grad(lambda_i) of the barycentric coordinate
 #pragma unroll 1
         for (int i = 0; i < 3; ++i) {
-            const double gx = i == 0 ? -(xx + ex) : (i == 1 ? xx : ex);
-            const double gy = i == 0 ? -(xy + ey) : (i == 1 ? xy : ey);
-            const double lnx = -2.0 * area * gx, lny = -2.0 * area * gy;
-            const double al = alpha * a.m.len[i * snc + c];
+            const T gx = i == 0 ? -(xx + ex) : (i == 1 ? xx : ex);
+            const T gy = i == 0 ? -(xy + ey) : (i == 1 ? xy : ey);
+            const T lnx = (T)-2.0 * areaT * gx, lny = (T)-2.0 * areaT * gy;
+            const T al = (T)(alpha * a.m.len[i * snc + c]);
             const int link = a.m.link[i * snc + c];
             const bool has = link >= 0;
             const int nb = has ? (link >> 2) : c;
             const int j = link & 3;
-            double un[NM];
+            T un[NM];
+            un[0] = (T)ua_p[nb];
 #pragma unroll
-            for (int l = 0; l < NM; ++l) un[l] = uv[l * snc + nb];
+            for (int l = 1; l < NM; ++l) un[l] = uh_p[(l - 1) * snc + nb];
 #pragma unroll 1
             for (int nu = 0; nu < R::NE; ++nu) {
-                const double* p = T.ep[i * R::NE + nu];
-                const double wsn = nu == 0 ? R::ws[0] : (nu == 1 ? R::ws[1] : R::ws[2]);
-                const double qi = dot<NM>(u, p);
-                double qe = qi;
+                const T* p = TB.ep[i * R::NE + nu];
+                const T wsn = (T)(nu == 0 ? R::ws[0] : (nu == 1 ? R::ws[1] : R::ws[2]));
+                const T qi = dot<NM>(u, p);
+                T qe = qi;
                 if (has) {
                     // the neighbour runs the shared edge the other way: its parameter is
                     // 1 - s_nu = s_{NE-1-nu} (symmetric Gauss nodes)
-                    qe = dot<NM>(un, T.ep[j * R::NE + (R::NE - 1 - nu)]);
+                    qe = dot<NM>(un, TB.ep[j * R::NE + (R::NE - 1 - nu)]);
                 }
-                const double fi = lane_flux(qi, qget<0>(qi), qget<1>(qi), qget<2>(qi), qget<3>(qi), lnx, lny, gm1,
-                                            s1, s2, s3);
-                const double fe = lane_flux(qe, qget<0>(qe), qget<1>(qe), qget<2>(qe), qget<3>(qe), lnx, lny, gm1,
-                                            s1, s2, s3);
-                const double fh = wsn * 0.5 * (fi + fe - al * (qe - qi));
+                const T fi = lane_flux(qi, qget<0>(qi), qget<1>(qi), qget<2>(qi), qget<3>(qi), lnx, lny, gm1,
+                                       s1, s2, s3);
+                const T fe = lane_flux(qe, qget<0>(qe), qget<1>(qe), qget<2>(qe), qget<3>(qe), lnx, lny, gm1,
+                                       s1, s2, s3);
+                const T fh = wsn * (T)0.5 * (fi + fe - al * (qe - qi));
+                r0 -= (double)fh;
 #pragma unroll
-                for (int l = 0; l < NM; ++l) r[l] = fma(-fh, p[l], r[l]);
+                for (int l = 1; l < NM; ++l) r[l] = fma(-fh, p[l], r[l]);
             }
         }
 
-        // diagonal mass a_K^(l) = |K| (a_l/|K|), then the SSP-RK3 combination
+        // diagonal mass a_K^(l) = |K| (a_l/|K|), then the SSP-RK3 combination; the
+        // average in FP64, the higher modes in the bulk type
         const double ia = frcp(area);
-        double w[NM];
+        const double adv0 = ua + dt * (r0 * ia * kInvMass[0]);
+        const double w0 = a.stage == 0 ? adv0 : sa * u0a_p[c] + sb * adv0;
+        wa_p[c] = w0;
+        const T iaT = (T)ia, dtT = (T)dt, saT = (T)sa, sbT = (T)sb;
+        T w[NM];
+        w[0] = (T)w0;
 #pragma unroll
-        for (int l = 0; l < NM; ++l) {
-            const double adv = u[l] + dt * (r[l] * ia * kInvMass[l]);
-            w[l] = a.stage == 0 ? adv : sa * u0v[l * snc + c] + sb * adv;
-            wv[l * snc + c] = w[l];
+        for (int l = 1; l < NM; ++l) {
+            const T adv = u[l] + dtT * (r[l] * iaT * (T)kInvMass[l]);
+            w[l] = a.stage == 0 ? adv : saT * u0h_p[(l - 1) * snc + c] + sbT * adv;
+            wh_p[(l - 1) * snc + c] = w[l];
         }
-        psum += area * w[0];
+        psum += area * w0;
 #pragma unroll 1
         for (int m = 0; m < R::NQ; ++m) {
-            const double q = dot<NM>(w, T.vp[m]);
+            const double q = (double)dot<NM>(w, TB.vp[m]);
             pmin = fmin(pmin, q);
             pmax = fmax(pmax, q);
         }
@@ -422,31 +506,41 @@ __global__ __launch_bounds__(kBlock) void k_residual(StageArgs a) {
 
 // ------------------------------------------------------------------------- pass 2: momentum norm
 
-template <int K>
+template <int K, typename T>
 __global__ __launch_bounds__(kBlock) void k_mnorm(StageArgs a) {
     using R = Rule<K>;
     constexpr int NM = R::NM;
+    constexpr bool kMixed = std::is_same<T, float>::value;
     const Glob* g = a.g;
     if (!g->active) return;
     const int nc = a.m.n_cell;
     const size_t snc = (size_t)nc;
     const double mb1 = g->ubar[1], mb2 = g->ubar[2];
+    // FP64: subtract mbar from the point value; mixed: from the FP64 average first
+    const T sh1 = kMixed ? (T)0.0 : (T)mb1, sh2 = kMixed ? (T)0.0 : (T)mb2;
+    const VarPtr<NM, T> p1 = var_ptr<NM, T>(a.w, a, 1, snc), p2 = var_ptr<NM, T>(a.w, a, 2, snc);
+    const double* a1 = p1.avg;
+    const double* a2 = p2.avg;
+    const T* h1 = p1.hi;
+    const T* h2 = p2.hi;
     double best = 0.0;
     const TileWalk tw = tile_walk((nc + kCellsPerTileScalar - 1) / kCellsPerTileScalar);
     for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
         const int c = tile * kCellsPerTileScalar + threadIdx.x;
         if (c >= nc) continue;
-        double m1[NM], m2[NM];
+        T m1[NM], m2[NM];
+        m1[0] = kMixed ? (T)(a1[c] - mb1) : (T)a1[c];
+        m2[0] = kMixed ? (T)(a2[c] - mb2) : (T)a2[c];
 #pragma unroll
-        for (int l = 0; l < NM; ++l) {
-            m1[l] = a.w[(1 * NM + l) * snc + c];
-            m2[l] = a.w[(2 * NM + l) * snc + c];
+        for (int l = 1; l < NM; ++l) {
+            m1[l] = h1[(l - 1) * snc + c];
+            m2[l] = h2[(l - 1) * snc + c];
         }
 #pragma unroll 1
         for (int m = 0; m < R::NQ; ++m) {
-            const double* p = tab<K>().vp[m];
-            const double d1 = dot<NM>(m1, p) - mb1, d2 = dot<NM>(m2, p) - mb2;
-            best = fmax(best, d1 * d1 + d2 * d2);
+            const T* p = tab<K, T>().vp[m];
+            const T d1 = dot<NM>(m1, p) - sh1, d2 = dot<NM>(m2, p) - sh2;
+            best = fmax(best, (double)(d1 * d1 + d2 * d2));
         }
     }
     best = wave_max(best);
@@ -463,26 +557,14 @@ __global__ __launch_bounds__(kBlock) void k_mnorm(StageArgs a) {
 // ------------------------------------------------------------------------- pass 3: OE, limiter, alpha
 
 // P2 physical Hessian (xx, xy, yy) of one variable with modes u[0..5] (constant per cell)
-__device__ __forceinline__ void hessian(const double* u, double xx, double xy, double ex, double ey, double* h) {
-    const double hxx = 48.0 * u[3];
-    const double hxe = 24.0 * u[3] + 20.0 * u[4];
-    const double hee = 8.0 * u[3] + 20.0 * u[4] + 20.0 * u[5];
-    h[0] = hxx * xx * xx + 2.0 * hxe * xx * ex + hee * ex * ex;
+template <typename T>
+__device__ __forceinline__ void hessian(const T* u, T xx, T xy, T ex, T ey, T* h) {
+    const T hxx = (T)48.0 * u[3];
+    const T hxe = (T)24.0 * u[3] + (T)20.0 * u[4];
+    const T hee = (T)8.0 * u[3] + (T)20.0 * u[4] + (T)20.0 * u[5];
+    h[0] = hxx * xx * xx + (T)2.0 * hxe * xx * ex + hee * ex * ex;
     h[1] = hxx * xx * xy + hxe * (xx * ey + xy * ex) + hee * ex * ey;
-    h[2] = hxx * xy * xy + 2.0 * hxe * xy * ey + hee * ey * ey;
-}
-
-// value and physical gradient of one variable at reference point (x, e)
-template <int K, int NM>
-__device__ __forceinline__ void value_grad(const double* u, double x, double e, double xx, double xy, double ex,
-                                           double ey, double& q, double& qx, double& qy) {
-    double p[NM], dx[NM], de[NM];
-    psi<K>(x, e, p);
-    dpsi<K>(x, e, dx, de);
-    q = dot<NM>(u, p);
-    const double sx = dot<NM>(u, dx), se = dot<NM>(u, de);
-    qx = sx * xx + se * ex;
-    qy = sx * xy + se * ey;
+    h[2] = hxx * xy * xy + (T)2.0 * hxe * xy * ey + hee * ey * ey;
 }
 
 // point t of the limiter's node set: 3 NE edge Gauss points, then the two extra points
@@ -502,93 +584,149 @@ __device__ __forceinline__ void node_point(int t, double n0x, double n0e, double
     }
 }
 
-template <int K>
-__global__ __launch_bounds__(kBlock) void k_filter(StageArgs a) {
+// rho e = E - |m|^2 / (2 rho) of a point value
+__device__ __forceinline__ double internal_energy(const double (&q)[4]) {
+    return q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) * frcp(q[0]);
+}
+
+// the full state (all four variables, FP64) at this lane's limiter points
+// t = v, v+4, v+8 of the NP-point node set
+template <int K, int NM>
+__device__ __forceinline__ void node_values(int v, const double (&W)[4][NM], double n0x, double n0e, double n1x,
+                                            double n1e, double (&pv)[3][4]) {
+    constexpr int NP = 3 * Rule<K>::NE + 2;
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+        const int t = v + 4 * kk;
+        double x, e, p[NM];
+        node_point<K>(t < NP ? t : v, n0x, n0e, n1x, n1e, x, e);
+        psi<K>(x, e, p);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pv[kk][q] = dot<NM>(W[q], p);
+    }
+}
+
+// all coefficients of the cell in every lane of its quad, in FP64
+template <int NM, typename T>
+__device__ __forceinline__ void gather_cell(double wa, const T (&w)[NM], double (&W)[4][NM]) {
+    W[0][0] = qget<0>(wa);
+    W[1][0] = qget<1>(wa);
+    W[2][0] = qget<2>(wa);
+    W[3][0] = qget<3>(wa);
+#pragma unroll
+    for (int l = 1; l < NM; ++l) {
+        W[0][l] = (double)qget<0>(w[l]);
+        W[1][l] = (double)qget<1>(w[l]);
+        W[2][l] = (double)qget<2>(w[l]);
+        W[3][l] = (double)qget<3>(w[l]);
+    }
+}
+
+// three waves per SIMD: the allocator then keeps the P2 instantiations within 168 VGPRs
+template <int K, typename T>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_filter(StageArgs a) {
     using R = Rule<K>;
+    using F = Fp<T>;
     constexpr int NM = R::NM;
     constexpr int NE = R::NE;
     constexpr int NP = 3 * NE + 2;   // limiter node set size
+    constexpr bool kMixed = std::is_same<T, float>::value;
     const Glob* g = a.g;
     if (!g->active) return;
     const int nc = a.m.n_cell;
     const size_t snc = (size_t)nc;
     const double gamma = a.gamma;
+    const T gammaT = (T)gamma;
     const int v = threadIdx.x & 3;
     const bool oe = a.oe_enable && a.stage >= 0;
     const bool ri = a.oe_mode == 0;
-    const double dt = g->dt;
+    const T dt = (T)g->dt;
     // inverse L-infinity norm of this lane's quantity (0 in the zero branch)
-    const double inv_my = v == 0 ? g->inv_nrm[0] : (v == 3 ? g->inv_nrm[3] : (ri ? g->inv_nrm_m : g->inv_nrm[v]));
-    const double* wsrc = a.w + (size_t)v * NM * snc;
-    double* wdst = a.uout + (size_t)v * NM * snc;
-    const Tab<K>& T = tab<K>();
+    const T inv_my =
+        (T)(v == 0 ? g->inv_nrm[0] : (v == 3 ? g->inv_nrm[3] : (ri ? g->inv_nrm_m : g->inv_nrm[v])));
+    const VarPtr<NM, T> wp = var_ptr<NM, T>(a.w, a, v, snc);
+    const VarPtr<NM, T> op = var_ptr<NM, T>(a.uout, a, v, snc);
+    const double* wa_p = wp.avg;
+    const T* wh_p = wp.hi;
+    double* oa_p = op.avg;
+    T* oh_p = op.hi;
+    const Tab<K, T>& TB = tab<K, T>();
 
-    double amax = 0.0, n_lim = 0.0, n_bad = 0.0;
+    double amax = 0.0, n_lim = 0.0, n_bad = 0.0, n_flat = 0.0;
     const TileWalk tw = tile_walk((nc + kCellsPerTile - 1) / kCellsPerTile);
     for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
         const int c = tile * kCellsPerTile + (threadIdx.x >> 2);
         if (c >= nc) continue;   // whole quad
-        double w[NM];
+        const double wa = wa_p[c];   // the average: untouched by the OE (eq. OE:m0) and the limiter
+        T w[NM];
+        w[0] = (T)wa;
 #pragma unroll
-        for (int l = 0; l < NM; ++l) w[l] = wsrc[l * snc + c];
-        const double xx = a.m.jinv[c], xy = a.m.jinv[snc + c];
-        const double ex = a.m.jinv[2 * snc + c], ey = a.m.jinv[3 * snc + c];
-        const double area = a.m.area[c];
+        for (int l = 1; l < NM; ++l) w[l] = wh_p[(l - 1) * snc + c];
+        const T xx = (T)a.m.jinv[c], xy = (T)a.m.jinv[snc + c];
+        const T ex = (T)a.m.jinv[2 * snc + c], ey = (T)a.m.jinv[3 * snc + c];
+        const T area = (T)a.m.area[c];
         // unit outward normals n_i = l_i n_i / l_i with l_i n_i = -2|K| grad(lambda_i)
-        double nxs[3], nys[3], ils[3];
+        T nxs[3], nys[3], ils[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            const double gx = i == 0 ? -(xx + ex) : (i == 1 ? xx : ex);
-            const double gy = i == 0 ? -(xy + ey) : (i == 1 ? xy : ey);
-            ils[i] = frcp(a.m.len[i * snc + c]);
-            nxs[i] = -2.0 * area * gx * ils[i];
-            nys[i] = -2.0 * area * gy * ils[i];
+            const T gx = i == 0 ? -(xx + ex) : (i == 1 ? xx : ex);
+            const T gy = i == 0 ? -(xy + ey) : (i == 1 ? xy : ey);
+            ils[i] = F::rcp((T)a.m.len[i * snc + c]);
+            nxs[i] = (T)-2.0 * area * gx * ils[i];
+            nys[i] = (T)-2.0 * area * gy * ils[i];
         }
 
         if (oe) {
-            double sig[K + 1];
+            T sig[K + 1];
 #pragma unroll
-            for (int jj = 0; jj <= K; ++jj) sig[jj] = 0.0;
-            double ho[3] = {0.0, 0.0, 0.0};
+            for (int jj = 0; jj <= K; ++jj) sig[jj] = (T)0.0;
+            T ho[3] = {(T)0.0, (T)0.0, (T)0.0};
             if constexpr (K == 2) hessian(w, xx, xy, ex, ey, ho);
 #pragma unroll 1
             for (int i = 0; i < 3; ++i) {
                 const int link = a.m.link[i * snc + c];
                 if (link < 0) continue;   // transmissive boundary: zero jump (whole quad)
                 const int nb = link >> 2, j = link & 3;
-                double wn[NM];
+                const double wna = wa_p[nb];
+                T wn[NM];
+                wn[0] = (T)wna;
 #pragma unroll
-                for (int l = 0; l < NM; ++l) wn[l] = wsrc[l * snc + nb];
-                const double nxx = a.m.jinv[nb], nxy = a.m.jinv[snc + nb];
-                const double nex = a.m.jinv[2 * snc + nb], ney = a.m.jinv[3 * snc + nb];
-                const double nx = i == 0 ? nxs[0] : (i == 1 ? nxs[1] : nxs[2]);
-                const double ny = i == 0 ? nys[0] : (i == 1 ? nys[1] : nys[2]);
-                const double h = 2.0 * area * (i == 0 ? ils[0] : (i == 1 ? ils[1] : ils[2]));
+                for (int l = 1; l < NM; ++l) wn[l] = wh_p[(l - 1) * snc + nb];
+                const T nxx = (T)a.m.jinv[nb], nxy = (T)a.m.jinv[snc + nb];
+                const T nex = (T)a.m.jinv[2 * snc + nb], ney = (T)a.m.jinv[3 * snc + nb];
+                const T nx = i == 0 ? nxs[0] : (i == 1 ? nxs[1] : nxs[2]);
+                const T ny = i == 0 ? nys[0] : (i == 1 ? nys[1] : nys[2]);
+                const T h = (T)2.0 * area * (i == 0 ? ils[0] : (i == 1 ? ils[1] : ils[2]));
                 // momentum lanes see m_n = m.n (lane 1) and m_t = m.(-n_y, n_x) (lane 2)
-                const double ca = (ri && (v == 1 || v == 2)) ? nx : 1.0;
-                const double cb = ri ? (v == 1 ? ny : (v == 2 ? -ny : 0.0)) : 0.0;
-                double S[K + 1];
+                const T ca = (ri && (v == 1 || v == 2)) ? nx : (T)1.0;
+                const T cb = ri ? (v == 1 ? ny : (v == 2 ? -ny : (T)0.0)) : (T)0.0;
+                T S[K + 1];
 #pragma unroll
-                for (int jj = 0; jj <= K; ++jj) S[jj] = 0.0;
-                double xs[4];   // own variable at: own end 0, neighbour end 0, own end 1, neighbour end 1
+                for (int jj = 0; jj <= K; ++jj) S[jj] = (T)0.0;
+                T xs[4];   // own variable at: own end 0, neighbour end 0, own end 1, neighbour end 1
 #pragma unroll
                 for (int end = 0; end < 2; ++end) {
                     // own vertex i+1 (then i+2) meets the neighbour's vertex j+2 (then j+1)
                     const int ov = (i + 1 + end) % 3, nv = (j + 2 - end) % 3;
-                    double q, qx, qy, r, rx, ry;
-                    {
-                        q = dot<NM>(w, T.vtp[ov]);
-                        const double sx = dot<NM>(w, T.vtdx[ov]), se = dot<NM>(w, T.vtde[ov]);
-                        qx = sx * xx + se * ex;
-                        qy = sx * xy + se * ey;
-                        r = dot<NM>(wn, T.vtp[nv]);
-                        const double tx = dot<NM>(wn, T.vtdx[nv]), te = dot<NM>(wn, T.vtde[nv]);
-                        rx = tx * nxx + te * nex;
-                        ry = tx * nxy + te * ney;
+                    T q, r, jv;
+                    if constexpr (kMixed) {
+                        // value jump from the FP64 averages plus the float higher modes
+                        const T qh = dot_hi<NM>(w, TB.vtp[ov]), rh = dot_hi<NM>(wn, TB.vtp[nv]);
+                        q = w[0] + qh;
+                        r = wn[0] + rh;
+                        jv = (T)(wna - wa) + (rh - qh);
+                    } else {
+                        q = dot<NM>(w, TB.vtp[ov]);
+                        r = dot<NM>(wn, TB.vtp[nv]);
+                        jv = r - q;
                     }
+                    const T sx = dot<NM>(w, TB.vtdx[ov]), se = dot<NM>(w, TB.vtde[ov]);
+                    const T qx = sx * xx + se * ex, qy = sx * xy + se * ey;
+                    const T tx = dot<NM>(wn, TB.vtdx[nv]), te = dot<NM>(wn, TB.vtde[nv]);
+                    const T rx = tx * nxx + te * nex, ry = tx * nxy + te * ney;
                     xs[2 * end] = q;
                     xs[2 * end + 1] = r;
-                    double jv = r - q, jx = rx - qx, jy = ry - qy;
+                    T jx = rx - qx, jy = ry - qy;
                     if (ri) {
                         jv = ca * jv + cb * qswap12(jv);
                         jx = ca * jx + cb * qswap12(jx);
@@ -600,26 +738,26 @@ __global__ __launch_bounds__(kBlock) void k_filter(StageArgs a) {
                 if constexpr (K == 2) {
                     // second derivatives are constant per cell: both endpoints carry the
                     // same jump, 2 (jxx^2 + 2 jxy^2 + jyy^2)
-                    double hn[3];
+                    T hn[3];
                     hessian(wn, nxx, nxy, nex, ney, hn);
-                    double d0 = hn[0] - ho[0], d1 = hn[1] - ho[1], d2 = hn[2] - ho[2];
+                    T d0 = hn[0] - ho[0], d1 = hn[1] - ho[1], d2 = hn[2] - ho[2];
                     if (ri) {
                         d0 = ca * d0 + cb * qswap12(d0);
                         d1 = ca * d1 + cb * qswap12(d1);
                         d2 = ca * d2 + cb * qswap12(d2);
                     }
-                    S[2] = 2.0 * (d0 * d0 + 2.0 * d1 * d1 + d2 * d2);
+                    S[2] = (T)2.0 * (d0 * d0 + (T)2.0 * d1 * d1 + d2 * d2);
                 }
                 // beta^(i): max spectral radius over both endpoints and both sides; lane v
                 // evaluates state v of the four
-                double st[4];
+                T st[4];
                 quad_transpose(v, xs, st);
-                const double beta = qmax(spectral_radius(st[0], st[1], st[2], st[3], nx, ny, gamma));
-                const double bh = beta / h;
-                double hj = 1.0;
+                const T beta = qmax(spectral_radius(st[0], st[1], st[2], st[3], nx, ny, gammaT));
+                const T bh = beta / h;
+                T hj = (T)1.0;
 #pragma unroll
                 for (int jj = 0; jj <= K; ++jj) {
-                    double d = kA[K][jj] * hj * inv_my * fsqrt(0.5 * S[jj]);
+                    T d = (T)kA[K][jj] * hj * inv_my * F::sqrt((T)0.5 * S[jj]);
                     if (ri) d = fmax(d, qswap12(d));   // delta(m) = max(delta(m_n), delta(m_t))
                     sig[jj] = fma(bh, d, sig[jj]);
                     hj *= h;
@@ -627,42 +765,27 @@ __global__ __launch_bounds__(kBlock) void k_filter(StageArgs a) {
             }
             // exact solution of the damping ODE: degree-m modes scaled by
             // exp(-dt sum_{j<=m} sigma^j); the cell average is untouched (eq. OE:m0)
-            double acc = sig[0];
+            T acc = sig[0];
 #pragma unroll
             for (int m = 1; m <= K; ++m) {
                 acc += sig[m];
-                const double f = exp(-dt * acc);
+                const T f = F::exp(-dt * acc);
 #pragma unroll
                 for (int l = m * (m + 1) / 2; l < (m + 1) * (m + 2) / 2; ++l) w[l] *= f;
             }
         }
 
-        // every lane of the quad gets all coefficients of the cell; lane v then
-        // evaluates the full state at its share of points t = v, v+4, v+8
+        // every lane of the quad gets all coefficients of the cell in FP64; lane v
+        // then evaluates the full state at its share of points t = v, v+4, v+8
         double W[4][NM];
-#pragma unroll
-        for (int l = 0; l < NM; ++l) {
-            W[0][l] = qget<0>(w[l]);
-            W[1][l] = qget<1>(w[l]);
-            W[2][l] = qget<2>(w[l]);
-            W[3][l] = qget<3>(w[l]);
-        }
+        gather_cell<NM, T>(wa, w, W);
         const double n0x = a.m.node_ref[c], n0e = a.m.node_ref[snc + c];
         const double n1x = a.m.node_ref[2 * snc + c], n1e = a.m.node_ref[3 * snc + c];
-
-        // the full state at this lane's points t = v, v+4, v+8 of the node set
         double pv[3][4];
+        node_values<K, NM>(v, W, n0x, n0e, n1x, n1e, pv);
         bool pin[3];
 #pragma unroll
-        for (int kk = 0; kk < 3; ++kk) {
-            const int t = v + 4 * kk;
-            pin[kk] = t < NP;
-            double x, e, p[NM];
-            node_point<K>(t < NP ? t : v, n0x, n0e, n1x, n1e, x, e);
-            psi<K>(x, e, p);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) pv[kk][q] = dot<NM>(W[q], p);
-        }
+        for (int kk = 0; kk < 3; ++kk) pin[kk] = v + 4 * kk < NP;
         const double ub0 = W[0][0], ub1 = W[1][0], ub2 = W[2][0], ub3 = W[3][0];
         double th1 = 1.0, th2 = 1.0;
         if (a.bp_enable) {
@@ -674,6 +797,15 @@ __global__ __launch_bounds__(kBlock) void k_filter(StageArgs a) {
             const double rmin = qmin(rloc);
             const double e1 = fmin(ub0, kEpsBP);
             th1 = rmin >= e1 ? 1.0 : fmin((ub0 - e1) / (ub0 - rmin), 1.0);
+            // factor of the stored density modes: in the mixed form it aims above the
+            // floor by the rounding bound; theta_2 below still comes from the density
+            // pinned at eps_1 (rho e grows with rho at nodes below the average, so
+            // that theta_2 is the smaller one), which keeps it at the FP64 value
+            double th1s = th1;
+            if constexpr (kMixed) {
+                const double t1 = e1 + kMixMargin * abs_sum_hi<NM>(W[0]);
+                th1s = rmin >= t1 ? 1.0 : fmax(fmin((ub0 - t1) / (ub0 - rmin), 1.0), 0.0);
+            }
             // step 2: internal energy E - |m|^2 / (2 rho) of the density-scaled state (eq. 1981)
             const double eb = ub3 - 0.5 * (ub1 * ub1 + ub2 * ub2) / ub0;
             const double e2 = fmin(eb, kEpsBP);
@@ -687,53 +819,108 @@ __global__ __launch_bounds__(kBlock) void k_filter(StageArgs a) {
             }
             const double emin = qmin(eloc);
             th2 = emin >= e2 ? 1.0 : fmin((eb - e2) / (eb - emin), 1.0);
+            if constexpr (kMixed) {
+                // Rounding the scaled modes moves rho e at a node by at most, to first
+                // order, |dE| + |v| (|dm1| + |dm2|) + |v|^2/2 |drho|, with v the
+                // velocity of the limited state there and each |d.| <= margin * theta
+                // * sum_l |c_l|; theta_2 aims that far above the floor.
+                double vloc = 0.0;
 #pragma unroll
-            for (int l = 1; l < NM; ++l) {
-                if (v == 0) w[l] *= th1;
-                w[l] *= th2;
+                for (int kk = 0; kk < 3; ++kk) {
+                    if (pin[kk]) {
+                        const double q0 = ub0 + th2 * (pv[kk][0] - ub0);
+                        const double q1 = ub1 + th2 * (pv[kk][1] - ub1), q2 = ub2 + th2 * (pv[kk][2] - ub2);
+                        vloc = fmax(vloc, (q1 * q1 + q2 * q2) * frcp(q0 * q0));
+                    }
+                }
+                const double vm = fsqrt(qmax(vloc));
+                const double t2 = e2 + kMixMargin * th2 *
+                                           (abs_sum_hi<NM>(W[3]) + vm * (abs_sum_hi<NM>(W[1]) + abs_sum_hi<NM>(W[2])) +
+                                            0.5 * vm * vm * th1 * abs_sum_hi<NM>(W[0]));
+                th2 = emin >= t2 ? 1.0 : fmax(fmin((eb - t2) / (eb - emin), 1.0), 0.0);
+                th1 = th1s;
+                const double f = v == 0 ? th1 * th2 : th2;
+                if (f < 1.0) {
+#pragma unroll
+                    for (int l = 1; l < NM; ++l) w[l] = (T)((double)w[l] * f);
+                }
+            } else {
+#pragma unroll
+                for (int l = 1; l < NM; ++l) {
+                    if (v == 0) w[l] *= th1;
+                    w[l] *= th2;
+                }
             }
             if (v == 0) {
                 n_lim += (th1 < 1.0 || th2 < 1.0) ? 1.0 : 0.0;
                 n_bad += (ub0 > 0.0 && eb > 0.0) ? 0.0 : 1.0;
             }
+            if constexpr (kMixed) {
+                if (th1 < 1.0 || th2 < 1.0) {   // the same in the four lanes of the quad
+                    // check the coefficients as stored (rounded to float)
+                    gather_cell<NM, T>(wa, w, W);
+                    node_values<K, NM>(v, W, n0x, n0e, n1x, n1e, pv);
+                    double ok = 1.0;
+#pragma unroll
+                    for (int kk = 0; kk < 3; ++kk)
+                        if (pin[kk] && !(pv[kk][0] >= 0.5 * e1 && internal_energy(pv[kk]) >= 0.5 * e2)) ok = 0.0;
+                    if (qmin(ok) == 0.0) {
+                        // keep the average only: admissible whenever the average is
+#pragma unroll
+                        for (int l = 1; l < NM; ++l) w[l] = (T)0.0;
+#pragma unroll
+                        for (int kk = 0; kk < 3; ++kk) {
+                            pv[kk][0] = ub0;
+                            pv[kk][1] = ub1;
+                            pv[kk][2] = ub2;
+                            pv[kk][3] = ub3;
+                        }
+                        if (v == 0) n_flat += 1.0;
+                    }
+                }
+            }
         }
 
-        // max wave speed over the edge Gauss points of the limited state (eq. 1250)
+        // max wave speed over the edge Gauss points of the limited state (eq. 1250);
+        // in the mixed form pv already holds the stored state's values
+        const double ta = kMixed ? 1.0 : th2;
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) {
             const int t = v + 4 * kk;
             if (t < 3 * NE) {
                 const int i = t / NE;
-                const double nx = i == 0 ? nxs[0] : (i == 1 ? nxs[1] : nxs[2]);
-                const double ny = i == 0 ? nys[0] : (i == 1 ? nys[1] : nys[2]);
-                const double rr = spectral_radius(ub0 + th2 * (pv[kk][0] - ub0), ub1 + th2 * (pv[kk][1] - ub1),
-                                                  ub2 + th2 * (pv[kk][2] - ub2), ub3 + th2 * (pv[kk][3] - ub3), nx,
+                const double nx = (double)(i == 0 ? nxs[0] : (i == 1 ? nxs[1] : nxs[2]));
+                const double ny = (double)(i == 0 ? nys[0] : (i == 1 ? nys[1] : nys[2]));
+                const double rr = spectral_radius(ub0 + ta * (pv[kk][0] - ub0), ub1 + ta * (pv[kk][1] - ub1),
+                                                  ub2 + ta * (pv[kk][2] - ub2), ub3 + ta * (pv[kk][3] - ub3), nx,
                                                   ny, gamma);
                 amax = (rr > amax || rr != rr) ? rr : amax;
             }
         }
+        oa_p[c] = wa;
 #pragma unroll
-        for (int l = 0; l < NM; ++l) wdst[l * snc + c] = w[l];
+        for (int l = 1; l < NM; ++l) oh_p[(l - 1) * snc + c] = w[l];
     }
 
     amax = wave_max(amax);
     n_lim = wave_sum(n_lim);
     n_bad = wave_sum(n_bad);
-    __shared__ double lds[kBlock / 64][3];
+    n_flat = wave_sum(n_flat);
+    __shared__ double lds[kBlock / 64][4];
     if ((threadIdx.x & 63) == 0) {
         lds[threadIdx.x >> 6][0] = amax;
         lds[threadIdx.x >> 6][1] = n_lim;
         lds[threadIdx.x >> 6][2] = n_bad;
+        lds[threadIdx.x >> 6][3] = n_flat;
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
+    if (threadIdx.x < 4) {
         const int k = threadIdx.x;
         double acc = lds[0][k];
         for (int w2 = 1; w2 < kBlock / 64; ++w2) acc = k == 0 ? fmax(acc, lds[w2][k]) : acc + lds[w2][k];
         a.part[(size_t)(kNumPartial + 1 + k) * kMaxBlocks + blockIdx.x] = acc;
     }
 }
-
 // ------------------------------------------------------------------------- finalize (one workgroup)
 
 constexpr int kFinThreads = 1024;
@@ -813,14 +1000,15 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_mnorm(const double* part, i
 // t, the step count and Delta t = C_SSP/alpha min_K C^DCW_{K,k}|K|, clamped to t_end
 __global__ __launch_bounds__(kFinThreads) void k_fin_filter(const double* part, int G, Glob* g, int stage) {
     if (!g->active) return;
-    const int col[3] = {kNumPartial + 1, kNumPartial + 2, kNumPartial + 3};
-    const int op[3] = {2, 0, 0};
-    double r[3];
-    reduce_columns<3>(part, G, col, op, r);
+    const int col[4] = {kNumPartial + 1, kNumPartial + 2, kNumPartial + 3, kNumPartial + 4};
+    const int op[4] = {2, 0, 0, 0};
+    double r[4];
+    reduce_columns<4>(part, G, col, op, r);
     if (threadIdx.x != 0) return;
     const double alpha = r[0], lim = r[1], bad = r[2];
     g->n_limited += (long long)lim;
     g->n_bad += (long long)bad;
+    g->n_flat += (long long)r[3];
     if (bad > 0) g->err = 1;
     if (stage < 2) {
         g->alpha = alpha;
@@ -893,10 +1081,11 @@ __device__ __forceinline__ void problem_state(int kind, const ProblemParams& P, 
     q[3] = p / (gamma - 1.0) + 0.5 * r * (u * u + v * v);
 }
 
-// L2 projection (mass diagonal): u^(l) = sum_mu w_mu q(x_mu) Psi_l(x_mu) / (a_l/|K|).
+// L2 projection (mass diagonal): u^(l) = sum_mu w_mu q(x_mu) Psi_l(x_mu) / (a_l/|K|),
+// accumulated in FP64 and stored in the state view (higher modes rounded to T).
 // vx holds the oriented vertex coordinates [6][cell]; for the blast, vx[6][cell]
 // flags the cells that own the origin vertex and P.p[4] is their total area.
-template <int K>
+template <int K, typename T>
 __global__ __launch_bounds__(kBlock) void k_project(StageArgs a, int kind, ProblemParams P, const double* vx) {
     constexpr int NM = Rule<K>::NM;
     const int nc = a.m.n_cell;
@@ -934,9 +1123,12 @@ __global__ __launch_bounds__(kBlock) void k_project(StageArgs a, int kind, Probl
             for (int l = 0; l < NM; ++l) acc[v][l] *= kInvMass[l];
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+    for (int v = 0; v < 4; ++v) {
+        const VarPtr<NM, T> op = var_ptr<NM, T>(a.uout, a, v, snc);
+        op.avg[c] = acc[v][0];
 #pragma unroll
-        for (int l = 0; l < NM; ++l) a.uout[(v * NM + l) * snc + c] = acc[v][l];
+        for (int l = 1; l < NM; ++l) op.hi[(l - 1) * snc + c] = (T)acc[v][l];
+    }
 }
 
 __global__ void k_set_end(Glob* g, double t_end) {
@@ -955,19 +1147,32 @@ __global__ void k_set_end(Glob* g, double t_end) {
 
 inline unsigned grid_for(int nc) { return (unsigned)((nc + kBlock - 1) / kBlock); }
 
-}  // namespace
+// host handles of the instantiations of one (degree, precision)
+struct KernelSet {
+    const void* pass[3];   // residual, momentum norm, filter
+    const void* project;
+};
+template <int K, typename T>
+KernelSet kernel_set() {
+    return {{reinterpret_cast<const void*>(&k_residual<K, T>), reinterpret_cast<const void*>(&k_mnorm<K, T>),
+             reinterpret_cast<const void*>(&k_filter<K, T>)},
+            reinterpret_cast<const void*>(&k_project<K, T>)};
+}
+const KernelSet& kernels_for(int k, int mixed) {
+    static const KernelSet sets[2][2] = {{kernel_set<1, double>(), kernel_set<1, float>()},
+                                         {kernel_set<2, double>(), kernel_set<2, float>()}};
+    return sets[k == 2 ? 1 : 0][mixed ? 1 : 0];
+}
 
 // Grid of a pass: one workgroup per tile while the tiles fit on the GPU at once,
 // otherwise as many workgroups as can be resident (occupancy x compute units),
 // rounded down to a multiple of 8 so every XCD gets the same share; workgroups
 // then stride over their XCD's tiles.  Bounded by kMaxBlocks (the partials).
-template <typename Kern>
-int resident_blocks(Kern kernel) {
+int resident_blocks(const void* kernel) {
     static std::mutex mu;
     static std::unordered_map<const void*, int> cache;
     std::lock_guard<std::mutex> lock(mu);
-    const void* key = reinterpret_cast<const void*>(kernel);
-    auto it = cache.find(key);
+    auto it = cache.find(kernel);
     if (it != cache.end()) return it->second;
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -975,48 +1180,34 @@ int resident_blocks(Kern kernel) {
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1)
         per_cu = 1, cus = cus > 0 ? cus : 256;
     const int g = std::min(kMaxBlocks, std::max(8, (cus * per_cu) / 8 * 8));
-    cache[key] = g;
+    cache[kernel] = g;
     return g;
 }
 
-int grid_for_pass(int which, int k, int n_cell) {
+int launch_pass(int which, int k, const StageArgs& a, void* stream) {
+    StageArgs args = a;
+    void* argv[] = {&args};
+    const int grid = grid_for_pass(which, k, a.mixed, a.m.n_cell);
+    return (int)hipLaunchKernel(kernels_for(k, a.mixed).pass[which], dim3(grid), dim3(kBlock), argv, 0,
+                                (hipStream_t)stream);
+}
+
+}  // namespace
+
+int grid_for_pass(int which, int k, int mixed, int n_cell) {
     const int per_tile = which == 1 ? kCellsPerTileScalar : kCellsPerTile;
     const int tiles = (n_cell + per_tile - 1) / per_tile;
     const int want = std::max(8, ((tiles + 7) / 8) * 8);
-    int cap;
-    if (which == 0) cap = k == 1 ? resident_blocks(k_residual<1>) : resident_blocks(k_residual<2>);
-    else if (which == 1) cap = k == 1 ? resident_blocks(k_mnorm<1>) : resident_blocks(k_mnorm<2>);
-    else cap = k == 1 ? resident_blocks(k_filter<1>) : resident_blocks(k_filter<2>);
-    return std::min(want, cap);
+    return std::min(want, resident_blocks(kernels_for(k, mixed).pass[which]));
 }
 
-int launch_residual(int k, const StageArgs& a, void* stream) {
-    hipStream_t s = (hipStream_t)stream;
-    const dim3 grid(grid_for_pass(0, k, a.m.n_cell));
-    if (k == 1) hipLaunchKernelGGL(k_residual<1>, grid, dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL(k_residual<2>, grid, dim3(kBlock), 0, s, a);
-    return (int)hipGetLastError();
-}
-
-int launch_mnorm(int k, const StageArgs& a, void* stream) {
-    hipStream_t s = (hipStream_t)stream;
-    const dim3 grid(grid_for_pass(1, k, a.m.n_cell));
-    if (k == 1) hipLaunchKernelGGL(k_mnorm<1>, grid, dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL(k_mnorm<2>, grid, dim3(kBlock), 0, s, a);
-    return (int)hipGetLastError();
-}
-
-int launch_filter(int k, const StageArgs& a, void* stream) {
-    hipStream_t s = (hipStream_t)stream;
-    const dim3 grid(grid_for_pass(2, k, a.m.n_cell));
-    if (k == 1) hipLaunchKernelGGL(k_filter<1>, grid, dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL(k_filter<2>, grid, dim3(kBlock), 0, s, a);
-    return (int)hipGetLastError();
-}
+int launch_residual(int k, const StageArgs& a, void* stream) { return launch_pass(0, k, a, stream); }
+int launch_mnorm(int k, const StageArgs& a, void* stream) { return launch_pass(1, k, a, stream); }
+int launch_filter(int k, const StageArgs& a, void* stream) { return launch_pass(2, k, a, stream); }
 
 int launch_finalize(int which, int k, const StageArgs& a, void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    const int G = grid_for_pass(which, k, a.m.n_cell);
+    const int G = grid_for_pass(which, k, a.mixed, a.m.n_cell);
     if (which == 0)
         hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(kFinThreads), 0, s, a.part, G, a.g);
     else if (which == 1)
@@ -1026,14 +1217,14 @@ int launch_finalize(int which, int k, const StageArgs& a, void* stream) {
     return (int)hipGetLastError();
 }
 
-int launch_project(int k, const StageArgs& a, int kind, const double* dparams, int n_params, void* stream) {
-    hipStream_t s = (hipStream_t)stream;
+int launch_project(int k, const StageArgs& a, int kind, const double* dparams, int n_params, const double* vx,
+                   void* stream) {
     ProblemParams P{};
     for (int i = 0; i < n_params && i < 20; ++i) P.p[i] = dparams[i];
-    const double* vx = a.w;   // the pre-filter buffer carries the coordinates during set-up
-    if (k == 1) hipLaunchKernelGGL(k_project<1>, dim3(grid_for(a.m.n_cell)), dim3(kBlock), 0, s, a, kind, P, vx);
-    else hipLaunchKernelGGL(k_project<2>, dim3(grid_for(a.m.n_cell)), dim3(kBlock), 0, s, a, kind, P, vx);
-    return (int)hipGetLastError();
+    StageArgs args = a;
+    void* argv[] = {&args, &kind, &P, &vx};
+    return (int)hipLaunchKernel(kernels_for(k, a.mixed).project, dim3(grid_for(a.m.n_cell)), dim3(kBlock), argv, 0,
+                                (hipStream_t)stream);
 }
 
 int launch_set_end(Glob* g, double t_end, void* stream) {

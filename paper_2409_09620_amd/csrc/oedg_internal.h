@@ -12,6 +12,7 @@ constexpr int kCellsPerTile = 64;      // a quad of 4 lanes per cell in the resi
 constexpr int kCellsPerTileScalar = 256;   // one lane per cell in the momentum-norm pass
 constexpr int kMaxBlocks = 4096;       // upper bound of a pass's grid (= number of partials)
 constexpr int kNumPartial = 12;        // per-block partials of the residual pass
+constexpr int kPartCols = kNumPartial + 1 + 4;   // + momentum norm + 4 filter partials
 
 // Host-side mesh tables built once per mesh (see mesh_host.cpp).  Per-cell arrays
 // that go to the device are structure-of-arrays: component-major, cell fastest.
@@ -54,6 +55,7 @@ struct Glob {
     long long n_limited;
     long long n_bad;
     long long n_cfl_exc;
+    long long n_flat;    // mixed precision: cells reset to their average by the rounding check
     int active;          // 0: t reached t_end, or an error stopped the run
     int err;             // sticky: 1 once a cell average left the admissible set
 };
@@ -67,33 +69,48 @@ struct DevMesh {
     const int32_t* link;
 };
 
+// One state buffer.  Cell averages (mode 0) are FP64 in every precision; modes
+// l >= 1 are stored in the bulk type (double for DG_PREC_FP64, float for
+// DG_PREC_MIXED).  Entry (var v, mode l, cell c) is avg[v * avs + c] for l = 0
+// and hi[v * hvs + (l - 1) * n_cell + c] for l >= 1, with the strides of
+// StageArgs.  The FP64 view of a [var][mode][cell] array is avg = base,
+// hi = base + n_cell, avs = hvs = n_modes * n_cell.
+struct StateView {
+    double* avg;
+    void* hi;
+};
+
 struct StageArgs {
     DevMesh m;
-    const double* uin;    // stage input (own + neighbours)
-    const double* u0;     // u^n for the SSP combination
-    double* w;            // pre-filter state (written by the residual pass)
-    double* uout;         // limited stage output
+    StateView uin;        // stage input (own + neighbours)
+    StateView u0;         // u^n for the SSP combination
+    StateView w;          // pre-filter state (written by the residual pass)
+    StateView uout;       // limited stage output
+    size_t avs, hvs;      // variable strides of the averages and of the higher modes
     double* part;         // per-block partials: [12][kMaxBlocks] residual, [kMaxBlocks] momentum
-                          // norm, [3][kMaxBlocks] filter
+                          // norm, [4][kMaxBlocks] filter
     Glob* g;
     double gamma;
     int stage;            // 0, 1, 2; -1 = limiter and alpha only (initial data)
     int oe_enable, oe_mode, bp_enable;
+    int mixed;            // 0: FP64 bulk, 1: FP32 bulk (averages and limiter stay FP64)
 };
 
-// Grid of pass `which` (0 residual, 1 momentum norm, 2 filter) at degree k: a
-// multiple of 8 (one share per XCD), at most kMaxBlocks and at most what is
-// resident at once; workgroups stride over their XCD's tiles.
-int grid_for_pass(int which, int k, int n_cell);
+// Grid of pass `which` (0 residual, 1 momentum norm, 2 filter) at degree k and
+// precision `mixed`: a multiple of 8 (one share per XCD), at most kMaxBlocks and
+// at most what is resident at once; workgroups stride over their XCD's tiles.
+int grid_for_pass(int which, int k, int mixed, int n_cell);
 
-// kernel launchers (kernels.hip); return a hipError_t as int.  Each pass kernel
-// writes per-workgroup partials; the matching finalize kernel (one workgroup)
-// reduces them in a fixed order into Glob.
+// kernel launchers (kernels.hip); the precision comes from a.mixed.  Return a
+// hipError_t as int.  Each pass kernel writes per-workgroup partials; the
+// matching finalize kernel (one workgroup) reduces them in a fixed order into Glob.
 int launch_residual(int k, const StageArgs& a, void* stream);
 int launch_mnorm(int k, const StageArgs& a, void* stream);
 int launch_filter(int k, const StageArgs& a, void* stream);
 int launch_finalize(int which, int k, const StageArgs& a, void* stream);   // 0 residual, 1 mnorm, 2 filter
-int launch_project(int k, const StageArgs& a, int kind, const double* dparams, int n_params,
+// L2 projection of a named problem into a.uout; vx holds the oriented vertex
+// coordinates [6][cell] (and, for the blast, the origin flags in row 6)
+int launch_project(int k, const StageArgs& a, int kind, const double* dparams, int n_params, const double* vx,
                    void* stream);
 int launch_set_end(Glob* g, double t_end, void* stream);
 

@@ -1,0 +1,197 @@
+"""The mixed-precision form (DG_PREC_MIXED) against the FP64 oracle.
+
+Mixed form: cell averages stored and updated in FP64, modes >= 1 stored in FP32
+with FP32 volume/surface quadrature and OE filter; the BP limiter and the max
+wave speed in FP64.  Its error against the FP64 oracle is bounded by the FP32
+arithmetic of the bulk (unit round-off u32 = 2^-24 ~ 6e-8):
+
+* one step (3 stages): each stage rounds every higher mode once on store and
+  carries ~u32-relative flux errors of a few dozen FP32 operations, so the state
+  moves by at most ~50 u32 ~ 3e-6 of the largest coefficient of a variable per
+  step (max-norm bound STEP_TOL);
+* 100 steps of the smooth P1 vortex: the errors add up at most linearly and the
+  scheme is stable, so rel. L1 <= 100 * 50 u32 / 10 ~ 3e-5 (bound L1_100_TOL;
+  L1 averages the max-norm bound over the cells).
+
+Positivity is exact in the sense of the library's guarantee: every limiter node
+of every stored state has rho >= eps_1 / 2 and rho e >= eps_2 / 2 (eps = 1e-13).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():   # collected on CPU-only hosts, skipped there
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2409_09620_amd import Solver  # noqa: E402
+
+U32 = 2.0 ** -24
+STEP_TOL = 50 * U32
+L1_100_TOL = 100 * 50 * U32 / 10
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel_err(a, b):
+    out = 0.0
+    for v in range(4):
+        scale = max(np.abs(b[v]).max(), 1e-300)
+        out = max(out, np.abs(a[v] - b[v]).max() / scale)
+    return out
+
+
+def rel_l1(a, b):
+    return np.abs(a - b).sum() / np.abs(b).sum()
+
+
+CASES = {
+    "p1_periodic_vortex": lambda: (1,) + workloads.periodic_vortex(n=32),
+    "p2_periodic_vortex": lambda: (2,) + workloads.periodic_vortex(n=12),
+    "p2_quadrant_3k": lambda: (2,) + workloads.quadrant_delaunay(n_cells=3000, seed=21),
+    "p1_quadrant_3k": lambda: (1,) + workloads.quadrant_delaunay(n_cells=3000, seed=22),
+}
+
+
+def make(case, precision="mixed"):
+    k, m, kind, p = CASES[case]()
+    say(f"[gpu case] {case} cells={m.n_cell} k={k} precision={precision}")
+    s = Solver(m, k)
+    s.init_problem(kind, p, precision=precision)
+    o = oracle.Oracle(m, k)
+    assert o.init_problem(kind, p) == 0
+    return s, o, m
+
+
+def node_admissibility(o, u):
+    """min rho and min rho e over every limiter node of every cell (FP64)."""
+    vals = o.limiter_node_values(u)
+    rho = vals[..., 0]
+    e = vals[..., 3] - 0.5 * (vals[..., 1] ** 2 + vals[..., 2] ** 2) / rho
+    return rho.min(), e.min()
+
+
+def test_mixed_storage_roundtrip():
+    """dg_init in the mixed form keeps averages bit for bit and rounds the higher
+    modes to nearest FP32 (the quadrant data needs no limiting at t = 0)."""
+    k, m, kind, p = CASES["p2_quadrant_3k"]()
+    o = oracle.Oracle(m, k)
+    o.init_problem(kind, p)
+    ref = o.state(0)
+    s = Solver(m, k)
+    s.init_modal(ref, precision="mixed")
+    u = s.readback()[0]
+    assert s.diag()["n_limited"] == 0
+    assert np.array_equal(u[:, 0], ref[:, 0])
+    assert np.array_equal(u[:, 1:], ref[:, 1:].astype(np.float32).astype(np.float64))
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_mixed_one_step_error(case):
+    s, o, m = make(case)
+    s.step()
+    assert o.step() == 0
+    u = s.readback()[0]
+    ref = o.state(0)
+    e, e_avg = rel_err(u, ref), rel_err(u[:, :1], ref[:, :1])
+    say(f"{case}: mixed vs FP64 oracle after 1 step: max rel {e:.3e}, averages {e_avg:.3e}")
+    assert e <= STEP_TOL, e
+    d, so = s.diag(), o.scalars()
+    assert abs(d["t"] - so["t"]) <= STEP_TOL * so["t"]
+    assert abs(d["alpha"] - so["alpha"]) <= STEP_TOL * so["alpha"]
+
+
+def test_mixed_hundred_steps_p1_vortex():
+    s, o, m = make("p1_periodic_vortex")
+    assert s.step_to(float("inf"), 100) == 100
+    r, done = o.run(float("inf"), 100)
+    assert r == 0 and done == 100
+    u = s.readback()[0]
+    ref = o.state(0)
+    e = rel_l1(u, ref)
+    say(f"p1 vortex 100 steps mixed: rel L1 = {e:.3e} (bound {L1_100_TOL:.1e})")
+    assert e <= L1_100_TOL
+
+
+@pytest.mark.parametrize("n_cells", [3000, 1_000_000])
+def test_mixed_blast_positivity_every_stage(n_cells):
+    """Near-vacuum blast in the mixed form: after every stage every limiter node of
+    the stored state has rho >= eps_1/2 and rho e >= eps_2/2."""
+    m, kind, p = workloads.blast_delaunay(n_cells=n_cells, seed=23 if n_cells == 3000 else 3)
+    say(f"[gpu case] mixed blast cells={m.n_cell}")
+    s = Solver(m, 2)
+    s.init_problem(kind, p, precision="mixed")
+    o = oracle.Oracle(m, 2)
+    steps = 6 if n_cells <= 3000 else 1
+    for step in range(steps):
+        for st in range(3):
+            s.stage(st)
+            rmin, emin = node_admissibility(o, s.read_state(1))
+            assert rmin >= 0.5e-13 * (1 - 1e-6) - 1e-16, (step, st, rmin)
+            assert emin >= 0.5e-13 * (1 - 1e-6) - 1e-15, (step, st, emin)
+    d = s.diag()
+    say(f"mixed blast: n_limited={d['n_limited']} n_flat={d['n_flat']}")
+    assert d["n_limited"] > 0 and d["n_bad"] == 0
+
+
+def test_mixed_full_size_quadrant_one_step():
+    """The 200k-cell P2 quadrant workload in the mixed form: one step against the oracle."""
+    m, kind, p = workloads.quadrant_delaunay(n_cells=200_000)
+    say(f"[gpu case] mixed full-size quadrant cells={m.n_cell}")
+    s = Solver(m, 2)
+    s.init_problem(kind, p, precision="mixed")
+    o = oracle.Oracle(m, 2)
+    o.init_problem(kind, p)
+    s.step()
+    o.step()
+    u = s.readback()[0]
+    e = rel_err(u, o.state(0))
+    say(f"mixed 200k quadrant one step: max rel {e:.3e}")
+    assert e <= STEP_TOL
+
+
+def test_mixed_deterministic_and_graph_matches_eager():
+    k, m, kind, p = CASES["p2_quadrant_3k"]()
+    g = Solver(m, k)
+    e = Solver(m, k)
+    e.profile(True)                      # eager launches
+    for s in (g, e):
+        s.init_problem(kind, p, precision="mixed")
+    for it in range(4):
+        g.step()
+        e.step()
+        e.profile_read()
+        ug, tg, ng = g.readback()
+        ue, te, ne = e.readback()
+        assert ng == ne == it + 1 and tg == te
+        assert np.array_equal(ug, ue), it
+
+
+def test_precision_switch_on_one_context():
+    """A context re-initialised in the other precision gives the same result as a
+    fresh one (the layouts share the workspace)."""
+    k, m, kind, p = CASES["p2_quadrant_3k"]()
+    a = Solver(m, k)
+    a.init_problem(kind, p, precision="mixed")
+    a.step()
+    a.init_problem(kind, p, precision="fp64")
+    a.step()
+    b = Solver(m, k)
+    b.init_problem(kind, p, precision="fp64")
+    b.step()
+    assert np.array_equal(a.readback()[0], b.readback()[0])
+    a.init_problem(kind, p, precision="mixed")
+    a.step()
+    c = Solver(m, k)
+    c.init_problem(kind, p, precision="mixed")
+    c.step()
+    assert np.array_equal(a.readback()[0], c.readback()[0])
