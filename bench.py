@@ -57,6 +57,8 @@ def kernel_source_hash():
 
 
 def load_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter
+    summary, or None when it was taken on other kernel sources."""
     try:
         with open(TRAFFIC_FILE) as f:
             d = json.load(f)
@@ -64,10 +66,8 @@ def load_traffic(kernel, workload):
         return None
     if d.get("kernel_source_sha") != kernel_source_hash():
         return None
-    rec = d.get("kernels", {}).get(kernel)
-    if not rec or d.get("workload") != workload:
-        return None
-    return rec.get("hbm_bytes_per_launch")
+    rec = d.get("workloads", {}).get(workload, {}).get(kernel)
+    return rec.get("hbm_bytes_per_launch") if rec else None
 
 
 def run_gpu(mesh, kind, params, k, steps, warmup, precision="fp64"):

@@ -106,6 +106,43 @@ __device__ __forceinline__ void edge_point(int i, double s, double& x, double& e
     e = i == 0 ? s : (i == 1 ? 1.0 - s : 0.0);
 }
 
+// Basis values at a point that differs between lanes, computed in the bulk type
+// (a table row picked by a per-lane index would cost a select per entry).
+template <int K, typename T>
+__device__ __forceinline__ void psi_at(T x, T e, T* p) {
+    p[0] = (T)1.0;
+    p[1] = (T)4.0 * x + (T)2.0 * e - (T)2.0;
+    p[2] = (T)3.0 * e - (T)1.0;
+    if constexpr (K == 2) {
+        p[3] = (T)24.0 * x * x + (T)24.0 * x * e + (T)4.0 * e * e - (T)24.0 * x - (T)8.0 * e + (T)4.0;
+        p[4] = (T)20.0 * x * e + (T)10.0 * e * e - (T)4.0 * x - (T)12.0 * e + (T)2.0;
+        p[5] = (T)10.0 * e * e - (T)8.0 * e + (T)1.0;
+    }
+}
+
+// At the reference vertices (0,0), (1,0), (0,1) every basis function and its
+// first derivatives are affine in the vertex's coordinates (sx, se) (there
+// x^2 = x, e^2 = e, xe = 0).  Returns sum_{l>=1} u_l Psi_l and the reference
+// derivatives of sum_l u_l Psi_l at vertex (sx, se).
+template <int K, typename T>
+__device__ __forceinline__ void vertex_eval(const T* u, T sx, T se, T& qh, T& dx, T& de) {
+    if constexpr (K == 1) {
+        qh = fma((T)4.0 * u[1], sx, fma((T)2.0 * u[1] + (T)3.0 * u[2], se, (T)-2.0 * u[1] - u[2]));
+        dx = (T)4.0 * u[1];
+        de = (T)2.0 * u[1] + (T)3.0 * u[2];
+    } else {
+        const T a = (T)-2.0 * u[1] - u[2] + (T)4.0 * u[3] + (T)2.0 * u[4] + u[5];
+        const T b = (T)4.0 * u[1] - (T)4.0 * u[4];
+        const T c = (T)2.0 * u[1] + (T)3.0 * u[2] - (T)4.0 * u[3] - (T)2.0 * u[4] + (T)2.0 * u[5];
+        qh = fma(b, sx, fma(c, se, a));
+        const T ax = (T)4.0 * u[1] - (T)24.0 * u[3] - (T)4.0 * u[4];
+        dx = fma((T)48.0 * u[3], sx, fma((T)24.0 * u[3] + (T)20.0 * u[4], se, ax));
+        const T ae = (T)2.0 * u[1] + (T)3.0 * u[2] - (T)8.0 * u[3] - (T)12.0 * u[4] - (T)8.0 * u[5];
+        const T bc = (T)24.0 * u[3] + (T)20.0 * u[4];
+        de = fma(bc, sx, fma((T)8.0 * u[3] + (T)20.0 * u[4] + (T)20.0 * u[5], se, ae));
+    }
+}
+
 // Basis values at the fixed points of a stage, in constant memory: the point loops
 // run with a wave-uniform index, so these become scalar loads instead of registers.
 template <int K, typename T>
@@ -432,6 +469,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(StageArgs a) {
             un[0] = (T)ua_p[nb];
 #pragma unroll
             for (int l = 1; l < NM; ++l) un[l] = uh_p[(l - 1) * snc + nb];
+            // the neighbour's local edge j as (x0 + xd s, e0 + ed s) in its reference frame
+            const T x0 = j == 0 ? (T)1.0 : (T)0.0, xd = j == 0 ? (T)-1.0 : (j == 2 ? (T)1.0 : (T)0.0);
+            const T e0 = j == 1 ? (T)1.0 : (T)0.0, ed = j == 0 ? (T)1.0 : (j == 1 ? (T)-1.0 : (T)0.0);
 #pragma unroll 1
             for (int nu = 0; nu < R::NE; ++nu) {
                 const T* p = TB.ep[i * R::NE + nu];
@@ -441,7 +481,11 @@ __global__ __launch_bounds__(kBlock) void k_residual(StageArgs a) {
                 if (has) {
                     // the neighbour runs the shared edge the other way: its parameter is
                     // 1 - s_nu = s_{NE-1-nu} (symmetric Gauss nodes)
-                    qe = dot<NM>(un, TB.ep[j * R::NE + (R::NE - 1 - nu)]);
+                    const int mu = R::NE - 1 - nu;
+                    const T sn = (T)(mu == 0 ? R::s[0] : (mu == 1 ? R::s[1] : R::s[2]));
+                    T pn[NM];
+                    psi_at<K, T>(fma(xd, sn, x0), fma(ed, sn, e0), pn);
+                    qe = dot<NM>(un, pn);
                 }
                 const T fi = lane_flux(qi, qget<0>(qi), qget<1>(qi), qget<2>(qi), qget<3>(qi), lnx, lny, gm1,
                                        s1, s2, s3);
@@ -709,20 +753,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                     // own vertex i+1 (then i+2) meets the neighbour's vertex j+2 (then j+1)
                     const int ov = (i + 1 + end) % 3, nv = (j + 2 - end) % 3;
                     T q, r, jv;
+                    // the neighbour's vertex nv, a per-lane index: closed form
+                    T rh, tx, te;
+                    vertex_eval<K, T>(wn, nv == 1 ? (T)1.0 : (T)0.0, nv == 2 ? (T)1.0 : (T)0.0, rh, tx, te);
                     if constexpr (kMixed) {
                         // value jump from the FP64 averages plus the float higher modes
-                        const T qh = dot_hi<NM>(w, TB.vtp[ov]), rh = dot_hi<NM>(wn, TB.vtp[nv]);
+                        const T qh = dot_hi<NM>(w, TB.vtp[ov]);
                         q = w[0] + qh;
                         r = wn[0] + rh;
                         jv = (T)(wna - wa) + (rh - qh);
                     } else {
                         q = dot<NM>(w, TB.vtp[ov]);
-                        r = dot<NM>(wn, TB.vtp[nv]);
+                        r = wn[0] + rh;
                         jv = r - q;
                     }
                     const T sx = dot<NM>(w, TB.vtdx[ov]), se = dot<NM>(w, TB.vtde[ov]);
                     const T qx = sx * xx + se * ex, qy = sx * xy + se * ey;
-                    const T tx = dot<NM>(wn, TB.vtdx[nv]), te = dot<NM>(wn, TB.vtde[nv]);
                     const T rx = tx * nxx + te * nex, ry = tx * nxy + te * ney;
                     xs[2 * end] = q;
                     xs[2 * end + 1] = r;
@@ -925,40 +971,44 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
 
 constexpr int kFinThreads = 1024;
 
-// Reduces NC columns part[col[k] * kMaxBlocks + b], b < G, with op[k] (0 sum,
-// 1 min, 2 max) in a fixed order; the result is valid in thread 0.
+// Reduces the NC consecutive columns part[(col0 + k) * kMaxBlocks + b], b < G, in
+// a fixed order; column k with op (opbits >> 2k) & 3 (0 sum, 1 min, 2 max).  Each
+// column gets 16/NC waves that stride over the blocks, so all loads are
+// coalesced and no thread holds more than one accumulator.  The results are
+// valid in thread 0.
 template <int NC>
-__device__ __forceinline__ void reduce_columns(const double* part, int G, const int (&col)[NC], const int (&op)[NC],
+__device__ __forceinline__ void reduce_columns(const double* part, int G, int col0, unsigned opbits,
                                                double (&out)[NC]) {
-    double acc[NC];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) acc[k] = op[k] == 0 ? 0.0 : (op[k] == 1 ? INFINITY : -INFINITY);
-    for (int b = threadIdx.x; b < G; b += kFinThreads) {
-        double x[NC];
-#pragma unroll
-        for (int k = 0; k < NC; ++k) x[k] = part[(size_t)col[k] * kMaxBlocks + b];
-#pragma unroll
-        for (int k = 0; k < NC; ++k) acc[k] = op[k] == 0 ? acc[k] + x[k] : (op[k] == 1 ? fmin(acc[k], x[k]) : fmax(acc[k], x[k]));
-    }
-    __shared__ double lds[kFinThreads / 64][NC];
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        double v = acc[k];
+    constexpr int kWaves = kFinThreads / 64, kPer = kWaves / NC;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int k = w / kPer, sub = w - k * kPer;
+    __shared__ double lds[kWaves];
+    if (k < NC) {
+        const int op = (opbits >> (2 * k)) & 3;
+        const double* col = part + (size_t)(col0 + k) * kMaxBlocks;
+        double acc = op == 0 ? 0.0 : (op == 1 ? INFINITY : -INFINITY);
+        for (int b = sub * 64 + lane; b < G; b += kPer * 64) {
+            const double x = col[b];
+            acc = op == 0 ? acc + x : (op == 1 ? fmin(acc, x) : fmax(acc, x));
+        }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
-            const double y = __shfl_xor(v, o, 64);
-            v = op[k] == 0 ? v + y : (op[k] == 1 ? fmin(v, y) : fmax(v, y));
+            const double y = __shfl_xor(acc, o, 64);
+            acc = op == 0 ? acc + y : (op == 1 ? fmin(acc, y) : fmax(acc, y));
         }
-        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6][k] = v;
+        if (lane == 0) lds[w] = acc;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            double v = lds[0][k];
-            for (int w2 = 1; w2 < kFinThreads / 64; ++w2)
-                v = op[k] == 0 ? v + lds[w2][k] : (op[k] == 1 ? fmin(v, lds[w2][k]) : fmax(v, lds[w2][k]));
-            out[k] = v;
+        for (int kk = 0; kk < NC; ++kk) {
+            const int op = (opbits >> (2 * kk)) & 3;
+            double v = lds[kk * kPer];
+            for (int s2 = 1; s2 < kPer; ++s2) {
+                const double y = lds[kk * kPer + s2];
+                v = op == 0 ? v + y : (op == 1 ? fmin(v, y) : fmax(v, y));
+            }
+            out[kk] = v;
         }
     }
 }
@@ -966,10 +1016,8 @@ __device__ __forceinline__ void reduce_columns(const double* part, int G, const 
 // domain averages and L-infinity norms (eq. normOmg): ||u - ubar|| = max(max u - ubar, ubar - min u)
 __global__ __launch_bounds__(kFinThreads) void k_fin_residual(const double* part, int G, Glob* g) {
     if (!g->active) return;
-    const int col[kNumPartial] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11};
-    const int op[kNumPartial] = {0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 2};
     double tot[kNumPartial];
-    reduce_columns<kNumPartial>(part, G, col, op, tot);
+    reduce_columns<kNumPartial>(part, G, 0, 0xAA5500u, tot);   // 4 sums, 4 mins, 4 maxima
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -984,10 +1032,8 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_residual(const double* part
 
 __global__ __launch_bounds__(kFinThreads) void k_fin_mnorm(const double* part, int G, Glob* g) {
     if (!g->active) return;
-    const int col[1] = {kNumPartial};
-    const int op[1] = {2};
     double best[1];
-    reduce_columns<1>(part, G, col, op, best);
+    reduce_columns<1>(part, G, kNumPartial, 2u, best);
     if (threadIdx.x == 0) {
         const double n = sqrt(best[0]);
         const double mb = sqrt(g->ubar[1] * g->ubar[1] + g->ubar[2] * g->ubar[2]);
@@ -1000,10 +1046,8 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_mnorm(const double* part, i
 // t, the step count and Delta t = C_SSP/alpha min_K C^DCW_{K,k}|K|, clamped to t_end
 __global__ __launch_bounds__(kFinThreads) void k_fin_filter(const double* part, int G, Glob* g, int stage) {
     if (!g->active) return;
-    const int col[4] = {kNumPartial + 1, kNumPartial + 2, kNumPartial + 3, kNumPartial + 4};
-    const int op[4] = {2, 0, 0, 0};
     double r[4];
-    reduce_columns<4>(part, G, col, op, r);
+    reduce_columns<4>(part, G, kNumPartial + 1, 2u, r);   // max, then three sums
     if (threadIdx.x != 0) return;
     const double alpha = r[0], lim = r[1], bad = r[2];
     g->n_limited += (long long)lim;
