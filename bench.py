@@ -104,6 +104,39 @@ def run_gpu(mesh, kind, params, k, steps, warmup, precision="fp64"):
     return t1 - t0, t3 - t2, prof, d
 
 
+def run_batch(scale, steps, warmup, precision):
+    """64 two-state instances (log-uniform sizes 5k-500k divided by `scale`, P1/P2
+    50/50) stepped as one batch: autotuned schedule, each step one graph replay."""
+    import torch
+    from paper_2409_09620_amd import Batch, Solver
+    from synth import workloads
+    sizes, degree = workloads.batch_sizes(n_inst=64)
+    sols, dof = [], 0
+    for i, (sz, k) in enumerate(zip(sizes, degree)):
+        m, kind, p = workloads.batch_instance(i, max(int(sz) // scale, 64))
+        s = Solver(m, int(k))
+        s.init_problem(kind, p, precision=precision)
+        sols.append(s)
+        dof += m.n_cell * 4 * (int(k) + 1) * (int(k) + 2) // 2
+    b = Batch(sols)
+    tuned = b.autotune(reps=2)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    act, st = b.status()
+    out = {"value": dof * 3 * steps / el, "ms_per_step": el / steps * 1e3, "instances": len(sols),
+           "cells": int(sum(s.nc for s in sols)), "p2_instances": int((degree == 2).sum()),
+           "steps": steps, "schedule": dict(b.schedule(), ms_stage0_tuned=tuned["ms_stage"]),
+           "members_active": act, "members_in_error": int((st[:, 1] != 0).sum())}
+    b.close()
+    for s in sols:
+        s.close()
+    return out
+
+
 def roofline(prof, k, n_cell, workload, precision="fp64"):
     per_cell = algorithmic_bytes_per_cell(k, precision)
     kernels = {}
@@ -158,6 +191,8 @@ def main():
     ap.add_argument("--cells", type=int, default=200_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra", action="store_true", help="also run the ~1M-cell blast")
+    ap.add_argument("--batch-scale", type=int, default=10, metavar="S",
+                    help="64-instance batch with sizes divided by S (1: the full 5k-500k sizes); 0 skips it")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized buffer 5 times (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -234,6 +269,11 @@ def main():
         out["extra"] = {f"{btag}_{pr}": dict(measure(bm, bk, bp, pr, bsteps, 2, btag), cells=bm.n_cell,
                                              steps=bsteps)
                         for pr in ("fp64", "mixed")}
+    if args.batch_scale > 0:
+        out["batch"] = {f"{pr}": run_batch(args.batch_scale, max(5, args.steps // 3), 2, pr)
+                        for pr in ("fp64", "mixed")}
+        out["batch"]["workload"] = (f"64 two-state instances, sizes log-uniform 5k-500k / {args.batch_scale}, "
+                                    "P1/P2 50/50, seeded Delaunay")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, kind, params, k)
     print(json.dumps(out), flush=True)

@@ -177,6 +177,71 @@ dg_status dg_diag(dg_ctx* ctx, dg_diag_t* out);
 dg_status dg_profile_enable(dg_ctx* ctx, int enable);
 dg_status dg_profile_read(dg_ctx* ctx, double* ms, int64_t* launches);
 
+/* Sets the stop time of a context's run without stepping (as dg_step_to does
+ * before it steps): the last step is shortened to land on t_end and the context
+ * turns inactive once t reaches it.  Stream-ordered, no synchronisation.  Used
+ * to give the members of a batch their own end times. */
+dg_status dg_set_t_end(dg_ctx* ctx, double t_end);
+
+/* ---------------------------------------------------------------------------
+ * Batches: several initialised contexts on one device (meshes of any size,
+ * degrees 1 and 2 mixed, one precision) stepped together, each pass of a
+ * stage one persistent launch over all members (the method is per instance;
+ * batching is this library's scheduling).  A chunk table cuts every member into
+ * runs of 256-cell reduction groups, split into one contiguous range per XCD by
+ * estimated cost; every group writes its own partial record and a
+ * per-member finalize reduces them in a fixed order.  A member's result
+ * therefore does not depend on the schedule or on the other members: it is the
+ * same, bit for bit, as in a batch of its own (not as dg_step, whose
+ * single-instance passes group the reductions differently, within round-off).
+ * Each member keeps its own alpha, Delta t, t and t_end (dg_set_t_end); members
+ * that reached their t_end are skipped.  The batch borrows the contexts: they
+ * must outlive it, must not be stepped on other streams while it runs, and
+ * re-initialising one (dg_init, dg_init_problem, dg_mesh_upload) makes the
+ * batch return DG_E_STATE.  The batch allocates its own device memory (stage
+ * arguments, chunk table, 17 doubles per 256 cells of partial records). */
+typedef struct dg_batch dg_batch;
+
+/* Builds a batch of n contexts on hip_stream (may be NULL).  Errors: DG_E_ARG
+ * (n <= 0, a context listed twice, different devices or precisions),
+ * DG_E_STATE (a context not initialised or failed), DG_E_NOMEM, DG_E_HIP.  On
+ * DG_E_NOMEM/DG_E_HIP *out is set and must still be destroyed. */
+dg_status dg_batch_create(dg_batch** out, dg_ctx* const* ctxs, int n, void* hip_stream);
+
+/* Schedule: chunk_groups reduction groups (256 cells each) per chunk, and the
+ * pass grids at occupancy_pct percent of the resident workgroups. */
+dg_status dg_batch_set_schedule(dg_batch* b, int chunk_groups, int occupancy_pct);
+dg_status dg_batch_get_schedule(const dg_batch* b, int* chunk_groups, int* occupancy_pct, int* n_chunks,
+                                int* grid /* 3: residual, momentum norm, filter */);
+
+/* Times stage 0 of the batch for chunk_groups in {1,2,4,8,16} and occupancy in
+ * {100, 50} percent (reps timed runs each, after a warm-up), keeps the fastest
+ * and returns it.  The members' states are unchanged: stage 0 only writes
+ * scratch buffers, and their device scalars are restored.  Synchronises. */
+dg_status dg_batch_autotune(dg_batch* b, int reps, int* chunk_groups, int* occupancy_pct, double* ms_stage);
+
+/* n_steps SSP-RK3 steps of every active member (no synchronisation). */
+dg_status dg_batch_step(dg_batch* b, int64_t n_steps);
+
+/* Steps until no member is active or max_steps steps were taken; polls every
+ * few steps.  DG_E_BOUNDS if a member's cell average left the admissible set. */
+dg_status dg_batch_run(dg_batch* b, int64_t max_steps, int64_t* steps_done);
+
+/* Synchronises and reports the number of active members and, if status is not
+ * NULL, {active, error, t, step} of member i in status[4 i .. 4 i + 3]. */
+dg_status dg_batch_status(dg_batch* b, int* n_active, double* status);
+
+/* Host-only planning (no device): the chunk table of n_inst instances with
+ * n_cell[i] cells at degree k[i] and chunk_groups groups per chunk.  Writes the
+ * number of chunks to *n_chunks and, when chunks is not NULL (capacity
+ * max_chunks), chunk c as (instance, first group, end group) in chunks[3c..];
+ * split (9 ints, may be NULL) receives the chunk range boundaries per XCD. */
+dg_status dg_plan_chunks(int n_inst, const int32_t* n_cell, const int* k, int chunk_groups, int32_t* chunks,
+                         int max_chunks, int* n_chunks, int32_t* split);
+
+const char* dg_batch_last_error(const dg_batch* b);
+void dg_batch_destroy(dg_batch* b);
+
 /* Number of cells, degree and modes of the uploaded mesh. */
 dg_status dg_sizes(dg_ctx* ctx, int32_t* n_cell, int* k, int* n_modes);
 

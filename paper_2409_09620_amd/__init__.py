@@ -5,8 +5,8 @@ include/oedg.h; `binding` marshals arguments to it with ctypes and uses PyTorch
 only for device memory and streams.
 """
 
-from .binding import (DG_OE_CW, DG_OE_RI, DgError, Solver, host_mesh_tables, lib_path, load_library,
-                      symbols_declared)
+from .binding import (DG_OE_CW, DG_OE_RI, Batch, DgError, Solver, host_mesh_tables, lib_path, load_library,
+                      plan_chunks, symbols_declared)
 
-__all__ = ["Solver", "DgError", "host_mesh_tables", "DG_OE_RI", "DG_OE_CW", "load_library", "lib_path",
-           "symbols_declared"]
+__all__ = ["Solver", "Batch", "DgError", "host_mesh_tables", "plan_chunks", "DG_OE_RI", "DG_OE_CW", "load_library",
+           "lib_path", "symbols_declared"]

@@ -76,6 +76,17 @@ _SIGS = {
     "dg_profile_read": (_c_i, [_c_p, _c_p, _c_p]),
     "dg_last_error": (ctypes.c_char_p, [_c_p]),
     "dg_destroy": (None, [_c_p]),
+    "dg_set_t_end": (_c_i, [_c_p, _c_d]),
+    "dg_batch_create": (_c_i, [_c_p, _c_p, _c_i, _c_p]),
+    "dg_batch_set_schedule": (_c_i, [_c_p, _c_i, _c_i]),
+    "dg_batch_get_schedule": (_c_i, [_c_p, _c_p, _c_p, _c_p, _c_p]),
+    "dg_batch_autotune": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p]),
+    "dg_batch_step": (_c_i, [_c_p, _c_i64]),
+    "dg_batch_run": (_c_i, [_c_p, _c_i64, _c_p]),
+    "dg_batch_status": (_c_i, [_c_p, _c_p, _c_p]),
+    "dg_plan_chunks": (_c_i, [_c_i, _c_p, _c_p, _c_i, _c_p, _c_i, _c_p, _c_p]),
+    "dg_batch_last_error": (ctypes.c_char_p, [_c_p]),
+    "dg_batch_destroy": (None, [_c_p]),
 }
 
 
@@ -187,6 +198,10 @@ class Solver:
     def stage(self, s):
         self._check(load_library().dg_stage(self.h, int(s)))
 
+    def set_t_end(self, t_end):
+        """Stop time of this instance's run (also when stepped inside a Batch)."""
+        self._check(load_library().dg_set_t_end(self.h, float(t_end)))
+
     def step(self, want_dt=False):
         dt = ctypes.c_double(0)
         self._check(load_library().dg_step(self.h, ctypes.byref(dt) if want_dt else None))
@@ -271,3 +286,92 @@ def host_mesh_tables(mesh, k):
         return out
     finally:
         L.dg_destroy(h)
+
+
+class Batch:
+    """Several initialised Solvers on one device stepped together (dg_batch_*).
+
+    The solvers must outlive the batch and keep their mesh and configuration
+    while it exists.  Work runs on torch's current stream of their device."""
+
+    def __init__(self, solvers):
+        import torch
+        L = load_library()
+        if not solvers:
+            raise ValueError("empty batch")
+        self.solvers = list(solvers)
+        self.stream = torch.cuda.current_stream(self.solvers[0].device)
+        arr = (ctypes.c_void_p * len(self.solvers))(*[s.h.value for s in self.solvers])
+        h = ctypes.c_void_p()
+        st = L.dg_batch_create(ctypes.byref(h), arr, len(self.solvers), ctypes.c_void_p(self.stream.cuda_stream))
+        self.h = h if h.value else None
+        if st != 0:
+            msg = L.dg_batch_last_error(self.h).decode() if self.h else "dg_batch_create failed"
+            self.close()
+            raise DgError(st, msg)
+
+    def _check(self, st):
+        if st != 0:
+            raise DgError(st, load_library().dg_batch_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().dg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        self._check(load_library().dg_batch_step(self.h, int(n)))
+
+    def run(self, max_steps=(1 << 62)):
+        n = ctypes.c_int64(0)
+        self._check(load_library().dg_batch_run(self.h, int(max_steps), ctypes.byref(n)))
+        return n.value
+
+    def status(self):
+        """(number of active members, array (n, 4) of active, error, t, step)."""
+        act = ctypes.c_int(0)
+        out = np.zeros((len(self.solvers), 4))
+        self._check(load_library().dg_batch_status(self.h, ctypes.byref(act), _ptr(out)))
+        return act.value, out
+
+    def set_schedule(self, chunk_groups, occupancy_pct=100):
+        self._check(load_library().dg_batch_set_schedule(self.h, int(chunk_groups), int(occupancy_pct)))
+
+    def schedule(self):
+        cg, occ, nch = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        grid = (ctypes.c_int * 3)()
+        self._check(load_library().dg_batch_get_schedule(self.h, ctypes.byref(cg), ctypes.byref(occ),
+                                                         ctypes.byref(nch), grid))
+        return {"chunk_groups": cg.value, "occupancy_pct": occ.value, "n_chunks": nch.value, "grid": list(grid)}
+
+    def autotune(self, reps=3):
+        cg, occ, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0)
+        self._check(load_library().dg_batch_autotune(self.h, int(reps), ctypes.byref(cg), ctypes.byref(occ),
+                                                     ctypes.byref(ms)))
+        return {"chunk_groups": cg.value, "occupancy_pct": occ.value, "ms_stage": ms.value}
+
+
+def plan_chunks(n_cell, k, chunk_groups=1):
+    """Host-only chunk table of instances with n_cell[i] cells at degree k[i]:
+    (chunks (n, 3) int32 of instance, first group, end group; split (9,) int32)."""
+    L = load_library()
+    nc = np.ascontiguousarray(n_cell, dtype=np.int32)
+    kk = np.ascontiguousarray(k, dtype=np.int32)
+    n = ctypes.c_int(0)
+    st = L.dg_plan_chunks(len(nc), _ptr(nc), _ptr(kk), int(chunk_groups), None, 0, ctypes.byref(n), None)
+    if st != 0:
+        raise DgError(st, "dg_plan_chunks failed")
+    chunks = np.zeros((n.value, 3), np.int32)
+    split = np.zeros(9, np.int32)
+    st = L.dg_plan_chunks(len(nc), _ptr(nc), _ptr(kk), int(chunk_groups), _ptr(chunks), n.value,
+                          ctypes.byref(n), _ptr(split))
+    if st != 0:
+        raise DgError(st, "dg_plan_chunks failed")
+    return chunks, split

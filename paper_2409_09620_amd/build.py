@@ -36,7 +36,11 @@ def build(verbose: bool = False) -> str:
     _run(["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I", CSRC, "-I", INCLUDE,
           "-c", os.path.join(CSRC, "mesh_host.cpp"), "-o", o], verbose)
     objs.append(o)
-    for src in ("kernels.hip", "capi.hip"):
+    o = os.path.join(BUILD, "schedule.o")
+    _run(["g++", "-O2", "-std=c++17", "-fPIC", "-I", CSRC, "-I", INCLUDE,
+          "-c", os.path.join(CSRC, "schedule.cpp"), "-o", o], verbose)
+    objs.append(o)
+    for src in ("kernels.hip", "capi.hip", "batch.hip"):
         o = os.path.join(BUILD, src.replace(".hip", ".o"))
         _run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o], verbose)
         objs.append(o)

@@ -11,49 +11,11 @@
 #include <string>
 #include <vector>
 
-#include "oedg.h"
-#include "oedg_internal.h"
+#include "capi_internal.h"
 
 using oedg::Glob;
 
-struct dg_ctx {
-    int device = 0;
-    bool host_only = false;
-    hipStream_t stream = nullptr;
-    dg_status status = DG_OK;
-    std::string err;
-
-    void* bound = nullptr;       // caller-owned workspace
-    size_t bound_bytes = 0;
-    void* owned = nullptr;       // library allocation
-    size_t used_bytes = 0;
-
-    oedg::HostMesh mesh;
-    bool have_mesh = false;
-    bool initialised = false;
-    dg_config cfg{};
-    int nm = 0;
-
-    double *jinv = nullptr, *area = nullptr, *len = nullptr, *node = nullptr;
-    int32_t* link = nullptr;
-    double *u0 = nullptr, *u = nullptr, *w = nullptr, *part = nullptr;
-    const double* last_out = nullptr;
-    Glob* g = nullptr;
-
-    // kernel timing (dg_profile_enable)
-    bool prof_on = false;
-    std::vector<hipEvent_t> prof_ev;    // pairs: start, stop
-    std::vector<int> prof_kind;         // kernel id of each pair
-    size_t prof_used = 0;               // pairs recorded since the last read
-
-    // one captured SSP-RK3 step, replayed on `stream` (rebuilt after set-up changes)
-    hipStream_t cap_stream = nullptr;
-    hipGraph_t step_graph = nullptr;
-    hipGraphExec_t step_exec = nullptr;
-    bool graph_failed = false;
-};
-
-namespace {
+namespace capi {
 
 dg_status fail(dg_ctx* c, dg_status s, const std::string& msg) {
     if (c && c->status == DG_OK) {
@@ -62,6 +24,12 @@ dg_status fail(dg_ctx* c, dg_status s, const std::string& msg) {
     }
     return s;
 }
+
+}  // namespace capi
+
+namespace {
+
+using capi::fail;
 
 #define HIP_TRY(ctx, call)                                                                       \
     do {                                                                                         \
@@ -159,7 +127,9 @@ void unpack_mixed(const std::vector<char>& in, size_t nc, size_t nm, double* u) 
 // copies a device state buffer to host [4][nm][nc] FP64 (synchronises)
 dg_status download_state(dg_ctx* c, const double* src, double* u_modal);
 
-oedg::StageArgs stage_args(dg_ctx* c, int s) {
+}  // namespace
+
+oedg::StageArgs capi::stage_args(dg_ctx* c, int s) {
     oedg::StageArgs a{};
     a.m.n_cell = c->mesh.n_cell;
     a.m.jinv = c->jinv;
@@ -182,8 +152,13 @@ oedg::StageArgs stage_args(dg_ctx* c, int s) {
     a.oe_enable = c->cfg.oe_enable;
     a.oe_mode = c->cfg.oe_mode;
     a.bp_enable = c->cfg.bp_enable;
+    a.k = c->cfg.k;
     return a;
 }
+
+namespace {
+
+using capi::stage_args;
 
 dg_status check_cfg(dg_ctx* c, const dg_config* cfg) {
     if (!cfg) return fail(c, DG_E_ARG, "null config");
@@ -219,6 +194,7 @@ dg_status start(dg_ctx* c) {
     HIP_TRY(c, hipMemcpyAsync(c->u, c->u0, state_bytes(c), hipMemcpyDeviceToDevice, c->stream));
     c->last_out = c->u0;
     c->initialised = true;
+    c->generation++;
     Glob h{};
     HIP_TRY(c, hipMemcpyAsync(&h, c->g, sizeof(Glob), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -463,6 +439,7 @@ dg_status dg_mesh_upload(dg_ctx* c, int k, int32_t n_vert, const double* xy, int
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->have_mesh = true;
     c->initialised = false;
+    c->generation++;
     drop_graph(c);
     return DG_OK;
 }

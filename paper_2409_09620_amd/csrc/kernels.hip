@@ -359,6 +359,14 @@ __device__ __forceinline__ TileWalk tile_walk(int n_tiles) {
     return {lo + r, min(lo + T, n_tiles), per_x};
 }
 
+// The batched passes: XCD x owns the chunk range [cs.b[x], cs.b[x+1]) (ranges of
+// equal estimated cost over the instances' cells in order).
+__device__ __forceinline__ TileWalk chunk_walk(const ChunkSplit& cs) {
+    const int per_x = gridDim.x >> 3;
+    const int x = blockIdx.x & 7, r = blockIdx.x >> 3;
+    return {cs.b[x] + r, cs.b[x + 1], per_x};
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -390,12 +398,92 @@ __device__ __forceinline__ VarPtr<NM, T> var_ptr(const StateView& sv, const Stag
 
 // ------------------------------------------------------------------------- pass 1: residual
 
-template <int K, typename T>
-__global__ __launch_bounds__(kBlock) void k_residual(StageArgs a) {
+// Reduces the lanes' (sum |K| ubar, min, max) over the workgroup, per variable, and
+// writes entry t = 4 k + v (k: sum, min, max) to dst[t * stride].
+__device__ __forceinline__ void residual_flush(double psum, double pmin, double pmax, double* dst, size_t stride) {
+    // over the lanes holding the same variable (xor of lane ids >= 4), then waves
+#pragma unroll
+    for (int o = 4; o < 64; o <<= 1) {
+        psum += __shfl_xor(psum, o, 64);
+        pmin = fmin(pmin, __shfl_xor(pmin, o, 64));
+        pmax = fmax(pmax, __shfl_xor(pmax, o, 64));
+    }
+    __shared__ double lds[kBlock / 64][3][4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane < 4) {
+        lds[wid][0][lane] = psum;
+        lds[wid][1][lane] = pmin;
+        lds[wid][2][lane] = pmax;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumPartial) {
+        const int k = threadIdx.x >> 2, vv = threadIdx.x & 3;
+        double acc = lds[0][k][vv];
+        for (int w2 = 1; w2 < kBlock / 64; ++w2) {
+            const double x = lds[w2][k][vv];
+            acc = k == 0 ? acc + x : (k == 1 ? fmin(acc, x) : fmax(acc, x));
+        }
+        dst[(size_t)threadIdx.x * stride] = acc;
+    }
+}
+
+// Max of the lanes' values over the workgroup, written to *dst.
+__device__ __forceinline__ void max_flush(double best, double* dst) {
+    best = wave_max(best);
+    __shared__ double lds[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double acc = lds[0];
+        for (int w2 = 1; w2 < kBlock / 64; ++w2) acc = fmax(acc, lds[w2]);
+        *dst = acc;
+    }
+}
+
+// Reduces the lanes' (max wave speed, limited, bad, flattened counts) over the
+// workgroup and writes entry k to dst[k * stride].
+__device__ __forceinline__ void filter_flush(double amax, double n_lim, double n_bad, double n_flat, double* dst,
+                                             size_t stride) {
+    amax = wave_max(amax);
+    n_lim = wave_sum(n_lim);
+    n_bad = wave_sum(n_bad);
+    n_flat = wave_sum(n_flat);
+    __shared__ double lds[kBlock / 64][4];
+    if ((threadIdx.x & 63) == 0) {
+        lds[threadIdx.x >> 6][0] = amax;
+        lds[threadIdx.x >> 6][1] = n_lim;
+        lds[threadIdx.x >> 6][2] = n_bad;
+        lds[threadIdx.x >> 6][3] = n_flat;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        double acc = lds[0][k];
+        for (int w2 = 1; w2 < kBlock / 64; ++w2) acc = k == 0 ? fmax(acc, lds[w2][k]) : acc + lds[w2][k];
+        dst[(size_t)k * stride] = acc;
+    }
+}
+
+// Batched passes: workgroup b walks its XCD's range of the chunk table; each
+// chunk is a run of reduction groups [g0, g1) of instance desc[chunk.inst], given
+// to run(a, g0, g1).
+template <typename F>
+__device__ __forceinline__ void for_each_chunk(const StageArgs* desc, const Chunk* chunks, const ChunkSplit& cs,
+                                               F run) {
+    const TileWalk w = chunk_walk(cs);
+    for (int ci = w.first; ci < w.end; ci += w.stride) {
+        const Chunk ch = chunks[ci];
+        const StageArgs& a = desc[ch.inst];
+        if (!a.g->active) continue;
+        run(a, ch.g0, ch.g1);
+    }
+}
+
+template <int K, typename T, bool kBatch>
+__device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1) {
     using R = Rule<K>;
     constexpr int NM = R::NM;
     const Glob* g = a.g;
-    if (!g->active) return;
     const int nc = a.m.n_cell;
     const size_t snc = (size_t)nc;
     const int v = threadIdx.x & 3;
@@ -416,11 +504,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(StageArgs a) {
     T* wh_p = wp.hi;
     const Tab<K, T>& TB = tab<K, T>();
 
-    double psum = 0.0, pmin = INFINITY, pmax = -INFINITY;
-    const TileWalk tw = tile_walk((nc + kCellsPerTile - 1) / kCellsPerTile);
-    for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
-        const int c = tile * kCellsPerTile + (threadIdx.x >> 2);
-        if (c >= nc) continue;   // whole quad
+    // one cell, owned by a quad of lanes: residual, SSP combination, partials
+    auto cell = [&](int c, double& psum, double& pmin, double& pmax) __attribute__((always_inline)) {
         const double ua = ua_p[c];
         T u[NM];
         u[0] = (T)ua;
@@ -520,43 +605,52 @@ __global__ __launch_bounds__(kBlock) void k_residual(StageArgs a) {
             pmin = fmin(pmin, q);
             pmax = fmax(pmax, q);
         }
-    }
-
-    // reduce over the lanes holding the same variable (xor of lane ids >= 4), then waves
-#pragma unroll
-    for (int o = 4; o < 64; o <<= 1) {
-        psum += __shfl_xor(psum, o, 64);
-        pmin = fmin(pmin, __shfl_xor(pmin, o, 64));
-        pmax = fmax(pmax, __shfl_xor(pmax, o, 64));
-    }
-    __shared__ double lds[kBlock / 64][3][4];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane < 4) {
-        lds[wid][0][lane] = psum;
-        lds[wid][1][lane] = pmin;
-        lds[wid][2][lane] = pmax;
-    }
-    __syncthreads();
-    if (threadIdx.x < kNumPartial) {
-        const int k = threadIdx.x >> 2, vv = threadIdx.x & 3;
-        double acc = lds[0][k][vv];
-        for (int w2 = 1; w2 < kBlock / 64; ++w2) {
-            const double x = lds[w2][k][vv];
-            acc = k == 0 ? acc + x : (k == 1 ? fmin(acc, x) : fmax(acc, x));
+    };
+    if constexpr (!kBatch) {
+        double psum = 0.0, pmin = INFINITY, pmax = -INFINITY;
+        const TileWalk tw = tile_walk((nc + kCellsPerTile - 1) / kCellsPerTile);
+        for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
+            const int c = tile * kCellsPerTile + (threadIdx.x >> 2);
+            if (c < nc) cell(c, psum, pmin, pmax);   // whole quad
         }
-        a.part[(size_t)threadIdx.x * kMaxBlocks + blockIdx.x] = acc;   // index k*4 + v
+        residual_flush(psum, pmin, pmax, a.part + blockIdx.x, kMaxBlocks);
+    } else {
+        for (int gi = g0; gi < g1; ++gi) {
+            double psum = 0.0, pmin = INFINITY, pmax = -INFINITY;
+#pragma unroll 1
+            for (int tile = 0; tile < kGroupCells / kCellsPerTile; ++tile) {
+                const int c = gi * kGroupCells + tile * kCellsPerTile + (threadIdx.x >> 2);
+                if (c < nc) cell(c, psum, pmin, pmax);
+            }
+            residual_flush(psum, pmin, pmax, a.part + a.gbase + gi, a.gstride);
+            __syncthreads();   // the flush's LDS is reused by the next group
+        }
     }
+}
+
+template <int K, typename T>
+__global__ __launch_bounds__(kBlock) void k_residual(StageArgs a) {
+    if (!a.g->active) return;
+    residual_run<K, T, false>(a, 0, 0);
+}
+// KM: degrees present in the launch (1: P1, 2: P2, 3: both)
+template <int KM, typename T>
+__global__ __launch_bounds__(kBlock) void k_residual_batch(const StageArgs* desc, const Chunk* chunks, ChunkSplit cs) {
+    for_each_chunk(desc, chunks, cs, [](const StageArgs& a, int g0, int g1) {
+        if constexpr (KM != 3) residual_run<KM, T, true>(a, g0, g1);
+        else if (a.k == 1) residual_run<1, T, true>(a, g0, g1);
+        else residual_run<2, T, true>(a, g0, g1);
+    });
 }
 
 // ------------------------------------------------------------------------- pass 2: momentum norm
 
-template <int K, typename T>
-__global__ __launch_bounds__(kBlock) void k_mnorm(StageArgs a) {
+template <int K, typename T, bool kBatch>
+__device__ __forceinline__ void mnorm_run(const StageArgs& a, int g0, int g1) {
     using R = Rule<K>;
     constexpr int NM = R::NM;
     constexpr bool kMixed = std::is_same<T, float>::value;
     const Glob* g = a.g;
-    if (!g->active) return;
     const int nc = a.m.n_cell;
     const size_t snc = (size_t)nc;
     const double mb1 = g->ubar[1], mb2 = g->ubar[2];
@@ -567,11 +661,8 @@ __global__ __launch_bounds__(kBlock) void k_mnorm(StageArgs a) {
     const double* a2 = p2.avg;
     const T* h1 = p1.hi;
     const T* h2 = p2.hi;
-    double best = 0.0;
-    const TileWalk tw = tile_walk((nc + kCellsPerTileScalar - 1) / kCellsPerTileScalar);
-    for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
-        const int c = tile * kCellsPerTileScalar + threadIdx.x;
-        if (c >= nc) continue;
+    // one cell per lane: max |m - mbar|^2 over its volume points
+    auto cell = [&](int c, double& best) __attribute__((always_inline)) {
         T m1[NM], m2[NM];
         m1[0] = kMixed ? (T)(a1[c] - mb1) : (T)a1[c];
         m2[0] = kMixed ? (T)(a2[c] - mb2) : (T)a2[c];
@@ -586,16 +677,39 @@ __global__ __launch_bounds__(kBlock) void k_mnorm(StageArgs a) {
             const T d1 = dot<NM>(m1, p) - sh1, d2 = dot<NM>(m2, p) - sh2;
             best = fmax(best, (double)(d1 * d1 + d2 * d2));
         }
+    };
+    static_assert(kCellsPerTileScalar == kGroupCells, "one scalar tile per reduction group");
+    if constexpr (!kBatch) {
+        double best = 0.0;
+        const TileWalk tw = tile_walk((nc + kCellsPerTileScalar - 1) / kCellsPerTileScalar);
+        for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
+            const int c = tile * kCellsPerTileScalar + threadIdx.x;
+            if (c < nc) cell(c, best);
+        }
+        max_flush(best, a.part + (size_t)kNumPartial * kMaxBlocks + blockIdx.x);
+    } else {
+        for (int gi = g0; gi < g1; ++gi) {
+            double best = 0.0;
+            const int c = gi * kGroupCells + threadIdx.x;
+            if (c < nc) cell(c, best);
+            max_flush(best, a.part + (size_t)kNumPartial * a.gstride + a.gbase + gi);
+            __syncthreads();
+        }
     }
-    best = wave_max(best);
-    __shared__ double lds[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double acc = lds[0];
-        for (int w2 = 1; w2 < kBlock / 64; ++w2) acc = fmax(acc, lds[w2]);
-        a.part[(size_t)kNumPartial * kMaxBlocks + blockIdx.x] = acc;
-    }
+}
+
+template <int K, typename T>
+__global__ __launch_bounds__(kBlock) void k_mnorm(StageArgs a) {
+    if (!a.g->active) return;
+    mnorm_run<K, T, false>(a, 0, 0);
+}
+template <int KM, typename T>
+__global__ __launch_bounds__(kBlock) void k_mnorm_batch(const StageArgs* desc, const Chunk* chunks, ChunkSplit cs) {
+    for_each_chunk(desc, chunks, cs, [](const StageArgs& a, int g0, int g1) {
+        if constexpr (KM != 3) mnorm_run<KM, T, true>(a, g0, g1);
+        else if (a.k == 1) mnorm_run<1, T, true>(a, g0, g1);
+        else mnorm_run<2, T, true>(a, g0, g1);
+    });
 }
 
 // ------------------------------------------------------------------------- pass 3: OE, limiter, alpha
@@ -666,9 +780,8 @@ __device__ __forceinline__ void gather_cell(double wa, const T (&w)[NM], double 
     }
 }
 
-// three waves per SIMD: the allocator then keeps the P2 instantiations within 168 VGPRs
-template <int K, typename T>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_filter(StageArgs a) {
+template <int K, typename T, bool kBatch>
+__device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
     using R = Rule<K>;
     using F = Fp<T>;
     constexpr int NM = R::NM;
@@ -676,7 +789,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     constexpr int NP = 3 * NE + 2;   // limiter node set size
     constexpr bool kMixed = std::is_same<T, float>::value;
     const Glob* g = a.g;
-    if (!g->active) return;
     const int nc = a.m.n_cell;
     const size_t snc = (size_t)nc;
     const double gamma = a.gamma;
@@ -696,11 +808,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     T* oh_p = op.hi;
     const Tab<K, T>& TB = tab<K, T>();
 
-    double amax = 0.0, n_lim = 0.0, n_bad = 0.0, n_flat = 0.0;
-    const TileWalk tw = tile_walk((nc + kCellsPerTile - 1) / kCellsPerTile);
-    for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
-        const int c = tile * kCellsPerTile + (threadIdx.x >> 2);
-        if (c >= nc) continue;   // whole quad
+    // one cell, owned by a quad of lanes: OE, limiter, wave speed of the result
+    auto cell = [&](int c, double& amax, double& n_lim, double& n_bad, double& n_flat)
+                    __attribute__((always_inline)) {
         const double wa = wa_p[c];   // the average: untouched by the OE (eq. OE:m0) and the limiter
         T w[NM];
         w[0] = (T)wa;
@@ -946,38 +1056,58 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
         oa_p[c] = wa;
 #pragma unroll
         for (int l = 1; l < NM; ++l) oh_p[(l - 1) * snc + c] = w[l];
-    }
-
-    amax = wave_max(amax);
-    n_lim = wave_sum(n_lim);
-    n_bad = wave_sum(n_bad);
-    n_flat = wave_sum(n_flat);
-    __shared__ double lds[kBlock / 64][4];
-    if ((threadIdx.x & 63) == 0) {
-        lds[threadIdx.x >> 6][0] = amax;
-        lds[threadIdx.x >> 6][1] = n_lim;
-        lds[threadIdx.x >> 6][2] = n_bad;
-        lds[threadIdx.x >> 6][3] = n_flat;
-    }
-    __syncthreads();
-    if (threadIdx.x < 4) {
-        const int k = threadIdx.x;
-        double acc = lds[0][k];
-        for (int w2 = 1; w2 < kBlock / 64; ++w2) acc = k == 0 ? fmax(acc, lds[w2][k]) : acc + lds[w2][k];
-        a.part[(size_t)(kNumPartial + 1 + k) * kMaxBlocks + blockIdx.x] = acc;
+    };
+    if constexpr (!kBatch) {
+        double amax = 0.0, n_lim = 0.0, n_bad = 0.0, n_flat = 0.0;
+        const TileWalk tw = tile_walk((nc + kCellsPerTile - 1) / kCellsPerTile);
+        for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
+            const int c = tile * kCellsPerTile + (threadIdx.x >> 2);
+            if (c < nc) cell(c, amax, n_lim, n_bad, n_flat);   // whole quad
+        }
+        filter_flush(amax, n_lim, n_bad, n_flat, a.part + (size_t)(kNumPartial + 1) * kMaxBlocks + blockIdx.x,
+                     kMaxBlocks);
+    } else {
+        for (int gi = g0; gi < g1; ++gi) {
+            double amax = 0.0, n_lim = 0.0, n_bad = 0.0, n_flat = 0.0;
+#pragma unroll 1
+            for (int tile = 0; tile < kGroupCells / kCellsPerTile; ++tile) {
+                const int c = gi * kGroupCells + tile * kCellsPerTile + (threadIdx.x >> 2);
+                if (c < nc) cell(c, amax, n_lim, n_bad, n_flat);
+            }
+            filter_flush(amax, n_lim, n_bad, n_flat,
+                         a.part + (size_t)(kNumPartial + 1) * a.gstride + a.gbase + gi, a.gstride);
+            __syncthreads();
+        }
     }
 }
+// three waves per SIMD: the allocator then keeps the P2 instantiations within 168 VGPRs
+template <int K, typename T>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_filter(StageArgs a) {
+    if (!a.g->active) return;
+    filter_run<K, T, false>(a, 0, 0);
+}
+// (no occupancy request: with the chunk indirection a 168-VGPR budget spills)
+template <int KM, typename T>
+__global__ __launch_bounds__(kBlock) void k_filter_batch(
+    const StageArgs* desc, const Chunk* chunks, ChunkSplit cs) {
+    for_each_chunk(desc, chunks, cs, [](const StageArgs& a, int g0, int g1) {
+        if constexpr (KM != 3) filter_run<KM, T, true>(a, g0, g1);
+        else if (a.k == 1) filter_run<1, T, true>(a, g0, g1);
+        else filter_run<2, T, true>(a, g0, g1);
+    });
+}
+
 // ------------------------------------------------------------------------- finalize (one workgroup)
 
 constexpr int kFinThreads = 1024;
 
-// Reduces the NC consecutive columns part[(col0 + k) * kMaxBlocks + b], b < G, in
-// a fixed order; column k with op (opbits >> 2k) & 3 (0 sum, 1 min, 2 max).  Each
-// column gets 16/NC waves that stride over the blocks, so all loads are
+// Reduces the NC consecutive columns base[(col0 + k) * cstride + b], b < G, in a
+// fixed order; column k with op (opbits >> 2k) & 3 (0 sum, 1 min, 2 max).  Each
+// column gets 16/NC waves that stride over the records, so all loads are
 // coalesced and no thread holds more than one accumulator.  The results are
 // valid in thread 0.
 template <int NC>
-__device__ __forceinline__ void reduce_columns(const double* part, int G, int col0, unsigned opbits,
+__device__ __forceinline__ void reduce_columns(const double* base, size_t cstride, int G, int col0, unsigned opbits,
                                                double (&out)[NC]) {
     constexpr int kWaves = kFinThreads / 64, kPer = kWaves / NC;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -985,7 +1115,7 @@ __device__ __forceinline__ void reduce_columns(const double* part, int G, int co
     __shared__ double lds[kWaves];
     if (k < NC) {
         const int op = (opbits >> (2 * k)) & 3;
-        const double* col = part + (size_t)(col0 + k) * kMaxBlocks;
+        const double* col = base + (size_t)(col0 + k) * cstride;
         double acc = op == 0 ? 0.0 : (op == 1 ? INFINITY : -INFINITY);
         for (int b = sub * 64 + lane; b < G; b += kPer * 64) {
             const double x = col[b];
@@ -1014,10 +1144,9 @@ __device__ __forceinline__ void reduce_columns(const double* part, int G, int co
 }
 
 // domain averages and L-infinity norms (eq. normOmg): ||u - ubar|| = max(max u - ubar, ubar - min u)
-__global__ __launch_bounds__(kFinThreads) void k_fin_residual(const double* part, int G, Glob* g) {
-    if (!g->active) return;
+__device__ __forceinline__ void fin_residual(const double* base, size_t cstride, int G, Glob* g) {
     double tot[kNumPartial];
-    reduce_columns<kNumPartial>(part, G, 0, 0xAA5500u, tot);   // 4 sums, 4 mins, 4 maxima
+    reduce_columns<kNumPartial>(base, cstride, G, 0, 0xAA5500u, tot);   // 4 sums, 4 mins, 4 maxima
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -1030,10 +1159,9 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_residual(const double* part
     }
 }
 
-__global__ __launch_bounds__(kFinThreads) void k_fin_mnorm(const double* part, int G, Glob* g) {
-    if (!g->active) return;
+__device__ __forceinline__ void fin_mnorm(const double* base, size_t cstride, int G, Glob* g) {
     double best[1];
-    reduce_columns<1>(part, G, kNumPartial, 2u, best);
+    reduce_columns<1>(base, cstride, G, kNumPartial, 2u, best);
     if (threadIdx.x == 0) {
         const double n = sqrt(best[0]);
         const double mb = sqrt(g->ubar[1] * g->ubar[1] + g->ubar[2] * g->ubar[2]);
@@ -1044,10 +1172,9 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_mnorm(const double* part, i
 
 // alpha of the stage output; after the third stage (or the initial limiter pass)
 // t, the step count and Delta t = C_SSP/alpha min_K C^DCW_{K,k}|K|, clamped to t_end
-__global__ __launch_bounds__(kFinThreads) void k_fin_filter(const double* part, int G, Glob* g, int stage) {
-    if (!g->active) return;
+__device__ __forceinline__ void fin_filter(const double* base, size_t cstride, int G, Glob* g, int stage) {
     double r[4];
-    reduce_columns<4>(part, G, kNumPartial + 1, 2u, r);   // max, then three sums
+    reduce_columns<4>(base, cstride, G, kNumPartial + 1, 2u, r);   // max, then three sums
     if (threadIdx.x != 0) return;
     const double alpha = r[0], lim = r[1], bad = r[2];
     g->n_limited += (long long)lim;
@@ -1072,6 +1199,31 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_filter(const double* part, 
         if (!(isinf(g->t_end) || rem > 1e-12 * fmax(1.0, fabs(g->t_end)))) g->active = 0;
     }
     if (g->err) g->active = 0;
+}
+
+// One instance: the partials of the G workgroups of its passes.
+__global__ __launch_bounds__(kFinThreads) void k_fin_residual(const double* part, int G, Glob* g) {
+    if (g->active) fin_residual(part, kMaxBlocks, G, g);
+}
+__global__ __launch_bounds__(kFinThreads) void k_fin_mnorm(const double* part, int G, Glob* g) {
+    if (g->active) fin_mnorm(part, kMaxBlocks, G, g);
+}
+__global__ __launch_bounds__(kFinThreads) void k_fin_filter(const double* part, int G, Glob* g, int stage) {
+    if (g->active) fin_filter(part, kMaxBlocks, G, g, stage);
+}
+
+// A batch: workgroup i reduces the group records of instance desc[i].
+__global__ __launch_bounds__(kFinThreads) void k_fin_residual_batch(const StageArgs* desc) {
+    const StageArgs& a = desc[blockIdx.x];
+    if (a.g->active) fin_residual(a.part + a.gbase, a.gstride, n_groups(a.m.n_cell), a.g);
+}
+__global__ __launch_bounds__(kFinThreads) void k_fin_mnorm_batch(const StageArgs* desc) {
+    const StageArgs& a = desc[blockIdx.x];
+    if (a.g->active) fin_mnorm(a.part + a.gbase, a.gstride, n_groups(a.m.n_cell), a.g);
+}
+__global__ __launch_bounds__(kFinThreads) void k_fin_filter_batch(const StageArgs* desc) {
+    const StageArgs& a = desc[blockIdx.x];
+    if (a.g->active) fin_filter(a.part + a.gbase, a.gstride, n_groups(a.m.n_cell), a.g, a.stage);
 }
 
 // ------------------------------------------------------------------------- initial data
@@ -1191,6 +1343,16 @@ __global__ void k_set_end(Glob* g, double t_end) {
 
 inline unsigned grid_for(int nc) { return (unsigned)((nc + kBlock - 1) / kBlock); }
 
+__global__ void k_gather_status(const StageArgs* desc, int n, double* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Glob* g = desc[i].g;
+    out[4 * i + 0] = (double)g->active;
+    out[4 * i + 1] = (double)g->err;
+    out[4 * i + 2] = g->t;
+    out[4 * i + 3] = (double)g->step;
+}
+
 // host handles of the instantiations of one (degree, precision)
 struct KernelSet {
     const void* pass[3];   // residual, momentum norm, filter
@@ -1206,6 +1368,23 @@ const KernelSet& kernels_for(int k, int mixed) {
     static const KernelSet sets[2][2] = {{kernel_set<1, double>(), kernel_set<1, float>()},
                                          {kernel_set<2, double>(), kernel_set<2, float>()}};
     return sets[k == 2 ? 1 : 0][mixed ? 1 : 0];
+}
+
+// host handles of the batched pass instantiations of one (degree mask, precision)
+struct BatchSet {
+    const void* pass[3];   // residual, momentum norm, filter
+};
+template <int KM, typename T>
+BatchSet batch_set() {
+    return {{reinterpret_cast<const void*>(&k_residual_batch<KM, T>),
+             reinterpret_cast<const void*>(&k_mnorm_batch<KM, T>),
+             reinterpret_cast<const void*>(&k_filter_batch<KM, T>)}};
+}
+const BatchSet& batch_kernels(int kmask, int mixed) {
+    static const BatchSet sets[3][2] = {{batch_set<1, double>(), batch_set<1, float>()},
+                                        {batch_set<2, double>(), batch_set<2, float>()},
+                                        {batch_set<3, double>(), batch_set<3, float>()}};
+    return sets[kmask - 1][mixed ? 1 : 0];
 }
 
 // Grid of a pass: one workgroup per tile while the tiles fit on the GPU at once,
@@ -1269,6 +1448,32 @@ int launch_project(int k, const StageArgs& a, int kind, const double* dparams, i
     void* argv[] = {&args, &kind, &P, &vx};
     return (int)hipLaunchKernel(kernels_for(k, a.mixed).project, dim3(grid_for(a.m.n_cell)), dim3(kBlock), argv, 0,
                                 (hipStream_t)stream);
+}
+
+int resident_grid_batch(int which, int kmask, int mixed) {
+    return std::max(8, resident_blocks(batch_kernels(kmask, mixed).pass[which]) / 8 * 8);
+}
+
+int launch_pass_batch(int which, int kmask, int mixed, const StageArgs* desc, const Chunk* chunks,
+                      const ChunkSplit& cs, int grid, void* stream) {
+    if (kmask < 1 || kmask > 3 || grid < 8 || (grid & 7) != 0) return (int)hipErrorInvalidValue;
+    ChunkSplit split = cs;
+    void* argv[] = {&desc, &chunks, &split};
+    return (int)hipLaunchKernel(batch_kernels(kmask, mixed).pass[which], dim3(grid), dim3(kBlock), argv, 0,
+                                (hipStream_t)stream);
+}
+
+int launch_finalize_batch(int which, const StageArgs* desc, int n_inst, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (which == 0) hipLaunchKernelGGL(k_fin_residual_batch, dim3(n_inst), dim3(kFinThreads), 0, s, desc);
+    else if (which == 1) hipLaunchKernelGGL(k_fin_mnorm_batch, dim3(n_inst), dim3(kFinThreads), 0, s, desc);
+    else hipLaunchKernelGGL(k_fin_filter_batch, dim3(n_inst), dim3(kFinThreads), 0, s, desc);
+    return (int)hipGetLastError();
+}
+
+int launch_gather_status(const StageArgs* desc, int n, double* out, void* stream) {
+    hipLaunchKernelGGL(k_gather_status, dim3((n + 63) / 64), dim3(64), 0, (hipStream_t)stream, desc, n, out);
+    return (int)hipGetLastError();
 }
 
 int launch_set_end(Glob* g, double t_end, void* stream) {

@@ -10,9 +10,16 @@ namespace oedg {
 constexpr int kBlock = 256;            // threads per workgroup of the stage kernels
 constexpr int kCellsPerTile = 64;      // a quad of 4 lanes per cell in the residual/filter passes
 constexpr int kCellsPerTileScalar = 256;   // one lane per cell in the momentum-norm pass
-constexpr int kMaxBlocks = 4096;       // upper bound of a pass's grid (= number of partials)
-constexpr int kNumPartial = 12;        // per-block partials of the residual pass
+constexpr int kMaxBlocks = 4096;       // upper bound of a single-instance pass grid (= partials)
+constexpr int kGroupCells = 256;       // cells per reduction group of the batched passes
+constexpr int kNumPartial = 12;        // partials of the residual pass per group
 constexpr int kPartCols = kNumPartial + 1 + 4;   // + momentum norm + 4 filter partials
+
+// Reduction groups of an instance in the batched passes: cells [g * kGroupCells,
+// (g + 1) * kGroupCells).  Every group writes its own partial record, so an
+// instance's reductions depend only on its own cells, whatever the schedule or
+// the other instances of the launch.
+constexpr int n_groups(int n_cell) { return (n_cell + kGroupCells - 1) / kGroupCells; }
 
 // Host-side mesh tables built once per mesh (see mesh_host.cpp).  Per-cell arrays
 // that go to the device are structure-of-arrays: component-major, cell fastest.
@@ -34,9 +41,9 @@ struct HostMesh {
 int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const int32_t* tri,
                const double* cell_xy, const int32_t* edge_bc, HostMesh& m, std::string& err);
 
-// Device-resident scalars of one context.  Written only by the last workgroup of a
-// kernel (after all others have published their partials) or by the host between
-// steps.
+// Device-resident scalars of one instance.  Written only by the finalize kernels
+// (one workgroup per instance, after the pass has published its partials) or by
+// the host between steps.
 struct Glob {
     double alpha;        // LF viscosity of the current stage input (eq. 1250)
     double alpha_step;   // alpha of u^n, which sets the step's Delta t
@@ -87,31 +94,67 @@ struct StageArgs {
     StateView w;          // pre-filter state (written by the residual pass)
     StateView uout;       // limited stage output
     size_t avs, hvs;      // variable strides of the averages and of the higher modes
-    double* part;         // per-block partials: [12][kMaxBlocks] residual, [kMaxBlocks] momentum
-                          // norm, [4][kMaxBlocks] filter
+    double* part;         // partial records, column-major; columns 0-11 residual, 12
+                          // momentum norm, 13-16 filter.  Single-instance passes:
+                          // column j of workgroup b at part[j * kMaxBlocks + b].
+                          // Batched passes: column j of group g of this instance at
+                          // part[j * gstride + gbase + g].
+    size_t gstride;       // batched: groups of all instances sharing `part`
+    int gbase;            // batched: first group of this instance in `part`
     Glob* g;
     double gamma;
+    int k;                // degree
     int stage;            // 0, 1, 2; -1 = limiter and alpha only (initial data)
     int oe_enable, oe_mode, bp_enable;
     int mixed;            // 0: FP64 bulk, 1: FP32 bulk (averages and limiter stay FP64)
 };
 
+// A run of groups [g0, g1) of instance `inst`: the unit a pass workgroup takes.
+struct Chunk {
+    int inst, g0, g1;
+};
+// Chunk ranges per XCD: XCD x takes chunks [b[x], b[x+1]).
+struct ChunkSplit {
+    int b[9];
+};
+
+// ---- single instance: persistent passes over the instance's tiles
 // Grid of pass `which` (0 residual, 1 momentum norm, 2 filter) at degree k and
 // precision `mixed`: a multiple of 8 (one share per XCD), at most kMaxBlocks and
 // at most what is resident at once; workgroups stride over their XCD's tiles.
 int grid_for_pass(int which, int k, int mixed, int n_cell);
-
-// kernel launchers (kernels.hip); the precision comes from a.mixed.  Return a
-// hipError_t as int.  Each pass kernel writes per-workgroup partials; the
-// matching finalize kernel (one workgroup) reduces them in a fixed order into Glob.
+// Kernel launchers; the precision comes from a.mixed.  Return a hipError_t as
+// int.  Each pass kernel writes per-workgroup partials; the matching finalize
+// kernel (one workgroup) reduces them in a fixed order into Glob.
 int launch_residual(int k, const StageArgs& a, void* stream);
 int launch_mnorm(int k, const StageArgs& a, void* stream);
 int launch_filter(int k, const StageArgs& a, void* stream);
 int launch_finalize(int which, int k, const StageArgs& a, void* stream);   // 0 residual, 1 mnorm, 2 filter
-// L2 projection of a named problem into a.uout; vx holds the oriented vertex
-// coordinates [6][cell] (and, for the blast, the origin flags in row 6)
+
+// ---- batch: passes over a chunk table of several instances
+// Workgroups of batched pass `which` resident at once for degree mask kmask
+// (1: P1, 2: P2, 3: both) and precision `mixed`; a multiple of 8.
+int resident_grid_batch(int which, int kmask, int mixed);
+// Launches batched pass `which`: desc[i] are the device stage arguments of
+// instance i, chunks the device chunk table split by XCD as in cs; grid a
+// multiple of 8.  Returns a hipError_t as int.
+int launch_pass_batch(int which, int kmask, int mixed, const StageArgs* desc, const Chunk* chunks,
+                      const ChunkSplit& cs, int grid, void* stream);
+// The matching finalize kernel, one workgroup per instance (desc[0..n_inst)):
+// reduces the instance's group records in a fixed order into its Glob.
+int launch_finalize_batch(int which, const StageArgs* desc, int n_inst, void* stream);
 int launch_project(int k, const StageArgs& a, int kind, const double* dparams, int n_params, const double* vx,
                    void* stream);
 int launch_set_end(Glob* g, double t_end, void* stream);
+// Copies {active, err, t, step} of every instance of desc[0..n) into out[4 n].
+int launch_gather_status(const StageArgs* desc, int n, double* out, void* stream);
+
+// schedule.cpp: chunks of chunk_groups groups over the instances in order, and
+// their split into 8 contiguous ranges of equal estimated cost (one per XCD).
+// Returns 0, or -1 for invalid sizes or degrees.
+int plan_chunks(int n_inst, const int32_t* n_cell, const int* k, int chunk_groups, std::vector<Chunk>& chunks,
+                ChunkSplit& split);
+// Grid of a pass over a split: 8 times the widest XCD range, at most `resident`.
+int grid_for_split(const ChunkSplit& split, int resident);
 
 }  // namespace oedg
