@@ -9,9 +9,12 @@ max wave speed, device-side Delta t) over the resident mesh and state.
 Default workload: P2, about 200k cells of a seeded Poisson-disk Delaunay mesh of
 the unit square, four-quadrant Riemann data (rho in [0.14, 1.5], p in [0.03, 1.5]),
 transmissive boundaries, run twice: FP64 (the headline value) and the mixed form
-(FP32 bulk, FP64 averages and limiter; reported under "mixed").  With --extra the
-near-vacuum blast on a ~1M-cell mesh is measured as well, in both forms
-(reported under "extra").
+(FP32 bulk, FP64 averages and limiter; reported under "mixed").  Also reported:
+"batch", 64 uneven P1/P2 instances stepped as one batch (sizes scaled by
+--batch-scale), and "serving", the continuous-batching server on a Poisson
+request stream at two arrival rates (p50/p99 latency, aggregate DOF-stage/s).
+With --extra the near-vacuum blast on a ~1M-cell mesh is measured as well, in
+both forms (reported under "extra").
 
 Prints one JSON line.  Only one GPU is supported: --gpus N with N > 1 exits.
 """
@@ -137,6 +140,31 @@ def run_batch(scale, steps, warmup, precision):
     return out
 
 
+def run_serving(n_req, rates, scale, t_scale, steps_per_tick=8):
+    """The continuous-batching server on a seeded request stream (sizes 1k-2M
+    divided by `scale`, t_end in [0.05, 0.5] times `t_scale`), once per arrival
+    rate.  Request meshes are built before the clock starts (the client's
+    payload); upload, host precompute, projection and stepping are timed."""
+    from paper_2409_09620_amd.serving import Request, Server
+    from synth import workloads
+    specs = workloads.serving_requests(n_req=n_req, rate=1.0, scale=scale, t_scale=t_scale)
+    built = {sp["id"]: workloads.serving_request(sp) for sp in specs}
+    out = {}
+    for rate in rates:
+        reqs = [Request(id=sp["id"], k=sp["k"], n_cell=built[sp["id"]][0].n_cell, t_end=sp["t_end"],
+                        build=(lambda b=built[sp["id"]]: b), arrival=sp["arrival"])
+                for sp in workloads.serving_requests(n_req=n_req, rate=rate, scale=scale, t_scale=t_scale)]
+        st = Server(steps_per_tick=steps_per_tick, keep_results=False).run(reqs)
+        out[f"rate_{rate:g}_per_s"] = {
+            "p50_ms": st.p50 * 1e3, "p99_ms": st.p99 * 1e3, "mean_ms": st.mean * 1e3,
+            "dof_stage_per_s": st.dof_stage_per_s, "wall_s": st.wall, "peak_members": st.peak_members,
+            "batch_rebuilds": st.rebuilds, "steps_total": int(sum(r.steps for r in reqs))}
+    out["workload"] = (f"{n_req} requests, sizes log-uniform 1k-2M / {scale} "
+                       f"({min(b[0].n_cell for b in built.values())}-{max(b[0].n_cell for b in built.values())} cells), "
+                       f"P1|P2, Riemann|vortex, t_end in [0.05, 0.5] x {t_scale}, Poisson arrivals")
+    return out
+
+
 def roofline(prof, k, n_cell, workload, precision="fp64"):
     per_cell = algorithmic_bytes_per_cell(k, precision)
     kernels = {}
@@ -191,6 +219,12 @@ def main():
     ap.add_argument("--cells", type=int, default=200_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra", action="store_true", help="also run the ~1M-cell blast")
+    ap.add_argument("--serving-requests", type=int, default=32, metavar="N",
+                    help="serving run with N requests per arrival rate; 0 skips it")
+    ap.add_argument("--serving-scale", type=int, default=20, metavar="S",
+                    help="serving request sizes 1k-2M divided by S")
+    ap.add_argument("--serving-t-scale", type=float, default=0.1,
+                    help="serving final times [0.05, 0.5] multiplied by this")
     ap.add_argument("--batch-scale", type=int, default=10, metavar="S",
                     help="64-instance batch with sizes divided by S (1: the full 5k-500k sizes); 0 skips it")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -274,6 +308,8 @@ def main():
                         for pr in ("fp64", "mixed")}
         out["batch"]["workload"] = (f"64 two-state instances, sizes log-uniform 5k-500k / {args.batch_scale}, "
                                     "P1/P2 50/50, seeded Delaunay")
+    if args.serving_requests > 0:
+        out["serving"] = run_serving(args.serving_requests, (20.0, 200.0), args.serving_scale, args.serving_t_scale)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, kind, params, k)
     print(json.dumps(out), flush=True)

@@ -6,6 +6,8 @@
 * blast_delaunay     Delaunay mesh of [-1.1,1.1]^2 with the origin as a vertex,
                      near-vacuum blast (ambient p = 1e-10, E_total = 0.25)
 * batch_instances    n meshes with log-uniform sizes, P1/P2 split, two-state data
+* serving_requests   a seeded request stream: log-uniform sizes, P1 or P2, Riemann
+                     or vortex data, final times, Poisson arrival times
 """
 
 import numpy as np
@@ -45,3 +47,33 @@ def batch_sizes(n_inst=64, lo=5_000, hi=500_000, seed=4):
 def batch_instance(i, size, seed=4):
     m = poisson_delaunay(int(size), seed=seed * 1000 + i, name=f"inst{i}")
     return m, PROBLEM_TWO_STATE, two_state_params(seed * 1000 + i)
+
+
+def serving_requests(n_req=32, rate=50.0, seed=5, lo=1_000, hi=2_000_000, scale=1, t_lo=0.05, t_hi=0.5,
+                     t_scale=1.0):
+    """Request specs of a serving run (meshes are built by serving_request).
+
+    Sizes log-uniform in [lo, hi] / scale triangles, degree 1 or 2 and Riemann
+    (two states at rest across a random line in the unit square, rho and p
+    log-uniform in [0.03, 1.5]) or vortex data (Delaunay mesh of [0,10]^2) with
+    probability 1/2 each, t_end uniform in [t_lo, t_hi] times t_scale, arrivals a
+    Poisson process of the given rate per second (exponential gaps by inversion)."""
+    st = Stream(seed * 53 + 7)
+    sizes = np.maximum(st.log_uniform(n_req, lo, hi) / scale, 64).astype(np.int64)
+    degree = np.where(st.uniform(n_req) < 0.5, 1, 2)
+    vortex = st.uniform(n_req) < 0.5
+    t_end = st.uniform(n_req, t_lo, t_hi) * t_scale
+    gaps = -np.log(1.0 - st.uniform(n_req)) / rate
+    arrival = np.cumsum(gaps) - gaps[0]
+    return [dict(id=i, n_cells=int(sizes[i]), k=int(degree[i]), vortex=bool(vortex[i]), t_end=float(t_end[i]),
+                 arrival=float(arrival[i]), seed=seed * 10_000 + i) for i in range(n_req)]
+
+
+def serving_request(spec):
+    """(mesh, kind, params) of one request spec."""
+    if spec["vortex"]:
+        m = poisson_delaunay(spec["n_cells"], lo=(0.0, 0.0), hi=(10.0, 10.0), seed=spec["seed"],
+                             name=f"req{spec['id']}")
+        return m, PROBLEM_VORTEX, vortex_params()
+    m = poisson_delaunay(spec["n_cells"], seed=spec["seed"], name=f"req{spec['id']}")
+    return m, PROBLEM_TWO_STATE, two_state_params(spec["seed"], lo=0.03, hi=1.5)

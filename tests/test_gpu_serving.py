@@ -1,0 +1,79 @@
+"""The continuous-batching server on the GPU: every request's result is the same
+alone and in the mix (bit for bit: a batch member's reductions never see the
+other members), admission respects the HBM budget, and the latency statistics
+cover every request."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from synth import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():   # collected on CPU-only hosts, skipped there
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2409_09620_amd import Solver  # noqa: E402
+from paper_2409_09620_amd.serving import Request, Server, footprint_bytes  # noqa: E402
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_requests(n=12, rate=400.0):
+    specs = workloads.serving_requests(n_req=n, rate=rate, lo=300, hi=6000, t_lo=0.01, t_hi=0.05)
+    built = {s["id"]: workloads.serving_request(s) for s in specs}
+    reqs = []
+    for s in specs:
+        m = built[s["id"]][0]
+        reqs.append(Request(id=s["id"], k=s["k"], n_cell=m.n_cell, t_end=s["t_end"],
+                            build=(lambda b=built[s["id"]]: b), arrival=s["arrival"]))
+    return reqs, built
+
+
+def rel_err(a, b):
+    return max(np.abs(a[v] - b[v]).max() / max(np.abs(b[v]).max(), 1e-300) for v in range(4))
+
+
+def test_results_same_alone_and_in_mix():
+    reqs, built = make_requests()
+    say(f"[gpu case] serving {len(reqs)} requests, cells {[r.n_cell for r in reqs]}")
+    stats = Server(steps_per_tick=4).run(reqs)
+    say(f"mix: wall {stats.wall:.3f}s p50 {stats.p50 * 1e3:.1f} ms p99 {stats.p99 * 1e3:.1f} ms "
+        f"peak members {stats.peak_members} rebuilds {stats.rebuilds}")
+    assert stats.peak_members > 1                   # requests really overlapped
+    for r in reqs:
+        assert r.error is None and r.done is not None and r.done >= r.arrival
+        assert abs(r.t - r.t_end) < 1e-14 and r.steps > 0
+        alone = Request(id=r.id, k=r.k, n_cell=r.n_cell, t_end=r.t_end, build=r.build)
+        Server(steps_per_tick=3).run([alone])
+        assert alone.steps == r.steps
+        assert np.array_equal(alone.result, r.result), r.id
+    # the single-instance path agrees to round-off
+    for r in reqs[:4]:
+        m, kind, p = built[r.id]
+        s = Solver(m, r.k)
+        s.init_problem(kind, p)
+        s.step_to(r.t_end)
+        u, t, steps = s.readback()
+        assert steps == r.steps and rel_err(u, r.result) < 1e-11
+
+
+def test_admission_respects_budget():
+    reqs, _ = make_requests(n=8, rate=1e4)          # all arrive at once
+    fps = sorted(footprint_bytes(r.n_cell, r.k) for r in reqs)
+    budget = fps[-1] + fps[-2]                      # room for two of the largest
+    stats = Server(hbm_budget=budget, steps_per_tick=4).run(reqs)
+    say(f"budget {budget} B: peak members {stats.peak_members}, rebuilds {stats.rebuilds}")
+    assert 1 <= stats.peak_members < len(reqs)
+    assert all(r.done is not None and r.error is None for r in reqs)
+    assert len(stats.latencies) == len(reqs) and stats.p99 >= stats.p50 > 0
+    # queueing never changes a result
+    again, _ = make_requests(n=8, rate=1e4)
+    Server(steps_per_tick=5).run(again)
+    for a, b in zip(reqs, again):
+        assert np.array_equal(a.result, b.result)
