@@ -56,6 +56,7 @@ def lib():
             "orc_get_state": (_I, [_P, _I, _P]),
             "orc_get_scalars": (_I, [_P, _P]),
             "orc_set_time": (_I, [_P, _D, _D, _D, _L]),
+            "orc_set_max_restarts": (_I, [_P, _I]),
             "orc_apply_residual": (_I, [_P, _P, _D, _P]),
             "orc_apply_oe": (_I, [_P, _P, _D]),
             "orc_apply_limiter": (_I, [_P, _P]),
@@ -80,13 +81,13 @@ def _ptr(a):
 
 SCALARS = ["t", "dt", "alpha", "step", "active", "err", "n_limited", "minck",
            "ubar_rho", "ubar_m1", "ubar_m2", "ubar_E",
-           "nrm_rho", "nrm_m1", "nrm_m2", "nrm_E", "nrm_m", "zero_rho", "zero_E", "zero_m"]
+           "nrm_rho", "nrm_m1", "nrm_m2", "nrm_E", "nrm_m", "zero_rho", "zero_E", "zero_m", "n_restarts"]
 
 
 class Oracle:
     """One mesh and state in the FP64 oracle."""
 
-    def __init__(self, mesh, k, gamma=1.4, cssp=1.0, oe=True, bp=True, oe_mode=0):
+    def __init__(self, mesh, k, gamma=1.4, cssp=1.0, oe=True, bp=True, oe_mode=0, max_restarts=8):
         self.k = int(k)
         self.nm = (k + 1) * (k + 2) // 2
         self.nc = mesh.n_cell
@@ -98,6 +99,7 @@ class Oracle:
             raise ValueError("oracle: invalid mesh")
         self.h = h
         lib().orc_config(h, gamma, cssp, int(oe), int(bp), int(oe_mode))
+        lib().orc_set_max_restarts(h, int(max_restarts))
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -154,6 +154,10 @@ typedef struct {
     long step;
     int active, err;
     long n_limited;
+    /* step restarts: a stage whose averages leave the admissible set ends the
+     * attempt; the step is retried from u^n with half the time step */
+    int skip, restarts_this_step, max_restarts;
+    long n_restarts;
     /* last stage's globals */
     double ubar[NVAR], nrm_v[NVAR], nrm_m; int zero_v[NVAR], zero_m;
 } Orc;
@@ -353,6 +357,7 @@ Orc* orc_create(int k, int nv, const double* xy, int nc, const int* tri_in, cons
     o->ne = k + 1;
     o->gamma = 1.4;
     o->cssp = 1.0;
+    o->max_restarts = 8;
     o->eps_oe = 1e-12;
     o->eps_bp = 1e-13;
     o->oe_on = 1;
@@ -790,17 +795,37 @@ static void next_dt(Orc* o) {
     o->active = isinf(o->t_end) || rem > 1e-12 * fmax(1.0, fabs(o->t_end));
 }
 
-/* eq. RKTime with the OE filter and the BP limiter after every stage (Sec. 4.5) */
+/* number of cells whose average leaves the admissible set (rho > 0, rho e > 0);
+ * the OE filter and the limiter keep every average, so the pre-filter state has
+ * the stage output's averages */
+static int bad_averages(const Orc* o, const double* arr) {
+    int bad = 0;
+    for (int c = 0; c < o->nc; ++c) {
+        double ub[NVAR];
+        for (int v = 0; v < NVAR; ++v) ub[v] = U(arr, c, v, 0);
+        if (!(ub[0] > 0) || !(int_energy(ub) > 0)) ++bad;
+    }
+    return bad;
+}
+
+/* eq. RKTime with the OE filter and the BP limiter after every stage (Sec. 4.5).
+ * With the limiter on, a stage whose averages leave the admissible set sets
+ * `skip`: the rest of the step does nothing and orc_step retries it. */
 int orc_stage(Orc* o, int s) {
     const double a[3] = {0.0, 0.75, 1.0 / 3.0}, b[3] = {1.0, 0.25, 2.0 / 3.0};
     const size_t ns = (size_t)o->nc * NVAR * o->nm;
     if (s < 0 || s > 2) return -1;
+    if (o->skip) return 0;
     const double* in = s == 0 ? o->u0 : o->u;
     const double alpha = max_wave_speed(o, in);
     if (s == 0) o->alpha = alpha;
     residual(o, in, alpha, o->L);
     for (size_t i = 0; i < ns; ++i) o->w[i] = a[s] * o->u0[i] + b[s] * (in[i] + o->dt * o->L[i]);
     memcpy(o->pre, o->w, sizeof(double) * ns);
+    if (o->bp_on && bad_averages(o, o->w)) {
+        o->skip = 1;
+        return 0;
+    }
     if (o->oe_on) oe_filter(o, o->w, o->dt);
     if (o->bp_on && bp_limit(o, o->w)) o->err = -5;
     memcpy(o->u, o->w, sizeof(double) * ns);
@@ -817,11 +842,32 @@ int orc_finish_step(Orc* o) {
     return 0;
 }
 
+/* One step.  An attempt whose stage left the admissible set is discarded (u^n is
+ * untouched) and the step is retried with half the time step, at most
+ * max_restarts times; then the run stops with an error. */
 int orc_step(Orc* o) {
     if (!o->active) return 1;
-    for (int s = 0; s < 3 && !o->err; ++s) orc_stage(o, s);
-    if (o->err) return o->err;
+    for (;;) {
+        o->skip = 0;
+        for (int s = 0; s < 3 && !o->err && !o->skip; ++s) orc_stage(o, s);
+        if (o->err) return o->err;
+        if (!o->skip) break;
+        o->skip = 0;
+        if (++o->restarts_this_step > o->max_restarts) {
+            o->err = -5;
+            o->active = 0;
+            return o->err;
+        }
+        o->dt *= 0.5;
+        o->n_restarts++;
+    }
+    o->restarts_this_step = 0;
     return orc_finish_step(o);
+}
+
+int orc_set_max_restarts(Orc* o, int n) {
+    o->max_restarts = n < 0 ? 0 : n;
+    return 0;
 }
 
 int orc_run(Orc* o, double t_end, long max_steps, long* done) {
@@ -916,6 +962,9 @@ int orc_start(Orc* o) {
     o->step = 0;
     o->err = 0;
     o->n_limited = 0;
+    o->skip = 0;
+    o->restarts_this_step = 0;
+    o->n_restarts = 0;
     o->t_end = INFINITY;
     if (o->bp_on && bp_limit(o, o->u0)) o->err = -5;
     memcpy(o->u, o->u0, sizeof(double) * (size_t)o->nc * NVAR * o->nm);
@@ -946,13 +995,15 @@ int orc_get_state(const Orc* o, int which, double* out) {
 }
 
 /* scalars: t, dt, alpha, step, active, err, n_limited, minck,
- *          ubar[4], nrm_rho, nrm_m1, nrm_m2, nrm_E, nrm_m, zero_rho, zero_E, zero_m */
+ *          ubar[4], nrm_rho, nrm_m1, nrm_m2, nrm_E, nrm_m, zero_rho, zero_E, zero_m,
+ *          n_restarts */
 int orc_get_scalars(const Orc* o, double* s) {
     s[0] = o->t; s[1] = o->dt; s[2] = o->alpha; s[3] = (double)o->step; s[4] = o->active;
     s[5] = o->err; s[6] = (double)o->n_limited; s[7] = o->minck;
     for (int v = 0; v < 4; ++v) s[8 + v] = o->ubar[v];
     for (int v = 0; v < 4; ++v) s[12 + v] = o->nrm_v[v];
     s[16] = o->nrm_m; s[17] = o->zero_v[0]; s[18] = o->zero_v[3]; s[19] = o->zero_m;
+    s[20] = (double)o->n_restarts;
     return 0;
 }
 

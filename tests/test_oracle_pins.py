@@ -517,6 +517,46 @@ def test_blast_positivity_and_failure_without_limiter():
     assert neg
 
 
+def _oversized_blast(**kw):
+    """Near-vacuum blast with c_SSP = 4, four times the SSP coefficient the BP time
+    step assumes: from the second step on, a stage leaves the admissible set."""
+    m, kind, p = workloads.blast_delaunay(n_cells=3000, seed=23)
+    o = oracle.Oracle(m, 2, cssp=4.0, **kw)
+    assert o.init_problem(kind, p) == 0
+    return o, m, kind, p
+
+
+def test_restart_is_the_step_with_halved_dt():
+    """A restarted step equals, bit for bit, a plain step taken with the halved
+    Delta t from u^n (u^n is untouched by the discarded attempt)."""
+    o, m, kind, p = _oversized_blast()
+    assert o.step() == 0 and o.scalars()["n_restarts"] == 0
+    s0, u_n = o.scalars(), o.state(0)
+    assert o.step() == 0
+    r = int(o.scalars()["n_restarts"])
+    assert r >= 1
+    ref, _, _, _ = _oversized_blast(max_restarts=0)
+    assert ref.step() == 0
+    assert np.array_equal(ref.state(0), u_n)
+    ref.set_time(s0["t"], s0["dt"] / 2 ** r, s0["alpha"], int(s0["step"]))
+    assert ref.step() == 0
+    assert np.array_equal(ref.state(0), o.state(0))
+    assert ref.scalars()["t"] == o.scalars()["t"] == s0["t"] + s0["dt"] / 2 ** r
+    u = o.state(0)
+    e = u[3, 0] - 0.5 * (u[1, 0] ** 2 + u[2, 0] ** 2) / u[0, 0]
+    assert u[0, 0].min() > 0 and e.min() > 0
+
+
+def test_restart_limit_stops_with_u_n_kept():
+    o, m, kind, p = _oversized_blast(max_restarts=0)
+    assert o.step() == 0
+    u_n = o.state(0)
+    assert o.step() == -5
+    sc = o.scalars()
+    assert sc["active"] == 0 and sc["step"] == 1
+    assert np.array_equal(o.state(0), u_n)
+
+
 # ----------------------------------------------------------------------------- convergence
 
 def exact_cell_averages(m, t, params, period):
