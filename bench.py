@@ -36,6 +36,11 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2409_09620_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 
 
+def log(*a):
+    """Progress on stderr (the JSON result is the only stdout line)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def algorithmic_bytes_per_cell(k, precision="fp64"):
     """Bytes each kernel must move per cell and launch.  Neighbour re-reads are
     cache hits and not counted.  S = state per cell (mixed: FP64 averages, FP32
@@ -116,6 +121,8 @@ def run_batch(scale, steps, warmup, precision):
     sizes, degree = workloads.batch_sizes(n_inst=64)
     sols, dof = [], 0
     for i, (sz, k) in enumerate(zip(sizes, degree)):
+        if i % 8 == 0:
+            log(f"batch {precision}: building instance {i}/64")
         m, kind, p = workloads.batch_instance(i, max(int(sz) // scale, 64))
         s = Solver(m, int(k))
         s.init_problem(kind, p, precision=precision)
@@ -148,12 +155,17 @@ def run_serving(n_req, rates, scale, t_scale, steps_per_tick=8):
     from paper_2409_09620_amd.serving import Request, Server
     from synth import workloads
     specs = workloads.serving_requests(n_req=n_req, rate=1.0, scale=scale, t_scale=t_scale)
-    built = {sp["id"]: workloads.serving_request(sp) for sp in specs}
+    built = {}
+    for sp in specs:
+        if sp["id"] % 4 == 0:
+            log(f"serving: building request {sp['id']}/{n_req}")
+        built[sp["id"]] = workloads.serving_request(sp)
     out = {}
     for rate in rates:
         reqs = [Request(id=sp["id"], k=sp["k"], n_cell=built[sp["id"]][0].n_cell, t_end=sp["t_end"],
                         build=(lambda b=built[sp["id"]]: b), arrival=sp["arrival"])
                 for sp in workloads.serving_requests(n_req=n_req, rate=rate, scale=scale, t_scale=t_scale)]
+        log(f"serving: rate {rate:g}/s")
         st = Server(steps_per_tick=steps_per_tick, keep_results=False).run(reqs)
         out[f"rate_{rate:g}_per_s"] = {
             "p50_ms": st.p50 * 1e3, "p99_ms": st.p99 * 1e3, "mean_ms": st.mean * 1e3,
@@ -271,6 +283,7 @@ def main():
                 "run": {"t": d_["t"], "step": d_["step"], "alpha": d_["alpha"], "n_limited": d_["n_limited"],
                         "n_flat": d_["n_flat"], "n_bad": d_["n_bad"]}}
 
+    log(f"main workload: {mesh.n_cell} cells")
     r64 = measure(mesh, kind, params, "fp64", args.steps, args.warmup, tag)
     rmx = measure(mesh, kind, params, "mixed", args.steps, args.warmup, tag)
     out = {

@@ -71,9 +71,21 @@ typedef struct {
     int oe_mode;       /* DG_OE_RI or DG_OE_CW */
     int bp_enable;     /* 1: apply the BP limiter after every stage and at init */
     int precision;     /* DG_PREC_FP64 or DG_PREC_MIXED */
+    int max_restarts;  /* retries of a step whose stage leaves the admissible set (8) */
 } dg_config;
 
-/* Fills *cfg with the defaults: k = 2, gamma = 1.4, c_ssp = 1, OE on (RI), BP on, FP64. */
+/* Fills *cfg with the defaults: k = 2, gamma = 1.4, c_ssp = 1, OE on (RI), BP on, FP64,
+ * max_restarts = 8.
+ *
+ * Step restarts (with the BP limiter on).  The BP time step bounds Delta t by the
+ * wave speed of u^n (Sec. 5), while each stage's LF flux uses its own input's
+ * speed; when a later stage's speed exceeds the step's, positivity of the averages
+ * is no longer guaranteed for that stage.  A stage whose averages leave the
+ * admissible set (rho <= 0 or rho e <= 0; the OE filter and the limiter keep the
+ * averages, so this is decided in the residual pass) ends the attempt: the rest
+ * of the step does nothing and u^n stays untouched; the step's last kernel then
+ * halves Delta t and the next step launch retries it.  After max_restarts retries
+ * of one step the run stops (DG_E_BOUNDS from the polling calls). */
 void dg_config_default(dg_config* cfg);
 
 /* Creates a context on HIP device `hip_device`.  `hip_stream` is a hipStream_t
@@ -140,10 +152,13 @@ dg_status dg_stage(dg_ctx* ctx, int s);
 dg_status dg_step(dg_ctx* ctx, double* dt_out);
 
 /* Steps until t reaches t_end (the last step is shortened to land on it) or
- * max_steps steps were taken.  Synchronises every few steps to poll. */
+ * max_steps steps were completed (retried attempts do not count).  Synchronises
+ * every few steps to poll. */
 dg_status dg_step_to(dg_ctx* ctx, double t_end, int64_t max_steps, int64_t* steps_done);
 
-/* Copies u^n (host, modal, layout above) and the time and step count. */
+/* Copies u^n (host, modal, layout above) and the time and step count.  After a
+ * DG_E_BOUNDS stop it still copies (the u^n the failed step started from) and
+ * returns DG_E_BOUNDS. */
 dg_status dg_readback(dg_ctx* ctx, double* u_modal, double* t, int64_t* step);
 
 /* Copies an internal state buffer: which = 0 u^n, 1 last stage output,
@@ -162,6 +177,7 @@ typedef struct {
     int active;                   /* 0 once t has reached the last t_end */
     int64_t n_flat;               /* DG_PREC_MIXED: cell-stages reset to their average by the
                                      check of the stored (FP32-rounded) coefficients */
+    int64_t n_restarts;           /* steps retried with half the time step */
 } dg_diag_t;
 
 /* Diagnostics of the context (synchronises). */
@@ -223,7 +239,8 @@ dg_status dg_batch_autotune(dg_batch* b, int reps, int* chunk_groups, int* occup
 /* n_steps SSP-RK3 steps of every active member (no synchronisation). */
 dg_status dg_batch_step(dg_batch* b, int64_t n_steps);
 
-/* Steps until no member is active or max_steps steps were taken; polls every
+/* Steps until no member is active or max_steps step launches were made (a
+ * launch completes or retries each active member's step); polls every
  * few steps.  DG_E_BOUNDS if a member's cell average left the admissible set. */
 dg_status dg_batch_run(dg_batch* b, int64_t max_steps, int64_t* steps_done);
 

@@ -30,14 +30,14 @@ _c_i32, _c_i64, _c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
 
 class DgConfig(ctypes.Structure):
     _fields_ = [("k", _c_i), ("gamma", _c_d), ("c_ssp", _c_d), ("oe_enable", _c_i),
-                ("oe_mode", _c_i), ("bp_enable", _c_i), ("precision", _c_i)]
+                ("oe_mode", _c_i), ("bp_enable", _c_i), ("precision", _c_i), ("max_restarts", _c_i)]
 
 
 class DgDiag(ctypes.Structure):
     _fields_ = [("t", _c_d), ("dt", _c_d), ("alpha", _c_d), ("step", _c_i64),
                 ("n_limited", _c_i64), ("n_bad", _c_i64), ("n_cfl_excursions", _c_i64),
                 ("ubar", _c_d * 4), ("nrm", _c_d * 4), ("nrm_m", _c_d), ("active", _c_i),
-                ("n_flat", _c_i64)]
+                ("n_flat", _c_i64), ("n_restarts", _c_i64)]
 
 
 class DgError(RuntimeError):
@@ -166,8 +166,10 @@ class Solver:
         except Exception:
             pass
 
-    def config(self, oe=True, bp=True, oe_mode=DG_OE_RI, gamma=1.4, c_ssp=1.0, precision="fp64"):
-        """precision: "fp64" or "mixed" (FP32 bulk, FP64 averages and limiter)."""
+    def config(self, oe=True, bp=True, oe_mode=DG_OE_RI, gamma=1.4, c_ssp=1.0, precision="fp64", max_restarts=8):
+        """precision: "fp64" or "mixed" (FP32 bulk, FP64 averages and limiter);
+        max_restarts: retries (each with half the time step) of a step whose stage
+        leaves the admissible set."""
         cfg = DgConfig()
         load_library().dg_config_default(ctypes.byref(cfg))
         cfg.k = self.k
@@ -179,6 +181,7 @@ class Solver:
         if precision not in PRECISION:
             raise ValueError(f"precision must be one of {sorted(PRECISION)}")
         cfg.precision = PRECISION[precision]
+        cfg.max_restarts = int(max_restarts)
         return cfg
 
     def shape(self):
@@ -213,10 +216,14 @@ class Solver:
         return n.value
 
     def readback(self):
+        """(u^n, t, step).  After DG_E_BOUNDS the library still copies the state it
+        kept (the u^n of the failed step), and so does this."""
         u = np.zeros(self.shape())
         t = ctypes.c_double(0)
         s = ctypes.c_int64(0)
-        self._check(load_library().dg_readback(self.h, _ptr(u), ctypes.byref(t), ctypes.byref(s)))
+        st = load_library().dg_readback(self.h, _ptr(u), ctypes.byref(t), ctypes.byref(s))
+        if st != -5:
+            self._check(st)
         return u, t.value, s.value
 
     def read_state(self, which):

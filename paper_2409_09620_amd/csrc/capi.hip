@@ -167,6 +167,7 @@ dg_status check_cfg(dg_ctx* c, const dg_config* cfg) {
         return fail(c, DG_E_ARG, "unsupported precision");
     if (cfg->oe_mode != DG_OE_RI && cfg->oe_mode != DG_OE_CW) return fail(c, DG_E_ARG, "bad oe_mode");
     if (!(cfg->gamma > 1.0) || !(cfg->c_ssp > 0.0)) return fail(c, DG_E_ARG, "bad gamma or c_ssp");
+    if (cfg->max_restarts < 0 || cfg->max_restarts > 60) return fail(c, DG_E_ARG, "bad max_restarts");
     return DG_OK;
 }
 
@@ -179,6 +180,7 @@ dg_status reset_glob(dg_ctx* c) {
     h.c_ssp = c->cfg.c_ssp;
     h.alpha = h.alpha_step = 0.0;
     h.active = 1;
+    h.max_restarts = c->cfg.max_restarts;
     HIP_TRY(c, hipMemcpyAsync(c->g, &h, sizeof(Glob), hipMemcpyHostToDevice, c->stream));
     return DG_OK;
 }
@@ -331,6 +333,7 @@ void dg_config_default(dg_config* cfg) {
     cfg->oe_mode = DG_OE_RI;
     cfg->bp_enable = 1;
     cfg->precision = DG_PREC_FP64;
+    cfg->max_restarts = 8;
 }
 
 dg_status dg_create(dg_ctx** out, int hip_device, void* hip_stream) {
@@ -546,14 +549,16 @@ dg_status dg_step_to(dg_ctx* c, double t_end, int64_t max_steps, int64_t* steps_
     if ((st = read_glob(c, &h)) != DG_OK) return st;
     const long long step0 = h.step;
     LAUNCH_TRY(c, oedg::launch_set_end(c->g, t_end, c->stream));
-    int64_t launched = 0;
+    // a launch either completes a step or retries it (at most max_restarts times
+    // per step), so counting completed steps terminates
+    int64_t completed = 0;
     int chunk = 4;
-    while (launched < max_steps) {
-        const int64_t n = std::min<int64_t>(chunk, max_steps - launched);
+    while (completed < max_steps) {
+        const int64_t n = std::min<int64_t>(chunk, max_steps - completed);
         for (int64_t i = 0; i < n; ++i)
             if ((st = run_step(c)) != DG_OK) return st;
-        launched += n;
         if ((st = read_glob(c, &h)) != DG_OK) return st;
+        completed = h.step - step0;
         if (!h.active || h.err) break;
         chunk = std::min(chunk * 2, 64);
     }
@@ -602,6 +607,7 @@ dg_status dg_diag(dg_ctx* c, dg_diag_t* out) {
     out->n_bad = h.n_bad;
     out->n_cfl_excursions = h.n_cfl_exc;
     out->n_flat = h.n_flat;
+    out->n_restarts = h.n_restarts;
     for (int v = 0; v < 4; ++v) {
         out->ubar[v] = h.ubar[v];
         out->nrm[v] = h.nrm[v];

@@ -399,8 +399,10 @@ __device__ __forceinline__ VarPtr<NM, T> var_ptr(const StateView& sv, const Stag
 // ------------------------------------------------------------------------- pass 1: residual
 
 // Reduces the lanes' (sum |K| ubar, min, max) over the workgroup, per variable, and
-// writes entry t = 4 k + v (k: sum, min, max) to dst[t * stride].
-__device__ __forceinline__ void residual_flush(double psum, double pmin, double pmax, double* dst, size_t stride) {
+// writes entry t = 4 k + v (k: sum, min, max) to dst[t * stride]; the count of
+// inadmissible averages goes to dst[kColBad * stride].
+__device__ __forceinline__ void residual_flush(double psum, double pmin, double pmax, double nbad, double* dst,
+                                               size_t stride) {
     // over the lanes holding the same variable (xor of lane ids >= 4), then waves
 #pragma unroll
     for (int o = 4; o < 64; o <<= 1) {
@@ -408,13 +410,16 @@ __device__ __forceinline__ void residual_flush(double psum, double pmin, double 
         pmin = fmin(pmin, __shfl_xor(pmin, o, 64));
         pmax = fmax(pmax, __shfl_xor(pmax, o, 64));
     }
+    nbad = wave_sum(nbad);
     __shared__ double lds[kBlock / 64][3][4];
+    __shared__ double lds_bad[kBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane < 4) {
         lds[wid][0][lane] = psum;
         lds[wid][1][lane] = pmin;
         lds[wid][2][lane] = pmax;
     }
+    if (lane == 0) lds_bad[wid] = nbad;
     __syncthreads();
     if (threadIdx.x < kNumPartial) {
         const int k = threadIdx.x >> 2, vv = threadIdx.x & 3;
@@ -424,6 +429,10 @@ __device__ __forceinline__ void residual_flush(double psum, double pmin, double 
             acc = k == 0 ? acc + x : (k == 1 ? fmin(acc, x) : fmax(acc, x));
         }
         dst[(size_t)threadIdx.x * stride] = acc;
+    } else if (threadIdx.x == kNumPartial) {
+        double acc = lds_bad[0];
+        for (int w2 = 1; w2 < kBlock / 64; ++w2) acc += lds_bad[w2];
+        dst[(size_t)kColBad * stride] = acc;
     }
 }
 
@@ -474,7 +483,7 @@ __device__ __forceinline__ void for_each_chunk(const StageArgs* desc, const Chun
     for (int ci = w.first; ci < w.end; ci += w.stride) {
         const Chunk ch = chunks[ci];
         const StageArgs& a = desc[ch.inst];
-        if (!a.g->active) continue;
+        if (!a.g->active || a.g->skip) continue;
         run(a, ch.g0, ch.g1);
     }
 }
@@ -505,7 +514,7 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
     const Tab<K, T>& TB = tab<K, T>();
 
     // one cell, owned by a quad of lanes: residual, SSP combination, partials
-    auto cell = [&](int c, double& psum, double& pmin, double& pmax) __attribute__((always_inline)) {
+    auto cell = [&](int c, double& psum, double& pmin, double& pmax, double& nbad) __attribute__((always_inline)) {
         const double ua = ua_p[c];
         T u[NM];
         u[0] = (T)ua;
@@ -589,6 +598,12 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
         const double adv0 = ua + dt * (r0 * ia * kInvMass[0]);
         const double w0 = a.stage == 0 ? adv0 : sa * u0a_p[c] + sb * adv0;
         wa_p[c] = w0;
+        if (a.bp_enable) {
+            // the OE filter and the limiter keep every average: an inadmissible one
+            // here ends the step's attempt (it is retried with half the time step)
+            const double q0 = qget<0>(w0), q1 = qget<1>(w0), q2 = qget<2>(w0), q3 = qget<3>(w0);
+            if (v == 0 && !(q0 > 0.0 && q3 - 0.5 * (q1 * q1 + q2 * q2) / q0 > 0.0)) nbad += 1.0;
+        }
         const T iaT = (T)ia, dtT = (T)dt, saT = (T)sa, sbT = (T)sb;
         T w[NM];
         w[0] = (T)w0;
@@ -607,22 +622,22 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
         }
     };
     if constexpr (!kBatch) {
-        double psum = 0.0, pmin = INFINITY, pmax = -INFINITY;
+        double psum = 0.0, pmin = INFINITY, pmax = -INFINITY, nbad = 0.0;
         const TileWalk tw = tile_walk((nc + kCellsPerTile - 1) / kCellsPerTile);
         for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
             const int c = tile * kCellsPerTile + (threadIdx.x >> 2);
-            if (c < nc) cell(c, psum, pmin, pmax);   // whole quad
+            if (c < nc) cell(c, psum, pmin, pmax, nbad);   // whole quad
         }
-        residual_flush(psum, pmin, pmax, a.part + blockIdx.x, kMaxBlocks);
+        residual_flush(psum, pmin, pmax, nbad, a.part + blockIdx.x, kMaxBlocks);
     } else {
         for (int gi = g0; gi < g1; ++gi) {
-            double psum = 0.0, pmin = INFINITY, pmax = -INFINITY;
+            double psum = 0.0, pmin = INFINITY, pmax = -INFINITY, nbad = 0.0;
 #pragma unroll 1
             for (int tile = 0; tile < kGroupCells / kCellsPerTile; ++tile) {
                 const int c = gi * kGroupCells + tile * kCellsPerTile + (threadIdx.x >> 2);
-                if (c < nc) cell(c, psum, pmin, pmax);
+                if (c < nc) cell(c, psum, pmin, pmax, nbad);
             }
-            residual_flush(psum, pmin, pmax, a.part + a.gbase + gi, a.gstride);
+            residual_flush(psum, pmin, pmax, nbad, a.part + a.gbase + gi, a.gstride);
             __syncthreads();   // the flush's LDS is reused by the next group
         }
     }
@@ -630,7 +645,7 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
 
 template <int K, typename T>
 __global__ __launch_bounds__(kBlock) void k_residual(StageArgs a) {
-    if (!a.g->active) return;
+    if (!a.g->active || a.g->skip) return;
     residual_run<K, T, false>(a, 0, 0);
 }
 // KM: degrees present in the launch (1: P1, 2: P2, 3: both)
@@ -700,7 +715,7 @@ __device__ __forceinline__ void mnorm_run(const StageArgs& a, int g0, int g1) {
 
 template <int K, typename T>
 __global__ __launch_bounds__(kBlock) void k_mnorm(StageArgs a) {
-    if (!a.g->active) return;
+    if (!a.g->active || a.g->skip) return;
     mnorm_run<K, T, false>(a, 0, 0);
 }
 template <int KM, typename T>
@@ -1083,7 +1098,7 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
 // three waves per SIMD: the allocator then keeps the P2 instantiations within 168 VGPRs
 template <int K, typename T>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_filter(StageArgs a) {
-    if (!a.g->active) return;
+    if (!a.g->active || a.g->skip) return;
     filter_run<K, T, false>(a, 0, 0);
 }
 // (no occupancy request: with the chunk indirection a 168-VGPR budget spills)
@@ -1144,10 +1159,14 @@ __device__ __forceinline__ void reduce_columns(const double* base, size_t cstrid
 }
 
 // domain averages and L-infinity norms (eq. normOmg): ||u - ubar|| = max(max u - ubar, ubar - min u)
+// An inadmissible average ends this attempt of the step: `skip` turns the rest
+// of it into no-ops (u^n is untouched) until the third stage's finalize.
 __device__ __forceinline__ void fin_residual(const double* base, size_t cstride, int G, Glob* g) {
-    double tot[kNumPartial];
+    double tot[kNumPartial], bad[1];
     reduce_columns<kNumPartial>(base, cstride, G, 0, 0xAA5500u, tot);   // 4 sums, 4 mins, 4 maxima
+    reduce_columns<1>(base, cstride, G, kColBad, 0u, bad);
     if (threadIdx.x == 0) {
+        if (bad[0] > 0.0) g->skip = 1;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const double ub = tot[v] / g->area_sum;
@@ -1160,6 +1179,7 @@ __device__ __forceinline__ void fin_residual(const double* base, size_t cstride,
 }
 
 __device__ __forceinline__ void fin_mnorm(const double* base, size_t cstride, int G, Glob* g) {
+    if (g->skip) return;
     double best[1];
     reduce_columns<1>(base, cstride, G, kNumPartial, 2u, best);
     if (threadIdx.x == 0) {
@@ -1171,8 +1191,26 @@ __device__ __forceinline__ void fin_mnorm(const double* base, size_t cstride, in
 }
 
 // alpha of the stage output; after the third stage (or the initial limiter pass)
-// t, the step count and Delta t = C_SSP/alpha min_K C^DCW_{K,k}|K|, clamped to t_end
+// t, the step count and Delta t = C_SSP/alpha min_K C^DCW_{K,k}|K|, clamped to t_end.
+// After the third stage of a skipped attempt: the step is retried from u^n with
+// half the time step, or the run stops once max_restarts retries are used.
 __device__ __forceinline__ void fin_filter(const double* base, size_t cstride, int G, Glob* g, int stage) {
+    const int skip = g->skip;
+    __syncthreads();   // every thread has read `skip` before thread 0 may clear it
+    if (skip) {
+        if (threadIdx.x == 0 && stage == 2) {
+            g->skip = 0;
+            if (++g->restarts > g->max_restarts) {
+                g->err = 1;
+                g->active = 0;
+            } else {
+                g->dt *= 0.5;
+                g->alpha = g->alpha_step;   // the retry's first stage starts from u^n again
+                g->n_restarts += 1;
+            }
+        }
+        return;
+    }
     double r[4];
     reduce_columns<4>(base, cstride, G, kNumPartial + 1, 2u, r);   // max, then three sums
     if (threadIdx.x != 0) return;
@@ -1190,6 +1228,7 @@ __device__ __forceinline__ void fin_filter(const double* base, size_t cstride, i
         g->step += 1;
         g->alpha = alpha;
         g->alpha_step = alpha;
+        g->restarts = 0;
     }
     if (stage < 0 || stage == 2) {
         double dt = g->c_ssp * g->minck / alpha;

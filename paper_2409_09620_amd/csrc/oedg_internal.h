@@ -13,7 +13,8 @@ constexpr int kCellsPerTileScalar = 256;   // one lane per cell in the momentum-
 constexpr int kMaxBlocks = 4096;       // upper bound of a single-instance pass grid (= partials)
 constexpr int kGroupCells = 256;       // cells per reduction group of the batched passes
 constexpr int kNumPartial = 12;        // partials of the residual pass per group
-constexpr int kPartCols = kNumPartial + 1 + 4;   // + momentum norm + 4 filter partials
+constexpr int kPartCols = kNumPartial + 1 + 4 + 1;   // + momentum norm, 4 filter partials, bad averages
+constexpr int kColBad = kPartCols - 1;   // residual pass: cells whose average left the admissible set
 
 // Reduction groups of an instance in the batched passes: cells [g * kGroupCells,
 // (g + 1) * kGroupCells).  Every group writes its own partial record, so an
@@ -63,6 +64,10 @@ struct Glob {
     long long n_bad;
     long long n_cfl_exc;
     long long n_flat;    // mixed precision: cells reset to their average by the rounding check
+    long long n_restarts;   // steps retried with half the time step
+    int skip;            // a stage of this step left the admissible set: the rest of the step is skipped
+    int restarts;        // retries of the current step so far
+    int max_restarts;
     int active;          // 0: t reached t_end, or an error stopped the run
     int err;             // sticky: 1 once a cell average left the admissible set
 };
