@@ -151,7 +151,6 @@ struct Tab {
     T vp[NQ][NM], vdx[NQ][NM], vde[NQ][NM];   // volume points: Psi, dPsi/dxi, dPsi/deta
     T vw[NQ];                                 // volume weights
     T ep[3 * NE][NM];                         // own edge Gauss points (edge i, node nu)
-    T vtp[3][NM], vtdx[3][NM], vtde[3][NM];   // reference vertices
 };
 
 template <typename T>
@@ -184,8 +183,6 @@ constexpr Tab<K, T> make_tab() {
             const double e = i == 0 ? s : (i == 1 ? 1.0 - s : 0.0);
             basis_at<T>(R::NM, x, e, t.ep[i * R::NE + nu], scratch, scratch2);
         }
-    for (int vtx = 0; vtx < 3; ++vtx)
-        basis_at<T>(R::NM, vtx == 1 ? 1.0 : 0.0, vtx == 2 ? 1.0 : 0.0, t.vtp[vtx], t.vtdx[vtx], t.vtde[vtx]);
     return t;
 }
 
@@ -271,17 +268,19 @@ struct Fp<float> {
 
 // ------------------------------------------------------------------------- quad exchanges
 
-// DPP quad_perm move: lane q of every quad receives lane perm[q]'s value
+// DPP quad_perm move: lane q of every quad receives lane perm[q]'s value (every
+// source lane of a quad permutation exists, so the destination's old value is
+// never kept and needs no initialisation)
 template <int CTRL>
 __device__ __forceinline__ double qperm(double x) {
     const long long b = __builtin_bit_cast(long long, x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
 }
 template <int CTRL>
 __device__ __forceinline__ float qperm(float x) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, true));
 }
 template <int L, typename T>
 __device__ __forceinline__ T qget(T x) { return qperm<L * 0x55>(x); }   // broadcast lane L
@@ -301,24 +300,24 @@ __device__ __forceinline__ T qmin(T x) {
     x = fmin(x, qxor1(x));
     return fmin(x, qxor2(x));
 }
-template <typename T>
-__device__ __forceinline__ T sel4(int v, T a0, T a1, T a2, T a3) {
-    return v == 0 ? a0 : (v == 1 ? a1 : (v == 2 ? a2 : a3));
-}
-// 4x4 transpose inside a quad: lane w holds x[c] = (its variable w at state c);
-// on return q[w] = variable w at state v, where v is the calling lane
+// 4x4 transpose inside a quad through LDS: lane w holds x[c] = (its variable w at
+// state c); on return q[w] = variable w at state v, where v is the calling lane.
+// Each lane stores its four entries and reads the four it needs (8 LDS operations
+// instead of three quad rotations and their select chains).
+// Layout [entry][thread] keeps both the stores and the loads free of bank
+// conflicts; LDS executes a wave's operations in order, and the wave barriers keep
+// the compiler from moving the loads above the stores or the next stores above
+// these loads.
 template <typename T>
 __device__ __forceinline__ void quad_transpose(int v, const T (&x)[4], T (&q)[4]) {
-    // round k: lane v reads lane (v+k)&3, which offers its entry (owner - k)&3 = v
-    const T r0 = sel4(v, x[0], x[1], x[2], x[3]);
-    const T r1 = qperm<0x39>(sel4(v, x[3], x[0], x[1], x[2]));   // rotate by 1: [1,2,3,0]
-    const T r2 = qperm<0x4E>(sel4(v, x[2], x[3], x[0], x[1]));   // rotate by 2: [2,3,0,1]
-    const T r3 = qperm<0x93>(sel4(v, x[1], x[2], x[3], x[0]));   // rotate by 3: [3,0,1,2]
-    // r_k is variable (v+k)&3
-    q[0] = sel4(v, r0, r3, r2, r1);
-    q[1] = sel4(v, r1, r0, r3, r2);
-    q[2] = sel4(v, r2, r1, r0, r3);
-    q[3] = sel4(v, r3, r2, r1, r0);
+    __shared__ T buf[4][kBlock];
+    const int t = threadIdx.x, quad = t & ~3;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) buf[c][t] = x[c];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int w = 0; w < 4; ++w) q[w] = buf[v][quad + w];
+    __builtin_amdgcn_wave_barrier();
 }
 
 // ------------------------------------------------------------------------- Euler
@@ -851,7 +850,12 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
             for (int jj = 0; jj <= K; ++jj) sig[jj] = (T)0.0;
             T ho[3] = {(T)0.0, (T)0.0, (T)0.0};
             if constexpr (K == 2) hessian(w, xx, xy, ex, ey, ho);
-#pragma unroll 1
+            // own value (higher modes) and reference gradient at the three vertices
+            T oh[3], ox[3], oe[3];
+#pragma unroll
+            for (int vt = 0; vt < 3; ++vt)
+                vertex_eval<K, T>(w, vt == 1 ? (T)1.0 : (T)0.0, vt == 2 ? (T)1.0 : (T)0.0, oh[vt], ox[vt], oe[vt]);
+#pragma unroll
             for (int i = 0; i < 3; ++i) {
                 const int link = a.m.link[i * snc + c];
                 if (link < 0) continue;   // transmissive boundary: zero jump (whole quad)
@@ -881,18 +885,16 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
                     // the neighbour's vertex nv, a per-lane index: closed form
                     T rh, tx, te;
                     vertex_eval<K, T>(wn, nv == 1 ? (T)1.0 : (T)0.0, nv == 2 ? (T)1.0 : (T)0.0, rh, tx, te);
+                    const T qh = oh[ov];
+                    q = w[0] + qh;
+                    r = wn[0] + rh;
                     if constexpr (kMixed) {
                         // value jump from the FP64 averages plus the float higher modes
-                        const T qh = dot_hi<NM>(w, TB.vtp[ov]);
-                        q = w[0] + qh;
-                        r = wn[0] + rh;
                         jv = (T)(wna - wa) + (rh - qh);
                     } else {
-                        q = dot<NM>(w, TB.vtp[ov]);
-                        r = wn[0] + rh;
                         jv = r - q;
                     }
-                    const T sx = dot<NM>(w, TB.vtdx[ov]), se = dot<NM>(w, TB.vtde[ov]);
+                    const T sx = ox[ov], se = oe[ov];
                     const T qx = sx * xx + se * ex, qy = sx * xy + se * ey;
                     const T rx = tx * nxx + te * nex, ry = tx * nxy + te * ney;
                     xs[2 * end] = q;
