@@ -106,20 +106,6 @@ __device__ __forceinline__ void edge_point(int i, double s, double& x, double& e
     e = i == 0 ? s : (i == 1 ? 1.0 - s : 0.0);
 }
 
-// Basis values at a point that differs between lanes, computed in the bulk type
-// (a table row picked by a per-lane index would cost a select per entry).
-template <int K, typename T>
-__device__ __forceinline__ void psi_at(T x, T e, T* p) {
-    p[0] = (T)1.0;
-    p[1] = (T)4.0 * x + (T)2.0 * e - (T)2.0;
-    p[2] = (T)3.0 * e - (T)1.0;
-    if constexpr (K == 2) {
-        p[3] = (T)24.0 * x * x + (T)24.0 * x * e + (T)4.0 * e * e - (T)24.0 * x - (T)8.0 * e + (T)4.0;
-        p[4] = (T)20.0 * x * e + (T)10.0 * e * e - (T)4.0 * x - (T)12.0 * e + (T)2.0;
-        p[5] = (T)10.0 * e * e - (T)8.0 * e + (T)1.0;
-    }
-}
-
 // At the reference vertices (0,0), (1,0), (0,1) every basis function and its
 // first derivatives are affine in the vertex's coordinates (sx, se) (there
 // x^2 = x, e^2 = e, xe = 0).  Returns sum_{l>=1} u_l Psi_l and the reference
@@ -143,6 +129,31 @@ __device__ __forceinline__ void vertex_eval(const T* u, T sx, T se, T& qh, T& dx
     }
 }
 
+// The restriction of sum_l u_l Psi_l to local edge j (from vertex j+1 to vertex
+// j+2, parameter s in [0, 1]) has degree K in s, so it is the Lagrange
+// interpolant of its values at the edge's ends (q0 at s = 0, q1 at s = 1) and,
+// for K = 2, its midpoint (qm).  The midpoints (1/2,1/2), (0,1/2), (1/2,0) of
+// edges 0, 1, 2 give affine forms in the indicators i1 = [j==1], i2 = [j==2].
+template <int K, typename T>
+__device__ __forceinline__ void edge_trace_nodes(const T* u, int j, T& q0, T& qm, T& q1) {
+    const int sv = j == 2 ? 0 : j + 1, ev = j == 0 ? 2 : j - 1;   // (j+1) % 3, (j+2) % 3
+    T qh0, qh1, dx, de;
+    vertex_eval<K, T>(u, sv == 1 ? (T)1.0 : (T)0.0, sv == 2 ? (T)1.0 : (T)0.0, qh0, dx, de);
+    vertex_eval<K, T>(u, ev == 1 ? (T)1.0 : (T)0.0, ev == 2 ? (T)1.0 : (T)0.0, qh1, dx, de);
+    q0 = u[0] + qh0;
+    q1 = u[0] + qh1;
+    qm = (T)0.0;
+    if constexpr (K == 2) {
+        // Psi_1..5 at the midpoints: edge 0 (1, 1/2, 1, 3/2, -1/2), edge 1 (-1, 1/2,
+        // 1, -3/2, -1/2), edge 2 (0, -1, -2, 0, 1)
+        const T i1 = j == 1 ? (T)1.0 : (T)0.0, i2 = j == 2 ? (T)1.0 : (T)0.0;
+        const T m0 = u[0] + u[1] + (T)0.5 * u[2] + u[3] + (T)1.5 * u[4] - (T)0.5 * u[5];
+        const T m1 = (T)-2.0 * u[1] - (T)3.0 * u[4];
+        const T m2 = -u[1] - (T)1.5 * u[2] - (T)3.0 * u[3] - (T)1.5 * u[4] + (T)1.5 * u[5];
+        qm = fma(i1, m1, fma(i2, m2, m0));
+    }
+}
+
 // Basis values at the fixed points of a stage, in constant memory: the point loops
 // run with a wave-uniform index, so these become scalar loads instead of registers.
 template <int K, typename T>
@@ -151,6 +162,8 @@ struct Tab {
     T vp[NQ][NM], vdx[NQ][NM], vde[NQ][NM];   // volume points: Psi, dPsi/dxi, dPsi/deta
     T vw[NQ];                                 // volume weights
     T ep[3 * NE][NM];                         // own edge Gauss points (edge i, node nu)
+    T nbw[NE][3];   // Lagrange weights (end 0, midpoint, end 1) of the neighbour's trace at its
+                    // parameter 1 - s_nu = s_{NE-1-nu}
 };
 
 template <typename T>
@@ -183,6 +196,12 @@ constexpr Tab<K, T> make_tab() {
             const double e = i == 0 ? s : (i == 1 ? 1.0 - s : 0.0);
             basis_at<T>(R::NM, x, e, t.ep[i * R::NE + nu], scratch, scratch2);
         }
+    for (int nu = 0; nu < R::NE; ++nu) {
+        const double s = R::s[R::NE - 1 - nu];
+        t.nbw[nu][0] = (T)(K == 2 ? (1.0 - s) * (1.0 - 2.0 * s) : 1.0 - s);
+        t.nbw[nu][1] = (T)(K == 2 ? 4.0 * s * (1.0 - s) : 0.0);
+        t.nbw[nu][2] = (T)(K == 2 ? s * (2.0 * s - 1.0) : s);
+    }
     return t;
 }
 
@@ -562,9 +581,9 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
             un[0] = (T)ua_p[nb];
 #pragma unroll
             for (int l = 1; l < NM; ++l) un[l] = uh_p[(l - 1) * snc + nb];
-            // the neighbour's local edge j as (x0 + xd s, e0 + ed s) in its reference frame
-            const T x0 = j == 0 ? (T)1.0 : (T)0.0, xd = j == 0 ? (T)-1.0 : (j == 2 ? (T)1.0 : (T)0.0);
-            const T e0 = j == 1 ? (T)1.0 : (T)0.0, ed = j == 0 ? (T)1.0 : (j == 1 ? (T)-1.0 : (T)0.0);
+            // the neighbour's trace along its local edge j, from its ends and midpoint
+            T n0 = (T)0.0, nm = (T)0.0, n1 = (T)0.0;
+            if (has) edge_trace_nodes<K, T>(un, j, n0, nm, n1);
 #pragma unroll 1
             for (int nu = 0; nu < R::NE; ++nu) {
                 const T* p = TB.ep[i * R::NE + nu];
@@ -574,11 +593,8 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
                 if (has) {
                     // the neighbour runs the shared edge the other way: its parameter is
                     // 1 - s_nu = s_{NE-1-nu} (symmetric Gauss nodes)
-                    const int mu = R::NE - 1 - nu;
-                    const T sn = (T)(mu == 0 ? R::s[0] : (mu == 1 ? R::s[1] : R::s[2]));
-                    T pn[NM];
-                    psi_at<K, T>(fma(xd, sn, x0), fma(ed, sn, e0), pn);
-                    qe = dot<NM>(un, pn);
+                    const T* lw = TB.nbw[nu];
+                    qe = fma(lw[0], n0, fma(lw[1], nm, lw[2] * n1));
                 }
                 const T fi = lane_flux(qi, qget<0>(qi), qget<1>(qi), qget<2>(qi), qget<3>(qi), lnx, lny, gm1,
                                        s1, s2, s3);
