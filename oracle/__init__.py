@@ -66,6 +66,8 @@ def lib():
             "orc_basis": (None, [_D, _D, _P, _P, _P]),
             "orc_quadrature": (_I, [_I, _P, _P]),
             "orc_decompose": (_I, [_I, _P, _P, _P, _P, _P, _P]),
+            "orc_set_bc": (_I, [_P, _P]),
+            "orc_set_decomp": (_I, [_P, _I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -87,7 +89,12 @@ SCALARS = ["t", "dt", "alpha", "step", "active", "err", "n_limited", "minck",
 class Oracle:
     """One mesh and state in the FP64 oracle."""
 
-    def __init__(self, mesh, k, gamma=1.4, cssp=1.0, oe=True, bp=True, oe_mode=0, max_restarts=8):
+    def __init__(self, mesh, k, gamma=1.4, cssp=1.0, oe=True, bp=True, oe_mode=0, max_restarts=8,
+                 decomposition="dcw", edge_bc=None):
+        """decomposition: "dcw" (the optimal one) or "zxs" (the classical one) for the
+        limiter and Delta t; edge_bc: (n_cell, 3) tags of boundary edges, the edge
+        opposite input vertex i (0 transmissive, 1 reflective), default from
+        mesh.edge_bc."""
         self.k = int(k)
         self.nm = (k + 1) * (k + 2) // 2
         self.nc = mesh.n_cell
@@ -100,6 +107,15 @@ class Oracle:
         self.h = h
         lib().orc_config(h, gamma, cssp, int(oe), int(bp), int(oe_mode))
         lib().orc_set_max_restarts(h, int(max_restarts))
+        if edge_bc is None:
+            edge_bc = getattr(mesh, "edge_bc", None)
+        if edge_bc is not None:
+            bc = np.ascontiguousarray(edge_bc, dtype=np.int32).reshape(self.nc, 3)
+            if lib().orc_set_bc(h, _ptr(bc)) != 0:
+                raise ValueError("oracle: boundary tags must be 0 or 1")
+        if decomposition not in ("dcw", "zxs"):
+            raise ValueError("decomposition is 'dcw' or 'zxs'")
+        lib().orc_set_decomp(h, 1 if decomposition == "zxs" else 0)
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -18,6 +18,9 @@
  *   optimal convex decomposition ............. eq. 1040 (P1), eq. 1139 with eq. 1703 (P2)
  *   BP limiter ............................... Sec. 4.4, eqs. 1944 and 1981
  *   BP time step ............................. Sec. 5 (Delta t with C^DCW), eqs. 1692, 1713
+ *   classical decomposition (comparison) ..... Sec. 4.2 (Zhang-Xia-Shu weights), the ZXS CFL
+ *                                              remarks after eqs. 1692 and 1713, Sec. 4.4
+ *                                              (classical branch of the limiter), Sec. 6 Delta t
  *
  * Readings of points the paper leaves open (they are listed in the design notes):
  *   - edge Gauss nodes on [0,1] as s = (1 + x^nu)/2, weights summing to one (App. B);
@@ -27,7 +30,12 @@
  *   - beta^(i) uses a guarded spectral radius: rho_s = max(rho, 1e-13), p from rho_s,
  *     sqrt(gamma max(p,0)/rho_s);
  *   - jumps are the neighbour's trace minus the own trace at the same physical
- *     point; on a boundary (transmissive) edge the jump is zero;
+ *     point; on a boundary edge (transmissive or reflective) the jump is zero;
+ *   - boundary edges: transmissive (exterior trace = interior trace) or reflective
+ *     (exterior trace = interior trace with its normal momentum reversed);
+ *   - classical decomposition: the limiter takes the edge Gauss points (P1) or the
+ *     edge Gauss points and the vector u* of Sec. 4.4's classical branch, with the
+ *     Zhang-Xia-Shu edge weights 2 w1^GL / 3 (P2); its energy bound is E(u*);
  *   - m_n, m_t on both sides use K's own normal n^(i);
  *   - limiter node form: the min runs over the 3Q edge Gauss points plus the P1
  *     vertices v1, v2 (eq. 1944) or the two P2 internal nodes of eq. 1139; the
@@ -143,8 +151,12 @@ typedef struct {
     int* perm;                     /* nc*3 local edges sorted by length, descending, stable */
     int* limv;                     /* nc*2 P1: local vertices opposite the two longest edges */
     double* node;                  /* nc*4 P2: internal nodes (x1,y1,x2,y2) */
-    double* ck;                    /* nc: C^DCW_{K,k} |K| */
-    double minck, area_sum;
+    double* ck;                    /* nc: C_{K,k} |K| of the active decomposition */
+    double *ck_dcw, *ck_zxs;       /* nc: C^DCW_{K,k} |K| and C^ZXS_{K,k} |K| */
+    double minck, minck_dcw, minck_zxs, area_sum;
+    int* bc;                       /* nc*3: boundary tag of unmatched edges, 0 transmissive, 1 reflective */
+    unsigned char* swapped;        /* nc: input vertices 1 and 2 were swapped to orient the cell */
+    int zxs;                       /* 1: classical (Zhang-Xia-Shu) decomposition: limiter and Delta t */
     /* configuration */
     double gamma, cssp, eps_oe, eps_bp;
     int oe_on, bp_on, oe_mode;     /* oe_mode 0 = rotation invariant, 1 = component-wise */
@@ -340,7 +352,7 @@ void orc_destroy(Orc* o) {
     if (!o) return;
     free(o->tri); free(o->vx); free(o->nbr); free(o->nbe); free(o->area); free(o->len);
     free(o->nrm); free(o->jinv); free(o->mass); free(o->perm); free(o->limv); free(o->node);
-    free(o->ck); free(o->u0); free(o->u); free(o->w); free(o->L); free(o->pre);
+    free(o->ck); free(o->ck_dcw); free(o->ck_zxs); free(o->bc); free(o->swapped); free(o->u0); free(o->u); free(o->w); free(o->L); free(o->pre);
     free(o);
 }
 
@@ -376,6 +388,10 @@ Orc* orc_create(int k, int nv, const double* xy, int nc, const int* tri_in, cons
     o->limv = (int*)xcalloc((size_t)nc * 2, sizeof(int));
     o->node = (double*)xcalloc((size_t)nc * 4, sizeof(double));
     o->ck = (double*)xcalloc(nc, sizeof(double));
+    o->ck_dcw = (double*)xcalloc(nc, sizeof(double));
+    o->ck_zxs = (double*)xcalloc(nc, sizeof(double));
+    o->bc = (int*)xcalloc((size_t)nc * 3, sizeof(int));
+    o->swapped = (unsigned char*)xcalloc(nc, 1);
     const size_t ns = (size_t)nc * NVAR * o->nm;
     o->u0 = (double*)xcalloc(ns, sizeof(double));
     o->u = (double*)xcalloc(ns, sizeof(double));
@@ -396,6 +412,7 @@ Orc* orc_create(int k, int nv, const double* xy, int nc, const int* tri_in, cons
         const double det = (v[2] - v[0]) * (v[5] - v[1]) - (v[4] - v[0]) * (v[3] - v[1]);
         if (det == 0.0) { orc_destroy(o); return NULL; }
         if (det < 0) {  /* swap vertices 1 and 2 */
+            o->swapped[c] = 1;
             int ti = id[1]; id[1] = id[2]; id[2] = ti;
             double tx = v[2], ty = v[3];
             v[2] = v[4]; v[3] = v[5]; v[4] = tx; v[5] = ty;
@@ -433,7 +450,7 @@ Orc* orc_create(int k, int nv, const double* xy, int nc, const int* tri_in, cons
     free(E);
 
     /* geometry: |K|, lengths, outward normals, J^{-1}; decomposition; mass */
-    o->minck = INFINITY;
+    o->minck_dcw = o->minck_zxs = INFINITY;
     o->area_sum = 0;
     for (int c = 0; c < nc; ++c) {
         const double* v = o->vx + 6 * c;
@@ -455,8 +472,13 @@ Orc* orc_create(int k, int nv, const double* xy, int nc, const int* tri_in, cons
         }
         double wts[3], nw[2], cd;
         decompose(k, v, o->len + 3 * c, o->perm + 3 * c, o->limv + 2 * c, o->node + 4 * c, wts, nw, &cd);
-        o->ck[c] = cd * o->area[c];
-        if (o->ck[c] < o->minck) o->minck = o->ck[c];
+        o->ck_dcw[c] = cd * o->area[c];
+        if (o->ck_dcw[c] < o->minck_dcw) o->minck_dcw = o->ck_dcw[c];
+        /* classical decomposition: C^ZXS = 1/(9 lbar) (P1), 1/(27 lbar) (P2), lbar the
+         * mean edge length (remarks after eqs. 1692 and 1713) */
+        const double lbar = (o->len[3 * c] + o->len[3 * c + 1] + o->len[3 * c + 2]) / 3.0;
+        o->ck_zxs[c] = o->area[c] / ((k == 1 ? 9.0 : 27.0) * lbar);
+        if (o->ck_zxs[c] < o->minck_zxs) o->minck_zxs = o->ck_zxs[c];
         /* a_K^(l) = int_K Psi_l^2, exact with the degree-4 rule */
         for (int l = 0; l < o->nm; ++l) {
             double s = 0;
@@ -468,8 +490,36 @@ Orc* orc_create(int k, int nv, const double* xy, int nc, const int* tri_in, cons
             o->mass[(size_t)c * o->nm + l] = o->area[c] * s;
         }
     }
+    memcpy(o->ck, o->ck_dcw, sizeof(double) * nc);
+    o->minck = o->minck_dcw;
     o->active = 1;
     return o;
+}
+
+/* boundary tags of the unmatched edges: tags[3c+i] for the edge of cell c opposite
+ * its input vertex i (entries of matched edges are ignored); 0 transmissive,
+ * 1 reflective.  Orienting a cell swaps its vertices 1 and 2, and so its edges 1
+ * and 2. */
+int orc_set_bc(Orc* o, const int* tags) {
+    for (int c = 0; c < o->nc; ++c)
+        for (int i = 0; i < 3; ++i) {
+            const int in = o->swapped[c] && i > 0 ? 3 - i : i;
+            const int t = tags ? tags[3 * c + in] : 0;
+            if (o->nbr[3 * c + i] >= 0) { o->bc[3 * c + i] = 0; continue; }
+            if (t != 0 && t != 1) return -1;
+            o->bc[3 * c + i] = t;
+        }
+    return 0;
+}
+
+/* 0: the optimal decomposition (DCW), 1: the classical one (ZXS), for the limiter
+ * and the time step; call before the initial state is set */
+int orc_set_decomp(Orc* o, int zxs) {
+    if (zxs != 0 && zxs != 1) return -1;
+    o->zxs = zxs;
+    memcpy(o->ck, zxs ? o->ck_zxs : o->ck_dcw, sizeof(double) * o->nc);
+    o->minck = zxs ? o->minck_zxs : o->minck_dcw;
+    return 0;
 }
 
 int orc_export_mesh(const Orc* o, int* tri, int* nbr, int* nbe, int* perm, int* limv, double* area,
@@ -548,6 +598,13 @@ static void residual(Orc* o, const double* arr, double alpha, double* Lout) {
                     const double xn = vn[2 * qa] + s * (vn[2 * qb] - vn[2 * qa]);
                     const double yn = vn[2 * qa + 1] + s * (vn[2 * qb + 1] - vn[2 * qa + 1]);
                     eval_at_xy(o, arr, nb, xn, yn, qe);
+                } else if (o->bc[3 * c + i] == 1) {
+                    /* reflective wall: the normal momentum reversed */
+                    const double mn = qi[1] * n[0] + qi[2] * n[1];
+                    qe[0] = qi[0];
+                    qe[1] = qi[1] - 2.0 * mn * n[0];
+                    qe[2] = qi[2] - 2.0 * mn * n[1];
+                    qe[3] = qi[3];
                 } else {
                     for (int v = 0; v < NVAR; ++v) qe[v] = qi[v];
                 }
@@ -638,7 +695,7 @@ static void oe_filter(Orc* o, double* arr, double dt) {
         memset(sigma, 0, sizeof(sigma));
         for (int i = 0; i < 3; ++i) {
             const int nb = o->nbr[3 * c + i];
-            if (nb < 0) continue;   /* transmissive boundary: zero jump */
+            if (nb < 0) continue;   /* boundary edge (transmissive or reflective): zero jump */
             const int la = (i + 1) % 3, lb = (i + 2) % 3;
             const int qa = local_vertex(o, nb, o->tri[3 * c + la]);
             const int qb = local_vertex(o, nb, o->tri[3 * c + lb]);
@@ -713,8 +770,9 @@ static void oe_filter(Orc* o, double* arr, double dt) {
 
 /* ----------------------------------------------------------------------- BP limiter (Sec. 4.4) */
 
-/* physical points of the limiter's node set: 3Q edge Gauss points, then the P1
- * vertices v1, v2 (eq. 1944) or the two P2 internal nodes (eq. 1139) */
+/* physical points of the optimal decomposition's limiter node set: 3Q edge Gauss
+ * points, then the P1 vertices v1, v2 (eq. 1944) or the two P2 internal nodes
+ * (eq. 1139) */
 static int limiter_points(const Orc* o, int c, double* px, double* py) {
     const int Q = o->ne;
     const double* vc = o->vx + 6 * c;
@@ -746,35 +804,58 @@ static int limiter_points(const Orc* o, int c, double* px, double* py) {
     return n;
 }
 
+/* The state at the limiter's node set of cell c, q[t][v], t < 3Q + 2.
+ * Optimal decomposition: the points above.  Classical decomposition (Sec. 4.4,
+ * classical branch): the 3Q edge Gauss points, then for P2 the vector
+ *   u* = (ubar - sum_i w_i sum_nu w^G_nu u(x_i,nu)) / (1 - sum_i w_i),
+ * w_i = 2 w1^GL / 3 with w1^GL = 1/(L(L-1)), L = ceil((k+3)/2) (Sec. 4.2), the
+ * average of the internal nodes of that decomposition; P1 has no internal nodes
+ * (sum_i w_i = 1).  The two trailing entries repeat edge points 0 and 1 (P1) or
+ * hold u* twice (P2), which leaves every minimum unchanged. */
+static int limiter_values(const Orc* o, const double* arr, int c, double q[12][NVAR]) {
+    double px[12], py[12];
+    const int n = limiter_points(o, c, px, py), ne = 3 * o->ne;
+    for (int t = 0; t < (o->zxs ? ne : n); ++t) eval_at_xy(o, arr, c, px[t], py[t], q[t]);
+    if (!o->zxs) return n;
+    if (o->k == 1) {
+        for (int v = 0; v < NVAR; ++v) { q[ne][v] = q[0][v]; q[ne + 1][v] = q[1][v]; }
+        return n;
+    }
+    const int L = (o->k + 4) / 2;   /* ceil((k+3)/2) */
+    const double w1 = 1.0 / (L * (L - 1)), wi = 2.0 * w1 / 3.0;
+    double acc[NVAR] = {0, 0, 0, 0};
+    for (int i = 0; i < 3; ++i)
+        for (int g = 0; g < o->ne; ++g)
+            for (int v = 0; v < NVAR; ++v) acc[v] += wi * GW[o->ne][g] * q[i * o->ne + g][v];
+    for (int v = 0; v < NVAR; ++v) {
+        const double us = (U(arr, c, v, 0) - acc[v]) / (1.0 - 3.0 * wi);
+        q[ne][v] = q[ne + 1][v] = us;
+    }
+    return n;
+}
+
 /* returns the number of cells whose average is not admissible */
 static int bp_limit(Orc* o, double* arr) {
     int bad = 0;
     for (int c = 0; c < o->nc; ++c) {
-        double px[12], py[12];
-        const int np = limiter_points(o, c, px, py);
+        double q[12][NVAR];
         /* step 1: density */
+        const int np = limiter_values(o, arr, c, q);
         const double rb = U(arr, c, 0, 0);
         double rmin = INFINITY;
-        for (int t = 0; t < np; ++t) {
-            double q[NVAR];
-            eval_at_xy(o, arr, c, px[t], py[t], q);
-            rmin = fmin(rmin, q[0]);
-        }
+        for (int t = 0; t < np; ++t) rmin = fmin(rmin, q[t][0]);
         const double e1 = fmin(rb, o->eps_bp);
         double th1 = 1.0;
         if (!(rmin >= e1)) th1 = fmin((rb - e1) / (rb - rmin), 1.0);
         for (int l = 1; l < o->nm; ++l) U(arr, c, 0, l) *= th1;
-        /* step 2: internal energy E - |m|^2/(2 rho) */
+        /* step 2: internal energy E - |m|^2/(2 rho) of the density-limited state */
         double ub[NVAR];
         for (int v = 0; v < NVAR; ++v) ub[v] = U(arr, c, v, 0);
         const double eb = int_energy(ub);
         const double e2 = fmin(eb, o->eps_bp);
+        limiter_values(o, arr, c, q);
         double emin = INFINITY;
-        for (int t = 0; t < np; ++t) {
-            double q[NVAR];
-            eval_at_xy(o, arr, c, px[t], py[t], q);
-            emin = fmin(emin, int_energy(q));
-        }
+        for (int t = 0; t < np; ++t) emin = fmin(emin, int_energy(q[t]));
         double th2 = 1.0;
         if (!(emin >= e2)) th2 = fmin((eb - e2) / (eb - emin), 1.0);
         for (int v = 0; v < NVAR; ++v)
@@ -1040,9 +1121,10 @@ int orc_limiter_node_values(Orc* o, const double* in, double* out) {
     from_soa(o, in, o->w);
     const int npt = o->k == 1 ? 8 : 11;
     for (int c = 0; c < o->nc; ++c) {
-        double px[12], py[12];
-        limiter_points(o, c, px, py);
-        for (int t = 0; t < npt; ++t) eval_at_xy(o, o->w, c, px[t], py[t], out + ((size_t)c * npt + t) * NVAR);
+        double q[12][NVAR];
+        limiter_values(o, o->w, c, q);
+        for (int t = 0; t < npt; ++t)
+            for (int v = 0; v < NVAR; ++v) out[((size_t)c * npt + t) * NVAR + v] = q[t][v];
     }
     return npt;
 }

@@ -28,6 +28,8 @@ class Mesh:
     tri: np.ndarray                 # (n_cell, 3) int32 vertex ids, CCW
     cell_xy: Optional[np.ndarray] = None   # (n_cell, 6) unwrapped coords (periodic only)
     periodic: bool = False
+    edge_bc: Optional[np.ndarray] = None   # (n_cell, 3) int32 tags of boundary edges (edge opposite vertex i):
+                                           # 0 transmissive, 1 reflective; None: all transmissive
     name: str = ""
     meta: dict = field(default_factory=dict)
 

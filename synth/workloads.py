@@ -8,6 +8,9 @@
 * batch_instances    n meshes with log-uniform sizes, P1/P2 split, two-state data
 * serving_requests   a seeded request stream: log-uniform sizes, P1 or P2, Riemann
                      or vortex data, final times, Poisson arrival times
+* implosion          the implosion quadrant [0,0.3]^2 with reflective walls, low state
+                     in x + y <= 0.15 (Example EulerImp), optionally turned clockwise
+                     by pi/4 with its data (the rotation-invariance test)
 """
 
 import numpy as np
@@ -35,6 +38,37 @@ def blast_delaunay(n_cells=1_000_000, seed=3):
     ov = find_vertex(m, (0.0, 0.0))
     assert ov >= 0
     return m, PROBLEM_BLAST, blast_params(ov)
+
+
+def implosion(n_cells=20_000, seed=6, rotate=False):
+    """Example EulerImp on a seeded Delaunay stand-in for its mesh: (rho, v, p) =
+    (0.125, 0, 0.14) where x + y < 0.15, (1, 0, 1) elsewhere, every wall reflective.
+    rotate: the mesh turned clockwise by pi/4, x' = M x with M = [[c, c], [-c, c]],
+    c = sqrt(2)/2 (same cells and ids); the data turn with it (v = 0, so only the
+    dividing line moves)."""
+    m = poisson_delaunay(n_cells, lo=(0.0, 0.0), hi=(0.3, 0.3), seed=seed, name=f"implosion{n_cells}")
+    m.edge_bc = np.ones((m.n_cell, 3), np.int32)       # every boundary edge is a wall
+    lo_state, hi_state = [0.125, 0.0, 0.0, 0.14], [1.0, 0.0, 0.0, 1.0]
+    if not rotate:
+        p = np.array([0.15, 0.0, 1.0, 1.0] + lo_state + hi_state)
+        return m, PROBLEM_TWO_STATE, p
+    c = np.sqrt(2.0) / 2.0
+    M = np.array([[c, c], [-c, c]])
+    m.xy = np.ascontiguousarray(m.xy @ M.T)
+    m.name += "_rot"
+    p = np.array([0.15 * c, -0.15 * c, 1.0, 0.0] + lo_state + hi_state)
+    return m, PROBLEM_TWO_STATE, p
+
+
+def wall_tags(m, on_line):
+    """(n_cell, 3) tags: 1 for the edges (opposite vertex i) whose two ends satisfy
+    on_line(x, y), else 0."""
+    x, y = m.xy[m.tri, 0], m.xy[m.tri, 1]
+    on = on_line(x, y)
+    tags = np.zeros((m.n_cell, 3), np.int32)
+    for i in range(3):
+        tags[:, i] = on[:, (i + 1) % 3] & on[:, (i + 2) % 3]
+    return tags
 
 
 def batch_sizes(n_inst=64, lo=5_000, hi=500_000, seed=4):
