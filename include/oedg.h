@@ -63,6 +63,24 @@ enum { DG_OE_RI = 0, DG_OE_CW = 1 };           /* rotation-invariant (Sec. 3.3) 
  * are rounded to nearest FP32 on input). */
 enum { DG_PREC_FP64 = 0, DG_PREC_MIXED = 1 };
 
+/* Convex decomposition behind the BP limiter and the time step (Sec. 6 compares
+ * the two).  DG_DECOMP_DCW: the optimal decomposition (Sec. 4.3): limiter nodes
+ * are the 3Q edge Gauss points plus the P1 vertices opposite the two longest
+ * edges (eq. 1944) or the two P2 internal nodes (eq. 1139), and
+ * Delta t = C_SSP/alpha min_K C^DCW_{K,k}|K| (eqs. 1692, 1713).  DG_DECOMP_ZXS: the
+ * classical Zhang-Xia-Shu decomposition (Sec. 4.2): the limiter takes the edge
+ * Gauss points and, for P2, the vector u* = (ubar - sum_i w_i sum_nu w_nu
+ * u(x_i,nu)) / (1 - sum_i w_i) with w_i = 1/9 (classical branch of Sec. 4.4; its
+ * energy bound is E(u*)); C^ZXS_{K,k} = 1/(9 lbar_K) (P1), 1/(27 lbar_K) (P2),
+ * lbar_K the mean edge length (remarks after eqs. 1692 and 1713). */
+enum { DG_DECOMP_DCW = 0, DG_DECOMP_ZXS = 1 };
+
+/* Boundary tags of unmatched edges (dg_mesh_upload's edge_bc).  Transmissive:
+ * the exterior trace equals the interior one.  Reflective: the interior trace
+ * with its normal momentum reversed, m - 2 (m.n) n.  The OE jump is zero on every
+ * boundary edge and the wave speed uses the interior trace. */
+enum { DG_BC_TRANSMISSIVE = 0, DG_BC_REFLECTIVE = 1 };
+
 typedef struct {
     int k;             /* polynomial degree, 1 or 2 */
     double gamma;      /* adiabatic index (1.4 in the paper's Euler tests) */
@@ -72,10 +90,11 @@ typedef struct {
     int bp_enable;     /* 1: apply the BP limiter after every stage and at init */
     int precision;     /* DG_PREC_FP64 or DG_PREC_MIXED */
     int max_restarts;  /* retries of a step whose stage leaves the admissible set (8) */
+    int decomposition; /* DG_DECOMP_DCW or DG_DECOMP_ZXS */
 } dg_config;
 
 /* Fills *cfg with the defaults: k = 2, gamma = 1.4, c_ssp = 1, OE on (RI), BP on, FP64,
- * max_restarts = 8.
+ * max_restarts = 8, the optimal decomposition (DG_DECOMP_DCW).
  *
  * Step restarts (with the BP limiter on).  The BP time step bounds Delta t by the
  * wave speed of u^n (Sec. 5), while each stage's LF flux uses its own input's
@@ -112,8 +131,11 @@ dg_status dg_bind_workspace(dg_ctx* ctx, void* dev_ptr, size_t bytes);
  *   tri      host, 3*n_cell vertex ids (any orientation)
  *   cell_xy  host, 6*n_cell doubles or NULL: per-cell vertex coordinates used for
  *            the geometry instead of xy[tri] (periodic meshes: unwrapped images)
- *   edge_bc  host, 3*n_cell ints or NULL: tag of unmatched edges; only 0
- *            (transmissive: exterior trace = interior trace) is defined
+ *   edge_bc  host, 3*n_cell ints or NULL (all transmissive): edge_bc[3c+i] tags
+ *            the edge of cell c opposite its input vertex i, DG_BC_TRANSMISSIVE
+ *            or DG_BC_REFLECTIVE; entries of edges shared by two cells are
+ *            ignored (a cell given clockwise is oriented by swapping its
+ *            vertices 1 and 2, and its tags move with them)
  *   k        degree (1 or 2) the decomposition and the buffers are built for;
  *            dg_init must be called with the same degree
  * Errors: DG_E_ARG, DG_E_MESH (the context is then unusable), DG_E_NOMEM, DG_E_HIP. */
@@ -125,7 +147,8 @@ dg_status dg_mesh_upload(dg_ctx* ctx, int k, int32_t n_vert, const double* xy, i
  * (neighbour's local edge), perm 3*n_cell (local edges by decreasing length,
  * stable), node_ref 4*n_cell (reference coordinates (xi, eta) of the two extra
  * limiter points: P1 the vertices opposite the two longest edges (eq. 1944),
- * P2 the two internal nodes of eq. 1139), ck n_cell (C^DCW_{K,k}|K|), minck. */
+ * P2 the two internal nodes of eq. 1139), ck n_cell (C^DCW_{K,k}|K|), minck.  The
+ * classical decomposition's C^ZXS_{K,k}|K| is fixed by the lengths and areas. */
 dg_status dg_mesh_tables(dg_ctx* ctx, int32_t* tri, int32_t* nbr, int32_t* nbe, int32_t* perm,
                          double* node_ref, double* ck, double* minck);
 

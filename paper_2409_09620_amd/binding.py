@@ -20,6 +20,11 @@ DG_OE_CW = 1
 DG_PREC_FP64 = 0
 DG_PREC_MIXED = 1
 PRECISION = {"fp64": DG_PREC_FP64, "mixed": DG_PREC_MIXED}
+DG_DECOMP_DCW = 0
+DG_DECOMP_ZXS = 1
+DECOMPOSITION = {"dcw": DG_DECOMP_DCW, "zxs": DG_DECOMP_ZXS}
+DG_BC_TRANSMISSIVE = 0
+DG_BC_REFLECTIVE = 1
 STATUS = {0: "DG_OK", -1: "DG_E_ARG", -2: "DG_E_MESH", -3: "DG_E_NOMEM", -4: "DG_E_HIP",
           -5: "DG_E_BOUNDS", -6: "DG_E_STATE"}
 
@@ -30,7 +35,8 @@ _c_i32, _c_i64, _c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
 
 class DgConfig(ctypes.Structure):
     _fields_ = [("k", _c_i), ("gamma", _c_d), ("c_ssp", _c_d), ("oe_enable", _c_i),
-                ("oe_mode", _c_i), ("bp_enable", _c_i), ("precision", _c_i), ("max_restarts", _c_i)]
+                ("oe_mode", _c_i), ("bp_enable", _c_i), ("precision", _c_i), ("max_restarts", _c_i),
+                ("decomposition", _c_i)]
 
 
 class DgDiag(ctypes.Structure):
@@ -44,6 +50,12 @@ class DgError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+def _edge_tags(mesh, nc):
+    """mesh.edge_bc as the (n_cell, 3) int32 array of dg_mesh_upload, or None."""
+    bc = getattr(mesh, "edge_bc", None)
+    return None if bc is None else np.ascontiguousarray(bc, dtype=np.int32).reshape(nc, 3)
 
 
 def lib_path():
@@ -144,8 +156,9 @@ class Solver:
         tri = np.ascontiguousarray(mesh.tri, dtype=np.int32)
         cxy = getattr(mesh, "cell_xy", None)
         cxy = None if cxy is None else np.ascontiguousarray(cxy, dtype=np.float64)
+        bc = _edge_tags(mesh, self.nc)
         self._check(L.dg_mesh_upload(self.h, self.k, int(xy.shape[0]), _ptr(xy), self.nc, _ptr(tri),
-                                     _ptr(cxy), None))
+                                     _ptr(cxy), _ptr(bc)))
 
     # ------------------------------------------------------------------ plumbing
     def _check(self, st):
@@ -166,10 +179,12 @@ class Solver:
         except Exception:
             pass
 
-    def config(self, oe=True, bp=True, oe_mode=DG_OE_RI, gamma=1.4, c_ssp=1.0, precision="fp64", max_restarts=8):
+    def config(self, oe=True, bp=True, oe_mode=DG_OE_RI, gamma=1.4, c_ssp=1.0, precision="fp64", max_restarts=8,
+               decomposition="dcw"):
         """precision: "fp64" or "mixed" (FP32 bulk, FP64 averages and limiter);
         max_restarts: retries (each with half the time step) of a step whose stage
-        leaves the admissible set."""
+        leaves the admissible set; decomposition: "dcw" (optimal) or "zxs"
+        (classical) for the limiter's node set and the time step."""
         cfg = DgConfig()
         load_library().dg_config_default(ctypes.byref(cfg))
         cfg.k = self.k
@@ -182,6 +197,9 @@ class Solver:
             raise ValueError(f"precision must be one of {sorted(PRECISION)}")
         cfg.precision = PRECISION[precision]
         cfg.max_restarts = int(max_restarts)
+        if decomposition not in DECOMPOSITION:
+            raise ValueError(f"decomposition must be one of {sorted(DECOMPOSITION)}")
+        cfg.decomposition = DECOMPOSITION[decomposition]
         return cfg
 
     def shape(self):
@@ -278,7 +296,8 @@ def host_mesh_tables(mesh, k):
         cxy = getattr(mesh, "cell_xy", None)
         cxy = None if cxy is None else np.ascontiguousarray(cxy, dtype=np.float64)
         nc = int(tri.shape[0])
-        st = L.dg_mesh_upload(h, int(k), int(xy.shape[0]), _ptr(xy), nc, _ptr(tri), _ptr(cxy), None)
+        bc = _edge_tags(mesh, nc)
+        st = L.dg_mesh_upload(h, int(k), int(xy.shape[0]), _ptr(xy), nc, _ptr(tri), _ptr(cxy), _ptr(bc))
         if st != 0:
             raise DgError(st, L.dg_last_error(h).decode())
         out = dict(tri=np.zeros((nc, 3), np.int32), nbr=np.zeros((nc, 3), np.int32),

@@ -153,6 +153,7 @@ oedg::StageArgs capi::stage_args(dg_ctx* c, int s) {
     a.oe_mode = c->cfg.oe_mode;
     a.bp_enable = c->cfg.bp_enable;
     a.k = c->cfg.k;
+    a.zxs = c->cfg.decomposition == DG_DECOMP_ZXS;
     return a;
 }
 
@@ -168,6 +169,8 @@ dg_status check_cfg(dg_ctx* c, const dg_config* cfg) {
     if (cfg->oe_mode != DG_OE_RI && cfg->oe_mode != DG_OE_CW) return fail(c, DG_E_ARG, "bad oe_mode");
     if (!(cfg->gamma > 1.0) || !(cfg->c_ssp > 0.0)) return fail(c, DG_E_ARG, "bad gamma or c_ssp");
     if (cfg->max_restarts < 0 || cfg->max_restarts > 60) return fail(c, DG_E_ARG, "bad max_restarts");
+    if (cfg->decomposition != DG_DECOMP_DCW && cfg->decomposition != DG_DECOMP_ZXS)
+        return fail(c, DG_E_ARG, "bad decomposition");
     return DG_OK;
 }
 
@@ -175,7 +178,7 @@ dg_status check_cfg(dg_ctx* c, const dg_config* cfg) {
 dg_status reset_glob(dg_ctx* c) {
     Glob h{};
     h.t_end = INFINITY;
-    h.minck = c->mesh.minck;
+    h.minck = c->cfg.decomposition == DG_DECOMP_ZXS ? c->mesh.minck_zxs : c->mesh.minck;
     h.area_sum = c->mesh.area_sum;
     h.c_ssp = c->cfg.c_ssp;
     h.alpha = h.alpha_step = 0.0;
@@ -334,6 +337,7 @@ void dg_config_default(dg_config* cfg) {
     cfg->bp_enable = 1;
     cfg->precision = DG_PREC_FP64;
     cfg->max_restarts = 8;
+    cfg->decomposition = DG_DECOMP_DCW;
 }
 
 dg_status dg_create(dg_ctx** out, int hip_device, void* hip_stream) {

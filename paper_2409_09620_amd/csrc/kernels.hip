@@ -164,6 +164,7 @@ struct Tab {
     T ep[3 * NE][NM];                         // own edge Gauss points (edge i, node nu)
     T nbw[NE][3];   // Lagrange weights (end 0, midpoint, end 1) of the neighbour's trace at its
                     // parameter 1 - s_nu = s_{NE-1-nu}
+    double zr[NM];  // classical decomposition: u* = sum_l zr_l u_l (P2; Sec. 4.4, classical branch)
 };
 
 template <typename T>
@@ -196,6 +197,25 @@ constexpr Tab<K, T> make_tab() {
             const double e = i == 0 ? s : (i == 1 ? 1.0 - s : 0.0);
             basis_at<T>(R::NM, x, e, t.ep[i * R::NE + nu], scratch, scratch2);
         }
+    // u* = (ubar - sum_i w_i sum_nu w_nu u(x_i,nu)) / (1 - sum_i w_i) with the
+    // Zhang-Xia-Shu edge weights w_i = 2 w1^GL / 3, w1^GL = 1/(L(L-1)),
+    // L = ceil((k+3)/2) (Sec. 4.2); a linear form in the modes.  P1 has no internal
+    // nodes (the edge weights sum to one) and no u*.
+    if constexpr (K == 2) {
+        constexpr int L = (K + 4) / 2;
+        const double wi = 2.0 / (3.0 * L * (L - 1));
+        double acc[6] = {};
+        double pp[6] = {}, px[6] = {}, pe[6] = {};
+        for (int i = 0; i < 3; ++i)
+            for (int nu = 0; nu < R::NE; ++nu) {
+                const double s = R::s[nu];
+                const double x = i == 0 ? 1.0 - s : (i == 1 ? 0.0 : s);
+                const double e = i == 0 ? s : (i == 1 ? 1.0 - s : 0.0);
+                basis_at<double>(R::NM, x, e, pp, px, pe);
+                for (int l = 0; l < R::NM; ++l) acc[l] += wi * R::ws[nu] * pp[l];
+            }
+        for (int l = 0; l < R::NM; ++l) t.zr[l] = ((l == 0 ? 1.0 : 0.0) - acc[l]) / (1.0 - 3.0 * wi);
+    }
     for (int nu = 0; nu < R::NE; ++nu) {
         const double s = R::s[R::NE - 1 - nu];
         t.nbw[nu][0] = (T)(K == 2 ? (1.0 - s) * (1.0 - 2.0 * s) : 1.0 - s);
@@ -542,6 +562,23 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
         const T ex = (T)a.m.jinv[2 * snc + c], ey = (T)a.m.jinv[3 * snc + c];
         const double area = a.m.area[c];
         const T areaT = (T)area;
+        // edge links and lengths with the cell's own data, so that each edge's
+        // neighbour loads issue at once (holding a neighbour ahead of its use costs
+        // occupancy and measured slower); at a transmissive boundary the own cell is
+        // fetched and not used
+        int lk[3];
+        double ln[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            lk[i] = a.m.link[i * snc + c];
+            ln[i] = a.m.len[i * snc + c];
+        }
+        auto fetch = [&](int link, T (&d)[NM]) __attribute__((always_inline)) {
+            const int nb = link >= 0 ? (link >> 2) : c;
+            d[0] = (T)ua_p[nb];
+#pragma unroll
+            for (int l = 1; l < NM; ++l) d[l] = uh_p[(l - 1) * snc + nb];
+        };
 
         // mode 0 accumulates in FP64 in both forms (its volume term is zero)
         double r0 = 0.0;
@@ -572,25 +609,40 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
             const T gx = i == 0 ? -(xx + ex) : (i == 1 ? xx : ex);
             const T gy = i == 0 ? -(xy + ey) : (i == 1 ? xy : ey);
             const T lnx = (T)-2.0 * areaT * gx, lny = (T)-2.0 * areaT * gy;
-            const T al = (T)(alpha * a.m.len[i * snc + c]);
-            const int link = a.m.link[i * snc + c];
+            const T al = (T)(alpha * (i == 0 ? ln[0] : (i == 1 ? ln[1] : ln[2])));
+            const int link = i == 0 ? lk[0] : (i == 1 ? lk[1] : lk[2]);
             const bool has = link >= 0;
-            const int nb = has ? (link >> 2) : c;
+            const bool wall = link == kLinkWall;
             const int j = link & 3;
             T un[NM];
-            un[0] = (T)ua_p[nb];
-#pragma unroll
-            for (int l = 1; l < NM; ++l) un[l] = uh_p[(l - 1) * snc + nb];
-            // the neighbour's trace along its local edge j, from its ends and midpoint
+            fetch(link, un);
+            // the exterior trace from its ends and midpoint: the neighbour's along its
+            // local edge j, or at a reflective wall the mirrored own trace
+            const bool ext = has || wall;
             T n0 = (T)0.0, nm = (T)0.0, n1 = (T)0.0;
-            if (has) edge_trace_nodes<K, T>(un, j, n0, nm, n1);
+            if (ext) edge_trace_nodes<K, T>(un, has ? j : i, n0, nm, n1);
+            if (wall) {
+                // reflective wall (un holds the own cell): the exterior trace is the own
+                // trace with its normal momentum reversed, m - 2 (m.n) n, again of degree
+                // K along the edge; its end and midpoint values stand in for the
+                // neighbour's, ends swapped (the neighbour's parameter runs the other way)
+                const T il = (T)frcp(i == 0 ? ln[0] : (i == 1 ? ln[1] : ln[2]));
+                const T nxu = lnx * il, nyu = lny * il;
+                const T cn = (T)-2.0 * fma(s1, nxu, s2 * nyu);   // this lane's share of -2n
+                const T b0 = fma(cn, fma(qget<1>(n1), nxu, qget<2>(n1) * nyu), n1);
+                const T bm = fma(cn, fma(qget<1>(nm), nxu, qget<2>(nm) * nyu), nm);
+                const T b1 = fma(cn, fma(qget<1>(n0), nxu, qget<2>(n0) * nyu), n0);
+                n0 = b0;
+                nm = bm;
+                n1 = b1;
+            }
 #pragma unroll 1
             for (int nu = 0; nu < R::NE; ++nu) {
                 const T* p = TB.ep[i * R::NE + nu];
                 const T wsn = (T)(nu == 0 ? R::ws[0] : (nu == 1 ? R::ws[1] : R::ws[2]));
                 const T qi = dot<NM>(u, p);
                 T qe = qi;
-                if (has) {
+                if (ext) {
                     // the neighbour runs the shared edge the other way: its parameter is
                     // 1 - s_nu = s_{NE-1-nu} (symmetric Gauss nodes)
                     const T* lw = TB.nbw[nu];
@@ -778,17 +830,27 @@ __device__ __forceinline__ double internal_energy(const double (&q)[4]) {
 }
 
 // the full state (all four variables, FP64) at this lane's limiter points
-// t = v, v+4, v+8 of the NP-point node set
+// t = v, v+4, v+8 of the NP-point node set.  Classical decomposition (zxs): the
+// two extra slots repeat edge points 0 and 1 (P1: no internal nodes) or hold u*
+// (P2), which leaves every minimum over the set unchanged.
 template <int K, int NM>
 __device__ __forceinline__ void node_values(int v, const double (&W)[4][NM], double n0x, double n0e, double n1x,
-                                            double n1e, double (&pv)[3][4]) {
-    constexpr int NP = 3 * Rule<K>::NE + 2;
+                                            double n1e, bool zxs, double (&pv)[3][4]) {
+    constexpr int NE3 = 3 * Rule<K>::NE, NP = NE3 + 2;
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk) {
-        const int t = v + 4 * kk;
+        int t = v + 4 * kk;
+        t = t < NP ? t : v;
+        if (K == 1 && zxs && t >= NE3) t -= NE3;
         double x, e, p[NM];
-        node_point<K>(t < NP ? t : v, n0x, n0e, n1x, n1e, x, e);
+        node_point<K>(t, n0x, n0e, n1x, n1e, x, e);
         psi<K>(x, e, p);
+        if constexpr (K == 2) {
+            if (zxs && t >= NE3) {
+#pragma unroll
+                for (int l = 0; l < NM; ++l) p[l] = tab<K, double>().zr[l];
+            }
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) pv[kk][q] = dot<NM>(W[q], p);
     }
@@ -846,6 +908,9 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
         w[0] = (T)wa;
 #pragma unroll
         for (int l = 1; l < NM; ++l) w[l] = wh_p[(l - 1) * snc + c];
+        int lk[3];   // edge links, loaded with the cell's own data (one round trip less per edge)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) lk[i] = a.m.link[i * snc + c];
         const T xx = (T)a.m.jinv[c], xy = (T)a.m.jinv[snc + c];
         const T ex = (T)a.m.jinv[2 * snc + c], ey = (T)a.m.jinv[3 * snc + c];
         const T area = (T)a.m.area[c];
@@ -873,7 +938,7 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
                 vertex_eval<K, T>(w, vt == 1 ? (T)1.0 : (T)0.0, vt == 2 ? (T)1.0 : (T)0.0, oh[vt], ox[vt], oe[vt]);
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const int link = a.m.link[i * snc + c];
+                const int link = lk[i];
                 if (link < 0) continue;   // transmissive boundary: zero jump (whole quad)
                 const int nb = link >> 2, j = link & 3;
                 const double wna = wa_p[nb];
@@ -971,7 +1036,7 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
         const double n0x = a.m.node_ref[c], n0e = a.m.node_ref[snc + c];
         const double n1x = a.m.node_ref[2 * snc + c], n1e = a.m.node_ref[3 * snc + c];
         double pv[3][4];
-        node_values<K, NM>(v, W, n0x, n0e, n1x, n1e, pv);
+        node_values<K, NM>(v, W, n0x, n0e, n1x, n1e, a.zxs, pv);
         bool pin[3];
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) pin[kk] = v + 4 * kk < NP;
@@ -1048,7 +1113,7 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
                 if (th1 < 1.0 || th2 < 1.0) {   // the same in the four lanes of the quad
                     // check the coefficients as stored (rounded to float)
                     gather_cell<NM, T>(wa, w, W);
-                    node_values<K, NM>(v, W, n0x, n0e, n1x, n1e, pv);
+                    node_values<K, NM>(v, W, n0x, n0e, n1x, n1e, a.zxs, pv);
                     double ok = 1.0;
 #pragma unroll
                     for (int kk = 0; kk < 3; ++kk)
@@ -1134,25 +1199,34 @@ __global__ __launch_bounds__(kBlock) void k_filter_batch(
 
 constexpr int kFinThreads = 1024;
 
-// Reduces the NC consecutive columns base[(col0 + k) * cstride + b], b < G, in a
-// fixed order; column k with op (opbits >> 2k) & 3 (0 sum, 1 min, 2 max).  Each
-// column gets 16/NC waves that stride over the records, so all loads are
-// coalesced and no thread holds more than one accumulator.  The results are
-// valid in thread 0.
+// Reduces NC columns base[col(k) * cstride + b], b < G, in a fixed order, where
+// col(k) = col0 + k except that the last column is colN when colN >= 0; column k
+// with op (opbits >> 2k) & 3 (0 sum, 1 min, 2 max).  Each column gets 16/NC waves
+// that stride over the records with kBatchLoads independent loads in flight per
+// lane, so the loads are coalesced and the pass is not a chain of load
+// latencies.  The results are valid in thread 0.
+constexpr int kBatchLoads = 8;
 template <int NC>
 __device__ __forceinline__ void reduce_columns(const double* base, size_t cstride, int G, int col0, unsigned opbits,
-                                               double (&out)[NC]) {
+                                               double (&out)[NC], int colN = -1) {
     constexpr int kWaves = kFinThreads / 64, kPer = kWaves / NC;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int k = w / kPer, sub = w - k * kPer;
     __shared__ double lds[kWaves];
     if (k < NC) {
         const int op = (opbits >> (2 * k)) & 3;
-        const double* col = base + (size_t)(col0 + k) * cstride;
-        double acc = op == 0 ? 0.0 : (op == 1 ? INFINITY : -INFINITY);
-        for (int b = sub * 64 + lane; b < G; b += kPer * 64) {
-            const double x = col[b];
-            acc = op == 0 ? acc + x : (op == 1 ? fmin(acc, x) : fmax(acc, x));
+        const int c = (k == NC - 1 && colN >= 0) ? colN : col0 + k;
+        const double* col = base + (size_t)c * cstride;
+        const double ident = op == 0 ? 0.0 : (op == 1 ? INFINITY : -INFINITY);
+        double acc = ident;
+        constexpr int kStride = kPer * 64;
+        for (int b0 = sub * 64 + lane; b0 < G; b0 += kBatchLoads * kStride) {
+            double x[kBatchLoads];
+#pragma unroll
+            for (int i = 0; i < kBatchLoads; ++i) x[i] = b0 + i * kStride < G ? col[b0 + i * kStride] : ident;
+#pragma unroll
+            for (int i = 0; i < kBatchLoads; ++i)
+                acc = op == 0 ? acc + x[i] : (op == 1 ? fmin(acc, x[i]) : fmax(acc, x[i]));
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -1180,11 +1254,10 @@ __device__ __forceinline__ void reduce_columns(const double* base, size_t cstrid
 // An inadmissible average ends this attempt of the step: `skip` turns the rest
 // of it into no-ops (u^n is untouched) until the third stage's finalize.
 __device__ __forceinline__ void fin_residual(const double* base, size_t cstride, int G, Glob* g) {
-    double tot[kNumPartial], bad[1];
-    reduce_columns<kNumPartial>(base, cstride, G, 0, 0xAA5500u, tot);   // 4 sums, 4 mins, 4 maxima
-    reduce_columns<1>(base, cstride, G, kColBad, 0u, bad);
+    double tot[kNumPartial + 1];   // 4 sums, 4 mins, 4 maxima, then the bad-average count
+    reduce_columns<kNumPartial + 1>(base, cstride, G, 0, 0xAA5500u, tot, kColBad);
     if (threadIdx.x == 0) {
-        if (bad[0] > 0.0) g->skip = 1;
+        if (tot[kNumPartial] > 0.0) g->skip = 1;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const double ub = tot[v] / g->area_sum;

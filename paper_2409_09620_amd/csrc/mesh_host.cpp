@@ -18,6 +18,7 @@
 #include <cstring>
 #include <vector>
 
+#include "oedg.h"
 #include "oedg_internal.h"
 
 namespace oedg {
@@ -74,6 +75,8 @@ int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const in
     m.len.assign(3 * nc, 0.0);
     m.node_ref.assign(4 * nc, 0.0);
     m.ck.assign(nc, 0.0);
+    m.ck_zxs.assign(nc, 0.0);
+    std::vector<unsigned char> swapped(nc, 0);
     m.link.assign(3 * nc, -1);
     m.vx.assign(6 * nc, 0.0);
     std::vector<double> vx(6 * nc);
@@ -95,6 +98,7 @@ int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const in
         const double twice_area = (p[2] - p[0]) * (p[5] - p[1]) - (p[4] - p[0]) * (p[3] - p[1]);
         if (!(twice_area != 0.0) || !std::isfinite(twice_area)) { err = "degenerate cell"; return -2; }
         if (twice_area < 0) {
+            swapped[c] = 1;
             std::swap(id[1], id[2]);
             std::swap(p[2], p[4]);
             std::swap(p[3], p[5]);
@@ -105,6 +109,7 @@ int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const in
     }
 
     // edge table: sort half-edges by their unordered vertex pair
+    std::vector<unsigned char> wall(3 * nc, 0);
     std::vector<HalfEdge> he(3 * nc);
     for (size_t c = 0; c < nc; ++c)
         for (int i = 0; i < 3; ++i) {
@@ -129,9 +134,16 @@ int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const in
             m.nbe[3 * x.cell + x.edge] = y.edge;
             m.nbr[3 * y.cell + y.edge] = x.cell;
             m.nbe[3 * y.cell + y.edge] = x.edge;
-        } else if (edge_bc && edge_bc[3 * static_cast<size_t>(he[r].cell) + he[r].edge] != 0) {
-            err = "unsupported boundary tag (only 0 = transmissive)";
-            return -1;
+        } else if (edge_bc) {
+            // the tag names the edge opposite the input vertex; orienting swapped 1 and 2
+            const size_t c = static_cast<size_t>(he[r].cell);
+            const int e = he[r].edge, in = swapped[c] && e > 0 ? 3 - e : e;
+            const int32_t tag = edge_bc[3 * c + in];
+            if (tag != DG_BC_TRANSMISSIVE && tag != DG_BC_REFLECTIVE) {
+                err = "unknown boundary tag";
+                return -1;
+            }
+            if (tag == DG_BC_REFLECTIVE) wall[3 * c + e] = 1;
         }
         r = s;
     }
@@ -139,12 +151,12 @@ int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const in
     for (size_t c = 0; c < nc; ++c)
         for (int i = 0; i < 3; ++i) {
             const int32_t nb = m.nbr[3 * c + i];
-            m.link[i * nc + c] = nb >= 0 ? (nb << 2) | m.nbe[3 * c + i] : -1;
+            m.link[i * nc + c] = nb >= 0 ? (nb << 2) | m.nbe[3 * c + i] : (wall[3 * c + i] ? kLinkWall : kLinkOpen);
         }
 
     // geometry and decomposition
     const double ref[3][2] = {{0, 0}, {1, 0}, {0, 1}};
-    double minck = INFINITY;
+    double minck = INFINITY, minck_zxs = INFINITY;
     for (size_t c = 0; c < nc; ++c) {
         const double* p = &vx[6 * c];
         const double a = p[2] - p[0], b = p[4] - p[0], cc = p[3] - p[1], d = p[5] - p[1];
@@ -187,9 +199,14 @@ int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const in
         }
         m.ck[c] = cd * m.area[c];
         minck = std::min(minck, m.ck[c]);
+        // classical decomposition: 1/(9 lbar) (P1), 1/(27 lbar) (P2), lbar the mean edge length
+        const double lbar = (l[0] + l[1] + l[2]) / 3.0;
+        m.ck_zxs[c] = m.area[c] / ((k == 1 ? 9.0 : 27.0) * lbar);
+        minck_zxs = std::min(minck_zxs, m.ck_zxs[c]);
         m.area_sum += m.area[c];
     }
     m.minck = minck;
+    m.minck_zxs = minck_zxs;
     return 0;
 }
 

@@ -28,16 +28,22 @@ struct HostMesh {
     int32_t n_cell = 0;
     int k = 0;
     std::vector<int32_t> tri, nbr, nbe, perm;   // [cell][3]
-    std::vector<int32_t> link;                  // [3][cell]: (nbr << 2) | nbe, or -1
+    std::vector<int32_t> link;                  // [3][cell]: (nbr << 2) | nbe, or kLinkOpen / kLinkWall
     std::vector<double> jinv;                   // [4][cell]: xi_x, xi_y, eta_x, eta_y
     std::vector<double> area;                   // [cell]
     std::vector<double> len;                    // [3][cell]
     std::vector<double> node_ref;               // [4][cell]: xi_1, eta_1, xi_2, eta_2
     std::vector<double> ck;                     // [cell] C^DCW_{K,k} |K|
+    std::vector<double> ck_zxs;                 // [cell] C^ZXS_{K,k} |K|
     std::vector<double> vx;                     // [6][cell] oriented vertex coordinates
-    double minck = 0.0;
+    double minck = 0.0;       // min_K C^DCW_{K,k} |K|
+    double minck_zxs = 0.0;   // min_K C^ZXS_{K,k} |K|
     double area_sum = 0.0;
 };
+
+// link of a boundary edge: transmissive or reflective (interior links are >= 0)
+constexpr int32_t kLinkOpen = -1;
+constexpr int32_t kLinkWall = -2;
 
 int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const int32_t* tri,
                const double* cell_xy, const int32_t* edge_bc, HostMesh& m, std::string& err);
@@ -112,6 +118,7 @@ struct StageArgs {
     int stage;            // 0, 1, 2; -1 = limiter and alpha only (initial data)
     int oe_enable, oe_mode, bp_enable;
     int mixed;            // 0: FP64 bulk, 1: FP32 bulk (averages and limiter stay FP64)
+    int zxs;              // 1: classical decomposition's limiter node set (else the optimal one)
 };
 
 // A run of groups [g0, g1) of instance `inst`: the unit a pass workgroup takes.

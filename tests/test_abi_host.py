@@ -108,3 +108,42 @@ def test_product_path_has_no_fallback():
     src = inspect.getsource(binding)
     assert "oracle" not in src.replace("never the oracle", "")
     assert "import torch" in src
+
+
+def test_config_defaults_and_layout():
+    """dg_config_default fills the binding's mirror of dg_config field by field."""
+    L = pkg.load_library()
+    c = binding.DgConfig()
+    c.decomposition = 7
+    L.dg_config_default(ctypes.byref(c))
+    assert (c.k, c.oe_enable, c.oe_mode, c.bp_enable, c.precision) == (2, 1, 0, 1, 0)
+    assert c.gamma == 1.4 and c.c_ssp == 1.0 and c.max_restarts == 8
+    assert c.decomposition == binding.DG_DECOMP_DCW
+
+
+def test_boundary_tags_are_checked():
+    L = pkg.load_library()
+    m = smesh.poisson_delaunay(80, seed=3)
+    walls = workloads.wall_tags(m, lambda x, y: y == 0.0)
+    assert walls.sum() > 0
+
+    def upload(tags):
+        h = ctypes.c_void_p()
+        assert L.dg_create(ctypes.byref(h), -1, None) == 0
+        xy = np.ascontiguousarray(m.xy, np.float64)
+        tri = np.ascontiguousarray(m.tri, np.int32)
+        t = np.ascontiguousarray(tags, np.int32)
+        st = L.dg_mesh_upload(h, 2, len(xy), binding._ptr(xy), len(tri), binding._ptr(tri), None, binding._ptr(t))
+        L.dg_destroy(h)
+        return st
+
+    assert upload(walls) == 0
+    assert upload(np.ones_like(walls)) == 0        # tags of shared edges are ignored
+    bad = walls.copy()
+    bad[np.nonzero(walls)[0][0], np.nonzero(walls)[1][0]] = 2
+    assert upload(bad) == -1
+    inner = np.full_like(walls, 5)
+    inner[walls.astype(bool)] = 0                  # unknown tags on shared edges only
+    onb = workloads.wall_tags(m, lambda x, y: (x == 0) | (x == 1) | (y == 0) | (y == 1)).astype(bool)
+    inner[onb] = 0
+    assert upload(inner) == 0
