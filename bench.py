@@ -177,6 +177,46 @@ def run_serving(n_req, rates, scale, t_scale, steps_per_tick=8):
     return out
 
 
+def run_decompositions(mesh, kind, params, steps_dcw=60):
+    """Sec. 6's comparison of the two convex decompositions behind the BP time step:
+    the same problem run to the same final time t_end = steps_dcw x the optimal
+    decomposition's first Delta t, P1 and P2, FP64.  The mean time step is t_end over
+    the number of steps (as in Sec. 6).  Time to solution: the first step (which
+    captures the step graph) runs untimed, dg_step_to times the rest, and the total
+    is that rate times the number of steps."""
+    import torch
+    from paper_2409_09620_amd import Solver
+
+    out = {}
+    for k in (1, 2):
+        s = Solver(mesh, k, device=0)
+        s.init_problem(kind, params)
+        t_end = steps_dcw * s.diag()["dt"]
+        s.close()
+        res = {"t_end": t_end}
+        for dec in ("dcw", "zxs"):
+            s = Solver(mesh, k, device=0)
+            s.init_problem(kind, params, decomposition=dec)
+            s.step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n = s.step_to(t_end)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            d = s.diag()
+            steps = n + 1
+            res[dec] = {"steps": steps, "mean_dt": t_end / steps, "ms_per_step": (t1 - t0) / n * 1e3,
+                        "time_to_solution_s": (t1 - t0) / n * steps, "n_restarts": d["n_restarts"],
+                        "n_limited": d["n_limited"]}
+            s.close()
+        res["mean_dt_ratio_dcw_over_zxs"] = res["dcw"]["mean_dt"] / res["zxs"]["mean_dt"]
+        res["time_to_solution_speedup"] = res["zxs"]["time_to_solution_s"] / res["dcw"]["time_to_solution_s"]
+        out[f"p{k}"] = res
+        log(f"decompositions P{k}: mean dt ratio {res['mean_dt_ratio_dcw_over_zxs']:.4f}, "
+            f"time-to-solution speedup {res['time_to_solution_speedup']:.3f}")
+    return out
+
+
 def roofline(prof, k, n_cell, workload, precision="fp64"):
     per_cell = algorithmic_bytes_per_cell(k, precision)
     kernels = {}
@@ -239,6 +279,8 @@ def main():
                     help="serving final times [0.05, 0.5] multiplied by this")
     ap.add_argument("--batch-scale", type=int, default=10, metavar="S",
                     help="64-instance batch with sizes divided by S (1: the full 5k-500k sizes); 0 skips it")
+    ap.add_argument("--no-decompositions", action="store_true",
+                    help="skip the optimal-vs-classical decomposition comparison (Sec. 6)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized buffer 5 times (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -316,6 +358,9 @@ def main():
         out["extra"] = {f"{btag}_{pr}": dict(measure(bm, bk, bp, pr, bsteps, 2, btag), cells=bm.n_cell,
                                              steps=bsteps)
                         for pr in ("fp64", "mixed")}
+    if not args.no_decompositions:
+        out["decompositions"] = dict(run_decompositions(mesh, kind, params),
+                                     workload=f"{tag}, P1 and P2 FP64, same t_end (60 x the optimal decomposition's first dt)")
     if args.batch_scale > 0:
         out["batch"] = {f"{pr}": run_batch(args.batch_scale, max(5, args.steps // 3), 2, pr)
                         for pr in ("fp64", "mixed")}
