@@ -177,7 +177,7 @@ def run_serving(n_req, rates, scale, t_scale, steps_per_tick=8):
     return out
 
 
-def run_decompositions(mesh, kind, params, steps_dcw=60):
+def run_decompositions(mesh, kind, params, steps_dcw=150):
     """Sec. 6's comparison of the two convex decompositions behind the BP time step:
     the same problem run to the same final time t_end = steps_dcw x the optimal
     decomposition's first Delta t, P1 and P2, FP64.  The mean time step is t_end over
@@ -215,6 +215,25 @@ def run_decompositions(mesh, kind, params, steps_dcw=60):
         log(f"decompositions P{k}: mean dt ratio {res['mean_dt_ratio_dcw_over_zxs']:.4f}, "
             f"time-to-solution speedup {res['time_to_solution_speedup']:.3f}")
     return out
+
+
+def copy_bandwidth(mib=2048, reps=10):
+    """Practical HBM rate for context: a device-to-device copy of `mib` MiB, read plus
+    write bytes over the mean time of `reps` copies (HIP events)."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    return {"gbs": 2 * n * 8 / t / 1e9, "bytes_per_copy": 2 * n * 8, "kernel": "torch copy_ (device to device)"}
 
 
 def roofline(prof, k, n_cell, workload, precision="fp64"):
@@ -355,6 +374,7 @@ def main():
         "run": dict(r64["run"], device=torch.cuda.get_device_name(0)),
         "mixed": dict(rmx, dtype="f32 bulk / f64 averages and limiter",
                       speedup_vs_fp64=rmx["value"] / r64["value"]),
+        "measured_copy_bandwidth": copy_bandwidth(),
     }
     if args.extra:
         bm, bk, bp = workloads.blast_delaunay()
@@ -365,7 +385,7 @@ def main():
                         for pr in ("fp64", "mixed")}
     if not args.no_decompositions:
         out["decompositions"] = dict(run_decompositions(mesh, kind, params),
-                                     workload=f"{tag}, P1 and P2 FP64, same t_end (60 x the optimal decomposition's first dt)")
+                                     workload=f"{tag}, P1 and P2 FP64, same t_end (150 x the optimal decomposition's first dt)")
     if args.batch_scale > 0:
         out["batch"] = {f"{pr}": run_batch(args.batch_scale, max(5, args.steps // 3), 2, pr)
                         for pr in ("fp64", "mixed")}
