@@ -100,12 +100,6 @@ __device__ __forceinline__ void psi(double x, double e, double* p) {
     }
 }
 
-// reference point of local edge i at parameter s (edge i runs from vertex i+1 to i+2)
-__device__ __forceinline__ void edge_point(int i, double s, double& x, double& e) {
-    x = i == 0 ? 1.0 - s : (i == 1 ? 0.0 : s);
-    e = i == 0 ? s : (i == 1 ? 1.0 - s : 0.0);
-}
-
 // At the reference vertices (0,0), (1,0), (0,1) every basis function and its
 // first derivatives are affine in the vertex's coordinates (sx, se) (there
 // x^2 = x, e^2 = e, xe = 0).  Returns sum_{l>=1} u_l Psi_l and the reference
@@ -807,68 +801,51 @@ __device__ __forceinline__ void hessian(const T* u, T xx, T xy, T ex, T ey, T* h
     h[2] = hxx * xy * xy + (T)2.0 * hxe * xy * ey + hee * ey * ey;
 }
 
-// point t of the limiter's node set: 3 NE edge Gauss points, then the two extra points
-template <int K>
-__device__ __forceinline__ void node_point(int t, double n0x, double n0e, double n1x, double n1e, double& x,
-                                           double& e) {
-    using R = Rule<K>;
-    const int i = t / R::NE, nu = t - (t / R::NE) * R::NE;
-    const double s = nu == 0 ? R::s[0] : (nu == 1 ? R::s[1] : R::s[2]);
-    edge_point(i, s, x, e);
-    if (t == 3 * R::NE) {
-        x = n0x;
-        e = n0e;
-    } else if (t == 3 * R::NE + 1) {
-        x = n1x;
-        e = n1e;
-    }
-}
-
 // rho e = E - |m|^2 / (2 rho) of a point value
 __device__ __forceinline__ double internal_energy(const double (&q)[4]) {
     return q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) * frcp(q[0]);
 }
 
-// the full state (all four variables, FP64) at this lane's limiter points
-// t = v, v+4, v+8 of the NP-point node set.  Classical decomposition (zxs): the
-// two extra slots repeat edge points 0 and 1 (P1: no internal nodes) or hold u*
-// (P2), which leaves every minimum over the set unchanged.
-template <int K, int NM>
-__device__ __forceinline__ void node_values(int v, const double (&W)[4][NM], double n0x, double n0e, double n1x,
-                                            double n1e, bool zxs, double (&pv)[3][4]) {
+// The full state (all four variables, FP64) at this lane's limiter points t = v,
+// v+4, v+8 of the NP-point node set.  Each lane evaluates its own variable (average
+// wa, modes w) at every point of the set, with wave-uniform basis rows for the edge
+// points, and three quad transposes then hand lane v the four variables at its
+// points; no lane holds the whole cell's coefficients.  Classical decomposition
+// (zxs): the two extra slots repeat edge points 0 and 1 (P1: no internal nodes) or
+// hold u* (P2), which leaves every minimum over the set unchanged.
+template <int K, int NM, typename T>
+__device__ __forceinline__ void node_values_t(int v, double wa, const T (&w)[NM], double n0x, double n0e,
+                                              double n1x, double n1e, bool zxs, double (&pv)[3][4]) {
     constexpr int NE3 = 3 * Rule<K>::NE, NP = NE3 + 2;
+    const Tab<K, double>& TD = tab<K, double>();
+    double wd[NM];
+    wd[0] = wa;
+#pragma unroll
+    for (int l = 1; l < NM; ++l) wd[l] = (double)w[l];
+    double y[12];
+#pragma unroll
+    for (int t = 0; t < NE3; ++t) y[t] = dot<NM>(wd, TD.ep[t]);   // edge i = t / NE, node nu = t % NE
+    if (zxs) {
+        if constexpr (K == 1) {
+            y[NE3] = y[0];
+            y[NE3 + 1] = y[1];
+        } else {
+            y[NE3] = dot<NM>(wd, TD.zr);
+            y[NE3 + 1] = y[NE3];
+        }
+    } else {
+        double p[NM];
+        psi<K>(n0x, n0e, p);
+        y[NE3] = dot<NM>(wd, p);
+        psi<K>(n1x, n1e, p);
+        y[NE3 + 1] = dot<NM>(wd, p);
+    }
+#pragma unroll
+    for (int t = NP; t < 12; ++t) y[t] = y[0];   // slots past the set (not used)
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk) {
-        int t = v + 4 * kk;
-        t = t < NP ? t : v;
-        if (K == 1 && zxs && t >= NE3) t -= NE3;
-        double x, e, p[NM];
-        node_point<K>(t, n0x, n0e, n1x, n1e, x, e);
-        psi<K>(x, e, p);
-        if constexpr (K == 2) {
-            if (zxs && t >= NE3) {
-#pragma unroll
-                for (int l = 0; l < NM; ++l) p[l] = tab<K, double>().zr[l];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) pv[kk][q] = dot<NM>(W[q], p);
-    }
-}
-
-// all coefficients of the cell in every lane of its quad, in FP64
-template <int NM, typename T>
-__device__ __forceinline__ void gather_cell(double wa, const T (&w)[NM], double (&W)[4][NM]) {
-    W[0][0] = qget<0>(wa);
-    W[1][0] = qget<1>(wa);
-    W[2][0] = qget<2>(wa);
-    W[3][0] = qget<3>(wa);
-#pragma unroll
-    for (int l = 1; l < NM; ++l) {
-        W[0][l] = (double)qget<0>(w[l]);
-        W[1][l] = (double)qget<1>(w[l]);
-        W[2][l] = (double)qget<2>(w[l]);
-        W[3][l] = (double)qget<3>(w[l]);
+        const double x[4] = {y[4 * kk], y[4 * kk + 1], y[4 * kk + 2], y[4 * kk + 3]};
+        quad_transpose(v, x, pv[kk]);
     }
 }
 
@@ -1031,16 +1008,14 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
 
         // every lane of the quad gets all coefficients of the cell in FP64; lane v
         // then evaluates the full state at its share of points t = v, v+4, v+8
-        double W[4][NM];
-        gather_cell<NM, T>(wa, w, W);
         const double n0x = a.m.node_ref[c], n0e = a.m.node_ref[snc + c];
         const double n1x = a.m.node_ref[2 * snc + c], n1e = a.m.node_ref[3 * snc + c];
         double pv[3][4];
-        node_values<K, NM>(v, W, n0x, n0e, n1x, n1e, a.zxs, pv);
+        node_values_t<K, NM, T>(v, wa, w, n0x, n0e, n1x, n1e, a.zxs, pv);
         bool pin[3];
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) pin[kk] = v + 4 * kk < NP;
-        const double ub0 = W[0][0], ub1 = W[1][0], ub2 = W[2][0], ub3 = W[3][0];
+        const double ub0 = qget<0>(wa), ub1 = qget<1>(wa), ub2 = qget<2>(wa), ub3 = qget<3>(wa);
         double th1 = 1.0, th2 = 1.0;
         if (a.bp_enable) {
             // step 1: density (Sec. 4.4, eq. 1944)
@@ -1056,8 +1031,19 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
             // pinned at eps_1 (rho e grows with rho at nodes below the average, so
             // that theta_2 is the smaller one), which keeps it at the FP64 value
             double th1s = th1;
+            // mixed form: sum_{l>=1} |c_l| of each variable (lane v forms its own)
+            double as0 = 0.0, as1 = 0.0, as2 = 0.0, as3 = 0.0;
             if constexpr (kMixed) {
-                const double t1 = e1 + kMixMargin * abs_sum_hi<NM>(W[0]);
+                double wd[NM];
+                wd[0] = 0.0;
+#pragma unroll
+                for (int l = 1; l < NM; ++l) wd[l] = (double)w[l];
+                const double as = abs_sum_hi<NM>(wd);
+                as0 = qget<0>(as);
+                as1 = qget<1>(as);
+                as2 = qget<2>(as);
+                as3 = qget<3>(as);
+                const double t1 = e1 + kMixMargin * as0;
                 th1s = rmin >= t1 ? 1.0 : fmax(fmin((ub0 - t1) / (ub0 - rmin), 1.0), 0.0);
             }
             // step 2: internal energy E - |m|^2 / (2 rho) of the density-scaled state (eq. 1981)
@@ -1089,8 +1075,7 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
                 }
                 const double vm = fsqrt(qmax(vloc));
                 const double t2 = e2 + kMixMargin * th2 *
-                                           (abs_sum_hi<NM>(W[3]) + vm * (abs_sum_hi<NM>(W[1]) + abs_sum_hi<NM>(W[2])) +
-                                            0.5 * vm * vm * th1 * abs_sum_hi<NM>(W[0]));
+                                           (as3 + vm * (as1 + as2) + 0.5 * vm * vm * th1 * as0);
                 th2 = emin >= t2 ? 1.0 : fmax(fmin((eb - t2) / (eb - emin), 1.0), 0.0);
                 th1 = th1s;
                 const double f = v == 0 ? th1 * th2 : th2;
@@ -1112,8 +1097,7 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
             if constexpr (kMixed) {
                 if (th1 < 1.0 || th2 < 1.0) {   // the same in the four lanes of the quad
                     // check the coefficients as stored (rounded to float)
-                    gather_cell<NM, T>(wa, w, W);
-                    node_values<K, NM>(v, W, n0x, n0e, n1x, n1e, a.zxs, pv);
+                    node_values_t<K, NM, T>(v, wa, w, n0x, n0e, n1x, n1e, a.zxs, pv);
                     double ok = 1.0;
 #pragma unroll
                     for (int kk = 0; kk < 3; ++kk)
