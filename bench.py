@@ -303,6 +303,8 @@ def main():
                     help="serving final times [0.05, 0.5] multiplied by this")
     ap.add_argument("--batch-scale", type=int, default=10, metavar="S",
                     help="64-instance batch with sizes divided by S (1: the full 5k-500k sizes); 0 skips it")
+    ap.add_argument("--no-copy-bandwidth", action="store_true",
+                    help="skip the device-to-device copy that measures the practical HBM rate")
     ap.add_argument("--no-decompositions", action="store_true",
                     help="skip the optimal-vs-classical decomposition comparison (Sec. 6)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -374,8 +376,9 @@ def main():
         "run": dict(r64["run"], device=torch.cuda.get_device_name(0)),
         "mixed": dict(rmx, dtype="f32 bulk / f64 averages and limiter",
                       speedup_vs_fp64=rmx["value"] / r64["value"]),
-        "measured_copy_bandwidth": copy_bandwidth(),
     }
+    if not args.no_copy_bandwidth:
+        out["measured_copy_bandwidth"] = copy_bandwidth()
     if args.extra:
         bm, bk, bp = workloads.blast_delaunay()
         bsteps = max(5, args.steps // 3)
