@@ -554,15 +554,27 @@ dg_status dg_step_to(dg_ctx* c, double t_end, int64_t max_steps, int64_t* steps_
     const long long step0 = h.step;
     LAUNCH_TRY(c, oedg::launch_set_end(c->g, t_end, c->stream));
     // a launch either completes a step or retries it (at most max_restarts times
-    // per step), so counting completed steps terminates
+    // per step), so counting completed steps terminates.  Steps go out in chunks
+    // between polls (doubling up to 64), each chunk capped by the steps that remain
+    // at the current Delta t: a launch past t_end does nothing but still replays the
+    // step graph, and Delta t changes from step to step, so an estimate that falls
+    // short costs one more poll
     int64_t completed = 0;
     int chunk = 4;
+    double t = h.t, dt = h.dt;
     while (completed < max_steps) {
-        const int64_t n = std::min<int64_t>(chunk, max_steps - completed);
+        int64_t want = chunk;
+        if (std::isfinite(t_end) && dt > 0.0) {
+            const double est = std::ceil((t_end - t) / dt);
+            want = std::min<int64_t>(want, est < 1.0 ? 1 : (est > 64.0 ? 64 : (int64_t)est));
+        }
+        const int64_t n = std::min<int64_t>(want, max_steps - completed);
         for (int64_t i = 0; i < n; ++i)
             if ((st = run_step(c)) != DG_OK) return st;
         if ((st = read_glob(c, &h)) != DG_OK) return st;
         completed = h.step - step0;
+        t = h.t;
+        dt = h.dt;
         if (!h.active || h.err) break;
         chunk = std::min(chunk * 2, 64);
     }
