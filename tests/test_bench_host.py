@@ -1,0 +1,66 @@
+"""CPU checks of the benchmark's bookkeeping: the algorithmic bytes per cell are the
+figures the kernel design states, the roofline object follows from a profile by
+the contract's arithmetic, counter traffic is used only for the kernel sources it
+was taken on, and a multi-GPU request is refused."""
+
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_algorithmic_bytes_per_cell():
+    """P2 FP64: S = 4 x 6 x 8 = 192 B; geometry 76 B (J^-1, |K|, lengths, links) and
+    +32 B of limiter-point coordinates in the filter.  Mixed: S = 4 x (8 + 5 x 4) = 112 B."""
+    b = bench.algorithmic_bytes_per_cell(2, "fp64")
+    assert b["residual"] == pytest.approx(192 + 76 + 192 + 2 / 3 * 192)   # 588 B
+    assert b["mnorm"] == 2 * 48
+    assert b["filter"] == 192 + 108 + 192                                  # 492 B
+    m = bench.algorithmic_bytes_per_cell(2, "mixed")
+    assert m["residual"] == pytest.approx(112 + 76 + 112 + 2 / 3 * 112)
+    assert m["mnorm"] == 2 * 28 and m["filter"] == 112 + 108 + 112
+    p1 = bench.algorithmic_bytes_per_cell(1, "fp64")
+    assert p1["filter"] == 96 + 108 + 96
+    # per DOF-stage at P2 FP64 (24 DOF per cell): 1176 B / 24 = 49 B
+    assert sum(b.values()) / 24 == pytest.approx(49.0)
+
+
+def test_roofline_from_profile():
+    """achieved = algorithmic bytes per launch / mean launch time of the kernel with the
+    largest total time; frac against 8 TB/s."""
+    n_cell = 100_000
+    prof = {"residual": (50e-3 * 30, 30), "mnorm": (9e-3 * 30, 30), "filter": (60e-3 * 30, 30)}
+    roof, per_k = bench.roofline(prof, 2, n_cell, "no_such_workload", "fp64")
+    assert roof["kernel"] == "filter" and roof["bound"] == "hbm" and roof["unit"] == "GB/s"
+    alg = 492 * n_cell
+    assert roof["alg_bytes_per_launch"] == alg
+    assert roof["achieved"] == pytest.approx(alg / 60e-6 / 1e9, rel=1e-3)
+    assert roof["peak"] == 8000.0
+    assert roof["frac"] == pytest.approx(roof["achieved"] / 8000.0, rel=1e-3)
+    assert roof["traffic"] is None                  # no counters for this workload
+    assert set(per_k) == {"residual", "mnorm", "filter"}
+
+
+def test_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):
+    rec = {"kernel_source_sha": bench.kernel_source_hash(), "fetch_factor": 2.0, "write_factor": 1.0,
+           "workloads": {"w": {"filter": {"hbm_bytes_per_launch": 123, "read_bytes": 100, "write_bytes": 23}}}}
+    f = tmp_path / "traffic.json"
+    f.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.load_traffic("filter", "w") == 123
+    assert bench.load_traffic("residual", "w") is None
+    rec["kernel_source_sha"] = "0" * 16              # counters of other kernel sources
+    f.write_text(json.dumps(rec))
+    assert bench.load_traffic("filter", "w") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
