@@ -167,13 +167,13 @@ dg_status run_step(dg_batch* b) {
 
 dg_status poll(dg_batch* b, int* n_active, int* n_err) {
     BLAUNCH_TRY(b, oedg::launch_gather_status(b->d_desc, b->n, b->d_status, b->stream));
-    BHIP_TRY(b, hipMemcpyAsync(b->h_status.data(), b->d_status, 4 * (size_t)b->n * sizeof(double),
+    BHIP_TRY(b, hipMemcpyAsync(b->h_status.data(), b->d_status, oedg::kStatusCols * (size_t)b->n * sizeof(double),
                                hipMemcpyDeviceToHost, b->stream));
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
     int act = 0, err = 0;
     for (int i = 0; i < b->n; ++i) {
-        act += b->h_status[4 * i] != 0.0;
-        err += b->h_status[4 * i + 1] != 0.0;
+        act += b->h_status[oedg::kStatusCols * i] != 0.0;
+        err += b->h_status[oedg::kStatusCols * i + 1] != 0.0;
     }
     if (n_active) *n_active = act;
     if (n_err) *n_err = err;
@@ -253,14 +253,14 @@ dg_status dg_batch_create(dg_batch** out, dg_ctx* const* ctxs, int n, void* hip_
     const size_t o_desc = 0, o_chunk = al(n_desc * sizeof(oedg::StageArgs));
     const size_t o_part = o_chunk + al(n_chunk * sizeof(oedg::Chunk));
     const size_t o_stat = o_part + al((size_t)oedg::kPartCols * b->total_groups * sizeof(double));
-    const size_t total = o_stat + al(4 * (size_t)n * sizeof(double));
+    const size_t total = o_stat + al(oedg::kStatusCols * (size_t)n * sizeof(double));
     if (hipMalloc(&b->mem, total) != hipSuccess) return bfail(b, DG_E_NOMEM, "hipMalloc of the batch memory failed");
     char* base = (char*)b->mem;
     b->d_desc = (oedg::StageArgs*)(base + o_desc);
     b->d_chunks = (oedg::Chunk*)(base + o_chunk);
     b->d_part = (double*)(base + o_part);
     b->d_status = (double*)(base + o_stat);
-    b->h_status.assign(4 * (size_t)n, 0.0);
+    b->h_status.assign(oedg::kStatusCols * (size_t)n, 0.0);
     // stage arguments of every member, with the batch's partial records
     b->h_desc.resize(n_desc);
     for (int s = 0; s < 3; ++s)
@@ -313,7 +313,22 @@ dg_status dg_batch_run(dg_batch* b, int64_t max_steps, int64_t* steps_done) {
     int chunk = 4, act = 0, err = 0;
     if ((st = poll(b, &act, &err)) != DG_OK) return st;
     while (done < max_steps && act > 0) {
-        const int64_t m = std::min<int64_t>(chunk, max_steps - done);
+        // cap the chunk by the most steps any active member still needs at its current
+        // Delta t: a launch after every member has finished replays the graph for nothing
+        int64_t want = chunk;
+        double need = 0.0;
+        bool bounded = true;
+        for (int i = 0; i < b->n; ++i) {
+            const double* s = b->h_status.data() + oedg::kStatusCols * (size_t)i;
+            if (s[0] == 0.0) continue;
+            if (!std::isfinite(s[5]) || !(s[4] > 0.0)) {
+                bounded = false;
+                break;
+            }
+            need = std::max(need, std::ceil((s[5] - s[2]) / s[4]));
+        }
+        if (bounded) want = std::min<int64_t>(want, need < 1.0 ? 1 : (need > 64.0 ? 64 : (int64_t)need));
+        const int64_t m = std::min<int64_t>(want, max_steps - done);
         for (int64_t i = 0; i < m; ++i)
             if ((st = run_step(b)) != DG_OK) return st;
         done += m;
@@ -331,7 +346,9 @@ dg_status dg_batch_status(dg_batch* b, int* n_active, double* status) {
     int act = 0;
     if ((st = poll(b, &act, nullptr)) != DG_OK) return st;
     if (n_active) *n_active = act;
-    if (status) std::memcpy(status, b->h_status.data(), 4 * (size_t)b->n * sizeof(double));
+    if (status)
+        for (int i = 0; i < b->n; ++i)
+            std::memcpy(status + 4 * (size_t)i, b->h_status.data() + oedg::kStatusCols * (size_t)i, 4 * sizeof(double));
     return DG_OK;
 }
 

@@ -1461,10 +1461,13 @@ __global__ void k_gather_status(const StageArgs* desc, int n, double* out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const Glob* g = desc[i].g;
-    out[4 * i + 0] = (double)g->active;
-    out[4 * i + 1] = (double)g->err;
-    out[4 * i + 2] = g->t;
-    out[4 * i + 3] = (double)g->step;
+    double* o = out + kStatusCols * i;
+    o[0] = (double)g->active;
+    o[1] = (double)g->err;
+    o[2] = g->t;
+    o[3] = (double)g->step;
+    o[4] = g->dt;
+    o[5] = g->t_end;
 }
 
 // host handles of the instantiations of one (degree, precision)

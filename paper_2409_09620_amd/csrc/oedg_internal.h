@@ -159,6 +159,8 @@ int launch_project(int k, const StageArgs& a, int kind, const double* dparams, i
                    void* stream);
 int launch_set_end(Glob* g, double t_end, void* stream);
 // Copies {active, err, t, step} of every instance of desc[0..n) into out[4 n].
+// per member: active, err, t, step, Delta t, t_end
+constexpr int kStatusCols = 6;
 int launch_gather_status(const StageArgs* desc, int n, double* out, void* stream);
 
 // schedule.cpp: chunks of chunk_groups groups over the instances in order, and
