@@ -260,6 +260,33 @@ def test_full_size_quadrant_one_step(n_cells):
     assert rel_l1(u, ref) < 1e-13
 
 
+def test_full_size_blast_one_step():
+    """The ~1M-cell P2 blast (near vacuum, the large workload the benchmark times): one
+    full step against the oracle.  Nodes pinned at the density floor amplify round-off,
+    so the bound is the oracle's own response to a relative 1e-15 perturbation of u^0
+    (its one step from the perturbed state), with a 1e-11 floor."""
+    m, kind, p = workloads.blast_delaunay()
+    say(f"[gpu case] full-size blast cells={m.n_cell}")
+    s = Solver(m, 2)
+    s.init_problem(kind, p)
+    o = oracle.Oracle(m, 2)
+    o.init_problem(kind, p)
+    u0 = o.state(0)
+    s.step()
+    assert o.step() == 0
+    u, ref = s.readback()[0], o.state(0)
+    rng = np.random.default_rng(11)
+    op = oracle.Oracle(m, 2)
+    op.init_modal(u0 * (1.0 + 1e-15 * rng.standard_normal(u0.shape)))
+    assert op.step() == 0
+    sens, sens_l1 = rel_err(op.state(0), ref), rel_l1(op.state(0), ref)
+    e, e_l1 = rel_err(u, ref), rel_l1(u, ref)
+    say(f"blast 1M one step: max {e:.2e} (self {sens:.2e}), L1 {e_l1:.2e} (self {sens_l1:.2e})")
+    assert e < max(1e-11, 100.0 * sens)
+    assert e_l1 < max(1e-13, 100.0 * sens_l1)
+    assert s.diag()["n_bad"] == 0
+
+
 def test_graph_replay_matches_eager_steps():
     """Each step is replayed as a captured HIP graph unless kernel timing is on;
     every replay must equal the eager launch sequence bit for bit, with host reads
