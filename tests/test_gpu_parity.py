@@ -2,8 +2,8 @@
 
 Tolerances: both codes compute in FP64 but round differently (FMA contraction,
 summation order), so after one stage the element-wise difference is a few ulps of
-the largest coefficient of a variable; the benchmark spec fixes rel. L1 <= 1e-11 after
-100 steps.
+the largest coefficient of a variable; the FP64 path is held to rel. L1 <= 1e-11
+after 100 steps.
 """
 
 import math
