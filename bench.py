@@ -59,9 +59,17 @@ def algorithmic_bytes_per_cell(k, precision="fp64"):
     }
 
 
-def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_source_hash(path=KERNEL_SRC):
+    """Hash of the kernel source's code: line comments, trailing blanks and empty lines
+    are dropped first, so counters stay valid across edits of the comments only.  (The
+    kernel source has no block comments and no '//' inside string literals.)"""
+    lines = []
+    with open(path, encoding="utf-8") as f:
+        for line in f:
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                lines.append(code)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
 
 
 def load_traffic(kernel, workload):

@@ -1006,8 +1006,8 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
             }
         }
 
-        // every lane of the quad gets all coefficients of the cell in FP64; lane v
-        // then evaluates the full state at its share of points t = v, v+4, v+8
+        // the full state in FP64 at this lane's share of the limiter points, t = v,
+        // v+4, v+8
         const double n0x = a.m.node_ref[c], n0e = a.m.node_ref[snc + c];
         const double n1x = a.m.node_ref[2 * snc + c], n1e = a.m.node_ref[3 * snc + c];
         double pv[3][4];
