@@ -582,7 +582,7 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
 
         // volume term |K| sum_mu w_mu F(u).grad Psi_l with grad Psi = J^{-T} grad_ref Psi,
         // i.e. dPsi/dxi (F.grad xi) + dPsi/deta (F.grad eta)
-#pragma unroll 1
+#pragma unroll
         for (int m = 0; m < R::NQ; ++m) {
             const T* p = TB.vp[m];
             const T* dx = TB.vdx[m];
@@ -630,7 +630,7 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
                 nm = bm;
                 n1 = b1;
             }
-#pragma unroll 1
+#pragma unroll
             for (int nu = 0; nu < R::NE; ++nu) {
                 const T* p = TB.ep[i * R::NE + nu];
                 const T wsn = (T)(nu == 0 ? R::ws[0] : (nu == 1 ? R::ws[1] : R::ws[2]));
