@@ -747,7 +747,7 @@ __device__ __forceinline__ void mnorm_run(const StageArgs& a, int g0, int g1) {
             m1[l] = h1[(l - 1) * snc + c];
             m2[l] = h2[(l - 1) * snc + c];
         }
-#pragma unroll 1
+#pragma unroll
         for (int m = 0; m < R::NQ; ++m) {
             const T* p = tab<K, T>().vp[m];
             const T d1 = dot<NM>(m1, p) - sh1, d2 = dot<NM>(m2, p) - sh2;
