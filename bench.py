@@ -72,9 +72,9 @@ def kernel_source_hash(path=KERNEL_SRC):
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
 
 
-def load_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` on `workload` from the committed counter
-    summary, or None when it was taken on other kernel sources."""
+def load_counters(kernel, workload):
+    """The committed counter record of `kernel` on `workload` (HBM bytes, VALU
+    issue), or None when it was taken on other kernel sources."""
     try:
         with open(TRAFFIC_FILE) as f:
             d = json.load(f)
@@ -82,8 +82,26 @@ def load_traffic(kernel, workload):
         return None
     if d.get("kernel_source_sha") != kernel_source_hash():
         return None
-    rec = d.get("workloads", {}).get(workload, {}).get(kernel)
+    return d.get("workloads", {}).get(workload, {}).get(kernel)
+
+
+def load_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter
+    summary, or None when it was taken on other kernel sources."""
+    rec = load_counters(kernel, workload)
     return rec.get("hbm_bytes_per_launch") if rec else None
+
+
+def load_valu(kernel, workload):
+    """VALU issue of `kernel` on `workload` from the committed counter summary:
+    instructions per launch (wave-level), the fraction of the SIMDs' cycles spent
+    executing them, and the shader clock during the launch; None when absent or
+    taken on other kernel sources."""
+    rec = load_counters(kernel, workload)
+    v = rec.get("valu") if rec else None
+    if not v:
+        return None
+    return {"insts_per_launch": v["insts_per_launch"], "busy_frac": v["busy_frac"], "clock_ghz": v["clock_ghz"]}
 
 
 def run_gpu(mesh, kind, params, k, steps, warmup, precision="fp64"):
@@ -267,6 +285,7 @@ def roofline(prof, k, n_cell, workload, precision="fp64"):
         "traffic": traffic,
         "alg_bytes_per_launch": int(kd["alg_bytes"]),
         "avg_launch_us": round(kd["avg_us"], 2),
+        "valu": load_valu(dom, workload),
     }, {n: {kk: (round(v, 2) if isinstance(v, float) else v) for kk, v in kd_.items()}
         for n, kd_ in kernels.items()}
 

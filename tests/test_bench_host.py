@@ -1,7 +1,7 @@
 """CPU checks of the benchmark's bookkeeping: the algorithmic bytes per cell are the
 figures the kernel design states, the roofline object follows from a profile by
-the contract's arithmetic, counter traffic is used only for the kernel sources it
-was taken on, and a multi-GPU request is refused."""
+the contract's arithmetic, counter traffic and VALU issue are used only for the
+kernel sources they were taken on, and a multi-GPU request is refused."""
 
 import json
 import os
@@ -55,9 +55,17 @@ def test_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
     assert bench.load_traffic("filter", "w") == 123
     assert bench.load_traffic("residual", "w") is None
+    assert bench.load_valu("filter", "w") is None    # no VALU counters in this record
+    rec["workloads"]["w"]["filter"]["valu"] = {"insts_per_launch": 7, "busy_frac": 0.5, "clock_ghz": 2.1}
+    f.write_text(json.dumps(rec))
+    assert bench.load_valu("filter", "w") == {"insts_per_launch": 7, "busy_frac": 0.5, "clock_ghz": 2.1}
+    prof = {"residual": (0.05, 1), "mnorm": (0.009, 1), "filter": (0.06, 1)}
+    roof, _ = bench.roofline(prof, 2, 1000, "w", "fp64")
+    assert roof["traffic"] == 123 and roof["valu"]["busy_frac"] == 0.5
     rec["kernel_source_sha"] = "0" * 16              # counters of other kernel sources
     f.write_text(json.dumps(rec))
     assert bench.load_traffic("filter", "w") is None
+    assert bench.load_valu("filter", "w") is None
 
 
 def test_more_than_one_gpu_is_refused():
