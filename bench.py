@@ -322,6 +322,8 @@ def main():
     ap.add_argument("--cells", type=int, default=200_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra", action="store_true", help="also run the ~1M-cell blast")
+    ap.add_argument("--only-blast", action="store_true",
+                    help="run only the ~1M-cell blast, FP64 and mixed (for counter runs)")
     ap.add_argument("--serving-requests", type=int, default=32, metavar="N",
                     help="serving run with N requests per arrival rate; 0 skips it")
     ap.add_argument("--serving-scale", type=int, default=20, metavar="S",
@@ -378,6 +380,16 @@ def main():
                 "run": {"t": d_["t"], "step": d_["step"], "alpha": d_["alpha"], "n_limited": d_["n_limited"],
                         "n_flat": d_["n_flat"], "n_bad": d_["n_bad"]}}
 
+    def blast(steps):
+        bm, bk, bp = workloads.blast_delaunay()
+        btag = f"p2_blast_delaunay_{bm.n_cell // 1000}k"
+        return {f"{btag}_{pr}": dict(measure(bm, bk, bp, pr, steps, 2, btag), cells=bm.n_cell, steps=steps)
+                for pr in ("fp64", "mixed")}
+
+    if args.only_blast:
+        print(json.dumps({"extra": blast(args.steps)}), flush=True)
+        return
+
     log(f"main workload: {mesh.n_cell} cells")
     r64 = measure(mesh, kind, params, "fp64", args.steps, args.warmup, tag)
     rmx = measure(mesh, kind, params, "mixed", args.steps, args.warmup, tag)
@@ -407,12 +419,7 @@ def main():
     if not args.no_copy_bandwidth:
         out["measured_copy_bandwidth"] = copy_bandwidth()
     if args.extra:
-        bm, bk, bp = workloads.blast_delaunay()
-        bsteps = max(5, args.steps // 3)
-        btag = f"p2_blast_delaunay_{bm.n_cell // 1000}k"
-        out["extra"] = {f"{btag}_{pr}": dict(measure(bm, bk, bp, pr, bsteps, 2, btag), cells=bm.n_cell,
-                                             steps=bsteps)
-                        for pr in ("fp64", "mixed")}
+        out["extra"] = blast(max(5, args.steps // 3))
     if not args.no_decompositions:
         out["decompositions"] = dict(run_decompositions(mesh, kind, params),
                                      workload=f"{tag}, P1 and P2 FP64, same t_end (150 x the optimal decomposition's first dt)")
