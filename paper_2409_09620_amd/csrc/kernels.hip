@@ -241,14 +241,7 @@ __device__ __forceinline__ T dot(const T* u, const T* p) {
     for (int l = 1; l < NM; ++l) s = fma(u[l], p[l], s);
     return s;
 }
-// sum over the modes l >= 1 only
-template <int NM, typename T>
-__device__ __forceinline__ T dot_hi(const T* u, const T* p) {
-    T s = u[1] * p[1];
-#pragma unroll
-    for (int l = 2; l < NM; ++l) s = fma(u[l], p[l], s);
-    return s;
-}
+// sum over the modes l >= 1 of |u_l|
 template <int NM>
 __device__ __forceinline__ double abs_sum_hi(const double* u) {
     double s = fabs(u[1]);
