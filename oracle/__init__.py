@@ -68,6 +68,7 @@ def lib():
             "orc_decompose": (_I, [_I, _P, _P, _P, _P, _P, _P]),
             "orc_set_bc": (_I, [_P, _P]),
             "orc_set_decomp": (_I, [_P, _I]),
+            "orc_set_limiter_form": (_I, [_P, _I]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -90,11 +91,12 @@ class Oracle:
     """One mesh and state in the FP64 oracle."""
 
     def __init__(self, mesh, k, gamma=1.4, cssp=1.0, oe=True, bp=True, oe_mode=0, max_restarts=8,
-                 decomposition="dcw", edge_bc=None):
+                 decomposition="dcw", edge_bc=None, limiter_form="nodes"):
         """decomposition: "dcw" (the optimal one) or "zxs" (the classical one) for the
         limiter and Delta t; edge_bc: (n_cell, 3) tags of boundary edges, the edge
         opposite input vertex i (0 transmissive, 1 reflective), default from
-        mesh.edge_bc."""
+        mesh.edge_bc; limiter_form: "nodes" (the optimal decomposition's nodes) or
+        "ustar" (P2: the u* form of Sec. 4.4 with the optimal edge weights)."""
         self.k = int(k)
         self.nm = (k + 1) * (k + 2) // 2
         self.nc = mesh.n_cell
@@ -116,6 +118,9 @@ class Oracle:
         if decomposition not in ("dcw", "zxs"):
             raise ValueError("decomposition is 'dcw' or 'zxs'")
         lib().orc_set_decomp(h, 1 if decomposition == "zxs" else 0)
+        if limiter_form not in ("nodes", "ustar"):
+            raise ValueError("limiter_form is 'nodes' or 'ustar'")
+        lib().orc_set_limiter_form(h, 1 if limiter_form == "ustar" else 0)
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -40,6 +40,8 @@
  *   - limiter node form: the min runs over the 3Q edge Gauss points plus the P1
  *     vertices v1, v2 (eq. 1944) or the two P2 internal nodes of eq. 1139; the
  *     P2 energy bound is E(u*) of the vector u* (not the printed scalar formula);
+ *     optionally (P2) the u* form of Sec. 4.4: edge Gauss points plus the vector
+ *     u* formed with the optimal edge weights, energy bound E(u*);
  *   - theta = 1 when the nodal minimum is already >= epsilon (avoids 0/0);
  *   - L-infinity norms use the volume rule's points (eq. normOmg);
  *   - initial data: L2 projection with the 12-point rule (tab:6th), then the BP
@@ -151,12 +153,14 @@ typedef struct {
     int* perm;                     /* nc*3 local edges sorted by length, descending, stable */
     int* limv;                     /* nc*2 P1: local vertices opposite the two longest edges */
     double* node;                  /* nc*4 P2: internal nodes (x1,y1,x2,y2) */
+    double* wdcw;                  /* nc*3 optimal decomposition's edge weights, by local edge */
     double* ck;                    /* nc: C_{K,k} |K| of the active decomposition */
     double *ck_dcw, *ck_zxs;       /* nc: C^DCW_{K,k} |K| and C^ZXS_{K,k} |K| */
     double minck, minck_dcw, minck_zxs, area_sum;
     int* bc;                       /* nc*3: boundary tag of unmatched edges, 0 transmissive, 1 reflective */
     unsigned char* swapped;        /* nc: input vertices 1 and 2 were swapped to orient the cell */
     int zxs;                       /* 1: classical (Zhang-Xia-Shu) decomposition: limiter and Delta t */
+    int ustar;                     /* 1: optimal decomposition, P2 limiter in the u* form of Sec. 4.4 */
     /* configuration */
     double gamma, cssp, eps_oe, eps_bp;
     int oe_on, bp_on, oe_mode;     /* oe_mode 0 = rotation invariant, 1 = component-wise */
@@ -351,7 +355,7 @@ static void* xcalloc(size_t n, size_t s) { return calloc(n ? n : 1, s); }
 void orc_destroy(Orc* o) {
     if (!o) return;
     free(o->tri); free(o->vx); free(o->nbr); free(o->nbe); free(o->area); free(o->len);
-    free(o->nrm); free(o->jinv); free(o->mass); free(o->perm); free(o->limv); free(o->node);
+    free(o->nrm); free(o->jinv); free(o->mass); free(o->perm); free(o->limv); free(o->node); free(o->wdcw);
     free(o->ck); free(o->ck_dcw); free(o->ck_zxs); free(o->bc); free(o->swapped); free(o->u0); free(o->u); free(o->w); free(o->L); free(o->pre);
     free(o);
 }
@@ -387,6 +391,7 @@ Orc* orc_create(int k, int nv, const double* xy, int nc, const int* tri_in, cons
     o->perm = (int*)xcalloc((size_t)nc * 3, sizeof(int));
     o->limv = (int*)xcalloc((size_t)nc * 2, sizeof(int));
     o->node = (double*)xcalloc((size_t)nc * 4, sizeof(double));
+    o->wdcw = (double*)xcalloc((size_t)nc * 3, sizeof(double));
     o->ck = (double*)xcalloc(nc, sizeof(double));
     o->ck_dcw = (double*)xcalloc(nc, sizeof(double));
     o->ck_zxs = (double*)xcalloc(nc, sizeof(double));
@@ -472,6 +477,7 @@ Orc* orc_create(int k, int nv, const double* xy, int nc, const int* tri_in, cons
         }
         double wts[3], nw[2], cd;
         decompose(k, v, o->len + 3 * c, o->perm + 3 * c, o->limv + 2 * c, o->node + 4 * c, wts, nw, &cd);
+        for (int i = 0; i < 3; ++i) o->wdcw[3 * c + o->perm[3 * c + i]] = wts[i];
         o->ck_dcw[c] = cd * o->area[c];
         if (o->ck_dcw[c] < o->minck_dcw) o->minck_dcw = o->ck_dcw[c];
         /* classical decomposition: C^ZXS = 1/(9 lbar) (P1), 1/(27 lbar) (P2), lbar the
@@ -514,6 +520,14 @@ int orc_set_bc(Orc* o, const int* tags) {
 
 /* 0: the optimal decomposition (DCW), 1: the classical one (ZXS), for the limiter
  * and the time step; call before the initial state is set */
+/* limiter form of the optimal decomposition: 0 the node form, 1 the u* form of
+ * Sec. 4.4 (differs for P2 only) */
+int orc_set_limiter_form(Orc* o, int ustar) {
+    if (ustar != 0 && ustar != 1) return -1;
+    o->ustar = ustar;
+    return 0;
+}
+
 int orc_set_decomp(Orc* o, int zxs) {
     if (zxs != 0 && zxs != 1) return -1;
     o->zxs = zxs;
@@ -805,7 +819,11 @@ static int limiter_points(const Orc* o, int c, double* px, double* py) {
 }
 
 /* The state at the limiter's node set of cell c, q[t][v], t < 3Q + 2.
- * Optimal decomposition: the points above.  Classical decomposition (Sec. 4.4,
+ * Optimal decomposition: the points above; in the u* form of Sec. 4.4 (P2 only)
+ * the two internal nodes give way to the vector
+ *   u* = (ubar - sum_i w_i sum_nu w^G_nu u(x_i,nu)) / (1 - sum_i w_i)
+ * with the optimal decomposition's edge weights w_i (eq. 1139), held twice.
+ * Classical decomposition (Sec. 4.4,
  * classical branch): the 3Q edge Gauss points, then for P2 the vector
  *   u* = (ubar - sum_i w_i sum_nu w^G_nu u(x_i,nu)) / (1 - sum_i w_i),
  * w_i = 2 w1^GL / 3 with w1^GL = 1/(L(L-1)), L = ceil((k+3)/2) (Sec. 4.2), the
@@ -816,7 +834,19 @@ static int limiter_values(const Orc* o, const double* arr, int c, double q[12][N
     double px[12], py[12];
     const int n = limiter_points(o, c, px, py), ne = 3 * o->ne;
     for (int t = 0; t < (o->zxs ? ne : n); ++t) eval_at_xy(o, arr, c, px[t], py[t], q[t]);
-    if (!o->zxs) return n;
+    if (!o->zxs) {
+        if (o->ustar && o->k == 2) {
+            double acc[NVAR] = {0, 0, 0, 0}, wsum = 0.0;
+            for (int i = 0; i < 3; ++i) {
+                const double wi = o->wdcw[3 * c + i];
+                wsum += wi;
+                for (int g = 0; g < o->ne; ++g)
+                    for (int v = 0; v < NVAR; ++v) acc[v] += wi * GW[o->ne][g] * q[i * o->ne + g][v];
+            }
+            for (int v = 0; v < NVAR; ++v) q[ne][v] = q[ne + 1][v] = (U(arr, c, v, 0) - acc[v]) / (1.0 - wsum);
+        }
+        return n;
+    }
     if (o->k == 1) {
         for (int v = 0; v < NVAR; ++v) { q[ne][v] = q[0][v]; q[ne + 1][v] = q[1][v]; }
         return n;
