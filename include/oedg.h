@@ -75,6 +75,17 @@ enum { DG_PREC_FP64 = 0, DG_PREC_MIXED = 1 };
  * lbar_K the mean edge length (remarks after eqs. 1692 and 1713). */
 enum { DG_DECOMP_DCW = 0, DG_DECOMP_ZXS = 1 };
 
+/* Form of the P2 limiter with the optimal decomposition (Sec. 4.4).
+ * DG_LIMITER_NODES: the minima run over the 3Q edge Gauss points and both internal
+ * nodes of eq. 1139, so the limited state is admissible at every node of the
+ * decomposition.  DG_LIMITER_USTAR: Sec. 4.4's own form, the edge Gauss points and
+ * the vector u* = (ubar - sum_i w_i sum_nu w_nu u(x_i,nu)) / (1 - sum_i w_i) with
+ * the optimal edge weights w_i; u* is the mean of the two internal nodes, and
+ * rho e(u*) is the energy bound.  It scales the modes no more than the node form
+ * in each of its two steps.  P1 (eq. 1944) and the classical decomposition
+ * ignore the setting. */
+enum { DG_LIMITER_NODES = 0, DG_LIMITER_USTAR = 1 };
+
 /* Boundary tags of unmatched edges (dg_mesh_upload's edge_bc).  Transmissive:
  * the exterior trace equals the interior one.  Reflective: the interior trace
  * with its normal momentum reversed, m - 2 (m.n) n.  The OE jump is zero on every
@@ -91,10 +102,12 @@ typedef struct {
     int precision;     /* DG_PREC_FP64 or DG_PREC_MIXED */
     int max_restarts;  /* retries of a step whose stage leaves the admissible set (8) */
     int decomposition; /* DG_DECOMP_DCW or DG_DECOMP_ZXS */
+    int limiter_form;  /* DG_LIMITER_NODES or DG_LIMITER_USTAR */
 } dg_config;
 
 /* Fills *cfg with the defaults: k = 2, gamma = 1.4, c_ssp = 1, OE on (RI), BP on, FP64,
- * max_restarts = 8, the optimal decomposition (DG_DECOMP_DCW).
+ * max_restarts = 8, the optimal decomposition (DG_DECOMP_DCW) with the node-form
+ * limiter (DG_LIMITER_NODES).
  *
  * Step restarts (with the BP limiter on).  The BP time step bounds Delta t by the
  * wave speed of u^n (Sec. 5), while each stage's LF flux uses its own input's

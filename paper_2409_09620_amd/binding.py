@@ -23,6 +23,9 @@ PRECISION = {"fp64": DG_PREC_FP64, "mixed": DG_PREC_MIXED}
 DG_DECOMP_DCW = 0
 DG_DECOMP_ZXS = 1
 DECOMPOSITION = {"dcw": DG_DECOMP_DCW, "zxs": DG_DECOMP_ZXS}
+DG_LIMITER_NODES = 0
+DG_LIMITER_USTAR = 1
+LIMITER_FORM = {"nodes": DG_LIMITER_NODES, "ustar": DG_LIMITER_USTAR}
 DG_BC_TRANSMISSIVE = 0
 DG_BC_REFLECTIVE = 1
 STATUS = {0: "DG_OK", -1: "DG_E_ARG", -2: "DG_E_MESH", -3: "DG_E_NOMEM", -4: "DG_E_HIP",
@@ -36,7 +39,7 @@ _c_i32, _c_i64, _c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
 class DgConfig(ctypes.Structure):
     _fields_ = [("k", _c_i), ("gamma", _c_d), ("c_ssp", _c_d), ("oe_enable", _c_i),
                 ("oe_mode", _c_i), ("bp_enable", _c_i), ("precision", _c_i), ("max_restarts", _c_i),
-                ("decomposition", _c_i)]
+                ("decomposition", _c_i), ("limiter_form", _c_i)]
 
 
 class DgDiag(ctypes.Structure):
@@ -180,11 +183,12 @@ class Solver:
             pass
 
     def config(self, oe=True, bp=True, oe_mode=DG_OE_RI, gamma=1.4, c_ssp=1.0, precision="fp64", max_restarts=8,
-               decomposition="dcw"):
+               decomposition="dcw", limiter_form="nodes"):
         """precision: "fp64" or "mixed" (FP32 bulk, FP64 averages and limiter);
         max_restarts: retries (each with half the time step) of a step whose stage
         leaves the admissible set; decomposition: "dcw" (optimal) or "zxs"
-        (classical) for the limiter's node set and the time step."""
+        (classical) for the limiter's node set and the time step; limiter_form:
+        "nodes" or "ustar" (P2 with the optimal decomposition: the u* form)."""
         cfg = DgConfig()
         load_library().dg_config_default(ctypes.byref(cfg))
         cfg.k = self.k
@@ -200,6 +204,9 @@ class Solver:
         if decomposition not in DECOMPOSITION:
             raise ValueError(f"decomposition must be one of {sorted(DECOMPOSITION)}")
         cfg.decomposition = DECOMPOSITION[decomposition]
+        if limiter_form not in LIMITER_FORM:
+            raise ValueError(f"limiter_form must be one of {sorted(LIMITER_FORM)}")
+        cfg.limiter_form = LIMITER_FORM[limiter_form]
         return cfg
 
     def shape(self):

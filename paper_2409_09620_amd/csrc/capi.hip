@@ -154,6 +154,7 @@ oedg::StageArgs capi::stage_args(dg_ctx* c, int s) {
     a.bp_enable = c->cfg.bp_enable;
     a.k = c->cfg.k;
     a.zxs = c->cfg.decomposition == DG_DECOMP_ZXS;
+    a.ustar = !a.zxs && c->cfg.limiter_form == DG_LIMITER_USTAR;
     return a;
 }
 
@@ -171,6 +172,8 @@ dg_status check_cfg(dg_ctx* c, const dg_config* cfg) {
     if (cfg->max_restarts < 0 || cfg->max_restarts > 60) return fail(c, DG_E_ARG, "bad max_restarts");
     if (cfg->decomposition != DG_DECOMP_DCW && cfg->decomposition != DG_DECOMP_ZXS)
         return fail(c, DG_E_ARG, "bad decomposition");
+    if (cfg->limiter_form != DG_LIMITER_NODES && cfg->limiter_form != DG_LIMITER_USTAR)
+        return fail(c, DG_E_ARG, "bad limiter_form");
     return DG_OK;
 }
 
@@ -338,6 +341,7 @@ void dg_config_default(dg_config* cfg) {
     cfg->precision = DG_PREC_FP64;
     cfg->max_restarts = 8;
     cfg->decomposition = DG_DECOMP_DCW;
+    cfg->limiter_form = DG_LIMITER_NODES;
 }
 
 dg_status dg_create(dg_ctx** out, int hip_device, void* hip_stream) {

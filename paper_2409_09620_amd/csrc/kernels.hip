@@ -810,10 +810,12 @@ __device__ __forceinline__ double internal_energy(const double (&q)[4]) {
 // points, and three quad transposes then hand lane v the four variables at its
 // points; no lane holds the whole cell's coefficients.  Classical decomposition
 // (zxs): the two extra slots repeat edge points 0 and 1 (P1: no internal nodes) or
-// hold u* (P2), which leaves every minimum over the set unchanged.
+// hold u* (P2), which leaves every minimum over the set unchanged.  The u* form of
+// the optimal decomposition (ustar, P2) holds u* = the mean of its two internal
+// nodes (equal node weights) in both slots.
 template <int K, int NM, typename T>
 __device__ __forceinline__ void node_values_t(int v, double wa, const T (&w)[NM], double n0x, double n0e,
-                                              double n1x, double n1e, bool zxs, double (&pv)[3][4]) {
+                                              double n1x, double n1e, bool zxs, bool ustar, double (&pv)[3][4]) {
     constexpr int NE3 = 3 * Rule<K>::NE, NP = NE3 + 2;
     const Tab<K, double>& TD = tab<K, double>();
     double wd[NM];
@@ -837,6 +839,9 @@ __device__ __forceinline__ void node_values_t(int v, double wa, const T (&w)[NM]
         y[NE3] = dot<NM>(wd, p);
         psi<K>(n1x, n1e, p);
         y[NE3 + 1] = dot<NM>(wd, p);
+        if constexpr (K == 2) {
+            if (ustar) y[NE3] = y[NE3 + 1] = 0.5 * (y[NE3] + y[NE3 + 1]);
+        }
     }
 #pragma unroll
     for (int t = NP; t < 12; ++t) y[t] = y[0];   // slots past the set (not used)
@@ -1009,7 +1014,7 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
         const double n0x = a.m.node_ref[c], n0e = a.m.node_ref[snc + c];
         const double n1x = a.m.node_ref[2 * snc + c], n1e = a.m.node_ref[3 * snc + c];
         double pv[3][4];
-        node_values_t<K, NM, T>(v, wa, w, n0x, n0e, n1x, n1e, a.zxs, pv);
+        node_values_t<K, NM, T>(v, wa, w, n0x, n0e, n1x, n1e, a.zxs, a.ustar, pv);
         bool pin[3];
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) pin[kk] = v + 4 * kk < NP;
@@ -1095,7 +1100,7 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
             if constexpr (kMixed) {
                 if (th1 < 1.0 || th2 < 1.0) {   // the same in the four lanes of the quad
                     // check the coefficients as stored (rounded to float)
-                    node_values_t<K, NM, T>(v, wa, w, n0x, n0e, n1x, n1e, a.zxs, pv);
+                    node_values_t<K, NM, T>(v, wa, w, n0x, n0e, n1x, n1e, a.zxs, a.ustar, pv);
                     double ok = 1.0;
 #pragma unroll
                     for (int kk = 0; kk < 3; ++kk)

@@ -119,6 +119,7 @@ struct StageArgs {
     int oe_enable, oe_mode, bp_enable;
     int mixed;            // 0: FP64 bulk, 1: FP32 bulk (averages and limiter stay FP64)
     int zxs;              // 1: classical decomposition's limiter node set (else the optimal one)
+    int ustar;            // 1: optimal decomposition, P2 limiter in the u* form (the nodes' mean)
 };
 
 // A run of groups [g0, g1) of instance `inst`: the unit a pass workgroup takes.

@@ -2,6 +2,7 @@
 host-side mesh precompute matches the oracle's (integer tables bit for bit)."""
 
 import ctypes
+import os
 
 import numpy as np
 import pytest
@@ -115,10 +116,13 @@ def test_config_defaults_and_layout():
     L = pkg.load_library()
     c = binding.DgConfig()
     c.decomposition = 7
+    c.limiter_form = 7
     L.dg_config_default(ctypes.byref(c))
     assert (c.k, c.oe_enable, c.oe_mode, c.bp_enable, c.precision) == (2, 1, 0, 1, 0)
     assert c.gamma == 1.4 and c.c_ssp == 1.0 and c.max_restarts == 8
     assert c.decomposition == binding.DG_DECOMP_DCW
+    assert c.limiter_form == binding.DG_LIMITER_NODES   # the last field: the layouts agree
+    assert ctypes.sizeof(binding.DgConfig) == 56
 
 
 def test_boundary_tags_are_checked():
@@ -147,3 +151,17 @@ def test_boundary_tags_are_checked():
     onb = workloads.wall_tags(m, lambda x, y: (x == 0) | (x == 1) | (y == 0) | (y == 1)).astype(bool)
     inner[onb] = 0
     assert upload(inner) == 0
+
+
+def test_header_constants_match_the_binding():
+    """Every DG_ enum constant of include/oedg.h has the same value in the binding."""
+    import re
+    text = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                             "oedg.h")).read()
+    consts = dict((n, int(v)) for n, v in re.findall(r"\b(DG_[A-Z0-9_]+)\s*=\s*(-?\d+)", text))
+    assert len(consts) >= 17
+    for name, val in consts.items():
+        if name.startswith("DG_E_") or name == "DG_OK":
+            assert binding.STATUS[val] == name
+        else:
+            assert getattr(binding, name) == val, name

@@ -1,6 +1,7 @@
-"""Reflective walls and the classical (Zhang-Xia-Shu) decomposition on the GPU,
-against the FP64 oracle through the C ABI, plus the implosion rotation test of
-Example EulerImp and the DCW/ZXS time-step comparison of Sec. 6.
+"""Reflective walls, the classical (Zhang-Xia-Shu) decomposition and the u* form of
+the P2 limiter on the GPU, against the FP64 oracle through the C ABI, plus the
+implosion rotation test of Example EulerImp and the DCW/ZXS time-step comparison of
+Sec. 6.
 
 Tolerances: FP64 stage outputs within the larger of 1e-12, 100x the oracle's own
 response of the whole stage (residual, OE, limiter) to a relative 1e-15
@@ -73,7 +74,17 @@ CASES = {
     "p2_implosion_walls_zxs": lambda: (2,) + workloads.implosion(n_cells=2500, seed=45) + ("zxs",),
     "p2_vortex_box_walls": lambda: vortex_box_walls(3000, 53, 2),
     "p1_vortex_box_walls": lambda: vortex_box_walls(3000, 54, 1),
+    # the u* form of the P2 limiter with the optimal decomposition (Sec. 4.4)
+    "p2_quadrant_ustar": lambda: (2,) + workloads.quadrant_delaunay(n_cells=3000, seed=46) + ("dcw", "ustar"),
+    "p2_implosion_walls_ustar": lambda: (2,) + workloads.implosion(n_cells=2500, seed=47) + ("dcw", "ustar"),
+    "p2_blast_ustar": lambda: (2,) + workloads.blast_delaunay(n_cells=3000, seed=48) + ("dcw", "ustar"),
 }
+
+
+def case_of(name):
+    """(k, mesh, kind, params, decomposition, limiter form) of a case"""
+    k, m, kind, p, dec, *rest = CASES[name]()
+    return k, m, kind, p, dec, (rest[0] if rest else "nodes")
 
 
 @pytest.mark.parametrize("case", list(CASES))
@@ -81,11 +92,11 @@ def test_stage_parity(case):
     """Every stage of two steps: the GPU's pre-filter state and output against the
     oracle's stage applied to the GPU's own inputs (u^n, stage input, Delta t); then
     alpha and Delta t of the GPU's u^{n+1} against the oracle's on that state."""
-    k, m, kind, p, dec = CASES[case]()
-    say(f"[gpu case] {case} cells={m.n_cell} k={k} decomposition={dec}")
+    k, m, kind, p, dec, form = case_of(case)
+    say(f"[gpu case] {case} cells={m.n_cell} k={k} decomposition={dec} limiter={form}")
     s = Solver(m, k)
-    s.init_problem(kind, p, decomposition=dec)
-    o = oracle.Oracle(m, k, decomposition=dec)
+    s.init_problem(kind, p, decomposition=dec, limiter_form=form)
+    o = oracle.Oracle(m, k, decomposition=dec, limiter_form=form)
     assert o.init_problem(kind, p) == 0
     a_tol = alpha_tolerance(o, o.state(0))
     assert rel_err(s.readback()[0], o.state(0)) < max(1e-12, 10.0 * a_tol)
@@ -111,13 +122,14 @@ def test_stage_parity(case):
         assert d["step"] == step + 1
 
 
-@pytest.mark.parametrize("case", ["p2_vortex_box_walls", "p1_implosion_walls", "p2_quadrant_zxs"])
+@pytest.mark.parametrize("case", ["p2_vortex_box_walls", "p1_implosion_walls", "p2_quadrant_zxs",
+                                  "p2_quadrant_ustar"])
 def test_mixed_form_within_fp32_bound(case):
-    k, m, kind, p, dec = CASES[case]()
+    k, m, kind, p, dec, form = case_of(case)
     say(f"[gpu case] {case} mixed")
     s = Solver(m, k)
-    s.init_problem(kind, p, decomposition=dec, precision="mixed")
-    o = oracle.Oracle(m, k, decomposition=dec)
+    s.init_problem(kind, p, decomposition=dec, precision="mixed", limiter_form=form)
+    o = oracle.Oracle(m, k, decomposition=dec, limiter_form=form)
     assert o.init_problem(kind, p) == 0
     s.step()
     assert o.step() == 0
@@ -250,3 +262,22 @@ def test_mixed_implosion_keeps_nodes_admissible(dec):
     d = s.diag()
     say(f"limited {d['n_limited']}, flattened {d['n_flat']}, restarts {d['n_restarts']}")
     assert d["n_bad"] == 0 and d["step"] == 10
+
+
+def test_ustar_blast_positive_at_its_points_every_step():
+    """The u* form on the 3k blast, FP64: after every step rho >= eps_1 and rho e >=
+    eps_2 at the 9 edge points and at u* (Sec. 4.4), evaluated by the oracle in FP64;
+    no step is retried."""
+    m, kind, p = workloads.blast_delaunay(n_cells=3000, seed=49)
+    say(f"[gpu case] blast ustar cells={m.n_cell}")
+    s = Solver(m, 2)
+    s.init_problem(kind, p, limiter_form="ustar")
+    o = oracle.Oracle(m, 2, limiter_form="ustar")
+    for _ in range(10):
+        s.step()
+        v = o.limiter_node_values(s.readback()[0])
+        rho = v[..., 0]
+        e = v[..., 3] - 0.5 * (v[..., 1] ** 2 + v[..., 2] ** 2) / rho
+        assert rho.min() >= 1e-13 * (1 - 1e-9) - 1e-15
+        assert e.min() >= 1e-13 * (1 - 1e-9) - 1e-14
+    assert s.diag()["n_restarts"] == 0
