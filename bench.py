@@ -54,7 +54,6 @@ def algorithmic_bytes_per_cell(k, precision="fp64"):
     return {
         # stage input + pre-filter write, plus u^n in 2 of 3 stages
         "residual": S + g_res + S + (2.0 / 3.0) * S,
-        "mnorm": 2 * var,                      # momentum modes of the pre-filter state
         "filter": S + g_fil + S,               # pre-filter state in, limited state out
     }
 

@@ -223,9 +223,9 @@ dg_status dg_diag(dg_ctx* ctx, dg_diag_t* out);
  * stage kernel launch (a few microseconds of overhead per launch).
  * dg_profile_enable(ctx, 1) starts recording; dg_profile_read synchronises, adds
  * the elapsed times since the last read into ms[k] and the launch counts into
- * launches[k] for k = 0 residual pass, 1 momentum-norm pass, 2 filter pass, and
- * restarts the accumulation.  Both arrays have DG_PROFILE_KERNELS entries. */
-#define DG_PROFILE_KERNELS 3
+ * launches[k] for k = 0 residual pass, 1 filter pass, and restarts the
+ * accumulation.  Both arrays have DG_PROFILE_KERNELS entries. */
+#define DG_PROFILE_KERNELS 2
 dg_status dg_profile_enable(dg_ctx* ctx, int enable);
 dg_status dg_profile_read(dg_ctx* ctx, double* ms, int64_t* launches);
 
@@ -264,7 +264,7 @@ dg_status dg_batch_create(dg_batch** out, dg_ctx* const* ctxs, int n, void* hip_
  * pass grids at occupancy_pct percent of the resident workgroups. */
 dg_status dg_batch_set_schedule(dg_batch* b, int chunk_groups, int occupancy_pct);
 dg_status dg_batch_get_schedule(const dg_batch* b, int* chunk_groups, int* occupancy_pct, int* n_chunks,
-                                int* grid /* 3: residual, momentum norm, filter */);
+                                int* grid /* 2: residual, filter */);
 
 /* Times stage 0 of the batch for chunk_groups in {1,2,4,8,16} and occupancy in
  * {100, 50} percent (reps timed runs each, after a warm-up), keeps the fastest

@@ -264,15 +264,15 @@ class Solver:
         out["nrm"] = list(d.nrm)
         return out
 
-    KERNELS = ("residual", "mnorm", "filter")
+    KERNELS = ("residual", "filter")   # dg_profile_read's order (DG_PROFILE_KERNELS)
 
     def profile(self, enable=True):
         self._check(load_library().dg_profile_enable(self.h, int(enable)))
 
     def profile_read(self):
         """{kernel: (total_ms, launches)} since the last read (synchronises)."""
-        ms = np.zeros(3)
-        n = np.zeros(3, np.int64)
+        ms = np.zeros(len(self.KERNELS))
+        n = np.zeros(len(self.KERNELS), np.int64)
         self._check(load_library().dg_profile_read(self.h, _ptr(ms), _ptr(n)))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.KERNELS)}
 
@@ -379,7 +379,7 @@ class Batch:
 
     def schedule(self):
         cg, occ, nch = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
-        grid = (ctypes.c_int * 3)()
+        grid = (ctypes.c_int * 2)()   # residual, filter
         self._check(load_library().dg_batch_get_schedule(self.h, ctypes.byref(cg), ctypes.byref(occ),
                                                          ctypes.byref(nch), grid))
         return {"chunk_groups": cg.value, "occupancy_pct": occ.value, "n_chunks": nch.value, "grid": list(grid)}

@@ -23,7 +23,7 @@ struct dg_batch {
 
     std::vector<dg_ctx*> ctx;
     std::vector<unsigned long long> generation;   // of each member when the batch was built
-    int n = 0, mixed = 0, kmask = 0, any_oe = 0;
+    int n = 0, mixed = 0, kmask = 0;
     long long total_groups = 0;
 
     // schedule
@@ -31,7 +31,7 @@ struct dg_batch {
     int occupancy_pct = 100;
     std::vector<oedg::Chunk> chunks;
     oedg::ChunkSplit split{};
-    int grid[3] = {8, 8, 8};
+    int grid[oedg::kNumPasses] = {8, 8};
 
     // device memory (one library allocation): stage arguments [3][n], chunk
     // table (one chunk per group at most), partial records, status words
@@ -99,7 +99,7 @@ dg_status plan(dg_batch* b) {
     }
     if (oedg::plan_chunks(b->n, nc.data(), k.data(), b->chunk_groups, b->chunks, b->split) != 0)
         return bfail(b, DG_E_ARG, "bad schedule");
-    for (int w = 0; w < 3; ++w) {
+    for (int w = 0; w < oedg::kNumPasses; ++w) {
         const int resident = oedg::resident_grid_batch(w, b->kmask, b->mixed);
         const int cap = std::max(8, (int)((long long)resident * b->occupancy_pct / 100) / 8 * 8);
         b->grid[w] = oedg::grid_for_split(b->split, cap);
@@ -113,14 +113,11 @@ dg_status plan(dg_batch* b) {
 
 dg_status run_stage(dg_batch* b, int s) {
     const oedg::StageArgs* d = b->d_desc + (size_t)s * b->n;
-    BLAUNCH_TRY(b, oedg::launch_pass_batch(0, b->kmask, b->mixed, d, b->d_chunks, b->split, b->grid[0], b->stream));
-    BLAUNCH_TRY(b, oedg::launch_finalize_batch(0, d, b->n, b->stream));
-    if (b->any_oe) {
-        BLAUNCH_TRY(b, oedg::launch_pass_batch(1, b->kmask, b->mixed, d, b->d_chunks, b->split, b->grid[1], b->stream));
-        BLAUNCH_TRY(b, oedg::launch_finalize_batch(1, d, b->n, b->stream));
+    for (int w = 0; w < oedg::kNumPasses; ++w) {
+        BLAUNCH_TRY(b, oedg::launch_pass_batch(w, b->kmask, b->mixed, d, b->d_chunks, b->split, b->grid[w],
+                                               b->stream));
+        BLAUNCH_TRY(b, oedg::launch_finalize_batch(w, d, b->n, b->stream));
     }
-    BLAUNCH_TRY(b, oedg::launch_pass_batch(2, b->kmask, b->mixed, d, b->d_chunks, b->split, b->grid[2], b->stream));
-    BLAUNCH_TRY(b, oedg::launch_finalize_batch(2, d, b->n, b->stream));
     return DG_OK;
 }
 
@@ -238,7 +235,6 @@ dg_status dg_batch_create(dg_batch** out, dg_ctx* const* ctxs, int n, void* hip_
     for (int i = 0; i < n; ++i) {
         b->generation.push_back(ctxs[i]->generation);
         b->kmask |= ctxs[i]->cfg.k == 1 ? 1 : 2;
-        b->any_oe |= ctxs[i]->cfg.oe_enable ? 1 : 0;
         gbase[i] = (int)b->total_groups;
         b->total_groups += oedg::n_groups(ctxs[i]->mesh.n_cell);
     }
@@ -292,7 +288,7 @@ dg_status dg_batch_get_schedule(const dg_batch* b, int* chunk_groups, int* occup
     if (occupancy_pct) *occupancy_pct = b->occupancy_pct;
     if (n_chunks) *n_chunks = (int)b->chunks.size();
     if (grid)
-        for (int w = 0; w < 3; ++w) grid[w] = b->grid[w];
+        for (int w = 0; w < oedg::kNumPasses; ++w) grid[w] = b->grid[w];
     return DG_OK;
 }
 

@@ -198,7 +198,7 @@ dg_status start(dg_ctx* c) {
     a.uout = a.w;
     a.oe_enable = 0;
     LAUNCH_TRY(c, oedg::launch_filter(c->cfg.k, a, c->stream));
-    LAUNCH_TRY(c, oedg::launch_finalize(2, c->cfg.k, a, c->stream));
+    LAUNCH_TRY(c, oedg::launch_finalize(oedg::kPassFilter, c->cfg.k, a, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->u, c->u0, state_bytes(c), hipMemcpyDeviceToDevice, c->stream));
     c->last_out = c->u0;
     c->initialised = true;
@@ -250,14 +250,10 @@ dg_status prof_end(dg_ctx* c, long pair) {
 
 dg_status run_stage(dg_ctx* c, int s) {
     const oedg::StageArgs a = stage_args(c, s);
-    TIMED_LAUNCH(c, 0, oedg::launch_residual(c->cfg.k, a, c->stream));
-    LAUNCH_TRY(c, oedg::launch_finalize(0, c->cfg.k, a, c->stream));
-    if (c->cfg.oe_enable) {
-        TIMED_LAUNCH(c, 1, oedg::launch_mnorm(c->cfg.k, a, c->stream));
-        LAUNCH_TRY(c, oedg::launch_finalize(1, c->cfg.k, a, c->stream));
-    }
-    TIMED_LAUNCH(c, 2, oedg::launch_filter(c->cfg.k, a, c->stream));
-    LAUNCH_TRY(c, oedg::launch_finalize(2, c->cfg.k, a, c->stream));
+    TIMED_LAUNCH(c, oedg::kPassResidual, oedg::launch_residual(c->cfg.k, a, c->stream));
+    LAUNCH_TRY(c, oedg::launch_finalize(oedg::kPassResidual, c->cfg.k, a, c->stream));
+    TIMED_LAUNCH(c, oedg::kPassFilter, oedg::launch_filter(c->cfg.k, a, c->stream));
+    LAUNCH_TRY(c, oedg::launch_finalize(oedg::kPassFilter, c->cfg.k, a, c->stream));
     c->last_out = s == 2 ? c->u0 : c->u;
     return DG_OK;
 }

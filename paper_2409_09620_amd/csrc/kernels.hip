@@ -1,15 +1,17 @@
 // gfx950 kernels of one BP RI-OEDG stage (2D Euler, P1/P2 modal DG on triangles).
 //
-// Three passes per stage over a state stored as structure-of-arrays, cell
+// Two passes per stage over a state stored as structure-of-arrays, cell
 // fastest: cell averages [var][cell] and higher modes [var][mode][cell]:
 //   k_residual  volume + edge quadrature of eq. DGSystem:Dis with the LF flux
 //               (eq. fluxLF), the diagonal mass and the SSP-RK3 combination (eq.
 //               RKTime); writes the pre-filter state and per-workgroup partials of
-//               sum |K| ubar_K and of min/max at the volume points (eq. normOmg).
-//   k_mnorm     ||| m - mbar |||_inf at the volume points (needs mbar first).
+//               sum |K| ubar_K, of min/max at the volume points and of
+//               |m - mbar|^2 there (eq. normOmg; mbar known in advance by
+//               conservation, see the pass).
 //   k_filter    RIOE damping (eq. oe:sys with eqs. OEScalar:beta, OEScalar:Coef2,
 //               oe:sysdelta2, RIOESys:CoefM), the BP limiter at the decomposition
-//               nodes (Sec. 4.4) and the max wave speed of the result (eq. 1250).
+//               nodes (Sec. 4.4) and the max wave speed of the result (eq. 1250);
+//               also the momentum bookkeeping of its output for the next residual.
 // Each pass is followed by a one-workgroup finalize kernel that reduces the
 // partials in a fixed order, so results do not depend on scheduling and no
 // workgroup needs a device-scope fence.
@@ -355,15 +357,16 @@ __device__ __forceinline__ void quad_transpose(int v, const T (&x)[4], T (&q)[4]
 
 // ------------------------------------------------------------------------- Euler
 
-// component v of F(q).n for the lane's variable (s1, s2, s3 = [v==1], [v==2], [v==3]);
-// (nx, ny) may be a scaled normal
+// component v of F(q).n for the lane's variable; (nx, ny) may be a scaled normal,
+// sn is the lane's component of it (nx on lane 1, ny on lane 2, else 0) and
+// s3 = [v == 3]
 template <typename T>
-__device__ __forceinline__ T lane_flux(T qv, T q0, T q1, T q2, T q3, T nx, T ny, T gm1, T s1, T s2, T s3) {
+__device__ __forceinline__ T lane_flux(T qv, T q0, T q1, T q2, T q3, T nx, T ny, T gm1, T sn, T s3) {
     const T ir = Fp<T>::rcp(q0);
     const T mn = q1 * nx + q2 * ny;
     const T vn = mn * ir;
     const T p = gm1 * (q3 - (T)0.5 * (q1 * q1 + q2 * q2) * ir);
-    return qv * vn + p * (s1 * nx + s2 * ny + s3 * vn);
+    return qv * vn + p * (sn + s3 * vn);
 }
 
 // spectral radius |v.n| + c of F'(u).n (Example ex:euler); guarded so that a
@@ -428,13 +431,23 @@ __device__ __forceinline__ VarPtr<NM, T> var_ptr(const StateView& sv, const Stag
     }
 }
 
+// a wave-uniform double moved to scalar registers
+__device__ __forceinline__ double uniform(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)b), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
 // ------------------------------------------------------------------------- pass 1: residual
 
 // Reduces the lanes' (sum |K| ubar, min, max) over the workgroup, per variable, and
-// writes entry t = 4 k + v (k: sum, min, max) to dst[t * stride]; the count of
-// inadmissible averages goes to dst[kColBad * stride].
-__device__ __forceinline__ void residual_flush(double psum, double pmin, double pmax, double nbad, double* dst,
+// writes entry t = 4 k + v (k: sum, min, max) to dst[t * stride].  `pacc` holds the
+// count of inadmissible averages on lane 0 of each quad and the max of |m - mbar|^2
+// on lane 1; they go to dst[kColBad * stride] and dst[kNumPartial * stride].
+__device__ __forceinline__ void residual_flush(double psum, double pmin, double pmax, double pacc, double* dst,
                                                size_t stride) {
+    const int v = threadIdx.x & 3;
+    double nbad = v == 0 ? pacc : 0.0, pnm = v == 1 ? pacc : 0.0;
     // over the lanes holding the same variable (xor of lane ids >= 4), then waves
 #pragma unroll
     for (int o = 4; o < 64; o <<= 1) {
@@ -443,15 +456,19 @@ __device__ __forceinline__ void residual_flush(double psum, double pmin, double 
         pmax = fmax(pmax, __shfl_xor(pmax, o, 64));
     }
     nbad = wave_sum(nbad);
+    pnm = wave_max(pnm);
     __shared__ double lds[kBlock / 64][3][4];
-    __shared__ double lds_bad[kBlock / 64];
+    __shared__ double lds_bad[kBlock / 64][2];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane < 4) {
         lds[wid][0][lane] = psum;
         lds[wid][1][lane] = pmin;
         lds[wid][2][lane] = pmax;
     }
-    if (lane == 0) lds_bad[wid] = nbad;
+    if (lane == 0) {
+        lds_bad[wid][0] = nbad;
+        lds_bad[wid][1] = pnm;
+    }
     __syncthreads();
     if (threadIdx.x < kNumPartial) {
         const int k = threadIdx.x >> 2, vv = threadIdx.x & 3;
@@ -462,42 +479,43 @@ __device__ __forceinline__ void residual_flush(double psum, double pmin, double 
         }
         dst[(size_t)threadIdx.x * stride] = acc;
     } else if (threadIdx.x == kNumPartial) {
-        double acc = lds_bad[0];
-        for (int w2 = 1; w2 < kBlock / 64; ++w2) acc += lds_bad[w2];
+        double acc = lds_bad[0][0];
+        for (int w2 = 1; w2 < kBlock / 64; ++w2) acc += lds_bad[w2][0];
         dst[(size_t)kColBad * stride] = acc;
+    } else if (threadIdx.x == kNumPartial + 1) {
+        double acc = lds_bad[0][1];
+        for (int w2 = 1; w2 < kBlock / 64; ++w2) acc = fmax(acc, lds_bad[w2][1]);
+        dst[(size_t)kNumPartial * stride] = acc;
     }
 }
 
-// Max of the lanes' values over the workgroup, written to *dst.
-__device__ __forceinline__ void max_flush(double best, double* dst) {
-    best = wave_max(best);
-    __shared__ double lds[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double acc = lds[0];
-        for (int w2 = 1; w2 < kBlock / 64; ++w2) acc = fmax(acc, lds[w2]);
-        *dst = acc;
-    }
-}
+// Per-lane accumulators of the filter pass: the max wave speed, counts and sum
+// |K| ubar of the lane's variable in registers; the boundary momentum flux A_1,
+// A_2, B_1, B_2 at the lane's edge points (rarely touched) in LDS, one slot per
+// thread, so that it holds no register through the OE.
+struct FilterAcc {
+    double amax = 0.0, n_lim = 0.0, n_bad = 0.0, n_flat = 0.0, msum = 0.0;
+};
+constexpr int kBookCols = 4;
 
-// Reduces the lanes' (max wave speed, limited, bad, flattened counts) over the
-// workgroup and writes entry k to dst[k * stride].
-__device__ __forceinline__ void filter_flush(double amax, double n_lim, double n_bad, double n_flat, double* dst,
+// Reduces the lanes' accumulators over the workgroup and writes entry k to
+// dst[k * stride]: max wave speed, limited, bad and flattened counts, sum |K| m1bar,
+// sum |K| m2bar, A_1, A_2, B_1, B_2.
+__device__ __forceinline__ void filter_flush(const FilterAcc& f, const double (&book)[kBookCols][kBlock], double* dst,
                                              size_t stride) {
-    amax = wave_max(amax);
-    n_lim = wave_sum(n_lim);
-    n_bad = wave_sum(n_bad);
-    n_flat = wave_sum(n_flat);
-    __shared__ double lds[kBlock / 64][4];
+    const int v = threadIdx.x & 3, t = threadIdx.x;
+    double x[kFilterCols] = {f.amax, f.n_lim, f.n_bad, f.n_flat, v == 1 ? f.msum : 0.0,
+                             v == 2 ? f.msum : 0.0, book[0][t], book[1][t], book[2][t], book[3][t]};
+    x[0] = wave_max(x[0]);
+#pragma unroll
+    for (int k = 1; k < kFilterCols; ++k) x[k] = wave_sum(x[k]);
+    __shared__ double lds[kBlock / 64][kFilterCols];
     if ((threadIdx.x & 63) == 0) {
-        lds[threadIdx.x >> 6][0] = amax;
-        lds[threadIdx.x >> 6][1] = n_lim;
-        lds[threadIdx.x >> 6][2] = n_bad;
-        lds[threadIdx.x >> 6][3] = n_flat;
+#pragma unroll
+        for (int k = 0; k < kFilterCols; ++k) lds[threadIdx.x >> 6][k] = x[k];
     }
     __syncthreads();
-    if (threadIdx.x < 4) {
+    if (threadIdx.x < kFilterCols) {
         const int k = threadIdx.x;
         double acc = lds[0][k];
         for (int w2 = 1; w2 < kBlock / 64; ++w2) acc = k == 0 ? fmax(acc, lds[w2][k]) : acc + lds[w2][k];
@@ -528,7 +546,7 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
     const int nc = a.m.n_cell;
     const size_t snc = (size_t)nc;
     const int v = threadIdx.x & 3;
-    const T s1 = v == 1 ? 1.0 : 0.0, s2 = v == 2 ? 1.0 : 0.0, s3 = v == 3 ? 1.0 : 0.0;
+    const T s3 = v == 3 ? 1.0 : 0.0;
     const T gm1 = (T)(a.gamma - 1.0);
     const double alpha = g->alpha, dt = g->dt;
     const double sa = a.stage == 0 ? 0.0 : (a.stage == 1 ? 0.75 : 1.0 / 3.0);
@@ -544,9 +562,31 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
     double* wa_p = wp.avg;
     T* wh_p = wp.hi;
     const Tab<K, T>& TB = tab<K, T>();
+    // The domain average of the momentum of the state this pass writes, known before
+    // it is written: the discrete divergence form conserves sum_K |K| ubar_K up to
+    // the flux through the boundary (each interior edge's flux enters its two cells
+    // with opposite signs), so
+    //   sum |K| mbar(w) = sa sum |K| mbar(u^n) + sb (sum |K| mbar(u_in) - dt (A + alpha B))
+    // with the sums and the boundary flux A + alpha B of the inputs recorded by the
+    // filter pass that produced them (sa = 0, sb = 1 in the first stage).  The pass
+    // then forms ||| m - mbar |||_inf of eq. normOmg at its own volume points, which
+    // saves a pass over the state; the result equals the direct average up to the
+    // rounding of the interior fluxes' cancellation.
+    // mbar is wave-uniform: moved to scalar registers, it holds no vector register
+    // through the flux loops
+    double mb[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const bool first = a.stage == 0;
+        const double s_in = first ? g->mom_n[j] : g->mom_c[j];
+        const double b_in = first ? g->bfa_n[j] + alpha * g->bfb_n[j] : g->bfa_c[j] + alpha * g->bfb_c[j];
+        const double s_w = s_in - dt * b_in;
+        mb[j] = uniform((first ? s_w : sa * g->mom_n[j] + sb * s_w) / g->area_sum);
+    }
 
     // one cell, owned by a quad of lanes: residual, SSP combination, partials
-    auto cell = [&](int c, double& psum, double& pmin, double& pmax, double& nbad) __attribute__((always_inline)) {
+    // pacc: lane 0 counts inadmissible averages, lane 1 keeps the max of |m - mbar|^2
+    auto cell = [&](int c, double& psum, double& pmin, double& pmax, double& pacc) __attribute__((always_inline)) {
         const double ua = ua_p[c];
         T u[NM];
         u[0] = (T)ua;
@@ -590,8 +630,8 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
             const T qv = dot<NM>(u, p);
             const T q0 = qget<0>(qv), q1 = qget<1>(qv), q2 = qget<2>(qv), q3 = qget<3>(qv);
             const T wa = TB.vw[m] * areaT;
-            const T g1 = wa * lane_flux(qv, q0, q1, q2, q3, xx, xy, gm1, s1, s2, s3);
-            const T g2 = wa * lane_flux(qv, q0, q1, q2, q3, ex, ey, gm1, s1, s2, s3);
+            const T g1 = wa * lane_flux(qv, q0, q1, q2, q3, xx, xy, gm1, v == 1 ? xx : (v == 2 ? xy : (T)0.0), s3);
+            const T g2 = wa * lane_flux(qv, q0, q1, q2, q3, ex, ey, gm1, v == 1 ? ex : (v == 2 ? ey : (T)0.0), s3);
 #pragma unroll
             for (int l = 1; l < NM; ++l) r[l] = fma(dx[l], g1, fma(de[l], g2, r[l]));
         }
@@ -603,6 +643,7 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
             const T gx = i == 0 ? -(xx + ex) : (i == 1 ? xx : ex);
             const T gy = i == 0 ? -(xy + ey) : (i == 1 ? xy : ey);
             const T lnx = (T)-2.0 * areaT * gx, lny = (T)-2.0 * areaT * gy;
+            const T sn = v == 1 ? lnx : (v == 2 ? lny : (T)0.0);   // the lane's normal component
             const T al = (T)(alpha * (i == 0 ? ln[0] : (i == 1 ? ln[1] : ln[2])));
             const int link = i == 0 ? lk[0] : (i == 1 ? lk[1] : lk[2]);
             const bool has = link >= 0;
@@ -622,7 +663,7 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
                 // neighbour's, ends swapped (the neighbour's parameter runs the other way)
                 const T il = (T)frcp(i == 0 ? ln[0] : (i == 1 ? ln[1] : ln[2]));
                 const T nxu = lnx * il, nyu = lny * il;
-                const T cn = (T)-2.0 * fma(s1, nxu, s2 * nyu);   // this lane's share of -2n
+                const T cn = (T)-2.0 * (sn * il);   // this lane's share of -2n
                 const T b0 = fma(cn, fma(qget<1>(n1), nxu, qget<2>(n1) * nyu), n1);
                 const T bm = fma(cn, fma(qget<1>(nm), nxu, qget<2>(nm) * nyu), nm);
                 const T b1 = fma(cn, fma(qget<1>(n0), nxu, qget<2>(n0) * nyu), n0);
@@ -642,10 +683,8 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
                     const T* lw = TB.nbw[nu];
                     qe = fma(lw[0], n0, fma(lw[1], nm, lw[2] * n1));
                 }
-                const T fi = lane_flux(qi, qget<0>(qi), qget<1>(qi), qget<2>(qi), qget<3>(qi), lnx, lny, gm1,
-                                       s1, s2, s3);
-                const T fe = lane_flux(qe, qget<0>(qe), qget<1>(qe), qget<2>(qe), qget<3>(qe), lnx, lny, gm1,
-                                       s1, s2, s3);
+                const T fi = lane_flux(qi, qget<0>(qi), qget<1>(qi), qget<2>(qi), qget<3>(qi), lnx, lny, gm1, sn, s3);
+                const T fe = lane_flux(qe, qget<0>(qe), qget<1>(qe), qget<2>(qe), qget<3>(qe), lnx, lny, gm1, sn, s3);
                 const T fh = wsn * (T)0.5 * (fi + fe - al * (qe - qi));
                 r0 -= (double)fh;
 #pragma unroll
@@ -663,7 +702,7 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
             // the OE filter and the limiter keep every average: an inadmissible one
             // here ends the step's attempt (it is retried with half the time step)
             const double q0 = qget<0>(w0), q1 = qget<1>(w0), q2 = qget<2>(w0), q3 = qget<3>(w0);
-            if (v == 0 && !(q0 > 0.0 && q3 - 0.5 * (q1 * q1 + q2 * q2) / q0 > 0.0)) nbad += 1.0;
+            if (v == 0 && !(q0 > 0.0 && q3 - 0.5 * (q1 * q1 + q2 * q2) / q0 > 0.0)) pacc += 1.0;
         }
         const T iaT = (T)ia, dtT = (T)dt, saT = (T)sa, sbT = (T)sb;
         T w[NM];
@@ -675,30 +714,37 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1)
             wh_p[(l - 1) * snc + c] = w[l];
         }
         psum += area * w0;
+        // |m - mbar|^2 at the volume points, in the bulk type like the point values
+        const T mb0 = (T)mb[0], mb1 = (T)mb[1];
+        T cnm = (T)0.0;
 #pragma unroll 1
         for (int m = 0; m < R::NQ; ++m) {
-            const double q = (double)dot<NM>(w, TB.vp[m]);
+            const T qt = dot<NM>(w, TB.vp[m]);
+            const double q = (double)qt;
             pmin = fmin(pmin, q);
             pmax = fmax(pmax, q);
+            const T d1 = qget<1>(qt) - mb0, d2 = qget<2>(qt) - mb1;
+            cnm = fmax(cnm, fma(d1, d1, d2 * d2));
         }
+        pacc = v == 1 ? fmax(pacc, (double)cnm) : pacc;
     };
     if constexpr (!kBatch) {
-        double psum = 0.0, pmin = INFINITY, pmax = -INFINITY, nbad = 0.0;
+        double psum = 0.0, pmin = INFINITY, pmax = -INFINITY, pacc = 0.0;
         const TileWalk tw = tile_walk((nc + kCellsPerTile - 1) / kCellsPerTile);
         for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
             const int c = tile * kCellsPerTile + (threadIdx.x >> 2);
-            if (c < nc) cell(c, psum, pmin, pmax, nbad);   // whole quad
+            if (c < nc) cell(c, psum, pmin, pmax, pacc);   // whole quad
         }
-        residual_flush(psum, pmin, pmax, nbad, a.part + blockIdx.x, kMaxBlocks);
+        residual_flush(psum, pmin, pmax, pacc, a.part + blockIdx.x, kMaxBlocks);
     } else {
         for (int gi = g0; gi < g1; ++gi) {
-            double psum = 0.0, pmin = INFINITY, pmax = -INFINITY, nbad = 0.0;
+            double psum = 0.0, pmin = INFINITY, pmax = -INFINITY, pacc = 0.0;
 #pragma unroll 1
             for (int tile = 0; tile < kGroupCells / kCellsPerTile; ++tile) {
                 const int c = gi * kGroupCells + tile * kCellsPerTile + (threadIdx.x >> 2);
-                if (c < nc) cell(c, psum, pmin, pmax, nbad);
+                if (c < nc) cell(c, psum, pmin, pmax, pacc);
             }
-            residual_flush(psum, pmin, pmax, nbad, a.part + a.gbase + gi, a.gstride);
+            residual_flush(psum, pmin, pmax, pacc, a.part + a.gbase + gi, a.gstride);
             __syncthreads();   // the flush's LDS is reused by the next group
         }
     }
@@ -719,76 +765,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_batch(const StageArgs* desc
     });
 }
 
-// ------------------------------------------------------------------------- pass 2: momentum norm
-
-template <int K, typename T, bool kBatch>
-__device__ __forceinline__ void mnorm_run(const StageArgs& a, int g0, int g1) {
-    using R = Rule<K>;
-    constexpr int NM = R::NM;
-    constexpr bool kMixed = std::is_same<T, float>::value;
-    const Glob* g = a.g;
-    const int nc = a.m.n_cell;
-    const size_t snc = (size_t)nc;
-    const double mb1 = g->ubar[1], mb2 = g->ubar[2];
-    // FP64: subtract mbar from the point value; mixed: from the FP64 average first
-    const T sh1 = kMixed ? (T)0.0 : (T)mb1, sh2 = kMixed ? (T)0.0 : (T)mb2;
-    const VarPtr<NM, T> p1 = var_ptr<NM, T>(a.w, a, 1, snc), p2 = var_ptr<NM, T>(a.w, a, 2, snc);
-    const double* a1 = p1.avg;
-    const double* a2 = p2.avg;
-    const T* h1 = p1.hi;
-    const T* h2 = p2.hi;
-    // one cell per lane: max |m - mbar|^2 over its volume points
-    auto cell = [&](int c, double& best) __attribute__((always_inline)) {
-        T m1[NM], m2[NM];
-        m1[0] = kMixed ? (T)(a1[c] - mb1) : (T)a1[c];
-        m2[0] = kMixed ? (T)(a2[c] - mb2) : (T)a2[c];
-#pragma unroll
-        for (int l = 1; l < NM; ++l) {
-            m1[l] = h1[(l - 1) * snc + c];
-            m2[l] = h2[(l - 1) * snc + c];
-        }
-#pragma unroll
-        for (int m = 0; m < R::NQ; ++m) {
-            const T* p = tab<K, T>().vp[m];
-            const T d1 = dot<NM>(m1, p) - sh1, d2 = dot<NM>(m2, p) - sh2;
-            best = fmax(best, (double)(d1 * d1 + d2 * d2));
-        }
-    };
-    static_assert(kCellsPerTileScalar == kGroupCells, "one scalar tile per reduction group");
-    if constexpr (!kBatch) {
-        double best = 0.0;
-        const TileWalk tw = tile_walk((nc + kCellsPerTileScalar - 1) / kCellsPerTileScalar);
-        for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
-            const int c = tile * kCellsPerTileScalar + threadIdx.x;
-            if (c < nc) cell(c, best);
-        }
-        max_flush(best, a.part + (size_t)kNumPartial * kMaxBlocks + blockIdx.x);
-    } else {
-        for (int gi = g0; gi < g1; ++gi) {
-            double best = 0.0;
-            const int c = gi * kGroupCells + threadIdx.x;
-            if (c < nc) cell(c, best);
-            max_flush(best, a.part + (size_t)kNumPartial * a.gstride + a.gbase + gi);
-            __syncthreads();
-        }
-    }
-}
-
-template <int K, typename T>
-__global__ __launch_bounds__(kBlock) void k_mnorm(StageArgs a) {
-    if (!a.g->active || a.g->skip) return;
-    mnorm_run<K, T, false>(a, 0, 0);
-}
-template <int KM, typename T>
-__global__ __launch_bounds__(kBlock) void k_mnorm_batch(const StageArgs* desc, const Chunk* chunks, ChunkSplit cs) {
-    for_each_chunk(desc, chunks, cs, [](const StageArgs& a, int g0, int g1) {
-        if constexpr (KM != 3) mnorm_run<KM, T, true>(a, g0, g1);
-        else if (a.k == 1) mnorm_run<1, T, true>(a, g0, g1);
-        else mnorm_run<2, T, true>(a, g0, g1);
-    });
-}
-
-// ------------------------------------------------------------------------- pass 3: OE, limiter, alpha
+// ------------------------------------------------------------------------- pass 2: OE, limiter, alpha
 
 // P2 physical Hessian (xx, xy, yy) of one variable with modes u[0..5] (constant per cell)
 template <typename T>
@@ -881,10 +858,10 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
     double* oa_p = op.avg;
     T* oh_p = op.hi;
     const Tab<K, T>& TB = tab<K, T>();
+    __shared__ double book[kBookCols][kBlock];   // the output's momentum bookkeeping (FilterAcc)
 
     // one cell, owned by a quad of lanes: OE, limiter, wave speed of the result
-    auto cell = [&](int c, double& amax, double& n_lim, double& n_bad, double& n_flat)
-                    __attribute__((always_inline)) {
+    auto cell = [&](int c, FilterAcc& f) __attribute__((always_inline)) {
         const double wa = wa_p[c];   // the average: untouched by the OE (eq. OE:m0) and the limiter
         T w[NM];
         w[0] = (T)wa;
@@ -895,7 +872,8 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
         for (int i = 0; i < 3; ++i) lk[i] = a.m.link[i * snc + c];
         const T xx = (T)a.m.jinv[c], xy = (T)a.m.jinv[snc + c];
         const T ex = (T)a.m.jinv[2 * snc + c], ey = (T)a.m.jinv[3 * snc + c];
-        const T area = (T)a.m.area[c];
+        const double area_d = a.m.area[c];
+        const T area = (T)area_d;
         // unit outward normals n_i = l_i n_i / l_i with l_i n_i = -2|K| grad(lambda_i)
         T nxs[3], nys[3], ils[3];
 #pragma unroll
@@ -1096,8 +1074,8 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
                 }
             }
             if (v == 0) {
-                n_lim += (th1 < 1.0 || th2 < 1.0) ? 1.0 : 0.0;
-                n_bad += (ub0 > 0.0 && eb > 0.0) ? 0.0 : 1.0;
+                f.n_lim += (th1 < 1.0 || th2 < 1.0) ? 1.0 : 0.0;
+                f.n_bad += (ub0 > 0.0 && eb > 0.0) ? 0.0 : 1.0;
             }
             if constexpr (kMixed) {
                 if (th1 < 1.0 || th2 < 1.0) {   // the same in the four lanes of the quad
@@ -1118,14 +1096,17 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
                             pv[kk][2] = ub2;
                             pv[kk][3] = ub3;
                         }
-                        if (v == 0) n_flat += 1.0;
+                        if (v == 0) f.n_flat += 1.0;
                     }
                 }
             }
         }
 
         // max wave speed over the edge Gauss points of the limited state (eq. 1250);
-        // in the mixed form pv already holds the stored state's values
+        // in the mixed form pv already holds the stored state's values.  At a
+        // boundary edge the point also adds its momentum flux l w_nu F.n, as the
+        // next residual pass will take it, to the output's bookkeeping:
+        // transmissive F(u).n; reflective ((m.n)^2/rho + p) n plus alpha (m.n) n.
         const double ta = kMixed ? 1.0 : th2;
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) {
@@ -1137,32 +1118,64 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
                 const double rr = spectral_radius(ub0 + ta * (pv[kk][0] - ub0), ub1 + ta * (pv[kk][1] - ub1),
                                                   ub2 + ta * (pv[kk][2] - ub2), ub3 + ta * (pv[kk][3] - ub3), nx,
                                                   ny, gamma);
-                amax = (rr > amax || rr != rr) ? rr : amax;
+                f.amax = (rr > f.amax || rr != rr) ? rr : f.amax;
             }
         }
+        if (lk[0] < 0 || lk[1] < 0 || lk[2] < 0) {
+#pragma unroll
+            for (int kk = 0; kk < 3; ++kk) {
+                const int t = v + 4 * kk;
+                const int i = t / NE;
+                const int link = i == 0 ? lk[0] : (i == 1 ? lk[1] : lk[2]);
+                if (t < 3 * NE && link < 0) {
+                    const double nx = (double)(i == 0 ? nxs[0] : (i == 1 ? nxs[1] : nxs[2]));
+                    const double ny = (double)(i == 0 ? nys[0] : (i == 1 ? nys[1] : nys[2]));
+                    const double q0 = ub0 + ta * (pv[kk][0] - ub0), q1 = ub1 + ta * (pv[kk][1] - ub1);
+                    const double q2 = ub2 + ta * (pv[kk][2] - ub2), q3 = ub3 + ta * (pv[kk][3] - ub3);
+                    const int nu = t - i * NE, th = threadIdx.x;
+                    const double lw = a.m.len[i * snc + c] * (nu == 0 ? R::ws[0] : (nu == 1 ? R::ws[1] : R::ws[2]));
+                    const double ir = frcp(q0);
+                    const double mn = q1 * nx + q2 * ny;
+                    const double p = (gamma - 1.0) * (q3 - 0.5 * (q1 * q1 + q2 * q2) * ir);
+                    if (link == kLinkWall) {
+                        const double ca = lw * (mn * mn * ir + p), cb = lw * mn;
+                        book[0][th] += ca * nx;
+                        book[1][th] += ca * ny;
+                        book[2][th] += cb * nx;
+                        book[3][th] += cb * ny;
+                    } else {
+                        book[0][th] += lw * (q1 * mn * ir + p * nx);
+                        book[1][th] += lw * (q2 * mn * ir + p * ny);
+                    }
+                }
+            }
+        }
+        f.msum = fma(area_d, wa, f.msum);   // sum |K| ubar of this lane's variable
         oa_p[c] = wa;
 #pragma unroll
         for (int l = 1; l < NM; ++l) oh_p[(l - 1) * snc + c] = w[l];
     };
     if constexpr (!kBatch) {
-        double amax = 0.0, n_lim = 0.0, n_bad = 0.0, n_flat = 0.0;
+        FilterAcc f;
+#pragma unroll
+        for (int k = 0; k < kBookCols; ++k) book[k][threadIdx.x] = 0.0;
         const TileWalk tw = tile_walk((nc + kCellsPerTile - 1) / kCellsPerTile);
         for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
             const int c = tile * kCellsPerTile + (threadIdx.x >> 2);
-            if (c < nc) cell(c, amax, n_lim, n_bad, n_flat);   // whole quad
+            if (c < nc) cell(c, f);   // whole quad
         }
-        filter_flush(amax, n_lim, n_bad, n_flat, a.part + (size_t)(kNumPartial + 1) * kMaxBlocks + blockIdx.x,
-                     kMaxBlocks);
+        filter_flush(f, book, a.part + (size_t)(kNumPartial + 1) * kMaxBlocks + blockIdx.x, kMaxBlocks);
     } else {
         for (int gi = g0; gi < g1; ++gi) {
-            double amax = 0.0, n_lim = 0.0, n_bad = 0.0, n_flat = 0.0;
+            FilterAcc f;
+#pragma unroll
+            for (int k = 0; k < kBookCols; ++k) book[k][threadIdx.x] = 0.0;
 #pragma unroll 1
             for (int tile = 0; tile < kGroupCells / kCellsPerTile; ++tile) {
                 const int c = gi * kGroupCells + tile * kCellsPerTile + (threadIdx.x >> 2);
-                if (c < nc) cell(c, amax, n_lim, n_bad, n_flat);
+                if (c < nc) cell(c, f);
             }
-            filter_flush(amax, n_lim, n_bad, n_flat,
-                         a.part + (size_t)(kNumPartial + 1) * a.gstride + a.gbase + gi, a.gstride);
+            filter_flush(f, book, a.part + (size_t)(kNumPartial + 1) * a.gstride + a.gbase + gi, a.gstride);
             __syncthreads();
         }
     }
@@ -1242,11 +1255,13 @@ __device__ __forceinline__ void reduce_columns(const double* base, size_t cstrid
 // domain averages and L-infinity norms (eq. normOmg): ||u - ubar|| = max(max u - ubar, ubar - min u)
 // An inadmissible average ends this attempt of the step: `skip` turns the rest
 // of it into no-ops (u^n is untouched) until the third stage's finalize.
+// and ||| m - mbar |||_inf (eqs. normOmg, RIOESys:Coef1) with its zero branch
 __device__ __forceinline__ void fin_residual(const double* base, size_t cstride, int G, Glob* g) {
-    double tot[kNumPartial + 1];   // 4 sums, 4 mins, 4 maxima, then the bad-average count
-    reduce_columns<kNumPartial + 1>(base, cstride, G, 0, 0xAA5500u, tot, kColBad);
+    // 4 sums, 4 mins, 4 maxima, the max of |m - mbar|^2, then the bad-average count
+    double tot[kNumPartial + 2];
+    reduce_columns<kNumPartial + 2>(base, cstride, G, 0, 0x2AA5500u, tot, kColBad);
     if (threadIdx.x == 0) {
-        if (tot[kNumPartial] > 0.0) g->skip = 1;
+        if (tot[kNumPartial + 1] > 0.0) g->skip = 1;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const double ub = tot[v] / g->area_sum;
@@ -1255,15 +1270,7 @@ __device__ __forceinline__ void fin_residual(const double* base, size_t cstride,
             g->nrm[v] = n;
             g->inv_nrm[v] = n <= kEpsOE * fmax(1.0, fabs(ub)) ? 0.0 : 1.0 / n;
         }
-    }
-}
-
-__device__ __forceinline__ void fin_mnorm(const double* base, size_t cstride, int G, Glob* g) {
-    if (g->skip) return;
-    double best[1];
-    reduce_columns<1>(base, cstride, G, kNumPartial, 2u, best);
-    if (threadIdx.x == 0) {
-        const double n = sqrt(best[0]);
+        const double n = sqrt(tot[kNumPartial]);
         const double mb = sqrt(g->ubar[1] * g->ubar[1] + g->ubar[2] * g->ubar[2]);
         g->nrm_m = n;
         g->inv_nrm_m = n <= kEpsOE * fmax(1.0, mb) ? 0.0 : 1.0 / n;
@@ -1291,10 +1298,23 @@ __device__ __forceinline__ void fin_filter(const double* base, size_t cstride, i
         }
         return;
     }
-    double r[4];
-    reduce_columns<4>(base, cstride, G, kNumPartial + 1, 2u, r);   // max, then three sums
+    double r[kFilterCols];
+    reduce_columns<kFilterCols>(base, cstride, G, kNumPartial + 1, 2u, r);   // max, then sums
     if (threadIdx.x != 0) return;
     const double alpha = r[0], lim = r[1], bad = r[2];
+    // the output's momentum bookkeeping; after the third stage (or the initial
+    // limiter pass) the output is u^n
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        g->mom_c[j] = r[4 + j];
+        g->bfa_c[j] = r[6 + j];
+        g->bfb_c[j] = r[8 + j];
+        if (stage < 0 || stage == 2) {
+            g->mom_n[j] = r[4 + j];
+            g->bfa_n[j] = r[6 + j];
+            g->bfb_n[j] = r[8 + j];
+        }
+    }
     g->n_limited += (long long)lim;
     g->n_bad += (long long)bad;
     g->n_flat += (long long)r[3];
@@ -1324,9 +1344,6 @@ __device__ __forceinline__ void fin_filter(const double* base, size_t cstride, i
 __global__ __launch_bounds__(kFinThreads) void k_fin_residual(const double* part, int G, Glob* g) {
     if (g->active) fin_residual(part, kMaxBlocks, G, g);
 }
-__global__ __launch_bounds__(kFinThreads) void k_fin_mnorm(const double* part, int G, Glob* g) {
-    if (g->active) fin_mnorm(part, kMaxBlocks, G, g);
-}
 __global__ __launch_bounds__(kFinThreads) void k_fin_filter(const double* part, int G, Glob* g, int stage) {
     if (g->active) fin_filter(part, kMaxBlocks, G, g, stage);
 }
@@ -1335,10 +1352,6 @@ __global__ __launch_bounds__(kFinThreads) void k_fin_filter(const double* part, 
 __global__ __launch_bounds__(kFinThreads) void k_fin_residual_batch(const StageArgs* desc) {
     const StageArgs& a = desc[blockIdx.x];
     if (a.g->active) fin_residual(a.part + a.gbase, a.gstride, n_groups(a.m.n_cell), a.g);
-}
-__global__ __launch_bounds__(kFinThreads) void k_fin_mnorm_batch(const StageArgs* desc) {
-    const StageArgs& a = desc[blockIdx.x];
-    if (a.g->active) fin_mnorm(a.part + a.gbase, a.gstride, n_groups(a.m.n_cell), a.g);
 }
 __global__ __launch_bounds__(kFinThreads) void k_fin_filter_batch(const StageArgs* desc) {
     const StageArgs& a = desc[blockIdx.x];
@@ -1477,13 +1490,12 @@ __global__ void k_gather_status(const StageArgs* desc, int n, double* out) {
 
 // host handles of the instantiations of one (degree, precision)
 struct KernelSet {
-    const void* pass[3];   // residual, momentum norm, filter
+    const void* pass[kNumPasses];   // residual, filter
     const void* project;
 };
 template <int K, typename T>
 KernelSet kernel_set() {
-    return {{reinterpret_cast<const void*>(&k_residual<K, T>), reinterpret_cast<const void*>(&k_mnorm<K, T>),
-             reinterpret_cast<const void*>(&k_filter<K, T>)},
+    return {{reinterpret_cast<const void*>(&k_residual<K, T>), reinterpret_cast<const void*>(&k_filter<K, T>)},
             reinterpret_cast<const void*>(&k_project<K, T>)};
 }
 const KernelSet& kernels_for(int k, int mixed) {
@@ -1494,12 +1506,11 @@ const KernelSet& kernels_for(int k, int mixed) {
 
 // host handles of the batched pass instantiations of one (degree mask, precision)
 struct BatchSet {
-    const void* pass[3];   // residual, momentum norm, filter
+    const void* pass[kNumPasses];   // residual, filter
 };
 template <int KM, typename T>
 BatchSet batch_set() {
     return {{reinterpret_cast<const void*>(&k_residual_batch<KM, T>),
-             reinterpret_cast<const void*>(&k_mnorm_batch<KM, T>),
              reinterpret_cast<const void*>(&k_filter_batch<KM, T>)}};
 }
 const BatchSet& batch_kernels(int kmask, int mixed) {
@@ -1540,23 +1551,19 @@ int launch_pass(int which, int k, const StageArgs& a, void* stream) {
 }  // namespace
 
 int grid_for_pass(int which, int k, int mixed, int n_cell) {
-    const int per_tile = which == 1 ? kCellsPerTileScalar : kCellsPerTile;
-    const int tiles = (n_cell + per_tile - 1) / per_tile;
+    const int tiles = (n_cell + kCellsPerTile - 1) / kCellsPerTile;
     const int want = std::max(8, ((tiles + 7) / 8) * 8);
     return std::min(want, resident_blocks(kernels_for(k, mixed).pass[which]));
 }
 
-int launch_residual(int k, const StageArgs& a, void* stream) { return launch_pass(0, k, a, stream); }
-int launch_mnorm(int k, const StageArgs& a, void* stream) { return launch_pass(1, k, a, stream); }
-int launch_filter(int k, const StageArgs& a, void* stream) { return launch_pass(2, k, a, stream); }
+int launch_residual(int k, const StageArgs& a, void* stream) { return launch_pass(kPassResidual, k, a, stream); }
+int launch_filter(int k, const StageArgs& a, void* stream) { return launch_pass(kPassFilter, k, a, stream); }
 
 int launch_finalize(int which, int k, const StageArgs& a, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     const int G = grid_for_pass(which, k, a.mixed, a.m.n_cell);
-    if (which == 0)
+    if (which == kPassResidual)
         hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(kFinThreads), 0, s, a.part, G, a.g);
-    else if (which == 1)
-        hipLaunchKernelGGL(k_fin_mnorm, dim3(1), dim3(kFinThreads), 0, s, a.part, G, a.g);
     else
         hipLaunchKernelGGL(k_fin_filter, dim3(1), dim3(kFinThreads), 0, s, a.part, G, a.g, a.stage);
     return (int)hipGetLastError();
@@ -1587,8 +1594,7 @@ int launch_pass_batch(int which, int kmask, int mixed, const StageArgs* desc, co
 
 int launch_finalize_batch(int which, const StageArgs* desc, int n_inst, void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    if (which == 0) hipLaunchKernelGGL(k_fin_residual_batch, dim3(n_inst), dim3(kFinThreads), 0, s, desc);
-    else if (which == 1) hipLaunchKernelGGL(k_fin_mnorm_batch, dim3(n_inst), dim3(kFinThreads), 0, s, desc);
+    if (which == kPassResidual) hipLaunchKernelGGL(k_fin_residual_batch, dim3(n_inst), dim3(kFinThreads), 0, s, desc);
     else hipLaunchKernelGGL(k_fin_filter_batch, dim3(n_inst), dim3(kFinThreads), 0, s, desc);
     return (int)hipGetLastError();
 }

@@ -9,11 +9,11 @@ namespace oedg {
 
 constexpr int kBlock = 256;            // threads per workgroup of the stage kernels
 constexpr int kCellsPerTile = 64;      // a quad of 4 lanes per cell in the residual/filter passes
-constexpr int kCellsPerTileScalar = 256;   // one lane per cell in the momentum-norm pass
 constexpr int kMaxBlocks = 4096;       // upper bound of a single-instance pass grid (= partials)
 constexpr int kGroupCells = 256;       // cells per reduction group of the batched passes
 constexpr int kNumPartial = 12;        // partials of the residual pass per group
-constexpr int kPartCols = kNumPartial + 1 + 4 + 1;   // + momentum norm, 4 filter partials, bad averages
+constexpr int kFilterCols = 10;        // partials of the filter pass per group
+constexpr int kPartCols = kNumPartial + 1 + kFilterCols + 1;   // + momentum norm, filter, bad averages
 constexpr int kColBad = kPartCols - 1;   // residual pass: cells whose average left the admissible set
 
 // Reduction groups of an instance in the batched passes: cells [g * kGroupCells,
@@ -71,6 +71,13 @@ struct Glob {
     long long n_cfl_exc;
     long long n_flat;    // mixed precision: cells reset to their average by the rounding check
     long long n_restarts;   // steps retried with half the time step
+    // Momentum bookkeeping that gives the residual pass the domain average of the
+    // state it is about to write (see the residual kernel): sum_K |K| mbar_K of a
+    // limited state, and the momentum flux through the boundary edges that the
+    // residual of that state will see, as A + alpha B (B: the reflective edges'
+    // viscosity term).  _c: the last filter output; _n: u^n.
+    double mom_c[2], bfa_c[2], bfb_c[2];
+    double mom_n[2], bfa_n[2], bfb_n[2];
     int skip;            // a stage of this step left the admissible set: the rest of the step is skipped
     int restarts;        // retries of the current step so far
     int max_restarts;
@@ -105,8 +112,8 @@ struct StageArgs {
     StateView w;          // pre-filter state (written by the residual pass)
     StateView uout;       // limited stage output
     size_t avs, hvs;      // variable strides of the averages and of the higher modes
-    double* part;         // partial records, column-major; columns 0-11 residual, 12
-                          // momentum norm, 13-16 filter.  Single-instance passes:
+    double* part;         // partial records, column-major; columns 0-12 residual (12:
+                          // momentum norm), 13-22 filter.  Single-instance passes:
                           // column j of workgroup b at part[j * kMaxBlocks + b].
                           // Batched passes: column j of group g of this instance at
                           // part[j * gstride + gbase + g].
@@ -131,8 +138,11 @@ struct ChunkSplit {
     int b[9];
 };
 
+// the passes of a stage
+constexpr int kPassResidual = 0, kPassFilter = 1, kNumPasses = 2;
+
 // ---- single instance: persistent passes over the instance's tiles
-// Grid of pass `which` (0 residual, 1 momentum norm, 2 filter) at degree k and
+// Grid of pass `which` (kPassResidual, kPassFilter) at degree k and
 // precision `mixed`: a multiple of 8 (one share per XCD), at most kMaxBlocks and
 // at most what is resident at once; workgroups stride over their XCD's tiles.
 int grid_for_pass(int which, int k, int mixed, int n_cell);
@@ -140,9 +150,8 @@ int grid_for_pass(int which, int k, int mixed, int n_cell);
 // int.  Each pass kernel writes per-workgroup partials; the matching finalize
 // kernel (one workgroup) reduces them in a fixed order into Glob.
 int launch_residual(int k, const StageArgs& a, void* stream);
-int launch_mnorm(int k, const StageArgs& a, void* stream);
 int launch_filter(int k, const StageArgs& a, void* stream);
-int launch_finalize(int which, int k, const StageArgs& a, void* stream);   // 0 residual, 1 mnorm, 2 filter
+int launch_finalize(int which, int k, const StageArgs& a, void* stream);   // which: kPassResidual, kPassFilter
 
 // ---- batch: passes over a chunk table of several instances
 // Workgroups of batched pass `which` resident at once for degree mask kmask

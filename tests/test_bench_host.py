@@ -19,23 +19,23 @@ def test_algorithmic_bytes_per_cell():
     """P2 FP64: S = 4 x 6 x 8 = 192 B; geometry 76 B (J^-1, |K|, lengths, links) and
     +32 B of limiter-point coordinates in the filter.  Mixed: S = 4 x (8 + 5 x 4) = 112 B."""
     b = bench.algorithmic_bytes_per_cell(2, "fp64")
+    assert set(b) == {"residual", "filter"}
     assert b["residual"] == pytest.approx(192 + 76 + 192 + 2 / 3 * 192)   # 588 B
-    assert b["mnorm"] == 2 * 48
     assert b["filter"] == 192 + 108 + 192                                  # 492 B
     m = bench.algorithmic_bytes_per_cell(2, "mixed")
     assert m["residual"] == pytest.approx(112 + 76 + 112 + 2 / 3 * 112)
-    assert m["mnorm"] == 2 * 28 and m["filter"] == 112 + 108 + 112
+    assert m["filter"] == 112 + 108 + 112
     p1 = bench.algorithmic_bytes_per_cell(1, "fp64")
     assert p1["filter"] == 96 + 108 + 96
-    # per DOF-stage at P2 FP64 (24 DOF per cell): 1176 B / 24 = 49 B
-    assert sum(b.values()) / 24 == pytest.approx(49.0)
+    # per DOF-stage at P2 FP64 (24 DOF per cell): 1080 B / 24 = 45 B
+    assert sum(b.values()) / 24 == pytest.approx(45.0)
 
 
 def test_roofline_from_profile():
     """achieved = algorithmic bytes per launch / mean launch time of the kernel with the
     largest total time; frac against 8 TB/s."""
     n_cell = 100_000
-    prof = {"residual": (50e-3 * 30, 30), "mnorm": (9e-3 * 30, 30), "filter": (60e-3 * 30, 30)}
+    prof = {"residual": (50e-3 * 30, 30), "filter": (60e-3 * 30, 30)}
     roof, per_k = bench.roofline(prof, 2, n_cell, "no_such_workload", "fp64")
     assert roof["kernel"] == "filter" and roof["bound"] == "hbm" and roof["unit"] == "GB/s"
     alg = 492 * n_cell
@@ -44,7 +44,7 @@ def test_roofline_from_profile():
     assert roof["peak"] == 8000.0
     assert roof["frac"] == pytest.approx(roof["achieved"] / 8000.0, rel=1e-3)
     assert roof["traffic"] is None                  # no counters for this workload
-    assert set(per_k) == {"residual", "mnorm", "filter"}
+    assert set(per_k) == {"residual", "filter"}
 
 
 def test_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):
@@ -59,7 +59,7 @@ def test_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):
     rec["workloads"]["w"]["filter"]["valu"] = {"insts_per_launch": 7, "busy_frac": 0.5, "clock_ghz": 2.1}
     f.write_text(json.dumps(rec))
     assert bench.load_valu("filter", "w") == {"insts_per_launch": 7, "busy_frac": 0.5, "clock_ghz": 2.1}
-    prof = {"residual": (0.05, 1), "mnorm": (0.009, 1), "filter": (0.06, 1)}
+    prof = {"residual": (0.05, 1), "filter": (0.06, 1)}
     roof, _ = bench.roofline(prof, 2, 1000, "w", "fp64")
     assert roof["traffic"] == 123 and roof["valu"]["busy_frac"] == 0.5
     rec["kernel_source_sha"] = "0" * 16              # counters of other kernel sources
