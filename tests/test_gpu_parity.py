@@ -121,6 +121,10 @@ def test_stage_by_stage_parity(case):
             e_pre = rel_err(pre, o.state(2))
             e_out = rel_err(out, o.state(1))
             assert e_pre < tol and e_out < tol, (step, st, e_pre, e_out, tol)
+            # ||| m - mbar |||_inf of the pre-filter state: the GPU takes mbar from the
+            # conservation bookkeeping, the oracle sums the averages directly
+            n_gpu, n_orc = s.diag()["nrm_m"], o.scalars()["nrm_m"]
+            assert abs(n_gpu - n_orc) <= 10.0 * tol * np.abs(o.state(2)[1:3]).max(), (step, st, n_gpu, n_orc)
         o.finish_step()
         d, so = s.diag(), o.scalars()
         assert abs(d["t"] - so["t"]) <= 1e-14 * max(1.0, so["t"])

@@ -113,6 +113,10 @@ def test_stage_parity(case):
             e_out = rel_err(s.read_state(1), want_out)
             say(f"  step {step} stage {st}: pre {e_pre:.2e} out {e_out:.2e} tol {tol:.2e}")
             assert e_pre < tol and e_out < tol, (step, st, e_pre, e_out, tol)
+            # the momentum norm (mbar from the conservation bookkeeping on the GPU, the
+            # direct average in the oracle's OE of want_pre)
+            n_gpu, n_orc = s.diag()["nrm_m"], o.scalars()["nrm_m"]
+            assert abs(n_gpu - n_orc) <= 10.0 * tol * np.abs(want_pre[1:3]).max(), (step, st, n_gpu, n_orc)
         d = s.diag()
         ug = s.readback()[0]
         ag = o.alpha_of(ug)
