@@ -168,8 +168,8 @@ int launch_finalize_batch(int which, const StageArgs* desc, int n_inst, void* st
 int launch_project(int k, const StageArgs& a, int kind, const double* dparams, int n_params, const double* vx,
                    void* stream);
 int launch_set_end(Glob* g, double t_end, void* stream);
-// Copies {active, err, t, step} of every instance of desc[0..n) into out[4 n].
-// per member: active, err, t, step, Delta t, t_end
+// Copies the status of every instance of desc[0..n) into out[kStatusCols n]; per
+// member: active, err, t, step, Delta t, t_end
 constexpr int kStatusCols = 6;
 int launch_gather_status(const StageArgs* desc, int n, double* out, void* stream);
 
