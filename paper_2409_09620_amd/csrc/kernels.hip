@@ -1186,15 +1186,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     if (!a.g->active || a.g->skip) return;
     filter_run<K, T, false>(a, 0, 0);
 }
-// (no occupancy request: with the chunk indirection a 168-VGPR budget spills)
+// FP64: no occupancy request (with the chunk indirection a 168-VGPR budget spills
+// heavily); mixed: three waves per SIMD
 template <int KM, typename T>
-__global__ __launch_bounds__(kBlock) void k_filter_batch(
-    const StageArgs* desc, const Chunk* chunks, ChunkSplit cs) {
+__device__ __forceinline__ void filter_batch_body(const StageArgs* desc, const Chunk* chunks, const ChunkSplit& cs) {
     for_each_chunk(desc, chunks, cs, [](const StageArgs& a, int g0, int g1) {
         if constexpr (KM != 3) filter_run<KM, T, true>(a, g0, g1);
         else if (a.k == 1) filter_run<1, T, true>(a, g0, g1);
         else filter_run<2, T, true>(a, g0, g1);
     });
+}
+template <int KM, typename T>
+__global__ __launch_bounds__(kBlock) void k_filter_batch(const StageArgs* desc, const Chunk* chunks, ChunkSplit cs) {
+    filter_batch_body<KM, T>(desc, chunks, cs);
+}
+template <int KM>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_filter_batch_mixed(
+    const StageArgs* desc, const Chunk* chunks, ChunkSplit cs) {
+    filter_batch_body<KM, float>(desc, chunks, cs);
 }
 
 // ------------------------------------------------------------------------- finalize (one workgroup)
@@ -1510,8 +1519,10 @@ struct BatchSet {
 };
 template <int KM, typename T>
 BatchSet batch_set() {
-    return {{reinterpret_cast<const void*>(&k_residual_batch<KM, T>),
-             reinterpret_cast<const void*>(&k_filter_batch<KM, T>)}};
+    const void* filter;
+    if constexpr (std::is_same<T, float>::value) filter = reinterpret_cast<const void*>(&k_filter_batch_mixed<KM>);
+    else filter = reinterpret_cast<const void*>(&k_filter_batch<KM, T>);
+    return {{reinterpret_cast<const void*>(&k_residual_batch<KM, T>), filter}};
 }
 const BatchSet& batch_kernels(int kmask, int mixed) {
     static const BatchSet sets[3][2] = {{batch_set<1, double>(), batch_set<1, float>()},
