@@ -262,6 +262,14 @@ def test_full_size_quadrant_one_step(n_cells):
     ref = o.state(0)
     assert rel_err(u, ref) < 1e-11
     assert rel_l1(u, ref) < 1e-13
+    # the momentum norm of the last pre-filter state at full size: mbar from the
+    # conservation bookkeeping (GPU) against the direct average (oracle's OE on the
+    # GPU's own pre-filter state)
+    pre = s.read_state(2)
+    o.oe(pre, s.diag()["dt"])
+    n_gpu, n_orc = s.diag()["nrm_m"], o.scalars()["nrm_m"]
+    say(f"  nrm_m GPU {n_gpu:.17g} oracle {n_orc:.17g}")
+    assert abs(n_gpu - n_orc) <= 1e-12 * max(n_orc, np.abs(pre[1:3]).max())
 
 
 def test_full_size_blast_one_step():
