@@ -267,17 +267,18 @@ __device__ __forceinline__ double frcp(double x) {
 // correction.  v_rsq_f64 is within 2^-23 relative; the Goldschmidt step squares
 // that error and the correction squares it again, below the rounding of the last
 // FMA, so the result is within 1 ulp (correctly rounded in a 4M-sample check on
-// gfx950, where v_rsq_f64 stayed within 2^-24)
+// gfx950, where v_rsq_f64 stayed within 2^-24).  Arguments below 1e-300 (zero, and
+// NaN) give 1e-150: every use adds the root to O(1) terms or scales a damping rate,
+// where that is exactly nothing, and it spares the zero test and its selects.
 __device__ __forceinline__ double fsqrt(double x) {
-    const double xs = x > 0.0 ? x : 1.0;
+    const double xs = fmax(x, 1e-300);
     const double y = __builtin_amdgcn_rsq(xs);
     double g = xs * y, h = 0.5 * y;
     const double r = fma(-g, h, 0.5);
     g = fma(g, r, g);
     h = fma(h, r, h);
     const double d = fma(-g, g, xs);
-    g = fma(d, h, g);
-    return x > 0.0 ? g : 0.0;
+    return fma(d, h, g);
 }
 
 // reciprocal, square root (0 for x <= 0), exponential and quotient in the bulk type
