@@ -111,6 +111,11 @@ def load_library():
     if _lib is None:
         if not os.path.exists(_LIB):
             raise RuntimeError(f"HIP library {_LIB} is not built; run __graft_entry__.build()")
+        # torch first: its HIP runtime then satisfies the library's libamdhip64
+        # dependency, so the process holds one runtime, the one that owns the
+        # workspace and the streams.  Loaded the other way round, the library
+        # binds a second runtime, which finds no device once torch's has the GPU.
+        import torch  # noqa: F401
         L = ctypes.CDLL(_LIB)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)

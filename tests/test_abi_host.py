@@ -165,3 +165,21 @@ def test_header_constants_match_the_binding():
             assert binding.STATUS[val] == name
         else:
             assert getattr(binding, name) == val, name
+
+
+def test_library_loads_after_torch_in_a_fresh_process():
+    """The serving admission check sizes a request through the library before any
+    solver exists; the library must still come up on torch's HIP runtime, the only
+    one mapped into the process (a second runtime sees no device)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2409_09620_amd.serving import footprint_bytes\n"
+            "assert 'torch' not in sys.modules\n"
+            "assert footprint_bytes(1000, 2) > 0\n"
+            "assert 'torch' in sys.modules\n"
+            "hip = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "assert len(hip) == 1 and 'torch' in next(iter(hip)), hip\n" % root)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
