@@ -183,6 +183,25 @@ dg_status dg_init_problem(dg_ctx* ctx, const dg_config* cfg, int kind, const dou
  * Delta t.  No host synchronisation. */
 dg_status dg_stage(dg_ctx* ctx, int s);
 
+/* dg_stage without device memory of its own, for callers that cannot allocate
+ * (code under HIP graph capture, serving loops that forbid allocation): the same
+ * kernels in the same order, with the per-workgroup partial records of the two
+ * domain reductions in a device array of the library instead of the context's
+ * workspace.  Results are bit-identical to dg_stage.
+ *   The array holds the records of at most 4096 workgroups per pass (24 doubles
+ * each, 786,432 bytes per GPU); each GPU the library runs on keeps its own copy
+ * until the process ends.  Its address is looked up once per device, at
+ * dg_create (or at the first call on the device).  The passes size their grids
+ * by occupancy, at most 4096 workgroups, so every mesh fits; a grid beyond the
+ * array returns DG_E_ARG.  Every workgroup writes its whole record before the
+ * reduction reads it, so nothing needs clearing between calls.
+ *   The call performs no hipMalloc, hipFree or other allocation and does not
+ * synchronise.  All calls on one GPU share its array: calls that overlap on
+ * that GPU (other streams, other host threads, other contexts) race and give
+ * wrong results; calls ordered on one stream do not.
+ * Errors: as dg_stage; DG_E_HIP if the array's address cannot be obtained. */
+dg_status dg_stage_noalloc(dg_ctx* ctx, int s);
+
 /* One full step (three stages).  If dt_out is not NULL the stream is
  * synchronised and the step's Delta t is written there. */
 dg_status dg_step(dg_ctx* ctx, double* dt_out);

@@ -81,6 +81,7 @@ _SIGS = {
     "dg_init": (_c_i, [_c_p, _c_p, _c_p]),
     "dg_init_problem": (_c_i, [_c_p, _c_p, _c_i, _c_p, _c_i]),
     "dg_stage": (_c_i, [_c_p, _c_i]),
+    "dg_stage_noalloc": (_c_i, [_c_p, _c_i]),
     "dg_step": (_c_i, [_c_p, _c_p]),
     "dg_step_to": (_c_i, [_c_p, _c_d, _c_i64, _c_p]),
     "dg_readback": (_c_i, [_c_p, _c_p, _c_p, _c_p]),
@@ -230,6 +231,11 @@ class Solver:
 
     def stage(self, s):
         self._check(load_library().dg_stage(self.h, int(s)))
+
+    def stage_noalloc(self, s):
+        """dg_stage with the partial records in the library's device array
+        (no device memory of its own; calls overlapping on one GPU race)."""
+        self._check(load_library().dg_stage_noalloc(self.h, int(s)))
 
     def set_t_end(self, t_end):
         """Stop time of this instance's run (also when stepped inside a Batch)."""

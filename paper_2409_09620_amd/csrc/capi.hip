@@ -359,6 +359,9 @@ dg_status dg_create(dg_ctx** out, int hip_device, void* hip_stream) {
     c->device = hip_device;
     c->stream = (hipStream_t)hip_stream;
     dg_config_default(&c->cfg);
+    // the device's partial-record array of dg_stage_noalloc, looked up once per
+    // device with the device current (a failure surfaces there, not here)
+    (void)oedg::scratch_address(hip_device, &c->scratch);
     *out = c;
     return DG_OK;
 }
@@ -532,6 +535,34 @@ dg_status dg_stage(dg_ctx* c, int s) {
     if (st != DG_OK) return st;
     if (s < 0 || s > 2) return fail(c, DG_E_ARG, "stage must be 0, 1 or 2");
     return run_stage(c, s);
+}
+
+dg_status dg_stage_noalloc(dg_ctx* c, int s) {
+    dg_status st = ready(c, true);
+    if (st != DG_OK) return st;
+    if (s < 0 || s > 2) return fail(c, DG_E_ARG, "stage must be 0, 1 or 2");
+    if (!c->scratch) {
+        const int e = oedg::scratch_address(c->device, &c->scratch);
+        if (e != 0 || !c->scratch)
+            return fail(c, DG_E_HIP, std::string("hipGetSymbolAddress of the scratch records: ") +
+                                         hipGetErrorString((hipError_t)e));
+    }
+    const int k = c->cfg.k, mixed = is_mixed(c) ? 1 : 0, nc = c->mesh.n_cell;
+    for (int which = 0; which < oedg::kNumPasses; ++which) {
+        const int grid = oedg::grid_for_pass(which, k, mixed, nc);
+        if ((size_t)grid * oedg::kPartCols > oedg::kScratchDoubles)
+            return fail(c, DG_E_ARG, "pass grid of " + std::to_string(grid) +
+                                         " workgroups exceeds the scratch records (" +
+                                         std::to_string(oedg::kMaxBlocks) + ")");
+    }
+    oedg::StageArgs a = stage_args(c, s);
+    a.part = c->scratch;
+    LAUNCH_TRY(c, oedg::launch_residual(k, a, c->stream));
+    LAUNCH_TRY(c, oedg::launch_finalize(oedg::kPassResidual, k, a, c->stream));
+    LAUNCH_TRY(c, oedg::launch_filter(k, a, c->stream));
+    LAUNCH_TRY(c, oedg::launch_finalize(oedg::kPassFilter, k, a, c->stream));
+    c->last_out = s == 2 ? c->u0 : c->u;
+    return DG_OK;
 }
 
 dg_status dg_step(dg_ctx* c, double* dt_out) {

@@ -32,6 +32,7 @@ struct dg_ctx {
     double *u0 = nullptr, *u = nullptr, *w = nullptr, *part = nullptr;
     const double* last_out = nullptr;
     oedg::Glob* g = nullptr;
+    double* scratch = nullptr;   // the library's partial records on this device (dg_stage_noalloc)
 
     // kernel timing (dg_profile_enable)
     bool prof_on = false;

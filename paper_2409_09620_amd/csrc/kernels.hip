@@ -1560,7 +1560,36 @@ int launch_pass(int which, int k, const StageArgs& a, void* stream) {
                                 (hipStream_t)stream);
 }
 
+// Partial records of dg_stage_noalloc: a file-scope device array, one copy per
+// GPU at that GPU's own address.  Host code never uses its name as an address:
+// scratch_address() asks the runtime for it once per device, with that device
+// current, and the launches take the returned pointer.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
 }  // namespace
+
+int scratch_address(int device, double** out) {
+    static std::mutex mu;
+    static std::unordered_map<int, double*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    *out = nullptr;
+    auto it = addr.find(device);
+    if (it != addr.end()) {
+        *out = it->second;
+        return 0;
+    }
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return (int)e;
+    if (cur != device) return (int)hipErrorInvalidDevice;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    if (p == nullptr) return (int)hipErrorInvalidSymbol;
+    addr[device] = (double*)p;
+    *out = (double*)p;
+    return 0;
+}
 
 int grid_for_pass(int which, int k, int mixed, int n_cell) {
     const int tiles = (n_cell + kCellsPerTile - 1) / kCellsPerTile;

@@ -153,6 +153,14 @@ int launch_residual(int k, const StageArgs& a, void* stream);
 int launch_filter(int k, const StageArgs& a, void* stream);
 int launch_finalize(int which, int k, const StageArgs& a, void* stream);   // which: kPassResidual, kPassFilter
 
+// ---- no-allocation stage (dg_stage_noalloc): partial records in a device array of
+// the library, kScratchDoubles doubles per GPU (the records of kMaxBlocks workgroups)
+constexpr size_t kScratchDoubles = (size_t)kPartCols * kMaxBlocks;
+// Address of that array on `device`, which must be the current device.  Looked up
+// once per device (later calls return the cached address).  Returns a hipError_t
+// as int; *out is null on failure.
+int scratch_address(int device, double** out);
+
 // ---- batch: passes over a chunk table of several instances
 // Workgroups of batched pass `which` resident at once for degree mask kmask
 // (1: P1, 2: P2, 3: both) and precision `mixed`; a multiple of 8.
