@@ -592,3 +592,163 @@ def test_vortex_convergence_order(k, ns, lo):
         errs.append(np.sum(area * np.abs(o.state(0)[0, 0] - ex)) / area.sum())
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     assert min(rates) > lo, (errs, rates)
+
+
+# ----------------------------------------------------------------------------- OE, j >= 1, by hand
+
+def _unit_square():
+    """Cells A B C (lower right) and A C D (upper left) of the unit square; the
+    shared edge is the diagonal AC, of length sqrt(2), with h = 2|K|/l = 1/sqrt(2)."""
+    return smesh.Mesh(xy=np.array([[0, 0], [1, 0], [1, 1], [0, 1]], float),
+                      tri=np.array([[0, 1, 2], [0, 2, 3]], np.int32))
+
+
+def _modal(o, m, fields):
+    """Modal coefficients (4, nm, 2) of per-cell polynomial fields: fields[c](x, y)
+    returns the four conservative variables.  Interpolation at the vertices (and edge
+    midpoints for P2) of the reference triangle, through the oriented vertex order the
+    oracle built; exact for polynomials of the cell's degree."""
+    tri = o.mesh_arrays()["tri"]
+    ref = [(0, 0), (1, 0), (0, 1)] + ([(0.5, 0), (0.5, 0.5), (0, 0.5)] if o.k == 2 else [])
+    V = np.array([oracle.basis(xi, eta)[0][:o.nm] for xi, eta in ref])
+    u = np.zeros((4, o.nm, m.n_cell))
+    for c in range(m.n_cell):
+        P = m.xy[tri[c]]
+        vals = np.array([fields[c](*(P[0] + xi * (P[1] - P[0]) + eta * (P[2] - P[0]))) for xi, eta in ref])
+        u[:, :, c] = np.linalg.solve(V, vals).T
+    return u
+
+
+def _damping_factors(o, u, f, var):
+    """exp(-dt sum_{j<=m} sigma^j) per degree m (1..k) and cell, read from the modes of
+    `var` that are nonzero (None where a degree has no such mode)."""
+    out = {}
+    for c in range(u.shape[2]):
+        for deg, ls in ((1, (1, 2)), (2, (3, 4, 5))):
+            if deg > o.k:
+                continue
+            r = [f[var, l, c] / u[var, l, c] for l in ls if abs(u[var, l, c]) > 1e-9]
+            if r:
+                assert max(r) - min(r) < 1e-14       # one factor per degree (eq. oe:sys)
+                out[(c, deg)] = r[0]
+    return out
+
+
+# volume-point coordinate extremes of the quadrature rules (tab:2th, tab:4th): the
+# barycentric coordinates that occur at the 3-point rule's points are 1/6 and 2/3; at
+# the 6-point rule's points a, 1 - 2a, b, 1 - 2b
+B6 = 0.091576213509770743
+A6 = 0.44594849091596488
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_oe_hand_computed_sigma1(k):
+    """Density 1 + |x - y| (continuous on the diagonal, gradient jump (2, -2) at both
+    endpoints), p = 1, v = 0.  With no value jump sigma^0 = 0 and, by eq. OEScalar:Coef2,
+    sigma^1 = beta/h * A^{k,1} h / ||rho - rhobar|| * sqrt(1/2 (|j_A|^2 + |j_C|^2))
+            = sqrt(1.4) * A^{k,1} * sqrt(8) / ||rho - rhobar||,
+    A^{1,1} = 3, A^{2,1} = 1.  rhobar^Omega = 4/3; |x - y| at the volume points is a
+    barycentric coordinate of the point, so the norm is 2/3 - 1/3 = 1/3 (3-point rule)
+    or 1 - 2 b - 1/3 (6-point rule).  Degree-1 modes decay by exp(-dt sigma^1); for P2
+    the degree-2 modes (here zero) would too."""
+    m = _unit_square()
+    o = oracle.Oracle(m, k)
+    E = 1.0 / 0.4
+    u = _modal(o, m, [lambda x, y: (1 + (x - y), 0, 0, E), lambda x, y: (1 - (x - y), 0, 0, E)])
+    dt = 0.01
+    f = o.oe(u, dt)
+    nrm = 1.0 / 3.0 if k == 1 else (1 - 2 * B6) - 1.0 / 3.0
+    A1 = 3.0 if k == 1 else 1.0
+    sigma1 = math.sqrt(1.4) * A1 * math.sqrt(8.0) / nrm
+    fac = _damping_factors(o, u, f, 0)
+    for c in range(2):
+        assert abs(fac[(c, 1)] - math.exp(-dt * sigma1)) < 1e-13, (fac[(c, 1)], math.exp(-dt * sigma1))
+    # E is constant: its zero-norm branch leaves it alone; momentum is zero
+    assert np.array_equal(f[1:], u[1:])
+
+
+def test_oe_hand_computed_sigma2():
+    """P2, density 1 +- (x - y)^2 / 2 (value and gradient continuous on the diagonal,
+    Hessian jump (xx, xy, yy) = (-2, 2, -2)), p = 1 at the edge's ends, v = 0.  Only
+    sigma^2 survives: sigma^2 = beta/h * A^{2,2} h^2 / ||.|| * sqrt(1/2 * 2 * (4 + 2*4 + 4))
+    = sqrt(1.4) * (5/6) * h * 4 / ||.||, h = 1/sqrt(2) (the C_2 weight 2 on the mixed
+    derivative enters as the 2*4).  rhobar^Omega = 1 (the two cells' averages are
+    1 +- 1/12), and the norm is (1 - 2 b)^2 / 2 at the 6-point rule's points.  Degree-1
+    modes (present: (x - y)^2 has them) stay, degree-2 modes decay by exp(-dt sigma^2)."""
+    m = _unit_square()
+    o = oracle.Oracle(m, 2)
+    E = 1.0 / 0.4
+    u = _modal(o, m, [lambda x, y: (1 + 0.5 * (x - y) ** 2, 0, 0, E),
+                      lambda x, y: (1 - 0.5 * (x - y) ** 2, 0, 0, E)])
+    dt = 0.01
+    f = o.oe(u, dt)
+    h = 1 / math.sqrt(2)
+    nrm = 0.5 * (1 - 2 * B6) ** 2
+    sigma2 = math.sqrt(1.4) * (5.0 / 6.0) * h * 4.0 / nrm
+    fac = _damping_factors(o, u, f, 0)
+    for c in range(2):
+        assert abs(fac[(c, 1)] - 1.0) < 1e-13                 # sigma^0 = sigma^1 = 0
+        assert abs(fac[(c, 2)] - math.exp(-dt * sigma2)) < 1e-13, (fac[(c, 2)], math.exp(-dt * sigma2))
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_rioe_momentum_hand_computed(k):
+    """RIOE for the momentum (eqs. RIOESys:Coef1/Coef2, RIOESys:CoefM): m = (2 phi, phi)
+    with phi = +-(x - y) (a gradient jump only), rho = 1, E constant.  Across the
+    diagonal n = (-1, 1)/sqrt(2): m_n = -phi/sqrt(2), m_t = m.(-n_y, n_x) = -3 phi/sqrt(2),
+    so delta(m) = max(delta(m_n), delta(m_t)) takes m_t.  phi = |x - y| has mean 1/3 in
+    each cell, and |||m - mbar||| = sqrt(5) ||phi - 1/3|| with ||phi - 1/3|| = 1/3
+    (3-point rule) or 1 - 2 b - 1/3 (6-point rule).  v = 0 at the edge's ends, so
+    beta = sqrt(1.4 p) with p = 0.4 E there.  sigma^1 = beta A^{k,1} * 3/sqrt(2) * sqrt(8)
+    / (sqrt(5) ||phi||).  Both momentum components get that one factor; the
+    component-wise OE (the control) gives each component its own."""
+    m = _unit_square()
+    E = 2.5
+    fields = [lambda x, y: (1.0, 2 * (x - y), (x - y), E), lambda x, y: (1.0, -2 * (x - y), -(x - y), E)]
+    dt = 0.002
+    o = oracle.Oracle(m, k)
+    u = _modal(o, m, fields)
+    f = o.oe(u, dt)
+    nphi = 1.0 / 3.0 if k == 1 else (1 - 2 * B6) - 1.0 / 3.0
+    A1 = 3.0 if k == 1 else 1.0
+    beta = math.sqrt(1.4 * 0.4 * E)
+    sigma1 = beta * A1 * (3 / math.sqrt(2)) * math.sqrt(8.0) / (math.sqrt(5) * nphi)
+    for var in (1, 2):
+        fac = _damping_factors(o, u, f, var)
+        for c in range(2):
+            assert abs(fac[(c, 1)] - math.exp(-dt * sigma1)) < 1e-13, (var, c, fac[(c, 1)])
+    # component-wise: m1 = 2 phi has ||m1 - m1bar|| = 2 ||phi||, jump 2x phi's, so the
+    # same sigma^1 as phi alone: beta A sqrt(8) / ||phi||; the same for m2
+    ocw = oracle.Oracle(m, k, oe_mode=1)
+    fcw = ocw.oe(u, dt)
+    s_cw = beta * A1 * math.sqrt(8.0) / nphi
+    for var in (1, 2):
+        fac = _damping_factors(ocw, u, fcw, var)
+        for c in range(2):
+            assert abs(fac[(c, 1)] - math.exp(-dt * s_cw)) < 1e-13, (var, c, fac[(c, 1)])
+
+
+# ----------------------------------------------------------------------------- alpha, eq. 1250
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_alpha_hand_computed_point_set(k):
+    """alpha = max over every edge Gauss point of |v.n| + c (eq. 1250).  On the unit
+    square take rho = 1 + x + 2y, v = (0, w), p = 1 (every conservative variable is
+    linear).  The sound speed is largest where rho is smallest: along the bottom edge
+    (normal (0, -1), |v.n| = w) at its first Gauss point x = s_1 = 1/2 - sqrt(3)/6 (P1)
+    or 1/2 - sqrt(15)/10 (P2), so alpha = w + sqrt(1.4 / (1 + s_1)).  Vertices would give
+    w + sqrt(1.4), edge midpoints w + sqrt(1.4 / 1.5); the left edge (|v.n| = 0) and the
+    diagonal (|v.n| = w/sqrt(2), rho >= 1 + 3 s_1) give less."""
+    m = _unit_square()
+    o = oracle.Oracle(m, k)
+    w = 0.3
+    g = 1.4
+
+    def state(x, y):
+        r = 1 + x + 2 * y
+        return (r, 0.0, r * w, 1.0 / (g - 1) + 0.5 * r * w * w)
+
+    u = _modal(o, m, [state, state])
+    s1 = 0.5 - math.sqrt(3) / 6 if k == 1 else 0.5 - math.sqrt(15) / 10
+    want = w + math.sqrt(g / (1 + s1))
+    assert abs(o.alpha_of(u) - want) < 1e-14 * want, (o.alpha_of(u), want)
