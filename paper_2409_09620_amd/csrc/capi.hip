@@ -52,7 +52,7 @@ size_t mixed_state_bytes(size_t nc, size_t nm) { return mixed_hi_offset(nc) + 4 
 size_t fp64_state_bytes(size_t nc, size_t nm) { return 4 * nm * nc * sizeof(double); }
 
 struct Layout {
-    size_t jinv, area, len, node, link, u0, u, w, part, glob, total;
+    size_t jinv, area, len, node, link, llink, hptr, hcell, u0, u, w, part, glob, total;
 };
 
 // One layout for both precisions: each state buffer holds either form.
@@ -67,6 +67,10 @@ Layout layout(size_t nc, int k) {
     L.len = take(3 * nc * sizeof(double));
     L.node = take(4 * nc * sizeof(double));
     L.link = take(3 * nc * sizeof(int32_t));
+    L.llink = take(3 * nc * sizeof(int32_t));
+    const size_t n_tiles = (nc + oedg::kTileCells - 1) / oedg::kTileCells;
+    L.hptr = take((n_tiles + 1) * sizeof(int32_t));
+    L.hcell = take(n_tiles * oedg::kHaloCap * sizeof(int32_t));
     L.u0 = take(state);
     L.u = take(state);
     L.w = take(std::max(state, 7 * nc * sizeof(double)));   // also carries the coordinates at set-up
@@ -137,6 +141,9 @@ oedg::StageArgs capi::stage_args(dg_ctx* c, int s) {
     a.m.len = c->len;
     a.m.node_ref = c->node;
     a.m.link = c->link;
+    a.m.llink = c->llink;
+    a.m.halo_ptr = c->halo_ptr;
+    a.m.halo_cell = c->halo_cell;
     a.uin = view_of(c, s <= 0 ? c->u0 : c->u);
     a.u0 = view_of(c, c->u0);
     a.w = view_of(c, c->w);
@@ -389,6 +396,9 @@ dg_status dg_mesh_upload(dg_ctx* c, int k, int32_t n_vert, const double* xy, int
     if (k != 1 && k != 2) return fail(c, DG_E_ARG, "degree must be 1 or 2");
     if (n_cell <= 0 || n_vert <= 0) return fail(c, DG_E_MESH, "mesh has no cells or no vertices");
     if (!tri || (!xy && !cell_xy)) return fail(c, DG_E_ARG, "null mesh array");
+    // the kernels address a state buffer with 32-bit byte offsets
+    if ((double)n_cell * 4.0 * ((k + 1) * (k + 2) / 2) * sizeof(double) >= 4294967296.0)
+        return fail(c, DG_E_ARG, "mesh too large: a state buffer must stay below 4 GiB");
     oedg::HostMesh m;
     std::string err;
     const int r = oedg::build_mesh(k, n_vert, xy, n_cell, tri, cell_xy, edge_bc, m, err);
@@ -434,6 +444,9 @@ dg_status dg_mesh_upload(dg_ctx* c, int k, int32_t n_vert, const double* xy, int
     c->u = (double*)(base + L.u);
     c->w = (double*)(base + L.w);
     c->part = (double*)(base + L.part);
+    c->llink = (int32_t*)(base + L.llink);
+    c->halo_ptr = (int32_t*)(base + L.hptr);
+    c->halo_cell = (int32_t*)(base + L.hcell);
     c->g = (Glob*)(base + L.glob);
     c->mesh = std::move(m);
     c->nm = (k + 1) * (k + 2) / 2;
@@ -444,6 +457,12 @@ dg_status dg_mesh_upload(dg_ctx* c, int k, int32_t n_vert, const double* xy, int
     HIP_TRY(c, hipMemcpyAsync(c->len, hm.len.data(), 3 * nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->node, hm.node_ref.data(), 4 * nc * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->link, hm.link.data(), 3 * nc * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->llink, hm.llink.data(), 3 * nc * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->halo_ptr, hm.halo_ptr.data(), hm.halo_ptr.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, c->stream));
+    if (!hm.halo_cell.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->halo_cell, hm.halo_cell.data(), hm.halo_cell.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, c->stream));
     static const Glob zero{};
     HIP_TRY(c, hipMemcpyAsync(c->g, &zero, sizeof(Glob), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));

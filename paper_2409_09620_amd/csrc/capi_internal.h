@@ -30,6 +30,7 @@ struct dg_ctx {
     double *jinv = nullptr, *area = nullptr, *len = nullptr, *node = nullptr;
     int32_t* link = nullptr;
     double *u0 = nullptr, *u = nullptr, *w = nullptr, *part = nullptr;
+    int32_t *llink = nullptr, *halo_ptr = nullptr, *halo_cell = nullptr;
     const double* last_out = nullptr;
     oedg::Glob* g = nullptr;
     double* scratch = nullptr;   // the library's partial records on this device (dg_stage_noalloc)

@@ -16,12 +16,18 @@
 // partials in a fixed order, so results do not depend on scheduling and no
 // workgroup needs a device-scope fence.
 //
-// Lane layout of the residual and filter passes: the 4 lanes of a DPP quad own
-// one cell, lane v holding conservative variable v (rho, m1, m2, E).  A lane
-// keeps only its variable's modes in registers; values at a quadrature point are
-// exchanged inside the quad with DPP quad_perm moves.  Workgroups are spread so
-// that each XCD walks a contiguous range of the (Hilbert-ordered) cells, which
-// keeps neighbour gathers inside that XCD's L2.
+// Lane layout of the two passes: one lane per cell, all four conservative
+// variables and their modes in that lane's registers, so every point value,
+// 1/rho, pressure and flux is formed once.  A pass workgroup is one wave of 64
+// cells; workgroups are spread so that each XCD walks a contiguous range of the
+// (Hilbert-ordered) cells, which keeps neighbour gathers inside that XCD's L2.
+//
+// Edge fluxes are conservative to the last bit: both cells of an interior edge
+// evaluate its LF flux from the same two traces (each cell's trace computed by the
+// same arithmetic from the same table, whichever lane asks), with the lower-index
+// cell's scaled normal and length, and in a fixed operand order, so the two
+// contributions are exact negatives of each other.  The file is compiled with FMA
+// contraction off; every fused multiply-add is written out.
 //
 // Precision: every pass is instantiated for a bulk type T, double (FP64) or
 // float (mixed).  Cell averages are stored, updated and reduced in FP64 in both
@@ -41,6 +47,8 @@
 #include <unordered_map>
 
 #include "oedg_internal.h"
+
+#pragma clang fp contract(off)
 
 namespace oedg {
 namespace {
@@ -105,48 +113,56 @@ __device__ __forceinline__ void psi(double x, double e, double* p) {
 // At the reference vertices (0,0), (1,0), (0,1) every basis function and its
 // first derivatives are affine in the vertex's coordinates (sx, se) (there
 // x^2 = x, e^2 = e, xe = 0).  Returns sum_{l>=1} u_l Psi_l and the reference
-// derivatives of sum_l u_l Psi_l at vertex (sx, se).
+// derivatives of sum_l u_l Psi_l at vertex (sx, se), for a vertex known only at
+// run time (a neighbour's).
 template <int K, typename T>
 __device__ __forceinline__ void vertex_eval(const T* u, T sx, T se, T& qh, T& dx, T& de) {
     if constexpr (K == 1) {
-        qh = fma((T)4.0 * u[1], sx, fma((T)2.0 * u[1] + (T)3.0 * u[2], se, (T)-2.0 * u[1] - u[2]));
-        dx = (T)4.0 * u[1];
-        de = (T)2.0 * u[1] + (T)3.0 * u[2];
+        const T b = (T)4.0 * u[1], c = fma((T)2.0, u[1], (T)3.0 * u[2]);
+        qh = fma(b, sx, fma(c, se, fma((T)-2.0, u[1], -u[2])));
+        dx = b;
+        de = c;
     } else {
-        const T a = (T)-2.0 * u[1] - u[2] + (T)4.0 * u[3] + (T)2.0 * u[4] + u[5];
-        const T b = (T)4.0 * u[1] - (T)4.0 * u[4];
-        const T c = (T)2.0 * u[1] + (T)3.0 * u[2] - (T)4.0 * u[3] - (T)2.0 * u[4] + (T)2.0 * u[5];
+        const T a = fma((T)-2.0, u[1], fma((T)4.0, u[3], fma((T)2.0, u[4], u[5] - u[2])));
+        const T b = (T)4.0 * (u[1] - u[4]);
+        const T c = fma((T)2.0, u[1], fma((T)3.0, u[2], fma((T)-4.0, u[3], (T)2.0 * (u[5] - u[4]))));
         qh = fma(b, sx, fma(c, se, a));
-        const T ax = (T)4.0 * u[1] - (T)24.0 * u[3] - (T)4.0 * u[4];
-        dx = fma((T)48.0 * u[3], sx, fma((T)24.0 * u[3] + (T)20.0 * u[4], se, ax));
-        const T ae = (T)2.0 * u[1] + (T)3.0 * u[2] - (T)8.0 * u[3] - (T)12.0 * u[4] - (T)8.0 * u[5];
-        const T bc = (T)24.0 * u[3] + (T)20.0 * u[4];
-        de = fma(bc, sx, fma((T)8.0 * u[3] + (T)20.0 * u[4] + (T)20.0 * u[5], se, ae));
+        const T h1 = fma((T)24.0, u[3], (T)20.0 * u[4]);
+        const T ax = fma((T)4.0, u[1] - u[4], (T)-24.0 * u[3]);
+        dx = fma((T)48.0 * u[3], sx, fma(h1, se, ax));
+        const T ae = fma((T)2.0, u[1], fma((T)3.0, u[2], fma((T)-8.0, u[3], fma((T)-12.0, u[4], (T)-8.0 * u[5]))));
+        de = fma(h1, sx, fma(fma((T)8.0, u[3], (T)20.0 * (u[4] + u[5])), se, ae));
     }
 }
 
-// The restriction of sum_l u_l Psi_l to local edge j (from vertex j+1 to vertex
-// j+2, parameter s in [0, 1]) has degree K in s, so it is the Lagrange
-// interpolant of its values at the edge's ends (q0 at s = 0, q1 at s = 1) and,
-// for K = 2, its midpoint (qm).  The midpoints (1/2,1/2), (0,1/2), (1/2,0) of
-// edges 0, 1, 2 give affine forms in the indicators i1 = [j==1], i2 = [j==2].
-template <int K, typename T>
-__device__ __forceinline__ void edge_trace_nodes(const T* u, int j, T& q0, T& qm, T& q1) {
-    const int sv = j == 2 ? 0 : j + 1, ev = j == 0 ? 2 : j - 1;   // (j+1) % 3, (j+2) % 3
-    T qh0, qh1, dx, de;
-    vertex_eval<K, T>(u, sv == 1 ? (T)1.0 : (T)0.0, sv == 2 ? (T)1.0 : (T)0.0, qh0, dx, de);
-    vertex_eval<K, T>(u, ev == 1 ? (T)1.0 : (T)0.0, ev == 2 ? (T)1.0 : (T)0.0, qh1, dx, de);
-    q0 = u[0] + qh0;
-    q1 = u[0] + qh1;
-    qm = (T)0.0;
-    if constexpr (K == 2) {
-        // Psi_1..5 at the midpoints: edge 0 (1, 1/2, 1, 3/2, -1/2), edge 1 (-1, 1/2,
-        // 1, -3/2, -1/2), edge 2 (0, -1, -2, 0, 1)
-        const T i1 = j == 1 ? (T)1.0 : (T)0.0, i2 = j == 2 ? (T)1.0 : (T)0.0;
-        const T m0 = u[0] + u[1] + (T)0.5 * u[2] + u[3] + (T)1.5 * u[4] - (T)0.5 * u[5];
-        const T m1 = (T)-2.0 * u[1] - (T)3.0 * u[4];
-        const T m2 = -u[1] - (T)1.5 * u[2] - (T)3.0 * u[3] - (T)1.5 * u[4] + (T)1.5 * u[5];
-        qm = fma(i1, m1, fma(i2, m2, m0));
+// The same at a vertex VT known at compile time (the cell's own): no indicator terms.
+template <int K, int VT, typename T>
+__device__ __forceinline__ void vertex_eval_ct(const T* u, T& qh, T& dx, T& de) {
+    if constexpr (K == 1) {
+        const T b = (T)4.0 * u[1], c = fma((T)2.0, u[1], (T)3.0 * u[2]);
+        const T a = fma((T)-2.0, u[1], -u[2]);
+        qh = VT == 0 ? a : (VT == 1 ? a + b : a + c);
+        dx = b;
+        de = c;
+    } else {
+        const T a = fma((T)-2.0, u[1], fma((T)4.0, u[3], fma((T)2.0, u[4], u[5] - u[2])));
+        const T h1 = fma((T)24.0, u[3], (T)20.0 * u[4]);
+        const T ax = fma((T)4.0, u[1] - u[4], (T)-24.0 * u[3]);
+        const T ae = fma((T)2.0, u[1], fma((T)3.0, u[2], fma((T)-8.0, u[3], fma((T)-12.0, u[4], (T)-8.0 * u[5]))));
+        if constexpr (VT == 0) {
+            qh = a;
+            dx = ax;
+            de = ae;
+        } else if constexpr (VT == 1) {
+            qh = fma((T)4.0, u[1] - u[4], a);
+            dx = fma((T)48.0, u[3], ax);
+            de = h1 + ae;
+        } else {
+            const T c = fma((T)2.0, u[1], fma((T)3.0, u[2], fma((T)-4.0, u[3], (T)2.0 * (u[5] - u[4]))));
+            qh = c + a;
+            dx = h1 + ax;
+            de = fma((T)8.0, u[3], fma((T)20.0, u[4] + u[5], ae));
+        }
     }
 }
 
@@ -157,9 +173,7 @@ struct Tab {
     static constexpr int NM = Rule<K>::NM, NQ = Rule<K>::NQ, NE = Rule<K>::NE;
     T vp[NQ][NM], vdx[NQ][NM], vde[NQ][NM];   // volume points: Psi, dPsi/dxi, dPsi/deta
     T vw[NQ];                                 // volume weights
-    T ep[3 * NE][NM];                         // own edge Gauss points (edge i, node nu)
-    T nbw[NE][3];   // Lagrange weights (end 0, midpoint, end 1) of the neighbour's trace at its
-                    // parameter 1 - s_nu = s_{NE-1-nu}
+    T ep[3 * NE][NM];                         // edge Gauss points (edge i, node nu)
     double zr[NM];  // classical decomposition: u* = sum_l zr_l u_l (P2; Sec. 4.4, classical branch)
 };
 
@@ -212,12 +226,6 @@ constexpr Tab<K, T> make_tab() {
             }
         for (int l = 0; l < R::NM; ++l) t.zr[l] = ((l == 0 ? 1.0 : 0.0) - acc[l]) / (1.0 - 3.0 * wi);
     }
-    for (int nu = 0; nu < R::NE; ++nu) {
-        const double s = R::s[R::NE - 1 - nu];
-        t.nbw[nu][0] = (T)(K == 2 ? (1.0 - s) * (1.0 - 2.0 * s) : 1.0 - s);
-        t.nbw[nu][1] = (T)(K == 2 ? 4.0 * s * (1.0 - s) : 0.0);
-        t.nbw[nu][2] = (T)(K == 2 ? s * (2.0 * s - 1.0) : s);
-    }
     return t;
 }
 
@@ -236,11 +244,21 @@ __device__ __forceinline__ const Tab<K, T>& tab() {
     }
 }
 
+// sum_l u_l p_l with p_0 = Psi_0 = 1: the same operation sequence for every caller,
+// whether the row comes from constant memory or from its copy in LDS
 template <int NM, typename T>
 __device__ __forceinline__ T dot(const T* u, const T* p) {
-    T s = u[0] * p[0];
+    T s = u[0];
 #pragma unroll
     for (int l = 1; l < NM; ++l) s = fma(u[l], p[l], s);
+    return s;
+}
+// sum over the modes l >= 1 (the point value minus the average)
+template <int NM, typename T>
+__device__ __forceinline__ T dot_hi(const T* u, const T* p) {
+    T s = u[1] * p[1];
+#pragma unroll
+    for (int l = 2; l < NM; ++l) s = fma(u[l], p[l], s);
     return s;
 }
 // sum over the modes l >= 1 of |u_l|
@@ -294,80 +312,32 @@ struct Fp<double> {
 template <>
 struct Fp<float> {
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }   // 1 ulp
-    // v_sqrt_f32 itself (1 ulp) instead of the correctly rounded expansion: about 17
-    // instructions fewer per call in the mixed OE
+    // v_sqrt_f32 itself (1 ulp) instead of the correctly rounded expansion
     static __device__ __forceinline__ float sqrt(float x) { return x > 0.0f ? __builtin_amdgcn_sqrtf(x) : 0.0f; }
     // 2^(x log2 e) with v_exp_f32: a few ulp, results below the normal range flush to 0
     static __device__ __forceinline__ float exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
     static __device__ __forceinline__ float div(float x, float y) { return x * __builtin_amdgcn_rcpf(y); }
 };
 
-// ------------------------------------------------------------------------- quad exchanges
-
-// DPP quad_perm move: lane q of every quad receives lane perm[q]'s value (every
-// source lane of a quad permutation exists, so the destination's old value is
-// never kept and needs no initialisation)
-template <int CTRL>
-__device__ __forceinline__ double qperm(double x) {
-    const long long b = __builtin_bit_cast(long long, x);
-    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
-}
-template <int CTRL>
-__device__ __forceinline__ float qperm(float x) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, true));
-}
-template <int L, typename T>
-__device__ __forceinline__ T qget(T x) { return qperm<L * 0x55>(x); }   // broadcast lane L
-template <typename T>
-__device__ __forceinline__ T qswap12(T x) { return qperm<0xD8>(x); }   // [0,2,1,3]
-template <typename T>
-__device__ __forceinline__ T qxor1(T x) { return qperm<0xB1>(x); }     // [1,0,3,2]
-template <typename T>
-__device__ __forceinline__ T qxor2(T x) { return qperm<0x4E>(x); }     // [2,3,0,1]
-template <typename T>
-__device__ __forceinline__ T qmax(T x) {
-    x = fmax(x, qxor1(x));
-    return fmax(x, qxor2(x));
-}
-template <typename T>
-__device__ __forceinline__ T qmin(T x) {
-    x = fmin(x, qxor1(x));
-    return fmin(x, qxor2(x));
-}
-// 4x4 transpose inside a quad through LDS: lane w holds x[c] = (its variable w at
-// state c); on return q[w] = variable w at state v, where v is the calling lane.
-// Each lane stores its four entries and reads the four it needs (8 LDS operations
-// instead of three quad rotations and their select chains).
-// Layout [entry][thread] keeps both the stores and the loads free of bank
-// conflicts; LDS executes a wave's operations in order, and the wave barriers keep
-// the compiler from moving the loads above the stores or the next stores above
-// these loads.
-template <typename T>
-__device__ __forceinline__ void quad_transpose(int v, const T (&x)[4], T (&q)[4]) {
-    __shared__ T buf[4][kBlock];
-    const int t = threadIdx.x, quad = t & ~3;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) buf[c][t] = x[c];
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int w = 0; w < 4; ++w) q[w] = buf[v][quad + w];
-    __builtin_amdgcn_wave_barrier();
-}
-
 // ------------------------------------------------------------------------- Euler
 
-// component v of F(q).n for the lane's variable; (nx, ny) may be a scaled normal,
-// sn is the lane's component of it (nx on lane 1, ny on lane 2, else 0) and
-// s3 = [v == 3]
+// 1/rho and the pressure (gamma - 1)(E - |m|^2 / (2 rho)) of a point value
 template <typename T>
-__device__ __forceinline__ T lane_flux(T qv, T q0, T q1, T q2, T q3, T nx, T ny, T gm1, T sn, T s3) {
-    const T ir = Fp<T>::rcp(q0);
-    const T mn = q1 * nx + q2 * ny;
+__device__ __forceinline__ void euler_ip(const T (&q)[4], T gm1, T& ir, T& p) {
+    ir = Fp<T>::rcp(q[0]);
+    p = gm1 * fma((T)-0.5 * ir, fma(q[1], q[1], q[2] * q[2]), q[3]);
+}
+
+// F(q).n for the four conservative variables (Example ex:euler), (nx, ny) any
+// (scaled) normal, with 1/rho and the pressure given
+template <typename T>
+__device__ __forceinline__ void euler_flux_n(const T (&q)[4], T ir, T p, T nx, T ny, T (&f)[4]) {
+    const T mn = fma(q[1], nx, q[2] * ny);
     const T vn = mn * ir;
-    const T p = gm1 * (q3 - (T)0.5 * (q1 * q1 + q2 * q2) * ir);
-    return qv * vn + p * (sn + s3 * vn);
+    f[0] = mn;
+    f[1] = fma(q[1], vn, p * nx);
+    f[2] = fma(q[2], vn, p * ny);
+    f[3] = (q[3] + p) * vn;
 }
 
 // spectral radius |v.n| + c of F'(u).n (Example ex:euler); guarded so that a
@@ -375,8 +345,32 @@ __device__ __forceinline__ T lane_flux(T qv, T q0, T q1, T q2, T q3, T nx, T ny,
 template <typename T>
 __device__ __forceinline__ T spectral_radius(T q0, T q1, T q2, T q3, T nx, T ny, T gamma) {
     const T ir = Fp<T>::rcp(fmax(q0, (T)kEpsBP));
-    const T p = (gamma - (T)1.0) * (q3 - (T)0.5 * (q1 * q1 + q2 * q2) * ir);
-    return fabs(q1 * nx + q2 * ny) * ir + Fp<T>::sqrt(gamma * fmax(p, (T)0.0) * ir);
+    const T p = (gamma - (T)1.0) * fma((T)-0.5 * ir, fma(q1, q1, q2 * q2), q3);
+    return fma(fabs(fma(q1, nx, q2 * ny)), ir, Fp<T>::sqrt(gamma * fmax(p, (T)0.0) * ir));
+}
+
+// l_e n_e = -2 |K| grad(lambda_e), the scaled outward normal of local edge e from
+// the rows (xx, xy), (ex, ey) of J^-1: grad lambda_1 = (xx, xy), grad lambda_2 =
+// (ex, ey), grad lambda_0 = -(both).  e may be a run-time (per-lane) index: the
+// selects pick among the same three expressions, so the result does not depend on
+// which cell's lane forms it.
+template <typename T>
+__device__ __forceinline__ void scaled_normal(T xx, T xy, T ex, T ey, T area, int e, T& nx, T& ny) {
+    const T gx = e == 0 ? -(xx + ex) : (e == 1 ? xx : ex);
+    const T gy = e == 0 ? -(xy + ey) : (e == 1 ? xy : ey);
+    const T s = (T)-2.0 * area;
+    nx = s * gx;
+    ny = s * gy;
+}
+
+// the unit outward normal of local edge e, from J^-1, |K| and the edge's length l
+template <typename T>
+__device__ __forceinline__ void unit_normal(T xx, T xy, T ex, T ey, T area, int e, T len, T& nx, T& ny) {
+    T lnx, lny;
+    scaled_normal(xx, xy, ex, ey, area, e, lnx, lny);
+    const T il = Fp<T>::rcp(len);
+    nx = lnx * il;
+    ny = lny * il;
 }
 
 // ------------------------------------------------------------------------- work distribution
@@ -413,23 +407,117 @@ __device__ __forceinline__ double wave_max(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;
 }
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
 
-// Addresses of variable v in a state view: its FP64 average and its higher modes
-// (mode l at hi[(l - 1) * n_cell]).  The FP64 form is the plain [var][mode][cell]
-// array, so its higher modes follow the average at a fixed offset.
+// Raw buffer access.  Every load and store of the two passes goes through a
+// resource descriptor in scalar registers plus a 32-bit per-lane byte offset (the
+// cell index times the element size, shared by every array of a cell) and a
+// wave-uniform offset (variable, mode, component), instead of a 64-bit address in
+// vector registers per load.  num_records covers the array, so the hardware's
+// range check never drops a valid access.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kRsrcFlags = 0x00020000;   // dword 3 of a raw buffer resource on gfx9-family parts
+__device__ __forceinline__ Rsrc make_rsrc(const void* p, size_t bytes) {
+    const unsigned n = bytes > 0xffffffffull ? 0xffffffffu : (unsigned)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)n, kRsrcFlags);
+}
+template <typename T>
+__device__ __forceinline__ T bld(Rsrc r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ double bld<double>(Rsrc r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ float bld<float>(Rsrc r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ int bld<int>(Rsrc r, unsigned voff, unsigned soff) {
+    return (int)__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bst(double x, Rsrc r, unsigned voff, unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bst(float x, Rsrc r, unsigned voff, unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, (int)voff, (int)soff, 0);
+}
+
+// One state buffer: the FP64 averages (variable v of the cell at byte offset
+// c*8 + v*avs) and the higher modes in the bulk type (mode l of variable v at
+// c*sizeof(T) + v*hvs + (l-1)*ms).  The FP64 form is one [var][mode][cell] array
+// (both resources cover it); the mixed form has its averages and its float modes in
+// two regions.
 template <int NM, typename T>
-struct VarPtr {
-    double* avg;
-    T* hi;
+struct SView {
+    Rsrc avg, hi;
+    unsigned avs, hvs, ms;
+    __device__ __forceinline__ double a(int v, unsigned c8) const { return bld<double>(avg, c8, v * avs); }
+    __device__ __forceinline__ T h(int v, int l, unsigned cT) const { return bld<T>(hi, cT, v * hvs + (l - 1) * ms); }
+    __device__ __forceinline__ void put_a(int v, unsigned c8, double x) const { bst(x, avg, c8, v * avs); }
+    __device__ __forceinline__ void put_h(int v, int l, unsigned cT, T x) const {
+        bst(x, hi, cT, v * hvs + (l - 1) * ms);
+    }
 };
 template <int NM, typename T>
-__device__ __forceinline__ VarPtr<NM, T> var_ptr(const StateView& sv, const StageArgs& a, int v, size_t snc) {
+__device__ __forceinline__ SView<NM, T> sview(const StateView& sv, const StageArgs& a) {
+    const size_t nc = (size_t)a.m.n_cell;
+    SView<NM, T> s;
     if constexpr (std::is_same<T, double>::value) {
-        double* av = sv.avg + (size_t)v * NM * snc;
-        return {av, av + snc};
+        // [var][mode][cell]: sv.hi = sv.avg + n_cell, so mode l >= 1 of variable v is
+        // at v*NM*nc + (l-1)*nc elements from sv.hi
+        s.avg = make_rsrc(sv.avg, 4 * NM * nc * sizeof(double));
+        s.hi = make_rsrc(sv.hi, (4 * NM - 1) * nc * sizeof(double));
+        s.avs = s.hvs = (unsigned)(NM * nc * sizeof(double));
+        s.ms = (unsigned)(nc * sizeof(double));
     } else {
-        return {sv.avg + v * a.avs, (T*)sv.hi + v * a.hvs};
+        s.avg = make_rsrc(sv.avg, 4 * (size_t)a.avs * sizeof(double));
+        s.hi = make_rsrc(sv.hi, 4 * (size_t)a.hvs * sizeof(float));
+        s.avs = (unsigned)(a.avs * sizeof(double));
+        s.hvs = (unsigned)(a.hvs * sizeof(float));
+        s.ms = (unsigned)(nc * sizeof(float));
     }
+    return s;
+}
+// cell c of a state: FP64 averages and bulk-type modes (mode 0 = the average in T)
+template <int NM, typename T>
+__device__ __forceinline__ void load_cell(const SView<NM, T>& s, int c, double (&avg)[4], T (&u)[4][NM]) {
+    const unsigned c8 = (unsigned)c * 8u, cT = (unsigned)c * (unsigned)sizeof(T);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        avg[v] = s.a(v, c8);
+        u[v][0] = (T)avg[v];
+#pragma unroll
+        for (int l = 1; l < NM; ++l) u[v][l] = s.h(v, l, cT);
+    }
+}
+// The mesh arrays of an instance: J^-1 [4][cell], |K|, edge lengths [3][cell],
+// edge links [3][cell], limiter-node reference coordinates [4][cell].
+struct MView {
+    Rsrc jinv, area, len, link, llink, node;
+    unsigned n8, n4;   // byte strides of a component: n_cell * 8, n_cell * 4
+    __device__ __forceinline__ double J(int k, unsigned c8) const { return bld<double>(jinv, c8, k * n8); }
+    __device__ __forceinline__ double A(unsigned c8) const { return bld<double>(area, c8, 0); }
+    __device__ __forceinline__ double L(int i, unsigned c8) const { return bld<double>(len, c8, i * n8); }
+    __device__ __forceinline__ int link_of(int i, unsigned c4) const { return bld<int>(link, c4, i * n4); }
+    __device__ __forceinline__ double N(int k, unsigned c8) const { return bld<double>(node, c8, k * n8); }
+};
+__device__ __forceinline__ MView mview(const DevMesh& m) {
+    const size_t nc = (size_t)m.n_cell;
+    MView v;
+    v.jinv = make_rsrc(m.jinv, 4 * nc * 8);
+    v.area = make_rsrc(m.area, nc * 8);
+    v.len = make_rsrc(m.len, 3 * nc * 8);
+    v.link = make_rsrc(m.link, 3 * nc * 4);
+    v.llink = make_rsrc(m.llink, 3 * nc * 4);
+    v.node = make_rsrc(m.node_ref, 4 * nc * 8);
+    v.n8 = (unsigned)(nc * 8);
+    v.n4 = (unsigned)(nc * 4);
+    return v;
 }
 
 // a wave-uniform double moved to scalar registers
@@ -439,94 +527,458 @@ __device__ __forceinline__ double uniform(double x) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
 }
 
-// ------------------------------------------------------------------------- pass 1: residual
+// The edge Gauss point rows of the basis in LDS, for the exterior trace: a
+// neighbour's local edge is a per-lane index, so its rows cannot come from the
+// scalar path.  Filled by the workgroup before the first cell.
+template <int K, typename T>
+struct EdgeRowsLds {
+    T r[3 * Rule<K>::NE][Rule<K>::NM];
+};
+template <int K, typename T>
+__device__ __forceinline__ void fill_edge_rows(EdgeRowsLds<K, T>& dst) {
+    constexpr int N = 3 * Rule<K>::NE * Rule<K>::NM;
+    const T* src = &tab<K, T>().ep[0][0];
+    T* d = &dst.r[0][0];
+    for (int t = threadIdx.x; t < N; t += blockDim.x) d[t] = src[t];
+}
 
-// Reduces the lanes' (sum |K| ubar, min, max) over the workgroup, per variable, and
-// writes entry t = 4 k + v (k: sum, min, max) to dst[t * stride].  `pacc` holds the
-// count of inadmissible averages on lane 0 of each quad and the max of |m - mbar|^2
-// on lane 1; they go to dst[kColBad * stride] and dst[kNumPartial * stride].
-__device__ __forceinline__ void residual_flush(double psum, double pmin, double pmax, double pacc, double* dst,
-                                               size_t stride) {
-    const int v = threadIdx.x & 3;
-    double nbad = v == 0 ? pacc : 0.0, pnm = v == 1 ? pacc : 0.0;
-    // over the lanes holding the same variable (xor of lane ids >= 4), then waves
+#ifndef OEDG_RES_WAVES
+#define OEDG_RES_WAVES 2
+#endif
+#ifndef OEDG_FIL_WAVES
+#define OEDG_FIL_WAVES 2
+#endif
+
+// ------------------------------------------------------------------------- tiles in LDS
+
+// LDS image of a tile and its halo for one pass: per slot the four FP64 averages,
+// the modes l >= 1 in the bulk type and NG geometry entries in the bulk type (the
+// rows of J^-1, then |K| for the residual).  Slot s < kTileCells holds cell
+// tile * kTileCells + s, slot kTileCells + h the tile's halo cell h.  SoA per
+// entry, so a lane's slot reads are 8-byte (4-byte) strided accesses.
+template <int K, typename T, int NG>
+struct TileLds {
+    static constexpr int NM = Rule<K>::NM, S = kTileCells + kHaloCap;
+    double avg[4][S];
+    T hi[4][NM - 1][S];
+    T geo[NG][S];
+};
+template <int K, typename T, int NG>
+__device__ __forceinline__ void stage_put(TileLds<K, T, NG>& L, int s, const double (&avg)[4],
+                                          const T (&u)[4][Rule<K>::NM], const T (&geo)[NG]) {
+    constexpr int NM = Rule<K>::NM;
 #pragma unroll
-    for (int o = 4; o < 64; o <<= 1) {
-        psum += __shfl_xor(psum, o, 64);
-        pmin = fmin(pmin, __shfl_xor(pmin, o, 64));
-        pmax = fmax(pmax, __shfl_xor(pmax, o, 64));
+    for (int v = 0; v < 4; ++v) {
+        L.avg[v][s] = avg[v];
+#pragma unroll
+        for (int l = 1; l < NM; ++l) L.hi[v][l - 1][s] = u[v][l];
     }
-    nbad = wave_sum(nbad);
-    pnm = wave_max(pnm);
-    __shared__ double lds[kBlock / 64][3][4];
-    __shared__ double lds_bad[kBlock / 64][2];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane < 4) {
-        lds[wid][0][lane] = psum;
-        lds[wid][1][lane] = pmin;
-        lds[wid][2][lane] = pmax;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) L.geo[g][s] = geo[g];
+}
+// the geometry entries of cell c (byte offset c8) in the bulk type
+template <typename T, int NG>
+__device__ __forceinline__ void geo_of(const MView& mv, unsigned c8, T (&geo)[NG]) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) geo[g] = (T)mv.J(g, c8);
+    if constexpr (NG == 5) geo[4] = (T)mv.A(c8);
+}
+// The tile's halo cells into slots kTileCells.. (every thread takes some).
+template <int K, typename T, int NG>
+__device__ __forceinline__ void stage_halo(TileLds<K, T, NG>& L, const StageArgs& a, int tile,
+                                           const SView<Rule<K>::NM, T>& sv, const MView& mv) {
+    constexpr int NM = Rule<K>::NM;
+    const int h0 = a.m.halo_ptr[tile], hn = a.m.halo_ptr[tile + 1] - h0;
+    for (int h = threadIdx.x; h < hn; h += kPassThreads) {
+        const int cell = a.m.halo_cell[h0 + h];
+        double avg[4];
+        T u[4][NM];
+        T geo[NG];
+        load_cell<NM, T>(sv, cell, avg, u);
+        geo_of<T, NG>(mv, (unsigned)cell * 8u, geo);
+        stage_put<K, T, NG>(L, kTileCells + h, avg, u, geo);
     }
-    if (lane == 0) {
-        lds_bad[wid][0] = nbad;
-        lds_bad[wid][1] = pnm;
-    }
-    __syncthreads();
-    if (threadIdx.x < kNumPartial) {
-        const int k = threadIdx.x >> 2, vv = threadIdx.x & 3;
-        double acc = lds[0][k][vv];
-        for (int w2 = 1; w2 < kBlock / 64; ++w2) {
-            const double x = lds[w2][k][vv];
-            acc = k == 0 ? acc + x : (k == 1 ? fmin(acc, x) : fmax(acc, x));
+}
+// The neighbour across an interior edge with llink value ll: its averages, modes and
+// geometry, from the tile image or, beyond the halo cap, from global memory.
+template <int K, typename T, int NG>
+__device__ __forceinline__ void nb_get(const TileLds<K, T, NG>& L, int ll, const SView<Rule<K>::NM, T>& sv,
+                                       const MView& mv, double (&avg)[4], T (&u)[4][Rule<K>::NM], T (&geo)[NG]) {
+    constexpr int NM = Rule<K>::NM;
+    if (ll & kLinkGlobal) {
+        const int cell = (ll & ~kLinkGlobal) >> 3;
+        load_cell<NM, T>(sv, cell, avg, u);
+        geo_of<T, NG>(mv, (unsigned)cell * 8u, geo);
+    } else {
+        const int s = ll >> 3;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            avg[v] = L.avg[v][s];
+            u[v][0] = (T)avg[v];
+#pragma unroll
+            for (int l = 1; l < NM; ++l) u[v][l] = L.hi[v][l - 1][s];
         }
-        dst[(size_t)threadIdx.x * stride] = acc;
-    } else if (threadIdx.x == kNumPartial) {
-        double acc = lds_bad[0][0];
-        for (int w2 = 1; w2 < kBlock / 64; ++w2) acc += lds_bad[w2][0];
-        dst[(size_t)kColBad * stride] = acc;
-    } else if (threadIdx.x == kNumPartial + 1) {
-        double acc = lds_bad[0][1];
-        for (int w2 = 1; w2 < kBlock / 64; ++w2) acc = fmax(acc, lds_bad[w2][1]);
-        dst[(size_t)kNumPartial * stride] = acc;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) geo[g] = L.geo[g][s];
+    }
+}
+// one variable of that neighbour (its FP64 average and modes in the bulk type)
+template <int K, typename T, int NG>
+__device__ __forceinline__ void nb_var(const TileLds<K, T, NG>& L, int ll, const SView<Rule<K>::NM, T>& sv, int v,
+                                       double& avg, T (&u)[Rule<K>::NM]) {
+    constexpr int NM = Rule<K>::NM;
+    if (ll & kLinkGlobal) {
+        const int cell = (ll & ~kLinkGlobal) >> 3;
+        const unsigned c8 = (unsigned)cell * 8u, cT = (unsigned)cell * (unsigned)sizeof(T);
+        avg = sv.a(v, c8);
+#pragma unroll
+        for (int l = 1; l < NM; ++l) u[l] = sv.h(v, l, cT);
+    } else {
+        const int s = ll >> 3;
+        avg = L.avg[v][s];
+#pragma unroll
+        for (int l = 1; l < NM; ++l) u[l] = L.hi[v][l - 1][s];
+    }
+    u[0] = (T)avg;
+}
+
+// Running reductions of a pass workgroup over its tiles: after each tile every wave
+// reduces its lanes' contributions (one cell each) and lane 0 combines the result
+// into its wave's entry; the flush combines the waves in order.  op(k): 0 sum,
+// 1 min, 2 max.
+template <int NC>
+struct WaveAcc {
+    double x[kPassThreads / 64][NC];
+};
+__device__ __forceinline__ double acc_op(int op, double a, double b) {
+    return op == 0 ? a + b : (op == 1 ? fmin(a, b) : fmax(a, b));
+}
+__device__ __forceinline__ double acc_ident(int op) { return op == 0 ? 0.0 : (op == 1 ? INFINITY : -INFINITY); }
+template <int NC>
+__device__ __forceinline__ void wave_acc_reset(WaveAcc<NC>& W, const int (&ops)[NC]) {
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) W.x[threadIdx.x >> 6][k] = acc_ident(ops[k]);
+    }
+}
+template <int NC>
+__device__ __forceinline__ void wave_acc_add(WaveAcc<NC>& W, const int (&ops)[NC], const double (&val)[NC]) {
+    double r[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+        r[k] = ops[k] == 0 ? wave_sum(val[k]) : (ops[k] == 1 ? wave_min(val[k]) : wave_max(val[k]));
+    if ((threadIdx.x & 63) == 0) {
+        const int w = threadIdx.x >> 6;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) W.x[w][k] = acc_op(ops[k], W.x[w][k], r[k]);
+    }
+}
+// Writes entry k of the record to dst[col[k] * stride], dst the record's column 0
+// and col[k] < kPartCols the absolute column (call with every thread; synchronises
+// the workgroup first).
+template <int NC>
+__device__ __forceinline__ void wave_acc_flush(const WaveAcc<NC>& W, const int (&ops)[NC], const int (&col)[NC],
+                                               double* dst, size_t stride) {
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < NC) {
+        int op = 0, cl = 0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+            if (k == t) {
+                op = ops[k];
+                cl = col[k];
+            }
+        double v = W.x[0][t];
+#pragma unroll
+        for (int w = 1; w < kPassThreads / 64; ++w) v = acc_op(op, v, W.x[w][t]);
+        dst[(size_t)cl * stride] = v;
+    }
+    __syncthreads();   // the entries are reset for the next group after every thread has read them
+}
+
+// Persistent walk of a pass: workgroup b takes its XCD's tiles in turn (single
+// instance), or the tiles (= reduction groups) of its chunks (batch); body(a, tile)
+// computes one tile, flush(a, g) writes the record of group g (batch) or of the
+// workgroup (g < 0).
+template <bool kBatch, typename Body, typename Reset, typename Flush>
+__device__ __forceinline__ void walk_tiles(const StageArgs& a, int g0, int g1, Body body, Reset reset, Flush flush) {
+    if constexpr (!kBatch) {
+        reset();
+        const TileWalk tw = tile_walk(n_tiles_of(a.m.n_cell));
+        for (int tile = tw.first; tile < tw.end; tile += tw.stride) body(tile);
+        flush(-1);
+    } else {
+        for (int gi = g0; gi < g1; ++gi) {
+            reset();
+            body(gi);
+            flush(gi);
+        }
     }
 }
 
-// Per-lane accumulators of the filter pass: the max wave speed, counts and sum
-// |K| ubar of the lane's variable in registers; the boundary momentum flux A_1,
-// A_2, B_1, B_2 at the lane's edge points (rarely touched) in LDS, one slot per
-// thread, so that it holds no register through the OE.
-struct FilterAcc {
-    double amax = 0.0, n_lim = 0.0, n_bad = 0.0, n_flat = 0.0, msum = 0.0;
-};
-constexpr int kBookCols = 4;
+// ------------------------------------------------------------------------- pass 1: residual
 
-// Reduces the lanes' accumulators over the workgroup and writes entry k to
-// dst[k * stride]: max wave speed, limited, bad and flattened counts, sum |K| m1bar,
-// sum |K| m2bar, A_1, A_2, B_1, B_2.
-__device__ __forceinline__ void filter_flush(const FilterAcc& f, const double (&book)[kBookCols][kBlock], double* dst,
-                                             size_t stride) {
-    const int v = threadIdx.x & 3, t = threadIdx.x;
-    double x[kFilterCols] = {f.amax, f.n_lim, f.n_bad, f.n_flat, v == 1 ? f.msum : 0.0,
-                             v == 2 ? f.msum : 0.0, book[0][t], book[1][t], book[2][t], book[3][t]};
-    x[0] = wave_max(x[0]);
+constexpr int kResCols = 14;   // sums, minima, maxima (4 each), |m - mbar|^2 max, bad averages
+__device__ constexpr int kResOps[kResCols] = {0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 2, 2, 0};
+
+template <int K, typename T, bool kBatch>
+__device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1, const EdgeRowsLds<K, T>& er,
+                                             TileLds<K, T, 5>& L, WaveAcc<kResCols>& W) {
+    using R = Rule<K>;
+    constexpr int NM = R::NM, NE = R::NE;
+    constexpr bool kMixed = std::is_same<T, float>::value;
+    const Glob* g = a.g;
+    const int nc = a.m.n_cell;
+    const T gm1 = (T)(a.gamma - 1.0);
+    const double alpha = g->alpha, dt = g->dt;
+    const double sa = a.stage == 0 ? 0.0 : (a.stage == 1 ? 0.75 : 1.0 / 3.0);
+    const double sb = a.stage == 0 ? 1.0 : (a.stage == 1 ? 0.25 : 2.0 / 3.0);
+    const SView<NM, T> up = sview<NM, T>(a.uin, a);
+    const SView<NM, T> u0p = sview<NM, T>(a.u0, a);
+    const SView<NM, T> wp = sview<NM, T>(a.w, a);
+    const MView mv = mview(a.m);
+    const Tab<K, T>& TB = tab<K, T>();
+    const Tab<K, double>& TD = tab<K, double>();
+    int ops[kResCols], cols[kResCols];
 #pragma unroll
-    for (int k = 1; k < kFilterCols; ++k) x[k] = wave_sum(x[k]);
-    __shared__ double lds[kBlock / 64][kFilterCols];
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int k = 0; k < kFilterCols; ++k) lds[threadIdx.x >> 6][k] = x[k];
+    for (int k = 0; k < kResCols; ++k) {
+        ops[k] = kResOps[k];
+        cols[k] = k == kResCols - 1 ? kColBad : k;
     }
+    // The domain average of the momentum of the state this pass writes, known before
+    // it is written: the discrete divergence form conserves sum_K |K| ubar_K up to
+    // the flux through the boundary (each interior edge's flux enters its two cells
+    // with opposite signs, exactly: see the surface term), so
+    //   sum |K| mbar(w) = sa sum |K| mbar(u^n) + sb (sum |K| mbar(u_in) - dt (A + alpha B))
+    // with the sums and the boundary flux A + alpha B of the inputs recorded by the
+    // filter pass that produced them (sa = 0, sb = 1 in the first stage).  The pass
+    // then forms ||| m - mbar |||_inf of eq. normOmg at its own volume points, which
+    // saves a pass over the state.
+    double mb[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const bool first = a.stage == 0;
+        const double s_in = first ? g->mom_n[j] : g->mom_c[j];
+        const double b_in = first ? g->bfa_n[j] + alpha * g->bfb_n[j] : g->bfa_c[j] + alpha * g->bfb_c[j];
+        const double s_w = s_in - dt * b_in;
+        mb[j] = uniform((first ? s_w : sa * g->mom_n[j] + sb * s_w) / g->area_sum);
+    }
+
+    auto tile_body = [&](int tile) __attribute__((always_inline)) {
+        const int c = tile * kTileCells + (int)threadIdx.x;
+        const bool live = c < nc;
+        const unsigned c8 = (unsigned)c * 8u, c4 = (unsigned)c * 4u, cT = (unsigned)c * (unsigned)sizeof(T);
+        // the own cell (registers and the tile image), then the halo
+        double ua[4];
+        T u[4][NM];
+        T geo[5];
+        int lk[3];
+        if (live) {
+            load_cell<NM, T>(up, c, ua, u);
+            geo_of<T, 5>(mv, c8, geo);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) lk[i] = bld<int>(mv.llink, c4, (unsigned)i * mv.n4);
+            stage_put<K, T, 5>(L, threadIdx.x, ua, u, geo);
+        }
+        stage_halo<K, T, 5>(L, a, tile, up, mv);
+        __syncthreads();
+        double part[kResCols];
+#pragma unroll
+        for (int k = 0; k < kResCols; ++k) part[k] = acc_ident(kResOps[k]);
+        if (live) {
+            const T xx = geo[0], xy = geo[1], ex = geo[2], ey = geo[3], areaT = geo[4];
+            const double area = mv.A(c8);
+            // mode 0 accumulates in FP64 in both forms (its volume term is zero)
+            double r0[4] = {0.0, 0.0, 0.0, 0.0};
+            T r[4][NM];
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int l = 0; l < NM; ++l) r[v][l] = (T)0.0;
+
+            // volume term |K| sum_mu w_mu F(u).grad Psi_l with grad Psi = J^{-T} grad_ref Psi,
+            // i.e. dPsi/dxi (F.grad xi) + dPsi/deta (F.grad eta)
+#pragma unroll
+            for (int m = 0; m < R::NQ; ++m) {
+                T q[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) q[v] = dot<NM>(u[v], TB.vp[m]);
+                T ir, p;
+                euler_ip(q, gm1, ir, p);
+                const T wa = TB.vw[m] * areaT;
+                T g1[4], g2[4];
+                euler_flux_n(q, ir, p, wa * xx, wa * xy, g1);
+                euler_flux_n(q, ir, p, wa * ex, wa * ey, g2);
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int l = 1; l < NM; ++l)
+                        r[v][l] = fma(TB.vdx[m][l], g1[v], fma(TB.vde[m][l], g2[v], r[v][l]));
+            }
+
+            // surface term - sum_i l_i sum_nu w_nu Fhat(u_int, u_ext, n_i) Psi_l.  Both
+            // cells of an interior edge form Fhat with the scaled normal l n of the
+            // lower-index cell ("low") and l = |l n|, from the same two traces in
+            // commuted order, so their contributions are exact negatives (sgn = +1 on the
+            // low side):  Fhat_low = 1/2 (F(u_i).n + F(u_e).n - sgn alpha l (u_e - u_i)),
+            // and the own cell adds -sgn w_nu Fhat_low Psi_l.
+#pragma unroll 1
+            for (int i = 0; i < 3; ++i) {
+                const int ll = i == 0 ? lk[0] : (i == 1 ? lk[1] : lk[2]);
+                const bool has = ll >= 0;
+                const bool wall = ll == kLinkWall;
+                const int j = has ? (ll & 3) : i;
+                const bool low = !has || (ll & 4) != 0;
+                const T sgn = low ? (T)1.0 : (T)-1.0;
+                // the neighbour (the own cell at a boundary, replaced below)
+                double una[4];
+                T un[4][NM];
+                T ng[5];
+                if (has) {
+                    nb_get<K, T, 5>(L, ll, up, mv, una, un, ng);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+#pragma unroll
+                        for (int l = 0; l < NM; ++l) un[v][l] = u[v][l];
+#pragma unroll
+                    for (int k2 = 0; k2 < 5; ++k2) ng[k2] = geo[k2];
+                }
+                // the exterior trace at the edge's Gauss points: the neighbour runs the
+                // shared edge the other way, so its parameter is 1 - s_nu = s_{NE-1-nu}
+                // (symmetric Gauss nodes)
+                T qe[NE][4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int nu = 0; nu < NE; ++nu) qe[nu][v] = dot<NM>(un[v], er.r[j * NE + NE - 1 - nu]);
+                T lnx_o, lny_o, lnx_n, lny_n;
+                scaled_normal(xx, xy, ex, ey, areaT, i, lnx_o, lny_o);
+                scaled_normal(ng[0], ng[1], ng[2], ng[3], ng[4], j, lnx_n, lny_n);
+                const T lnx = low ? lnx_o : lnx_n, lny = low ? lny_o : lny_n;
+                const T lc = Fp<T>::sqrt(fma(lnx, lnx, lny * lny));   // the edge length, from the same bits on both sides
+                const T al = (T)alpha * lc;
+                // unit normal of a reflective wall (own edge, so own is low)
+                const T il = Fp<T>::rcp(lc);
+                const T nxu = lnx * il, nyu = lny * il;
+#pragma unroll
+                for (int nu = 0; nu < NE; ++nu) {
+                    const T* p = TB.ep[i * NE + nu];
+                    T qi[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) qi[v] = dot<NM>(u[v], p);
+                    if (!has) {
+                        // transmissive: the exterior trace is the interior one; reflective:
+                        // its normal momentum reversed, m - 2 (m.n) n
+                        const T mn2 = (T)-2.0 * fma(qi[1], nxu, qi[2] * nyu);
+                        qe[nu][0] = qi[0];
+                        qe[nu][1] = wall ? fma(mn2, nxu, qi[1]) : qi[1];
+                        qe[nu][2] = wall ? fma(mn2, nyu, qi[2]) : qi[2];
+                        qe[nu][3] = qi[3];
+                    }
+                    T iri, pi, ire, pe;
+                    euler_ip(qi, gm1, iri, pi);
+                    euler_ip(qe[nu], gm1, ire, pe);
+                    T fi[4], fe[4];
+                    euler_flux_n(qi, iri, pi, lnx, lny, fi);
+                    euler_flux_n(qe[nu], ire, pe, lnx, lny, fe);
+                    const T wsn = (T)R::ws[nu];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const T d = qe[nu][v] - qi[v];
+                        const T fh = sgn * (wsn * ((T)0.5 * ((fi[v] + fe[v]) - sgn * (al * d))));
+                        r0[v] -= (double)fh;
+#pragma unroll
+                        for (int l = 1; l < NM; ++l) r[v][l] = fma(-fh, p[l], r[v][l]);
+                    }
+                }
+            }
+
+            // diagonal mass a_K^(l) = |K| (a_l/|K|), then the SSP-RK3 combination; the
+            // average in FP64, the higher modes in the bulk type
+            const double ia = frcp(area);
+            double wavg[4];   // the pre-filter averages
+            T w[4][NM];
+            const T iaT = (T)ia, dtT = (T)dt, saT = (T)sa, sbT = (T)sb;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double adv0 = fma(dt, r0[v] * ia, ua[v]);
+                const double w0 = a.stage == 0 ? adv0 : fma(sa, u0p.a(v, c8), sb * adv0);
+                wp.put_a(v, c8, w0);
+                part[v] = area * w0;
+                wavg[v] = w0;
+                w[v][0] = (T)w0;
+#pragma unroll
+                for (int l = 1; l < NM; ++l) {
+                    const T adv = fma(dtT, r[v][l] * iaT * (T)kInvMass[l], u[v][l]);
+                    const T wl = a.stage == 0 ? adv : fma(saT, u0p.h(v, l, cT), sbT * adv);
+                    w[v][l] = wl;
+                    wp.put_h(v, l, cT, wl);
+                }
+            }
+            if (a.bp_enable) {
+                // the OE filter and the limiter keep every average: an inadmissible one
+                // here ends the step's attempt (it is retried with half the time step)
+                const double q0 = wavg[0], q1 = wavg[1], q2 = wavg[2], q3 = wavg[3];
+                if (!(q0 > 0.0 && q3 - 0.5 * (q1 * q1 + q2 * q2) / q0 > 0.0)) part[13] = 1.0;
+            }
+            // min/max of every variable and |m - mbar|^2 at the volume points, in FP64: the
+            // average plus the higher modes' part (formed in the bulk type), so a small
+            // deviation from the domain average is not lost to the bulk type's rounding
+            double cnm = 0.0;
+#pragma unroll 1
+            for (int m = 0; m < R::NQ; ++m) {
+                double q[4], hv[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    if constexpr (kMixed) {
+                        hv[v] = (double)dot_hi<NM>(w[v], TB.vp[m]);
+                        q[v] = wavg[v] + hv[v];
+                    } else {
+                        q[v] = dot<NM>(w[v], TD.vp[m]);
+                    }
+                    part[4 + v] = fmin(part[4 + v], q[v]);
+                    part[8 + v] = fmax(part[8 + v], q[v]);
+                }
+                double d1, d2;
+                if constexpr (kMixed) {
+                    d1 = (wavg[1] - mb[0]) + hv[1];
+                    d2 = (wavg[2] - mb[1]) + hv[2];
+                } else {
+                    d1 = q[1] - mb[0];
+                    d2 = q[2] - mb[1];
+                }
+                cnm = fmax(cnm, fma(d1, d1, d2 * d2));
+            }
+            part[12] = cnm;
+        }
+        wave_acc_add<kResCols>(W, ops, part);
+        __syncthreads();   // the tile image is rewritten by the next tile
+    };
+    walk_tiles<kBatch>(
+        a, g0, g1, tile_body, [&]() { wave_acc_reset<kResCols>(W, ops); },
+        [&](int gi) {
+            if (gi < 0) wave_acc_flush<kResCols>(W, ops, cols, a.part + blockIdx.x, kMaxBlocks);
+            else wave_acc_flush<kResCols>(W, ops, cols, a.part + a.gbase + gi, a.gstride);
+        });
+}
+
+template <int K, typename T>
+__global__ __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(OEDG_RES_WAVES))) void k_residual(
+    StageArgs a) {
+    if (!a.g->active || a.g->skip) return;
+    __shared__ EdgeRowsLds<K, T> er;
+    __shared__ TileLds<K, T, 5> L;
+    __shared__ WaveAcc<kResCols> W;
+    fill_edge_rows<K, T>(er);
     __syncthreads();
-    if (threadIdx.x < kFilterCols) {
-        const int k = threadIdx.x;
-        double acc = lds[0][k];
-        for (int w2 = 1; w2 < kBlock / 64; ++w2) acc = k == 0 ? fmax(acc, lds[w2][k]) : acc + lds[w2][k];
-        dst[(size_t)k * stride] = acc;
-    }
+    residual_run<K, T, false>(a, 0, 0, er, L, W);
 }
 
 // Batched passes: workgroup b walks its XCD's range of the chunk table; each
-// chunk is a run of reduction groups [g0, g1) of instance desc[chunk.inst], given
-// to run(a, g0, g1).
+// chunk is a run of reduction groups [g0, g1) (tiles) of instance desc[chunk.inst],
+// given to run(a, g0, g1).
 template <typename F>
 __device__ __forceinline__ void for_each_chunk(const StageArgs* desc, const Chunk* chunks, const ChunkSplit& cs,
                                                F run) {
@@ -539,301 +991,103 @@ __device__ __forceinline__ void for_each_chunk(const StageArgs* desc, const Chun
     }
 }
 
-template <int K, typename T, bool kBatch>
-__device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1) {
-    using R = Rule<K>;
-    constexpr int NM = R::NM;
-    const Glob* g = a.g;
-    const int nc = a.m.n_cell;
-    const size_t snc = (size_t)nc;
-    const int v = threadIdx.x & 3;
-    const T s3 = v == 3 ? 1.0 : 0.0;
-    const T gm1 = (T)(a.gamma - 1.0);
-    const double alpha = g->alpha, dt = g->dt;
-    const double sa = a.stage == 0 ? 0.0 : (a.stage == 1 ? 0.75 : 1.0 / 3.0);
-    const double sb = a.stage == 0 ? 1.0 : (a.stage == 1 ? 0.25 : 2.0 / 3.0);
-    // this lane's variable: FP64 average and bulk-type higher modes
-    const VarPtr<NM, T> up = var_ptr<NM, T>(a.uin, a, v, snc);
-    const VarPtr<NM, T> u0p = var_ptr<NM, T>(a.u0, a, v, snc);
-    const VarPtr<NM, T> wp = var_ptr<NM, T>(a.w, a, v, snc);
-    const double* ua_p = up.avg;
-    const T* uh_p = up.hi;
-    const double* u0a_p = u0p.avg;
-    const T* u0h_p = u0p.hi;
-    double* wa_p = wp.avg;
-    T* wh_p = wp.hi;
-    const Tab<K, T>& TB = tab<K, T>();
-    // The domain average of the momentum of the state this pass writes, known before
-    // it is written: the discrete divergence form conserves sum_K |K| ubar_K up to
-    // the flux through the boundary (each interior edge's flux enters its two cells
-    // with opposite signs), so
-    //   sum |K| mbar(w) = sa sum |K| mbar(u^n) + sb (sum |K| mbar(u_in) - dt (A + alpha B))
-    // with the sums and the boundary flux A + alpha B of the inputs recorded by the
-    // filter pass that produced them (sa = 0, sb = 1 in the first stage).  The pass
-    // then forms ||| m - mbar |||_inf of eq. normOmg at its own volume points, which
-    // saves a pass over the state; the result equals the direct average up to the
-    // rounding of the interior fluxes' cancellation.
-    // mbar is wave-uniform: moved to scalar registers, it holds no vector register
-    // through the flux loops
-    double mb[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const bool first = a.stage == 0;
-        const double s_in = first ? g->mom_n[j] : g->mom_c[j];
-        const double b_in = first ? g->bfa_n[j] + alpha * g->bfb_n[j] : g->bfa_c[j] + alpha * g->bfb_c[j];
-        const double s_w = s_in - dt * b_in;
-        mb[j] = uniform((first ? s_w : sa * g->mom_n[j] + sb * s_w) / g->area_sum);
-    }
+// the tile image of a batched pass: one per degree present (KM: 1 P1, 2 P2, 3 both)
+template <int KM, typename T, int NG>
+union TileLdsKM {
+    typename std::conditional<(KM & 1) != 0, TileLds<1, T, NG>, char>::type p1;
+    typename std::conditional<(KM & 2) != 0, TileLds<2, T, NG>, char>::type p2;
+};
 
-    // one cell, owned by a quad of lanes: residual, SSP combination, partials
-    // pacc: lane 0 counts inadmissible averages, lane 1 keeps the max of |m - mbar|^2
-    auto cell = [&](int c, double& psum, double& pmin, double& pmax, double& pacc) __attribute__((always_inline)) {
-        const double ua = ua_p[c];
-        T u[NM];
-        u[0] = (T)ua;
-#pragma unroll
-        for (int l = 1; l < NM; ++l) u[l] = uh_p[(l - 1) * snc + c];
-        const T xx = (T)a.m.jinv[c], xy = (T)a.m.jinv[snc + c];
-        const T ex = (T)a.m.jinv[2 * snc + c], ey = (T)a.m.jinv[3 * snc + c];
-        const double area = a.m.area[c];
-        const T areaT = (T)area;
-        // edge links and lengths with the cell's own data, so that each edge's
-        // neighbour loads issue at once (holding a neighbour ahead of its use costs
-        // occupancy and measured slower); at a transmissive boundary the own cell is
-        // fetched and not used
-        int lk[3];
-        double ln[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            lk[i] = a.m.link[i * snc + c];
-            ln[i] = a.m.len[i * snc + c];
-        }
-        auto fetch = [&](int link, T (&d)[NM]) __attribute__((always_inline)) {
-            const int nb = link >= 0 ? (link >> 2) : c;
-            d[0] = (T)ua_p[nb];
-#pragma unroll
-            for (int l = 1; l < NM; ++l) d[l] = uh_p[(l - 1) * snc + nb];
-        };
-
-        // mode 0 accumulates in FP64 in both forms (its volume term is zero)
-        double r0 = 0.0;
-        T r[NM];
-#pragma unroll
-        for (int l = 0; l < NM; ++l) r[l] = (T)0.0;
-
-        // volume term |K| sum_mu w_mu F(u).grad Psi_l with grad Psi = J^{-T} grad_ref Psi,
-        // i.e. dPsi/dxi (F.grad xi) + dPsi/deta (F.grad eta)
-#pragma unroll
-        for (int m = 0; m < R::NQ; ++m) {
-            const T* p = TB.vp[m];
-            const T* dx = TB.vdx[m];
-            const T* de = TB.vde[m];
-            const T qv = dot<NM>(u, p);
-            const T q0 = qget<0>(qv), q1 = qget<1>(qv), q2 = qget<2>(qv), q3 = qget<3>(qv);
-            const T wa = TB.vw[m] * areaT;
-            const T g1 = wa * lane_flux(qv, q0, q1, q2, q3, xx, xy, gm1, v == 1 ? xx : (v == 2 ? xy : (T)0.0), s3);
-            const T g2 = wa * lane_flux(qv, q0, q1, q2, q3, ex, ey, gm1, v == 1 ? ex : (v == 2 ? ey : (T)0.0), s3);
-#pragma unroll
-            for (int l = 1; l < NM; ++l) r[l] = fma(dx[l], g1, fma(de[l], g2, r[l]));
-        }
-
-        // surface term - sum_i l_i sum_nu w_nu Fhat(u_int, u_ext, n_i) Psi_l; the scaled
-        // normal l_i n_i equals -2|K| grad(lambda_i) of the barycentric coordinate
-#pragma unroll 1
-        for (int i = 0; i < 3; ++i) {
-            const T gx = i == 0 ? -(xx + ex) : (i == 1 ? xx : ex);
-            const T gy = i == 0 ? -(xy + ey) : (i == 1 ? xy : ey);
-            const T lnx = (T)-2.0 * areaT * gx, lny = (T)-2.0 * areaT * gy;
-            const T sn = v == 1 ? lnx : (v == 2 ? lny : (T)0.0);   // the lane's normal component
-            const T al = (T)(alpha * (i == 0 ? ln[0] : (i == 1 ? ln[1] : ln[2])));
-            const int link = i == 0 ? lk[0] : (i == 1 ? lk[1] : lk[2]);
-            const bool has = link >= 0;
-            const bool wall = link == kLinkWall;
-            const int j = link & 3;
-            T un[NM];
-            fetch(link, un);
-            // the exterior trace from its ends and midpoint: the neighbour's along its
-            // local edge j, or at a reflective wall the mirrored own trace
-            const bool ext = has || wall;
-            T n0 = (T)0.0, nm = (T)0.0, n1 = (T)0.0;
-            if (ext) edge_trace_nodes<K, T>(un, has ? j : i, n0, nm, n1);
-            if (wall) {
-                // reflective wall (un holds the own cell): the exterior trace is the own
-                // trace with its normal momentum reversed, m - 2 (m.n) n, again of degree
-                // K along the edge; its end and midpoint values stand in for the
-                // neighbour's, ends swapped (the neighbour's parameter runs the other way)
-                const T il = (T)frcp(i == 0 ? ln[0] : (i == 1 ? ln[1] : ln[2]));
-                const T nxu = lnx * il, nyu = lny * il;
-                const T cn = (T)-2.0 * (sn * il);   // this lane's share of -2n
-                const T b0 = fma(cn, fma(qget<1>(n1), nxu, qget<2>(n1) * nyu), n1);
-                const T bm = fma(cn, fma(qget<1>(nm), nxu, qget<2>(nm) * nyu), nm);
-                const T b1 = fma(cn, fma(qget<1>(n0), nxu, qget<2>(n0) * nyu), n0);
-                n0 = b0;
-                nm = bm;
-                n1 = b1;
-            }
-#pragma unroll
-            for (int nu = 0; nu < R::NE; ++nu) {
-                const T* p = TB.ep[i * R::NE + nu];
-                const T wsn = (T)(nu == 0 ? R::ws[0] : (nu == 1 ? R::ws[1] : R::ws[2]));
-                const T qi = dot<NM>(u, p);
-                T qe = qi;
-                if (ext) {
-                    // the neighbour runs the shared edge the other way: its parameter is
-                    // 1 - s_nu = s_{NE-1-nu} (symmetric Gauss nodes)
-                    const T* lw = TB.nbw[nu];
-                    qe = fma(lw[0], n0, fma(lw[1], nm, lw[2] * n1));
-                }
-                const T fi = lane_flux(qi, qget<0>(qi), qget<1>(qi), qget<2>(qi), qget<3>(qi), lnx, lny, gm1, sn, s3);
-                const T fe = lane_flux(qe, qget<0>(qe), qget<1>(qe), qget<2>(qe), qget<3>(qe), lnx, lny, gm1, sn, s3);
-                const T fh = wsn * (T)0.5 * (fi + fe - al * (qe - qi));
-                r0 -= (double)fh;
-#pragma unroll
-                for (int l = 1; l < NM; ++l) r[l] = fma(-fh, p[l], r[l]);
-            }
-        }
-
-        // diagonal mass a_K^(l) = |K| (a_l/|K|), then the SSP-RK3 combination; the
-        // average in FP64, the higher modes in the bulk type
-        const double ia = frcp(area);
-        const double adv0 = ua + dt * (r0 * ia * kInvMass[0]);
-        const double w0 = a.stage == 0 ? adv0 : sa * u0a_p[c] + sb * adv0;
-        wa_p[c] = w0;
-        if (a.bp_enable) {
-            // the OE filter and the limiter keep every average: an inadmissible one
-            // here ends the step's attempt (it is retried with half the time step)
-            const double q0 = qget<0>(w0), q1 = qget<1>(w0), q2 = qget<2>(w0), q3 = qget<3>(w0);
-            if (v == 0 && !(q0 > 0.0 && q3 - 0.5 * (q1 * q1 + q2 * q2) / q0 > 0.0)) pacc += 1.0;
-        }
-        const T iaT = (T)ia, dtT = (T)dt, saT = (T)sa, sbT = (T)sb;
-        T w[NM];
-        w[0] = (T)w0;
-#pragma unroll
-        for (int l = 1; l < NM; ++l) {
-            const T adv = u[l] + dtT * (r[l] * iaT * (T)kInvMass[l]);
-            w[l] = a.stage == 0 ? adv : saT * u0h_p[(l - 1) * snc + c] + sbT * adv;
-            wh_p[(l - 1) * snc + c] = w[l];
-        }
-        psum += area * w0;
-        // |m - mbar|^2 at the volume points, in the bulk type like the point values
-        const T mb0 = (T)mb[0], mb1 = (T)mb[1];
-        T cnm = (T)0.0;
-#pragma unroll 1
-        for (int m = 0; m < R::NQ; ++m) {
-            const T qt = dot<NM>(w, TB.vp[m]);
-            const double q = (double)qt;
-            pmin = fmin(pmin, q);
-            pmax = fmax(pmax, q);
-            const T d1 = qget<1>(qt) - mb0, d2 = qget<2>(qt) - mb1;
-            cnm = fmax(cnm, fma(d1, d1, d2 * d2));
-        }
-        pacc = v == 1 ? fmax(pacc, (double)cnm) : pacc;
-    };
-    if constexpr (!kBatch) {
-        double psum = 0.0, pmin = INFINITY, pmax = -INFINITY, pacc = 0.0;
-        const TileWalk tw = tile_walk((nc + kCellsPerTile - 1) / kCellsPerTile);
-        for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
-            const int c = tile * kCellsPerTile + (threadIdx.x >> 2);
-            if (c < nc) cell(c, psum, pmin, pmax, pacc);   // whole quad
-        }
-        residual_flush(psum, pmin, pmax, pacc, a.part + blockIdx.x, kMaxBlocks);
-    } else {
-        for (int gi = g0; gi < g1; ++gi) {
-            double psum = 0.0, pmin = INFINITY, pmax = -INFINITY, pacc = 0.0;
-#pragma unroll 1
-            for (int tile = 0; tile < kGroupCells / kCellsPerTile; ++tile) {
-                const int c = gi * kGroupCells + tile * kCellsPerTile + (threadIdx.x >> 2);
-                if (c < nc) cell(c, psum, pmin, pmax, pacc);
-            }
-            residual_flush(psum, pmin, pmax, pacc, a.part + a.gbase + gi, a.gstride);
-            __syncthreads();   // the flush's LDS is reused by the next group
-        }
-    }
-}
-
-template <int K, typename T>
-__global__ __launch_bounds__(kBlock) void k_residual(StageArgs a) {
-    if (!a.g->active || a.g->skip) return;
-    residual_run<K, T, false>(a, 0, 0);
-}
-// KM: degrees present in the launch (1: P1, 2: P2, 3: both)
 template <int KM, typename T>
-__global__ __launch_bounds__(kBlock) void k_residual_batch(const StageArgs* desc, const Chunk* chunks, ChunkSplit cs) {
-    for_each_chunk(desc, chunks, cs, [](const StageArgs& a, int g0, int g1) {
-        if constexpr (KM != 3) residual_run<KM, T, true>(a, g0, g1);
-        else if (a.k == 1) residual_run<1, T, true>(a, g0, g1);
-        else residual_run<2, T, true>(a, g0, g1);
+__global__ __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(OEDG_RES_WAVES))) void k_residual_batch(
+    const StageArgs* desc, const Chunk* chunks, ChunkSplit cs) {
+    __shared__ EdgeRowsLds<1, T> er1;
+    __shared__ EdgeRowsLds<2, T> er2;
+    __shared__ TileLdsKM<KM, T, 5> L;
+    __shared__ WaveAcc<kResCols> W;
+    if constexpr (KM & 1) fill_edge_rows<1, T>(er1);
+    if constexpr (KM & 2) fill_edge_rows<2, T>(er2);
+    __syncthreads();
+    for_each_chunk(desc, chunks, cs, [&](const StageArgs& a, int g0, int g1) {
+        if constexpr (KM == 1) residual_run<1, T, true>(a, g0, g1, er1, L.p1, W);
+        else if constexpr (KM == 2) residual_run<2, T, true>(a, g0, g1, er2, L.p2, W);
+        else if (a.k == 1) residual_run<1, T, true>(a, g0, g1, er1, L.p1, W);
+        else residual_run<2, T, true>(a, g0, g1, er2, L.p2, W);
     });
 }
 
 // ------------------------------------------------------------------------- pass 2: OE, limiter, alpha
 
-// P2 physical Hessian (xx, xy, yy) of one variable with modes u[0..5] (constant per cell)
+// P2 physical Hessian (xx, xy, yy) of one variable with modes u[0..5] (constant per
+// cell): J^-T H_ref J^-1 with H_ref = (48 u3, 24 u3 + 20 u4, 8 u3 + 20 u4 + 20 u5)
 template <typename T>
-__device__ __forceinline__ void hessian(const T* u, T xx, T xy, T ex, T ey, T* h) {
+__device__ __forceinline__ void hessian(const T* u, T xx, T xy, T ex, T ey, T (&h)[3]) {
     const T hxx = (T)48.0 * u[3];
-    const T hxe = (T)24.0 * u[3] + (T)20.0 * u[4];
-    const T hee = (T)8.0 * u[3] + (T)20.0 * u[4] + (T)20.0 * u[5];
-    h[0] = hxx * xx * xx + (T)2.0 * hxe * xx * ex + hee * ex * ex;
-    h[1] = hxx * xx * xy + hxe * (xx * ey + xy * ex) + hee * ex * ey;
-    h[2] = hxx * xy * xy + (T)2.0 * hxe * xy * ey + hee * ey * ey;
+    const T hxe = fma((T)24.0, u[3], (T)20.0 * u[4]);
+    const T hee = fma((T)8.0, u[3], (T)20.0 * (u[4] + u[5]));
+    const T ax = fma(hxx, xx, hxe * ex), ae = fma(hxe, xx, hee * ex);   // (H_ref J^-1) column x
+    const T bx = fma(hxx, xy, hxe * ey), be = fma(hxe, xy, hee * ey);   // column y
+    h[0] = fma(xx, ax, ex * ae);
+    h[1] = fma(xy, ax, ey * ae);
+    h[2] = fma(xy, bx, ey * be);
 }
 
-// rho e = E - |m|^2 / (2 rho) of a point value
-__device__ __forceinline__ double internal_energy(const double (&q)[4]) {
-    return q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) * frcp(q[0]);
-}
-
-// The full state (all four variables, FP64) at this lane's limiter points t = v,
-// v+4, v+8 of the NP-point node set.  Each lane evaluates its own variable (average
-// wa, modes w) at every point of the set, with wave-uniform basis rows for the edge
-// points, and three quad transposes then hand lane v the four variables at its
-// points; no lane holds the whole cell's coefficients.  Classical decomposition
-// (zxs): the two extra slots repeat edge points 0 and 1 (P1: no internal nodes) or
-// hold u* (P2), which leaves every minimum over the set unchanged.  The u* form of
-// the optimal decomposition (ustar, P2) holds u* = the mean of its two internal
-// nodes (equal node weights) in both slots.
-template <int K, int NM, typename T>
-__device__ __forceinline__ void node_values_t(int v, double wa, const T (&w)[NM], double n0x, double n0e,
-                                              double n1x, double n1e, bool zxs, bool ustar, double (&pv)[3][4]) {
-    constexpr int NE3 = 3 * Rule<K>::NE, NP = NE3 + 2;
+// The full state (FP64) at the NP-point limiter node set of a cell with averages
+// wa and modes w: the 3Q edge Gauss points, then two extra slots.  Optimal
+// decomposition: the P1 vertices v1, v2 (eq. 1944) or the two P2 internal nodes
+// (eq. 1139), at reference coordinates (n0x, n0e), (n1x, n1e); with the u* form
+// (ustar, P2) both slots hold u*, the mean of the two internal nodes (equal node
+// weights).  Classical decomposition (zxs): the slots repeat edge points 0 and 1
+// (P1: no internal nodes) or hold u* (P2), which leaves every minimum unchanged.
+template <int K, int NM>
+__device__ __forceinline__ void node_values(const double (&wd)[4][NM], double n0x, double n0e, double n1x,
+                                            double n1e, bool zxs, bool ustar, double (&pv)[3 * Rule<K>::NE + 2][4]) {
+    constexpr int NE3 = 3 * Rule<K>::NE;
     const Tab<K, double>& TD = tab<K, double>();
-    double wd[NM];
-    wd[0] = wa;
 #pragma unroll
-    for (int l = 1; l < NM; ++l) wd[l] = (double)w[l];
-    double y[12];
+    for (int t = 0; t < NE3; ++t)
 #pragma unroll
-    for (int t = 0; t < NE3; ++t) y[t] = dot<NM>(wd, TD.ep[t]);   // edge i = t / NE, node nu = t % NE
+        for (int v = 0; v < 4; ++v) pv[t][v] = dot<NM>(wd[v], TD.ep[t]);   // edge i = t / NE, node nu = t % NE
     if (zxs) {
-        if constexpr (K == 1) {
-            y[NE3] = y[0];
-            y[NE3 + 1] = y[1];
-        } else {
-            y[NE3] = dot<NM>(wd, TD.zr);
-            y[NE3 + 1] = y[NE3];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            if constexpr (K == 1) {
+                pv[NE3][v] = pv[0][v];
+                pv[NE3 + 1][v] = pv[1][v];
+            } else {
+                pv[NE3][v] = dot<NM>(wd[v], TD.zr);
+                pv[NE3 + 1][v] = pv[NE3][v];
+            }
         }
     } else {
-        double p[NM];
-        psi<K>(n0x, n0e, p);
-        y[NE3] = dot<NM>(wd, p);
-        psi<K>(n1x, n1e, p);
-        y[NE3 + 1] = dot<NM>(wd, p);
-        if constexpr (K == 2) {
-            if (ustar) y[NE3] = y[NE3 + 1] = 0.5 * (y[NE3] + y[NE3 + 1]);
+        double p0[NM], p1[NM];
+        psi<K>(n0x, n0e, p0);
+        psi<K>(n1x, n1e, p1);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            pv[NE3][v] = dot<NM>(wd[v], p0);
+            pv[NE3 + 1][v] = dot<NM>(wd[v], p1);
+            if constexpr (K == 2) {
+                if (ustar) pv[NE3][v] = pv[NE3 + 1][v] = 0.5 * (pv[NE3][v] + pv[NE3 + 1][v]);
+            }
         }
-    }
-#pragma unroll
-    for (int t = NP; t < 12; ++t) y[t] = y[0];   // slots past the set (not used)
-#pragma unroll
-    for (int kk = 0; kk < 3; ++kk) {
-        const double x[4] = {y[4 * kk], y[4 * kk + 1], y[4 * kk + 2], y[4 * kk + 3]};
-        quad_transpose(v, x, pv[kk]);
     }
 }
 
+__device__ __forceinline__ double internal_energy(const double (&q)[4]) {
+    return fma(-0.5 * frcp(q[0]), fma(q[1], q[1], q[2] * q[2]), q[3]);
+}
+
+// record of the filter pass: max wave speed, limited, bad and flattened counts,
+// sum |K| m1bar, sum |K| m2bar, the boundary momentum flux A_1, A_2, B_1, B_2
+constexpr int kFilCols = kFilterCols;
+static_assert(kNumPartial + 1 + kFilCols <= kPartCols && kColBad < kPartCols && kResCols == kNumPartial + 2,
+              "record columns");
+__device__ constexpr int kFilOps[kFilCols] = {2, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+
 template <int K, typename T, bool kBatch>
-__device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
+__device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, TileLds<K, T, 4>& L,
+                                           WaveAcc<kFilCols>& W) {
     using R = Rule<K>;
     using F = Fp<T>;
     constexpr int NM = R::NM;
@@ -842,369 +1096,410 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1) {
     constexpr bool kMixed = std::is_same<T, float>::value;
     const Glob* g = a.g;
     const int nc = a.m.n_cell;
-    const size_t snc = (size_t)nc;
     const double gamma = a.gamma;
     const T gammaT = (T)gamma;
-    const int v = threadIdx.x & 3;
     const bool oe = a.oe_enable && a.stage >= 0;
     const bool ri = a.oe_mode == 0;
     const T dt = (T)g->dt;
-    // inverse L-infinity norm of this lane's quantity (0 in the zero branch)
-    const T inv_my =
-        (T)(v == 0 ? g->inv_nrm[0] : (v == 3 ? g->inv_nrm[3] : (ri ? g->inv_nrm_m : g->inv_nrm[v])));
-    const VarPtr<NM, T> wp = var_ptr<NM, T>(a.w, a, v, snc);
-    const VarPtr<NM, T> op = var_ptr<NM, T>(a.uout, a, v, snc);
-    const double* wa_p = wp.avg;
-    const T* wh_p = wp.hi;
-    double* oa_p = op.avg;
-    T* oh_p = op.hi;
-    const Tab<K, T>& TB = tab<K, T>();
-    __shared__ double book[kBookCols][kBlock];   // the output's momentum bookkeeping (FilterAcc)
+    // inverse L-infinity norms (0 in the zero branch of eq. OEScalar:Coef2)
+    const T inv0 = (T)g->inv_nrm[0], inv3 = (T)g->inv_nrm[3];
+    const T inv1 = (T)(ri ? g->inv_nrm_m : g->inv_nrm[1]), inv2 = (T)(ri ? g->inv_nrm_m : g->inv_nrm[2]);
+    const SView<NM, T> wp = sview<NM, T>(a.w, a);
+    const SView<NM, T> op = sview<NM, T>(a.uout, a);
+    const MView mv = mview(a.m);
+    int ops[kFilCols], cols[kFilCols];
+#pragma unroll
+    for (int k = 0; k < kFilCols; ++k) {
+        ops[k] = kFilOps[k];
+        cols[k] = kNumPartial + 1 + k;
+    }
 
-    // one cell, owned by a quad of lanes: OE, limiter, wave speed of the result
-    auto cell = [&](int c, FilterAcc& f) __attribute__((always_inline)) {
-        const double wa = wa_p[c];   // the average: untouched by the OE (eq. OE:m0) and the limiter
-        T w[NM];
-        w[0] = (T)wa;
+    auto tile_body = [&](int tile) __attribute__((always_inline)) {
+        const int c = tile * kTileCells + (int)threadIdx.x;
+        const bool live = c < nc;
+        const unsigned c8 = (unsigned)c * 8u, c4 = (unsigned)c * 4u, cT = (unsigned)c * (unsigned)sizeof(T);
+        double wa[4];   // the averages: untouched by the OE (eq. OE:m0) and the limiter
+        T w[4][NM];
+        T geo[4];
+        int lk[3];
+        if (live) {
+            load_cell<NM, T>(wp, c, wa, w);
+            geo_of<T, 4>(mv, c8, geo);
 #pragma unroll
-        for (int l = 1; l < NM; ++l) w[l] = wh_p[(l - 1) * snc + c];
-        int lk[3];   // edge links, loaded with the cell's own data (one round trip less per edge)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) lk[i] = a.m.link[i * snc + c];
-        const T xx = (T)a.m.jinv[c], xy = (T)a.m.jinv[snc + c];
-        const T ex = (T)a.m.jinv[2 * snc + c], ey = (T)a.m.jinv[3 * snc + c];
-        const double area_d = a.m.area[c];
-        const T area = (T)area_d;
-        // unit outward normals n_i = l_i n_i / l_i with l_i n_i = -2|K| grad(lambda_i)
-        T nxs[3], nys[3], ils[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const T gx = i == 0 ? -(xx + ex) : (i == 1 ? xx : ex);
-            const T gy = i == 0 ? -(xy + ey) : (i == 1 ? xy : ey);
-            ils[i] = F::rcp((T)a.m.len[i * snc + c]);
-            nxs[i] = (T)-2.0 * area * gx * ils[i];
-            nys[i] = (T)-2.0 * area * gy * ils[i];
+            for (int i = 0; i < 3; ++i) lk[i] = bld<int>(mv.llink, c4, (unsigned)i * mv.n4);
+            if (oe) stage_put<K, T, 4>(L, threadIdx.x, wa, w, geo);
         }
-
         if (oe) {
-            T sig[K + 1];
-#pragma unroll
-            for (int jj = 0; jj <= K; ++jj) sig[jj] = (T)0.0;
-            T ho[3] = {(T)0.0, (T)0.0, (T)0.0};
-            if constexpr (K == 2) hessian(w, xx, xy, ex, ey, ho);
-            // own value (higher modes) and reference gradient at the three vertices
-            T oh[3], ox[3], oe[3];
-#pragma unroll
-            for (int vt = 0; vt < 3; ++vt)
-                vertex_eval<K, T>(w, vt == 1 ? (T)1.0 : (T)0.0, vt == 2 ? (T)1.0 : (T)0.0, oh[vt], ox[vt], oe[vt]);
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const int link = lk[i];
-                if (link < 0) continue;   // transmissive boundary: zero jump (whole quad)
-                const int nb = link >> 2, j = link & 3;
-                const double wna = wa_p[nb];
-                T wn[NM];
-                wn[0] = (T)wna;
-#pragma unroll
-                for (int l = 1; l < NM; ++l) wn[l] = wh_p[(l - 1) * snc + nb];
-                const T nxx = (T)a.m.jinv[nb], nxy = (T)a.m.jinv[snc + nb];
-                const T nex = (T)a.m.jinv[2 * snc + nb], ney = (T)a.m.jinv[3 * snc + nb];
-                const T nx = i == 0 ? nxs[0] : (i == 1 ? nxs[1] : nxs[2]);
-                const T ny = i == 0 ? nys[0] : (i == 1 ? nys[1] : nys[2]);
-                const T h = (T)2.0 * area * (i == 0 ? ils[0] : (i == 1 ? ils[1] : ils[2]));
-                // momentum lanes see m_n = m.n (lane 1) and m_t = m.(-n_y, n_x) (lane 2)
-                const T ca = (ri && (v == 1 || v == 2)) ? nx : (T)1.0;
-                const T cb = ri ? (v == 1 ? ny : (v == 2 ? -ny : (T)0.0)) : (T)0.0;
-                T S[K + 1];
-#pragma unroll
-                for (int jj = 0; jj <= K; ++jj) S[jj] = (T)0.0;
-                T xs[4];   // own variable at: own end 0, neighbour end 0, own end 1, neighbour end 1
-#pragma unroll
-                for (int end = 0; end < 2; ++end) {
-                    // own vertex i+1 (then i+2) meets the neighbour's vertex j+2 (then j+1)
-                    const int ov = (i + 1 + end) % 3, nv = (j + 2 - end) % 3;
-                    T q, r, jv;
-                    // the neighbour's vertex nv, a per-lane index: closed form
-                    T rh, tx, te;
-                    vertex_eval<K, T>(wn, nv == 1 ? (T)1.0 : (T)0.0, nv == 2 ? (T)1.0 : (T)0.0, rh, tx, te);
-                    const T qh = oh[ov];
-                    q = w[0] + qh;
-                    r = wn[0] + rh;
-                    if constexpr (kMixed) {
-                        // value jump from the FP64 averages plus the float higher modes
-                        jv = (T)(wna - wa) + (rh - qh);
-                    } else {
-                        jv = r - q;
-                    }
-                    const T sx = ox[ov], se = oe[ov];
-                    const T qx = sx * xx + se * ex, qy = sx * xy + se * ey;
-                    const T rx = tx * nxx + te * nex, ry = tx * nxy + te * ney;
-                    xs[2 * end] = q;
-                    xs[2 * end + 1] = r;
-                    T jx = rx - qx, jy = ry - qy;
-                    if (ri) {
-                        jv = ca * jv + cb * qswap12(jv);
-                        jx = ca * jx + cb * qswap12(jx);
-                        jy = ca * jy + cb * qswap12(jy);
-                    }
-                    S[0] = fma(jv, jv, S[0]);
-                    S[1] = fma(jx, jx, fma(jy, jy, S[1]));
-                }
-                if constexpr (K == 2) {
-                    // second derivatives are constant per cell: both endpoints carry the
-                    // same jump, 2 (jxx^2 + 2 jxy^2 + jyy^2)
-                    T hn[3];
-                    hessian(wn, nxx, nxy, nex, ney, hn);
-                    T d0 = hn[0] - ho[0], d1 = hn[1] - ho[1], d2 = hn[2] - ho[2];
-                    if (ri) {
-                        d0 = ca * d0 + cb * qswap12(d0);
-                        d1 = ca * d1 + cb * qswap12(d1);
-                        d2 = ca * d2 + cb * qswap12(d2);
-                    }
-                    S[2] = (T)2.0 * (d0 * d0 + (T)2.0 * d1 * d1 + d2 * d2);
-                }
-                // beta^(i): max spectral radius over both endpoints and both sides; lane v
-                // evaluates state v of the four
-                T st[4];
-                quad_transpose(v, xs, st);
-                const T beta = qmax(spectral_radius(st[0], st[1], st[2], st[3], nx, ny, gammaT));
-                const T bh = F::div(beta, h);
-                T hj = (T)1.0;
-#pragma unroll
-                for (int jj = 0; jj <= K; ++jj) {
-                    T d = (T)kA[K][jj] * hj * inv_my * F::sqrt((T)0.5 * S[jj]);
-                    if (ri) d = fmax(d, qswap12(d));   // delta(m) = max(delta(m_n), delta(m_t))
-                    sig[jj] = fma(bh, d, sig[jj]);
-                    hj *= h;
-                }
-            }
-            // exact solution of the damping ODE: degree-m modes scaled by
-            // exp(-dt sum_{j<=m} sigma^j); the cell average is untouched (eq. OE:m0)
-            T acc = sig[0];
-#pragma unroll
-            for (int m = 1; m <= K; ++m) {
-                acc += sig[m];
-                const T f = F::exp(-dt * acc);
-#pragma unroll
-                for (int l = m * (m + 1) / 2; l < (m + 1) * (m + 2) / 2; ++l) w[l] *= f;
-            }
-        }
-
-        // the full state in FP64 at this lane's share of the limiter points, t = v,
-        // v+4, v+8
-        const double n0x = a.m.node_ref[c], n0e = a.m.node_ref[snc + c];
-        const double n1x = a.m.node_ref[2 * snc + c], n1e = a.m.node_ref[3 * snc + c];
-        double pv[3][4];
-        node_values_t<K, NM, T>(v, wa, w, n0x, n0e, n1x, n1e, a.zxs, a.ustar, pv);
-        bool pin[3];
-#pragma unroll
-        for (int kk = 0; kk < 3; ++kk) pin[kk] = v + 4 * kk < NP;
-        const double ub0 = qget<0>(wa), ub1 = qget<1>(wa), ub2 = qget<2>(wa), ub3 = qget<3>(wa);
-        double th1 = 1.0, th2 = 1.0;
-        if (a.bp_enable) {
-            // step 1: density (Sec. 4.4, eq. 1944)
-            double rloc = INFINITY;
-#pragma unroll
-            for (int kk = 0; kk < 3; ++kk)
-                if (pin[kk]) rloc = fmin(rloc, pv[kk][0]);
-            const double rmin = qmin(rloc);
-            const double e1 = fmin(ub0, kEpsBP);
-            th1 = rmin >= e1 ? 1.0 : fmin((ub0 - e1) / (ub0 - rmin), 1.0);
-            // factor of the stored density modes: in the mixed form it aims above the
-            // floor by the rounding bound; theta_2 below still comes from the density
-            // pinned at eps_1 (rho e grows with rho at nodes below the average, so
-            // that theta_2 is the smaller one), which keeps it at the FP64 value
-            double th1s = th1;
-            // mixed form: sum_{l>=1} |c_l| of each variable (lane v forms its own)
-            double as0 = 0.0, as1 = 0.0, as2 = 0.0, as3 = 0.0;
-            if constexpr (kMixed) {
-                double wd[NM];
-                wd[0] = 0.0;
-#pragma unroll
-                for (int l = 1; l < NM; ++l) wd[l] = (double)w[l];
-                const double as = abs_sum_hi<NM>(wd);
-                as0 = qget<0>(as);
-                as1 = qget<1>(as);
-                as2 = qget<2>(as);
-                as3 = qget<3>(as);
-                const double t1 = e1 + kMixMargin * as0;
-                th1s = rmin >= t1 ? 1.0 : fmax(fmin((ub0 - t1) / (ub0 - rmin), 1.0), 0.0);
-            }
-            // step 2: internal energy E - |m|^2 / (2 rho) of the density-scaled state (eq. 1981)
-            const double eb = ub3 - 0.5 * (ub1 * ub1 + ub2 * ub2) / ub0;
-            const double e2 = fmin(eb, kEpsBP);
-            double eloc = INFINITY;
-#pragma unroll
-            for (int kk = 0; kk < 3; ++kk) {
-                pv[kk][0] = ub0 + th1 * (pv[kk][0] - ub0);
-                if (pin[kk])
-                    eloc = fmin(eloc, pv[kk][3] - 0.5 * (pv[kk][1] * pv[kk][1] + pv[kk][2] * pv[kk][2]) *
-                                                      frcp(pv[kk][0]));
-            }
-            const double emin = qmin(eloc);
-            th2 = emin >= e2 ? 1.0 : fmin((eb - e2) / (eb - emin), 1.0);
-            if constexpr (kMixed) {
-                // Rounding the scaled modes moves rho e at a node by at most, to first
-                // order, |dE| + |v| (|dm1| + |dm2|) + |v|^2/2 |drho|, with v the
-                // velocity of the limited state there and each |d.| <= margin * theta
-                // * sum_l |c_l|; theta_2 aims that far above the floor.
-                double vloc = 0.0;
-#pragma unroll
-                for (int kk = 0; kk < 3; ++kk) {
-                    if (pin[kk]) {
-                        const double q0 = ub0 + th2 * (pv[kk][0] - ub0);
-                        const double q1 = ub1 + th2 * (pv[kk][1] - ub1), q2 = ub2 + th2 * (pv[kk][2] - ub2);
-                        vloc = fmax(vloc, (q1 * q1 + q2 * q2) * frcp(q0 * q0));
-                    }
-                }
-                const double vm = fsqrt(qmax(vloc));
-                const double t2 = e2 + kMixMargin * th2 *
-                                           (as3 + vm * (as1 + as2) + 0.5 * vm * vm * th1 * as0);
-                th2 = emin >= t2 ? 1.0 : fmax(fmin((eb - t2) / (eb - emin), 1.0), 0.0);
-                th1 = th1s;
-                const double f = v == 0 ? th1 * th2 : th2;
-                if (f < 1.0) {
-#pragma unroll
-                    for (int l = 1; l < NM; ++l) w[l] = (T)((double)w[l] * f);
-                }
-            } else {
-#pragma unroll
-                for (int l = 1; l < NM; ++l) {
-                    if (v == 0) w[l] *= th1;
-                    w[l] *= th2;
-                }
-            }
-            if (v == 0) {
-                f.n_lim += (th1 < 1.0 || th2 < 1.0) ? 1.0 : 0.0;
-                f.n_bad += (ub0 > 0.0 && eb > 0.0) ? 0.0 : 1.0;
-            }
-            if constexpr (kMixed) {
-                if (th1 < 1.0 || th2 < 1.0) {   // the same in the four lanes of the quad
-                    // check the coefficients as stored (rounded to float)
-                    node_values_t<K, NM, T>(v, wa, w, n0x, n0e, n1x, n1e, a.zxs, a.ustar, pv);
-                    double ok = 1.0;
-#pragma unroll
-                    for (int kk = 0; kk < 3; ++kk)
-                        if (pin[kk] && !(pv[kk][0] >= 0.5 * e1 && internal_energy(pv[kk]) >= 0.5 * e2)) ok = 0.0;
-                    if (qmin(ok) == 0.0) {
-                        // keep the average only: admissible whenever the average is
-#pragma unroll
-                        for (int l = 1; l < NM; ++l) w[l] = (T)0.0;
-#pragma unroll
-                        for (int kk = 0; kk < 3; ++kk) {
-                            pv[kk][0] = ub0;
-                            pv[kk][1] = ub1;
-                            pv[kk][2] = ub2;
-                            pv[kk][3] = ub3;
-                        }
-                        if (v == 0) f.n_flat += 1.0;
-                    }
-                }
-            }
-        }
-
-        // max wave speed over the edge Gauss points of the limited state (eq. 1250);
-        // in the mixed form pv already holds the stored state's values.  At a
-        // boundary edge the point also adds its momentum flux l w_nu F.n, as the
-        // next residual pass will take it, to the output's bookkeeping:
-        // transmissive F(u).n; reflective ((m.n)^2/rho + p) n plus alpha (m.n) n.
-        const double ta = kMixed ? 1.0 : th2;
-#pragma unroll
-        for (int kk = 0; kk < 3; ++kk) {
-            const int t = v + 4 * kk;
-            if (t < 3 * NE) {
-                const int i = t / NE;
-                const double nx = (double)(i == 0 ? nxs[0] : (i == 1 ? nxs[1] : nxs[2]));
-                const double ny = (double)(i == 0 ? nys[0] : (i == 1 ? nys[1] : nys[2]));
-                const double rr = spectral_radius(ub0 + ta * (pv[kk][0] - ub0), ub1 + ta * (pv[kk][1] - ub1),
-                                                  ub2 + ta * (pv[kk][2] - ub2), ub3 + ta * (pv[kk][3] - ub3), nx,
-                                                  ny, gamma);
-                f.amax = (rr > f.amax || rr != rr) ? rr : f.amax;
-            }
-        }
-        if (lk[0] < 0 || lk[1] < 0 || lk[2] < 0) {
-#pragma unroll
-            for (int kk = 0; kk < 3; ++kk) {
-                const int t = v + 4 * kk;
-                const int i = t / NE;
-                const int link = i == 0 ? lk[0] : (i == 1 ? lk[1] : lk[2]);
-                if (t < 3 * NE && link < 0) {
-                    const double nx = (double)(i == 0 ? nxs[0] : (i == 1 ? nxs[1] : nxs[2]));
-                    const double ny = (double)(i == 0 ? nys[0] : (i == 1 ? nys[1] : nys[2]));
-                    const double q0 = ub0 + ta * (pv[kk][0] - ub0), q1 = ub1 + ta * (pv[kk][1] - ub1);
-                    const double q2 = ub2 + ta * (pv[kk][2] - ub2), q3 = ub3 + ta * (pv[kk][3] - ub3);
-                    const int nu = t - i * NE, th = threadIdx.x;
-                    const double lw = a.m.len[i * snc + c] * (nu == 0 ? R::ws[0] : (nu == 1 ? R::ws[1] : R::ws[2]));
-                    const double ir = frcp(q0);
-                    const double mn = q1 * nx + q2 * ny;
-                    const double p = (gamma - 1.0) * (q3 - 0.5 * (q1 * q1 + q2 * q2) * ir);
-                    if (link == kLinkWall) {
-                        const double ca = lw * (mn * mn * ir + p), cb = lw * mn;
-                        book[0][th] += ca * nx;
-                        book[1][th] += ca * ny;
-                        book[2][th] += cb * nx;
-                        book[3][th] += cb * ny;
-                    } else {
-                        book[0][th] += lw * (q1 * mn * ir + p * nx);
-                        book[1][th] += lw * (q2 * mn * ir + p * ny);
-                    }
-                }
-            }
-        }
-        f.msum = fma(area_d, wa, f.msum);   // sum |K| ubar of this lane's variable
-        oa_p[c] = wa;
-#pragma unroll
-        for (int l = 1; l < NM; ++l) oh_p[(l - 1) * snc + c] = w[l];
-    };
-    if constexpr (!kBatch) {
-        FilterAcc f;
-#pragma unroll
-        for (int k = 0; k < kBookCols; ++k) book[k][threadIdx.x] = 0.0;
-        const TileWalk tw = tile_walk((nc + kCellsPerTile - 1) / kCellsPerTile);
-        for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
-            const int c = tile * kCellsPerTile + (threadIdx.x >> 2);
-            if (c < nc) cell(c, f);   // whole quad
-        }
-        filter_flush(f, book, a.part + (size_t)(kNumPartial + 1) * kMaxBlocks + blockIdx.x, kMaxBlocks);
-    } else {
-        for (int gi = g0; gi < g1; ++gi) {
-            FilterAcc f;
-#pragma unroll
-            for (int k = 0; k < kBookCols; ++k) book[k][threadIdx.x] = 0.0;
-#pragma unroll 1
-            for (int tile = 0; tile < kGroupCells / kCellsPerTile; ++tile) {
-                const int c = gi * kGroupCells + tile * kCellsPerTile + (threadIdx.x >> 2);
-                if (c < nc) cell(c, f);
-            }
-            filter_flush(f, book, a.part + (size_t)(kNumPartial + 1) * a.gstride + a.gbase + gi, a.gstride);
+            stage_halo<K, T, 4>(L, a, tile, wp, mv);
             __syncthreads();
         }
-    }
+        double part[kFilCols];
+#pragma unroll
+        for (int k = 0; k < kFilCols; ++k) part[k] = acc_ident(kFilOps[k]);
+        if (live) {
+            const T xx = geo[0], xy = geo[1], ex = geo[2], ey = geo[3];
+            const double area_d = mv.A(c8);
+            const T area = (T)area_d;
+
+            if (oe) {
+                T sig[4][K + 1];
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int jj = 0; jj <= K; ++jj) sig[v][jj] = (T)0.0;
+#pragma unroll 1
+                for (int i = 0; i < 3; ++i) {
+                    const int ll = i == 0 ? lk[0] : (i == 1 ? lk[1] : lk[2]);
+                    if (ll < 0) continue;   // boundary edge: zero jump
+                    // The own cell's vertex values, gradients and Hessian are formed anew
+                    // for every edge: hoisted out of the edge loop they would hold about 70
+                    // more registers through it.  An empty asm marks the modes as changed.
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+#pragma unroll
+                        for (int l = 0; l < NM; ++l) asm volatile("" : "+v"(w[v][l]));
+                    const int j = ll & 3;
+                    T nxx, nxy, nex, ney;
+                    if (ll & kLinkGlobal) {
+                        const unsigned n8 = (unsigned)((ll & ~kLinkGlobal) >> 3) * 8u;
+                        nxx = (T)mv.J(0, n8);
+                        nxy = (T)mv.J(1, n8);
+                        nex = (T)mv.J(2, n8);
+                        ney = (T)mv.J(3, n8);
+                    } else {
+                        const int s = ll >> 3;
+                        nxx = L.geo[0][s];
+                        nxy = L.geo[1][s];
+                        nex = L.geo[2][s];
+                        ney = L.geo[3][s];
+                    }
+                    const T len = (T)mv.L(i, c8);
+                    T nx, ny;
+                    unit_normal(xx, xy, ex, ey, area, i, len, nx, ny);
+                    const T h = (T)2.0 * area * F::rcp(len);   // h_K^(i) = 2|K| / l_i
+                    // beta^(i): the max spectral radius over both ends of the edge and both
+                    // sides (own vertex i+1, then i+2, meets the neighbour's vertex j+2,
+                    // then j+1), with K's normal
+                    T beta = (T)0.0;
+                    {
+                        T qo[2][4], qn[2][4];
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            T t[NM];
+                            double tna;
+                            nb_var<K, T, 4>(L, ll, wp, v, tna, t);
+#pragma unroll
+                            for (int e = 0; e < 2; ++e) {
+                                const int ov = (i + 1 + e) % 3, nv = (j + 2 - e) % 3;
+                                T qh, qhn, d0, d1;
+                                vertex_eval<K, T>(w[v], ov == 1 ? (T)1.0 : (T)0.0, ov == 2 ? (T)1.0 : (T)0.0, qh, d0, d1);
+                                vertex_eval<K, T>(t, nv == 1 ? (T)1.0 : (T)0.0, nv == 2 ? (T)1.0 : (T)0.0, qhn, d0,
+                                                  d1);
+                                qo[e][v] = w[v][0] + qh;
+                                qn[e][v] = t[0] + qhn;
+                            }
+                        }
+#pragma unroll
+                        for (int e = 0; e < 2; ++e)
+                            beta = fmax(beta,
+                                        fmax(spectral_radius(qo[e][0], qo[e][1], qo[e][2], qo[e][3], nx, ny, gammaT),
+                                             spectral_radius(qn[e][0], qn[e][1], qn[e][2], qn[e][3], nx, ny, gammaT)));
+                    }
+                    // the neighbour's modes are read again below rather than kept in registers
+                    asm volatile("" ::: "memory");
+                    const T bh = F::div(beta, h);
+                    // Jumps (neighbour minus own) of variable v's value and physical
+                    // gradient at the two ends, and of its (constant) P2 Hessian.
+                    auto jumps = [&](int v, T (&jv)[2], T (&jx)[2], T (&jy)[2], T (&dh)[3])
+                                     __attribute__((always_inline)) {
+                        T t[NM];
+                        double tna;
+                        nb_var<K, T, 4>(L, ll, wp, v, tna, t);
+#pragma unroll
+                        for (int e = 0; e < 2; ++e) {
+                            const int ov = (i + 1 + e) % 3, nv = (j + 2 - e) % 3;
+                            T qh, dxo, deo, qhn, dxn, den;
+                            vertex_eval<K, T>(w[v], ov == 1 ? (T)1.0 : (T)0.0, ov == 2 ? (T)1.0 : (T)0.0, qh, dxo, deo);
+                            vertex_eval<K, T>(t, nv == 1 ? (T)1.0 : (T)0.0, nv == 2 ? (T)1.0 : (T)0.0, qhn, dxn, den);
+                            // value jump; mixed: the FP64 difference of averages plus the
+                            // float higher modes'
+                            if constexpr (kMixed) jv[e] = (T)(tna - wa[v]) + (qhn - qh);
+                            else jv[e] = (t[0] + qhn) - (w[v][0] + qh);
+                            jx[e] = fma(dxn, nxx, den * nex) - fma(dxo, xx, deo * ex);
+                            jy[e] = fma(dxn, nxy, den * ney) - fma(dxo, xy, deo * ey);
+                        }
+                        if constexpr (K == 2) {
+                            T hn[3], ho[3];
+                            hessian(t, nxx, nxy, nex, ney, hn);
+                            hessian(w[v], xx, xy, ex, ey, ho);
+#pragma unroll
+                            for (int k2 = 0; k2 < 3; ++k2) dh[k2] = hn[k2] - ho[k2];
+                        }
+                    };
+                    // sum over both ends of the squared jumps of order j: j = 0 value, 1
+                    // gradient; 2: the Hessian's jump, the same at both ends, weighted by
+                    // C_2 = (1, 2, 1), i.e. 2 (jxx^2 + 2 jxy^2 + jyy^2)
+                    auto energies = [&](const T (&jv)[2], const T (&jx)[2], const T (&jy)[2], const T (&dh)[3],
+                                        T (&Sv)[K + 1]) __attribute__((always_inline)) {
+                        Sv[0] = fma(jv[0], jv[0], jv[1] * jv[1]);
+                        Sv[1] = fma(jx[0], jx[0], fma(jy[0], jy[0], fma(jx[1], jx[1], jy[1] * jy[1])));
+                        if constexpr (K == 2)
+                            Sv[2] = (T)2.0 * fma(dh[0], dh[0], fma((T)2.0 * dh[1], dh[1], dh[2] * dh[2]));
+                    };
+                    // sigma^j += beta/h delta^j, delta^j = A^{k,j} h^j / ||.|| sqrt(S_j / 2)
+                    auto accumulate = [&](const T (&Sv)[K + 1], T inv, T (&sg)[K + 1]) __attribute__((always_inline)) {
+                        T hj = (T)1.0;
+#pragma unroll
+                        for (int jj = 0; jj <= K; ++jj) {
+                            sg[jj] = fma(bh, (T)kA[K][jj] * hj * inv * F::sqrt((T)0.5 * Sv[jj]), sg[jj]);
+                            hj *= h;
+                        }
+                    };
+                    {
+                        T jv[2], jx[2], jy[2], dh[3], Sv[K + 1];
+                        jumps(0, jv, jx, jy, dh);
+                        energies(jv, jx, jy, dh, Sv);
+                        accumulate(Sv, inv0, sig[0]);
+                        asm volatile("" ::: "memory");
+                        jumps(3, jv, jx, jy, dh);
+                        energies(jv, jx, jy, dh, Sv);
+                        accumulate(Sv, inv3, sig[3]);
+                    }
+                    asm volatile("" ::: "memory");
+                    {
+                        // RIOE: the momentum enters as m_n = m.n and m_t = m.(-n_y, n_x), with
+                        // K's normal on both sides, and delta(m) = max(delta(m_n), delta(m_t)),
+                        // one root of the larger energy; component-wise: m_1, m_2 apart
+                        T jv1[2], jx1[2], jy1[2], dh1[3], jv2[2], jx2[2], jy2[2], dh2[3];
+                        jumps(1, jv1, jx1, jy1, dh1);
+                        jumps(2, jv2, jx2, jy2, dh2);
+                        const T ca = ri ? nx : (T)1.0, cb = ri ? ny : (T)0.0;
+                        auto rot = [&](T& a1, T& a2) __attribute__((always_inline)) {
+                            const T b1 = fma(ca, a1, cb * a2), b2 = fma(ca, a2, -(cb * a1));
+                            a1 = b1;
+                            a2 = b2;
+                        };
+#pragma unroll
+                        for (int e = 0; e < 2; ++e) {
+                            rot(jv1[e], jv2[e]);
+                            rot(jx1[e], jx2[e]);
+                            rot(jy1[e], jy2[e]);
+                        }
+                        if constexpr (K == 2) {
+#pragma unroll
+                            for (int k2 = 0; k2 < 3; ++k2) rot(dh1[k2], dh2[k2]);
+                        }
+                        T S1[K + 1], S2[K + 1];
+                        energies(jv1, jx1, jy1, dh1, S1);
+                        energies(jv2, jx2, jy2, dh2, S2);
+                        if (ri) {
+#pragma unroll
+                            for (int jj = 0; jj <= K; ++jj) S1[jj] = fmax(S1[jj], S2[jj]);
+                            accumulate(S1, inv1, sig[1]);
+                        } else {
+                            accumulate(S1, inv1, sig[1]);
+                            accumulate(S2, inv2, sig[2]);
+                        }
+                    }
+                }
+                if (ri) {
+#pragma unroll
+                    for (int jj = 0; jj <= K; ++jj) sig[2][jj] = sig[1][jj];
+                }
+                // exact solution of the damping ODE: degree-m modes scaled by
+                // exp(-dt sum_{j<=m} sigma^j); the cell average is untouched (eq. OE:m0)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    T acc = sig[v][0];
+#pragma unroll
+                    for (int m = 1; m <= K; ++m) {
+                        acc += sig[v][m];
+                        const T fct = F::exp(-dt * acc);
+#pragma unroll
+                        for (int l = m * (m + 1) / 2; l < (m + 1) * (m + 2) / 2; ++l) w[v][l] *= fct;
+                    }
+                }
+            }
+            // the full state in FP64 at the limiter's node set
+            const double n0x = mv.N(0, c8), n0e = mv.N(1, c8);
+            const double n1x = mv.N(2, c8), n1e = mv.N(3, c8);
+            double wd[4][NM];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                wd[v][0] = wa[v];
+#pragma unroll
+                for (int l = 1; l < NM; ++l) wd[v][l] = (double)w[v][l];
+            }
+            double pv[NP][4];
+            node_values<K, NM>(wd, n0x, n0e, n1x, n1e, a.zxs, a.ustar, pv);
+            const double ub0 = wa[0], ub1 = wa[1], ub2 = wa[2], ub3 = wa[3];
+            double th1 = 1.0, th2 = 1.0;
+            if (a.bp_enable) {
+                // step 1: density (Sec. 4.4, eq. 1944)
+                double rmin = pv[0][0];
+#pragma unroll
+                for (int t = 1; t < NP; ++t) rmin = fmin(rmin, pv[t][0]);
+                const double e1 = fmin(ub0, kEpsBP);
+                th1 = rmin >= e1 ? 1.0 : fmin((ub0 - e1) / (ub0 - rmin), 1.0);
+                // factor of the stored density modes: in the mixed form it aims above the
+                // floor by the rounding bound; theta_2 below still comes from the density
+                // pinned at eps_1 (rho e grows with rho at nodes below the average, so
+                // that theta_2 is the smaller one), which keeps it at the FP64 value
+                double th1s = th1;
+                double as0 = 0.0, as1 = 0.0, as2 = 0.0, as3 = 0.0;   // mixed: sum_{l>=1} |c_l| per variable
+                if constexpr (kMixed) {
+                    as0 = abs_sum_hi<NM>(wd[0]);
+                    as1 = abs_sum_hi<NM>(wd[1]);
+                    as2 = abs_sum_hi<NM>(wd[2]);
+                    as3 = abs_sum_hi<NM>(wd[3]);
+                    const double t1 = fma(kMixMargin, as0, e1);
+                    th1s = rmin >= t1 ? 1.0 : fmax(fmin((ub0 - t1) / (ub0 - rmin), 1.0), 0.0);
+                }
+                // step 2: internal energy E - |m|^2 / (2 rho) of the density-scaled state (eq. 1981)
+                const double eb = ub3 - 0.5 * (ub1 * ub1 + ub2 * ub2) / ub0;
+                const double e2 = fmin(eb, kEpsBP);
+                double emin = INFINITY;
+#pragma unroll
+                for (int t = 0; t < NP; ++t) {
+                    pv[t][0] = fma(th1, pv[t][0] - ub0, ub0);
+                    emin = fmin(emin, internal_energy(pv[t]));
+                }
+                th2 = emin >= e2 ? 1.0 : fmin((eb - e2) / (eb - emin), 1.0);
+                if constexpr (kMixed) {
+                    // Rounding the scaled modes moves rho e at a node by at most, to first
+                    // order, |dE| + |v| (|dm1| + |dm2|) + |v|^2/2 |drho|, with v the
+                    // velocity of the limited state there and each |d.| <= margin * theta
+                    // * sum_l |c_l|; theta_2 aims that far above the floor.
+                    double vloc = 0.0;
+#pragma unroll
+                    for (int t = 0; t < NP; ++t) {
+                        const double q0 = fma(th2, pv[t][0] - ub0, ub0);
+                        const double q1 = fma(th2, pv[t][1] - ub1, ub1), q2 = fma(th2, pv[t][2] - ub2, ub2);
+                        vloc = fmax(vloc, fma(q1, q1, q2 * q2) * frcp(q0 * q0));
+                    }
+                    const double vm = fsqrt(vloc);
+                    const double t2 = e2 + kMixMargin * th2 * (as3 + vm * (as1 + as2) + 0.5 * vm * vm * th1 * as0);
+                    th2 = emin >= t2 ? 1.0 : fmax(fmin((eb - t2) / (eb - emin), 1.0), 0.0);
+                    th1 = th1s;
+                    if (th1 * th2 < 1.0 || th2 < 1.0) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const double fct = v == 0 ? th1 * th2 : th2;
+#pragma unroll
+                            for (int l = 1; l < NM; ++l) w[v][l] = (T)((double)w[v][l] * fct);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int l = 1; l < NM; ++l) {
+                        w[0][l] *= th1;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) w[v][l] *= th2;
+                    }
+                }
+                part[1] = (th1 < 1.0 || th2 < 1.0) ? 1.0 : 0.0;
+                part[2] = (ub0 > 0.0 && eb > 0.0) ? 0.0 : 1.0;
+                if constexpr (kMixed) {
+                    if (th1 < 1.0 || th2 < 1.0) {
+                        // check the coefficients as stored (rounded to float)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+#pragma unroll
+                            for (int l = 1; l < NM; ++l) wd[v][l] = (double)w[v][l];
+                        node_values<K, NM>(wd, n0x, n0e, n1x, n1e, a.zxs, a.ustar, pv);
+                        bool ok = true;
+#pragma unroll
+                        for (int t = 0; t < NP; ++t)
+                            ok = ok && pv[t][0] >= 0.5 * e1 && internal_energy(pv[t]) >= 0.5 * e2;
+                        if (!ok) {
+                            // keep the average only: admissible whenever the average is
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+#pragma unroll
+                                for (int l = 1; l < NM; ++l) w[v][l] = (T)0.0;
+#pragma unroll
+                                for (int t = 0; t < NP; ++t) pv[t][v] = wa[v];
+                            }
+                            part[3] = 1.0;
+                        }
+                    }
+                }
+            }
+
+            // max wave speed over the edge Gauss points of the limited state (eq. 1250);
+            // in the mixed form pv already holds the stored state's values.  At a
+            // boundary edge the point also adds its momentum flux l w_nu F.n, as the
+            // next residual pass will take it, to the output's bookkeeping:
+            // transmissive F(u).n; reflective ((m.n)^2/rho + p) n plus alpha (m.n) n.
+            const double ta = kMixed ? 1.0 : th2;
+            const bool any_bnd = lk[0] < 0 || lk[1] < 0 || lk[2] < 0;
+            double amax = 0.0;
+#pragma unroll
+            for (int t = 0; t < 3 * NE; ++t) {
+                const int i = t / NE, nu = t % NE;
+                T nxT, nyT;
+                unit_normal(xx, xy, ex, ey, area, i, (T)mv.L(i, c8), nxT, nyT);
+                const double nx = (double)nxT, ny = (double)nyT;
+                const double q0 = fma(ta, pv[t][0] - ub0, ub0), q1 = fma(ta, pv[t][1] - ub1, ub1);
+                const double q2 = fma(ta, pv[t][2] - ub2, ub2), q3 = fma(ta, pv[t][3] - ub3, ub3);
+                const double rr = spectral_radius(q0, q1, q2, q3, nx, ny, gamma);
+                amax = (rr > amax || rr != rr) ? rr : amax;
+                if (any_bnd && lk[i] < 0) {
+                    const double lw = mv.L(i, c8) * R::ws[nu];
+                    const double ir = frcp(q0);
+                    const double mn = fma(q1, nx, q2 * ny);
+                    const double p = (gamma - 1.0) * fma(-0.5 * ir, fma(q1, q1, q2 * q2), q3);
+                    if (lk[i] == kLinkWall) {
+                        const double ca = lw * fma(mn * mn, ir, p), cb = lw * mn;
+                        part[6] = fma(ca, nx, part[6]);
+                        part[7] = fma(ca, ny, part[7]);
+                        part[8] = fma(cb, nx, part[8]);
+                        part[9] = fma(cb, ny, part[9]);
+                    } else {
+                        part[6] = fma(lw, fma(q1 * mn, ir, p * nx), part[6]);
+                        part[7] = fma(lw, fma(q2 * mn, ir, p * ny), part[7]);
+                    }
+                }
+            }
+            part[0] = amax;
+            part[4] = area_d * wa[1];
+            part[5] = area_d * wa[2];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                op.put_a(v, c8, wa[v]);
+#pragma unroll
+                for (int l = 1; l < NM; ++l) op.put_h(v, l, cT, w[v][l]);
+            }
+        }
+        wave_acc_add<kFilCols>(W, ops, part);
+        if (oe) __syncthreads();   // the tile image is rewritten by the next tile
+    };
+    walk_tiles<kBatch>(
+        a, g0, g1, tile_body, [&]() { wave_acc_reset<kFilCols>(W, ops); },
+        [&](int gi) {
+            if (gi < 0) wave_acc_flush<kFilCols>(W, ops, cols, a.part + blockIdx.x, kMaxBlocks);
+            else wave_acc_flush<kFilCols>(W, ops, cols, a.part + a.gbase + gi, a.gstride);
+        });
 }
-// three waves per SIMD: the allocator then keeps the P2 instantiations within 168 VGPRs
 template <int K, typename T>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_filter(StageArgs a) {
+__global__ __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(OEDG_FIL_WAVES))) void k_filter(
+    StageArgs a) {
     if (!a.g->active || a.g->skip) return;
-    filter_run<K, T, false>(a, 0, 0);
-}
-// FP64: no occupancy request (with the chunk indirection a 168-VGPR budget spills
-// heavily); mixed: three waves per SIMD
-template <int KM, typename T>
-__device__ __forceinline__ void filter_batch_body(const StageArgs* desc, const Chunk* chunks, const ChunkSplit& cs) {
-    for_each_chunk(desc, chunks, cs, [](const StageArgs& a, int g0, int g1) {
-        if constexpr (KM != 3) filter_run<KM, T, true>(a, g0, g1);
-        else if (a.k == 1) filter_run<1, T, true>(a, g0, g1);
-        else filter_run<2, T, true>(a, g0, g1);
-    });
+    __shared__ TileLds<K, T, 4> L;
+    __shared__ WaveAcc<kFilCols> W;
+    filter_run<K, T, false>(a, 0, 0, L, W);
 }
 template <int KM, typename T>
-__global__ __launch_bounds__(kBlock) void k_filter_batch(const StageArgs* desc, const Chunk* chunks, ChunkSplit cs) {
-    filter_batch_body<KM, T>(desc, chunks, cs);
-}
-template <int KM>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_filter_batch_mixed(
+__global__ __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(OEDG_FIL_WAVES))) void k_filter_batch(
     const StageArgs* desc, const Chunk* chunks, ChunkSplit cs) {
-    filter_batch_body<KM, float>(desc, chunks, cs);
+    __shared__ TileLdsKM<KM, T, 4> L;
+    __shared__ WaveAcc<kFilCols> W;
+    for_each_chunk(desc, chunks, cs, [&](const StageArgs& a, int g0, int g1) {
+        if constexpr (KM == 1) filter_run<1, T, true>(a, g0, g1, L.p1, W);
+        else if constexpr (KM == 2) filter_run<2, T, true>(a, g0, g1, L.p2, W);
+        else if (a.k == 1) filter_run<1, T, true>(a, g0, g1, L.p1, W);
+        else filter_run<2, T, true>(a, g0, g1, L.p2, W);
+    });
 }
 
 // ------------------------------------------------------------------------- finalize (one workgroup)
@@ -1460,12 +1755,13 @@ __global__ __launch_bounds__(kBlock) void k_project(StageArgs a, int kind, Probl
 #pragma unroll
             for (int l = 0; l < NM; ++l) acc[v][l] *= kInvMass[l];
     }
+    const SView<NM, T> op = sview<NM, T>(a.uout, a);
+    const unsigned c8 = (unsigned)c * 8u, cT = (unsigned)c * (unsigned)sizeof(T);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const VarPtr<NM, T> op = var_ptr<NM, T>(a.uout, a, v, snc);
-        op.avg[c] = acc[v][0];
+        op.put_a(v, c8, acc[v][0]);
 #pragma unroll
-        for (int l = 1; l < NM; ++l) op.hi[(l - 1) * snc + c] = (T)acc[v][l];
+        for (int l = 1; l < NM; ++l) op.put_h(v, l, cT, (T)acc[v][l]);
     }
 }
 
@@ -1520,10 +1816,8 @@ struct BatchSet {
 };
 template <int KM, typename T>
 BatchSet batch_set() {
-    const void* filter;
-    if constexpr (std::is_same<T, float>::value) filter = reinterpret_cast<const void*>(&k_filter_batch_mixed<KM>);
-    else filter = reinterpret_cast<const void*>(&k_filter_batch<KM, T>);
-    return {{reinterpret_cast<const void*>(&k_residual_batch<KM, T>), filter}};
+    return {{reinterpret_cast<const void*>(&k_residual_batch<KM, T>),
+             reinterpret_cast<const void*>(&k_filter_batch<KM, T>)}};
 }
 const BatchSet& batch_kernels(int kmask, int mixed) {
     static const BatchSet sets[3][2] = {{batch_set<1, double>(), batch_set<1, float>()},
@@ -1545,7 +1839,7 @@ int resident_blocks(const void* kernel) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kPassThreads, 0) != hipSuccess || per_cu < 1)
         per_cu = 1, cus = cus > 0 ? cus : 256;
     const int g = std::min(kMaxBlocks, std::max(8, (cus * per_cu) / 8 * 8));
     cache[kernel] = g;
@@ -1556,7 +1850,7 @@ int launch_pass(int which, int k, const StageArgs& a, void* stream) {
     StageArgs args = a;
     void* argv[] = {&args};
     const int grid = grid_for_pass(which, k, a.mixed, a.m.n_cell);
-    return (int)hipLaunchKernel(kernels_for(k, a.mixed).pass[which], dim3(grid), dim3(kBlock), argv, 0,
+    return (int)hipLaunchKernel(kernels_for(k, a.mixed).pass[which], dim3(grid), dim3(kPassThreads), argv, 0,
                                 (hipStream_t)stream);
 }
 
@@ -1592,7 +1886,7 @@ int scratch_address(int device, double** out) {
 }
 
 int grid_for_pass(int which, int k, int mixed, int n_cell) {
-    const int tiles = (n_cell + kCellsPerTile - 1) / kCellsPerTile;
+    const int tiles = n_tiles_of(n_cell);
     const int want = std::max(8, ((tiles + 7) / 8) * 8);
     return std::min(want, resident_blocks(kernels_for(k, mixed).pass[which]));
 }
@@ -1629,7 +1923,7 @@ int launch_pass_batch(int which, int kmask, int mixed, const StageArgs* desc, co
     if (kmask < 1 || kmask > 3 || grid < 8 || (grid & 7) != 0) return (int)hipErrorInvalidValue;
     ChunkSplit split = cs;
     void* argv[] = {&desc, &chunks, &split};
-    return (int)hipLaunchKernel(batch_kernels(kmask, mixed).pass[which], dim3(grid), dim3(kBlock), argv, 0,
+    return (int)hipLaunchKernel(batch_kernels(kmask, mixed).pass[which], dim3(grid), dim3(kPassThreads), argv, 0,
                                 (hipStream_t)stream);
 }
 

@@ -147,12 +147,56 @@ int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const in
         }
         r = s;
     }
-    if (static_cast<uint64_t>(n_cell) * 4 >= (1ull << 31)) { err = "too many cells"; return -1; }
+    if (static_cast<uint64_t>(n_cell) * 8 >= (1ull << 30)) { err = "too many cells"; return -1; }
     for (size_t c = 0; c < nc; ++c)
         for (int i = 0; i < 3; ++i) {
             const int32_t nb = m.nbr[3 * c + i];
             m.link[i * nc + c] = nb >= 0 ? (nb << 2) | m.nbe[3 * c + i] : (wall[3 * c + i] ? kLinkWall : kLinkOpen);
         }
+
+    // Halo map of the tiles of kTileCells consecutive cells: the distinct out-of-tile
+    // neighbours of each tile, sorted, at most kHaloCap of them (a neighbour beyond the
+    // cap is reached in global memory), and every interior edge's link re-expressed
+    // as the neighbour's slot in the tile's LDS image (see kLinkGlobal).
+    {
+        const size_t n_tiles = (nc + kTileCells - 1) / kTileCells;
+        m.halo_ptr.assign(n_tiles + 1, 0);
+        m.halo_cell.clear();
+        m.llink.assign(3 * nc, 0);
+        std::vector<int32_t> halo;
+        for (size_t t = 0; t < n_tiles; ++t) {
+            const size_t c0 = t * kTileCells, c1 = std::min(nc, c0 + kTileCells);
+            halo.clear();
+            for (size_t c = c0; c < c1; ++c)
+                for (int i = 0; i < 3; ++i) {
+                    const int32_t nb = m.nbr[3 * c + i];
+                    if (nb >= 0 && ((size_t)nb < c0 || (size_t)nb >= c1)) halo.push_back(nb);
+                }
+            std::sort(halo.begin(), halo.end());
+            halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
+            if (halo.size() > (size_t)kHaloCap) halo.resize(kHaloCap);
+            m.halo_cell.insert(m.halo_cell.end(), halo.begin(), halo.end());
+            m.halo_ptr[t + 1] = (int32_t)m.halo_cell.size();
+            for (size_t c = c0; c < c1; ++c)
+                for (int i = 0; i < 3; ++i) {
+                    const int32_t nb = m.nbr[3 * c + i];
+                    int32_t v = m.link[i * nc + c];
+                    if (nb >= 0) {
+                        const int32_t tag = ((size_t)nb < c ? 0 : 4) | m.nbe[3 * c + i];
+                        if ((size_t)nb >= c0 && (size_t)nb < c1) {
+                            v = ((int32_t)(nb - c0) << 3) | tag;
+                        } else {
+                            const auto it = std::lower_bound(halo.begin(), halo.end(), nb);
+                            if (it != halo.end() && *it == nb)
+                                v = ((int32_t)(kTileCells + (it - halo.begin())) << 3) | tag;
+                            else
+                                v = kLinkGlobal | (nb << 3) | tag;
+                        }
+                    }
+                    m.llink[i * nc + c] = v;
+                }
+        }
+    }
 
     // geometry and decomposition
     const double ref[3][2] = {{0, 0}, {1, 0}, {0, 1}};

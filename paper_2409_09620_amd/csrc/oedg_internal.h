@@ -7,8 +7,14 @@
 
 namespace oedg {
 
-constexpr int kBlock = 256;            // threads per workgroup of the stage kernels
-constexpr int kCellsPerTile = 64;      // a quad of 4 lanes per cell in the residual/filter passes
+constexpr int kBlock = 256;            // threads per workgroup of the set-up kernels
+// The residual and filter passes take the cells in tiles of kTileCells consecutive
+// cells, one lane per cell; a pass workgroup stages a tile and its halo (at most
+// kHaloCap out-of-tile neighbours) in LDS before it computes the tile.
+constexpr int kTileCells = 256;
+constexpr int kPassThreads = kTileCells;
+constexpr int kHaloCap = 80;
+constexpr int n_tiles_of(int n_cell) { return (n_cell + kTileCells - 1) / kTileCells; }
 constexpr int kMaxBlocks = 4096;       // upper bound of a single-instance pass grid (= partials)
 constexpr int kGroupCells = 256;       // cells per reduction group of the batched passes
 constexpr int kNumPartial = 12;        // partials of the residual pass per group
@@ -29,6 +35,10 @@ struct HostMesh {
     int k = 0;
     std::vector<int32_t> tri, nbr, nbe, perm;   // [cell][3]
     std::vector<int32_t> link;                  // [3][cell]: (nbr << 2) | nbe, or kLinkOpen / kLinkWall
+    // the tiles' halo map for the stage kernels (see kLinkGlobal)
+    std::vector<int32_t> llink;                 // [3][cell]
+    std::vector<int32_t> halo_ptr;              // [n_tiles + 1]: tile t's halo is halo_cell[halo_ptr[t]..)
+    std::vector<int32_t> halo_cell;             // the halo cells of every tile, at most kHaloCap per tile
     std::vector<double> jinv;                   // [4][cell]: xi_x, xi_y, eta_x, eta_y
     std::vector<double> area;                   // [cell]
     std::vector<double> len;                    // [3][cell]
@@ -44,6 +54,12 @@ struct HostMesh {
 // link of a boundary edge: transmissive or reflective (interior links are >= 0)
 constexpr int32_t kLinkOpen = -1;
 constexpr int32_t kLinkWall = -2;
+// llink of an interior edge: (slot << 3) | (low << 2) | nbe, slot the neighbour's LDS
+// slot in the tile image (its offset in the tile, or kTileCells + its halo index),
+// low = 1 when this cell's index is below the neighbour's.  A neighbour beyond the
+// halo cap is read from global memory: kLinkGlobal | (nbr << 3) | (low << 2) | nbe.
+// Boundary edges carry kLinkOpen / kLinkWall.
+constexpr int32_t kLinkGlobal = 1 << 30;
 
 int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const int32_t* tri,
                const double* cell_xy, const int32_t* edge_bc, HostMesh& m, std::string& err);
@@ -92,6 +108,9 @@ struct DevMesh {
     const double* len;
     const double* node_ref;
     const int32_t* link;
+    const int32_t* llink;
+    const int32_t* halo_ptr;
+    const int32_t* halo_cell;
 };
 
 // One state buffer.  Cell averages (mode 0) are FP64 in every precision; modes
