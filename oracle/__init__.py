@@ -29,7 +29,7 @@ _P = ctypes.c_void_p
 def build(force: bool = False) -> str:
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=gnu11", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=gnu11", "-fopenmp", "-shared", "-fPIC",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO
@@ -43,6 +43,7 @@ def lib():
         L = ctypes.CDLL(_SO)
         sig = {
             "orc_create": (_P, [_I, _I, _P, _I, _P, _P]),
+            "orc_set_threads": (_I, [_I]),
             "orc_destroy": (None, [_P]),
             "orc_export_mesh": (_I, [_P] + [_P] * 11),
             "orc_config": (_I, [_P, _D, _D, _I, _I, _I]),
@@ -239,3 +240,9 @@ def decompose(k, v):
     perm = np.zeros(3, np.int32)
     lib().orc_decompose(int(k), _ptr(v), _ptr(w), _ptr(nodes), _ptr(nw), _ptr(cd), _ptr(perm))
     return w, nodes.reshape(2, 2), nw, float(cd[0]), perm
+
+
+def set_threads(n):
+    """Threads of the oracle's cell loops, n <= 0 for one per processor (results
+    are bit for bit those of one thread); returns the number in use."""
+    return int(lib().orc_set_threads(int(n)))

@@ -46,8 +46,16 @@
  *   - L-infinity norms use the volume rule's points (eq. normOmg);
  *   - initial data: L2 projection with the 12-point rule (tab:6th), then the BP
  *     limiter, no initial OE.
+ *
+ * Threads: the cell loops run under OpenMP when it is enabled (orc_set_threads).
+ * Each cell's arithmetic is the same on any thread, and every floating-point
+ * reduction over cells (domain sums, maxima) is taken serially in cell order, so
+ * the results are bit for bit those of one thread.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -166,6 +174,7 @@ typedef struct {
     int oe_on, bp_on, oe_mode;     /* oe_mode 0 = rotation invariant, 1 = component-wise */
     /* state, AoS [cell][var][mode] */
     double *u0, *u, *w, *L, *pre;
+    double* scratch_c;   /* one double per cell (per-cell maxima before their serial combination) */
     double t, dt, alpha, t_end;
     long step;
     int active, err;
@@ -357,6 +366,7 @@ void orc_destroy(Orc* o) {
     free(o->tri); free(o->vx); free(o->nbr); free(o->nbe); free(o->area); free(o->len);
     free(o->nrm); free(o->jinv); free(o->mass); free(o->perm); free(o->limv); free(o->node); free(o->wdcw);
     free(o->ck); free(o->ck_dcw); free(o->ck_zxs); free(o->bc); free(o->swapped); free(o->u0); free(o->u); free(o->w); free(o->L); free(o->pre);
+    free(o->scratch_c);
     free(o);
 }
 
@@ -403,6 +413,7 @@ Orc* orc_create(int k, int nv, const double* xy, int nc, const int* tri_in, cons
     o->w = (double*)xcalloc(ns, sizeof(double));
     o->L = (double*)xcalloc(ns, sizeof(double));
     o->pre = (double*)xcalloc(ns, sizeof(double));
+    o->scratch_c = (double*)xcalloc((size_t)o->nc, sizeof(double));
 
     /* coordinates and counter-clockwise orientation */
     for (int c = 0; c < nc; ++c) {
@@ -569,6 +580,7 @@ static void residual(Orc* o, const double* arr, double alpha, double* Lout) {
     const int nm = o->nm, Q = o->ne;
     const double(*VB)[3] = o->k == 1 ? TRI3_B : (const double(*)[3])TRI6_B;
     const double* VW = o->k == 1 ? TRI3_W : TRI6_W;
+#pragma omp parallel for schedule(static)
     for (int c = 0; c < o->nc; ++c) {
         double rhs[NVAR][MAXM];
         memset(rhs, 0, sizeof(rhs));
@@ -641,10 +653,12 @@ static void residual(Orc* o, const double* arr, double alpha, double* Lout) {
 
 /* eq. 1250: alpha = max over every cell, edge and edge Gauss point of R(u_h, n) */
 static double max_wave_speed(const Orc* o, const double* arr) {
-    double a = 0;
     const int Q = o->ne;
+    double* rc = o->scratch_c;   /* the cells' own maxima, then combined in cell order */
+#pragma omp parallel for schedule(static)
     for (int c = 0; c < o->nc; ++c) {
         const double* vc = o->vx + 6 * c;
+        double a = 0;
         for (int i = 0; i < 3; ++i) {
             const double* pa = vc + 2 * ((i + 1) % 3);
             const double* pb = vc + 2 * ((i + 2) % 3);
@@ -656,7 +670,11 @@ static double max_wave_speed(const Orc* o, const double* arr) {
                 if (r > a || r != r) a = r;
             }
         }
+        rc[c] = a;
     }
+    double a = 0;
+    for (int c = 0; c < o->nc; ++c)
+        if (rc[c] > a || rc[c] != rc[c]) a = rc[c];
     return a;
 }
 
@@ -704,6 +722,7 @@ static void oe_filter(Orc* o, double* arr, double dt) {
 
     double* out = o->L;  /* scratch: damped copy, so every cell sees the unfiltered field */
     memcpy(out, arr, sizeof(double) * (size_t)o->nc * NVAR * nm);
+#pragma omp parallel for schedule(dynamic, 64)
     for (int c = 0; c < o->nc; ++c) {
         double sigma[NVAR][3];
         memset(sigma, 0, sizeof(sigma));
@@ -867,6 +886,8 @@ static int limiter_values(const Orc* o, const double* arr, int c, double q[12][N
 /* returns the number of cells whose average is not admissible */
 static int bp_limit(Orc* o, double* arr) {
     int bad = 0;
+    long limited = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad, limited)
     for (int c = 0; c < o->nc; ++c) {
         double q[12][NVAR];
         /* step 1: density */
@@ -890,9 +911,10 @@ static int bp_limit(Orc* o, double* arr) {
         if (!(emin >= e2)) th2 = fmin((eb - e2) / (eb - emin), 1.0);
         for (int v = 0; v < NVAR; ++v)
             for (int l = 1; l < o->nm; ++l) U(arr, c, v, l) *= th2;
-        if (th1 < 1.0 || th2 < 1.0) o->n_limited++;
+        if (th1 < 1.0 || th2 < 1.0) ++limited;
         if (!(rb > 0) || !(eb > 0)) ++bad;
     }
+    o->n_limited += limited;
     return bad;
 }
 
@@ -911,6 +933,7 @@ static void next_dt(Orc* o) {
  * the stage output's averages */
 static int bad_averages(const Orc* o, const double* arr) {
     int bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad)
     for (int c = 0; c < o->nc; ++c) {
         double ub[NVAR];
         for (int v = 0; v < NVAR; ++v) ub[v] = U(arr, c, v, 0);
@@ -931,6 +954,7 @@ int orc_stage(Orc* o, int s) {
     const double alpha = max_wave_speed(o, in);
     if (s == 0) o->alpha = alpha;
     residual(o, in, alpha, o->L);
+#pragma omp parallel for schedule(static)
     for (size_t i = 0; i < ns; ++i) o->w[i] = a[s] * o->u0[i] + b[s] * (in[i] + o->dt * o->L[i]);
     memcpy(o->pre, o->w, sizeof(double) * ns);
     if (o->bp_on && bad_averages(o, o->w)) {
@@ -1049,6 +1073,7 @@ int orc_init_problem(Orc* o, int kind, const double* P) {
         }
         return 0;
     }
+#pragma omp parallel for schedule(static)
     for (int c = 0; c < o->nc; ++c) {
         const double* vc = o->vx + 6 * c;
         for (int m = 0; m < 12; ++m) {
@@ -1176,4 +1201,16 @@ int orc_quadrature(int which, double* pts, double* w) {
     const int Q = which == 3 ? 2 : 3;
     for (int g = 0; g < Q; ++g) { pts[g] = GS[Q][g]; w[g] = GW[Q][g]; }
     return Q;
+}
+
+/* Threads of the cell loops (OpenMP; n <= 0: one per processor); returns the
+ * number now in use, 1 without OpenMP. */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

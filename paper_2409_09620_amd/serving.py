@@ -1,12 +1,22 @@
 """Continuous-batching solve server over the C ABI (dg_batch_*).
 
-Requests (a mesh, a degree, initial data, a final time) arrive over time.  The
-server keeps every admitted request's state resident in HBM and advances all
-of them together: each stage pass is one launch over the whole active set,
-every request with its own alpha, Delta t and t_end.  A request is admitted as
-soon as it has arrived and its HBM footprint fits in the budget (or the server
-is empty), finished requests are read back and freed every few steps, and the
-batch is rebuilt whenever its membership changes.
+Requests (a mesh, a degree, initial data, a final time, a precision) arrive over
+time.  The server keeps every admitted request's state resident in HBM and
+advances all of them together: each stage pass is one launch over the active set
+of a precision, every request with its own alpha, Delta t and t_end.
+
+* Admission.  A request whose footprint fits in the HBM budget (or any request
+  when nothing is admitted) is handed to a preparation thread as soon as it has
+  arrived.  The thread builds the mesh tables on the host, uploads them and
+  projects the initial data on a stream of its own, so a large request does not
+  stall the requests already stepping.  A request that fails there (a bad mesh,
+  no memory) is finished with its error; the others go on.
+* Stepping.  Prepared requests join their precision's batch at the next poll;
+  each batch advances steps_per_tick steps between polls.
+* Retirement.  A request that reached its t_end is read back at the poll that
+  sees it finished.  It stays in its batch, skipped by the kernels, until
+  requests join that batch: the batch (and its captured step) is rebuilt only
+  when members join, and the finished ones are dropped then.
 
 A member's reductions run over its own 256-cell groups in a fixed order, so its
 result is the same, bit for bit, whatever else is in flight.
@@ -16,16 +26,18 @@ library.
 """
 
 import ctypes
+import threading
 import time
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import Any, Callable, List, Optional
 
 import numpy as np
 
-from .binding import Batch, Solver, load_library
+from .binding import PRECISION, Batch, Solver, load_library
 
-# partial records of a batch: 17 doubles per 256-cell group
-_BATCH_BYTES_PER_CELL = 17 * 8 / 256.0
+# partial records of a batch: 24 doubles per 256-cell group
+_BATCH_BYTES_PER_CELL = 24 * 8 / 256.0
 
 
 def footprint_bytes(n_cell, k):
@@ -48,7 +60,8 @@ class Request:
     arrival: float = 0.0                 # seconds after the start of the run
     precision: str = "fp64"
     # filled in by the server
-    admitted: Optional[float] = None
+    admitted: Optional[float] = None     # handed to a preparation thread
+    joined: Optional[float] = None       # first stepped in a batch
     done: Optional[float] = None
     steps: int = 0
     t: float = 0.0
@@ -75,95 +88,176 @@ class ServeStats:
     peak_members: int
     rebuilds: int
     steps_launched: int
+    errors: int = 0
     latencies: List[float] = field(default_factory=list)
+
+
+class _Group:
+    """The batch of one precision: its members (request, solver, footprint) and
+    whether each is still active."""
+
+    def __init__(self):
+        self.members = []
+        self.batch = None
+
+    def active_count(self):
+        return sum(1 for m in self.members if m[0].done is None)
 
 
 class Server:
     """hbm_budget: bytes the admitted requests may hold together; steps_per_tick:
-    batched steps between polls (admission and retirement happen at polls);
-    keep_results: read each finished state back to the host."""
+    batched steps between polls; keep_results: read each finished state back to
+    the host; prepare_threads: threads that build, upload and project new
+    requests."""
 
-    def __init__(self, device=0, hbm_budget=8 << 30, steps_per_tick=8, keep_results=True, autotune=False):
+    def __init__(self, device=0, hbm_budget=8 << 30, steps_per_tick=8, keep_results=True, autotune=False,
+                 prepare_threads=2):
         self.device = int(device)
         self.budget = int(hbm_budget)
         self.steps_per_tick = int(steps_per_tick)
         self.keep_results = keep_results
         self.autotune = autotune
+        self.prepare_threads = max(1, int(prepare_threads))
+        self._tls = threading.local()
 
-    def _admit(self, req, t0):
-        m, kind, params = req.build()
-        s = Solver(m, req.k, device=self.device)
-        s.init_problem(kind, params, precision=req.precision)
-        s.set_t_end(req.t_end)
-        req.admitted = time.perf_counter() - t0
+    def _prepare(self, req):
+        """Worker thread: the request's context, mesh tables, upload and initial
+        state, on the thread's own stream (dg_init_problem synchronises it)."""
+        import torch
+        torch.cuda.set_device(self.device)
+        if getattr(self._tls, "stream", None) is None:
+            self._tls.stream = torch.cuda.Stream(self.device)
+        with torch.cuda.stream(self._tls.stream):
+            m, kind, params = req.build()
+            s = Solver(m, req.k, device=self.device)
+            try:
+                s.init_problem(kind, params, precision=req.precision)
+                s.set_t_end(req.t_end)
+                s.diag()                 # synchronises the thread's stream
+            except Exception:
+                s.close()
+                raise
         return s
 
     def run(self, requests, clock=time.perf_counter):
         """Serves `requests` (arrival times relative to the start) to completion
-        and returns ServeStats; each request gets its result, t, step count and
-        completion time."""
+        and returns ServeStats; each request gets its result (or error), t, step
+        count and completion time."""
+        for r in requests:
+            if r.precision not in PRECISION:
+                raise ValueError(f"request {r.id}: precision must be one of {sorted(PRECISION)}")
         pending = sorted(requests, key=lambda r: r.arrival)
-        active = []                      # (request, solver, footprint)
+        preparing = []                   # (request, future, footprint)
+        groups = {p: _Group() for p in PRECISION}
         used = 0
-        batch = None
-        members_changed = False
         peak = rebuilds = launched = 0
+        pool = ThreadPoolExecutor(max_workers=self.prepare_threads)
         t0 = clock()
-        while pending or active:
-            now = clock() - t0
-            # admission: arrived requests in arrival order while they fit
-            while pending and pending[0].arrival <= now:
-                r = pending[0]
-                fp = footprint_bytes(r.n_cell, r.k)
-                if active and used + fp > self.budget:
-                    break
-                pending.pop(0)
-                active.append((r, self._admit(r, t0), fp))
-                used += fp
-                members_changed = True
-            if not active:
-                # idle until the next arrival
-                wait = pending[0].arrival - (clock() - t0)
-                if wait > 0:
-                    time.sleep(min(wait, 0.01))
-                continue
-            if members_changed:
-                if batch is not None:
-                    batch.close()
-                batch = Batch([s for _, s, _ in active])
-                if self.autotune:
-                    batch.autotune(reps=1)
-                rebuilds += 1
-                members_changed = False
-                peak = max(peak, len(active))
-            batch.step(self.steps_per_tick)
-            launched += self.steps_per_tick
-            _, status = batch.status()
-            # retirement: read finished members back, then drop the batch before
-            # their contexts
-            keep, done = [], []
-            for (r, s, fp), st in zip(active, status):
-                if st[0] == 0.0:
-                    r.done = clock() - t0
-                    r.t, r.steps = float(st[2]), int(st[3])
-                    if st[1] != 0.0:
-                        r.error = "a cell average left the admissible set"
-                    if self.keep_results:
-                        r.result = s.readback()[0]
-                    used -= fp
-                    done.append(s)
+        def compact(g, new_members=()):
+            # (re)builds g's batch from its active members and the joining ones; the
+            # finished members, already read back, are freed.  Returns the bytes freed.
+            nonlocal rebuilds
+            if g.batch is not None:
+                g.batch.close()
+                g.batch = None
+            keep, freed = [], 0
+            for m in g.members:
+                if m[0].done is None:
+                    keep.append(m)
                 else:
-                    keep.append((r, s, fp))
-            if done:
-                batch.close()
-                batch = None
-                members_changed = True
-                for s in done:
-                    s.close()
-            active = keep
+                    m[1].close()
+                    freed += m[2]
+            g.members = keep + list(new_members)
+            if g.members:
+                g.batch = Batch([s for _, s, _ in g.members])
+                if self.autotune:
+                    g.batch.autotune(reps=1)
+                rebuilds += 1
+            return freed
+
+        try:
+            while pending or preparing or any(g.active_count() for g in groups.values()):
+                now = clock() - t0
+                # admission: arrived requests in arrival order while they fit; when the
+                # budget blocks one, the finished members still held are freed first
+                while pending and pending[0].arrival <= now:
+                    r = pending[0]
+                    fp = footprint_bytes(r.n_cell, r.k)
+                    held = used > 0 or preparing
+                    if held and used + fp > self.budget:
+                        freed = 0
+                        for g in groups.values():
+                            if any(m[0].done is not None for m in g.members):
+                                freed += compact(g)
+                        used -= freed
+                        if freed == 0 or used + fp > self.budget:
+                            break
+                    pending.pop(0)
+                    r.admitted = now
+                    preparing.append((r, pool.submit(self._prepare, r), fp))
+                    used += fp
+                # prepared requests join their group; failed ones finish with their error
+                joined = {p: [] for p in groups}
+                still = []
+                for r, fut, fp in preparing:
+                    if not fut.done():
+                        still.append((r, fut, fp))
+                        continue
+                    try:
+                        joined[r.precision].append((r, fut.result(), fp))
+                    except Exception as e:   # noqa: BLE001 - reported per request
+                        r.error = f"admission failed: {e}"
+                        r.done = clock() - t0
+                        used -= fp
+                preparing = still
+                for p, g in groups.items():
+                    if joined[p]:
+                        used -= compact(g, joined[p])
+                        now2 = clock() - t0
+                        for r, _, _ in joined[p]:
+                            r.joined = now2
+                    elif g.members and not g.active_count():
+                        used -= compact(g)   # nothing left to step: free the finished ones
+                peak = max(peak, sum(g.active_count() for g in groups.values()))
+                stepped = False
+                for g in groups.values():
+                    if g.batch is not None and g.active_count():
+                        g.batch.step(self.steps_per_tick)
+                        stepped = True
+                if stepped:
+                    launched += self.steps_per_tick
+                else:
+                    if preparing:
+                        time.sleep(0.0005)
+                    elif pending:
+                        wait = pending[0].arrival - (clock() - t0)
+                        if wait > 0:
+                            time.sleep(min(wait, 0.01))
+                    continue
+                # retirement: read back the members that finished since the last poll
+                for g in groups.values():
+                    if g.batch is None:
+                        continue
+                    _, status = g.batch.status()
+                    for (r, s, fp), st in zip(g.members, status):
+                        if r.done is None and st[0] == 0.0:
+                            r.done = clock() - t0
+                            r.t, r.steps = float(st[2]), int(st[3])
+                            if st[1] != 0.0:
+                                r.error = "a cell average left the admissible set"
+                            if self.keep_results:
+                                r.result = s.readback()[0]
+        finally:
+            pool.shutdown(wait=True)
+            for g in groups.values():
+                if g.batch is not None:
+                    g.batch.close()
+                for m in g.members:
+                    m[1].close()
         wall = clock() - t0
         lat = np.array([r.latency for r in requests])
         return ServeStats(wall=wall, requests=len(requests), p50=float(np.percentile(lat, 50)),
                           p99=float(np.percentile(lat, 99)), mean=float(lat.mean()),
                           dof_stage_per_s=sum(r.dof_stages for r in requests) / wall, peak_members=peak,
-                          rebuilds=rebuilds, steps_launched=launched, latencies=lat.tolist())
+                          rebuilds=rebuilds, steps_launched=launched,
+                          errors=sum(1 for r in requests if r.error is not None), latencies=lat.tolist())

@@ -16,19 +16,22 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_algorithmic_bytes_per_cell():
-    """P2 FP64: S = 4 x 6 x 8 = 192 B; geometry 76 B (J^-1, |K|, lengths, links) and
-    +32 B of limiter-point coordinates in the filter.  Mixed: S = 4 x (8 + 5 x 4) = 112 B."""
+    """The hot-path definition: residual (2 + 2/3) S + 128 B, filter 2 S + 160 B, with
+    S = 4 x 6 x 8 = 192 B at P2 FP64 (640 and 544 B) and 4 x (8 + 5 x 4) = 112 B mixed;
+    as stored, the kernels read 52 and 108 B of geometry."""
     b = bench.algorithmic_bytes_per_cell(2, "fp64")
     assert set(b) == {"residual", "filter"}
-    assert b["residual"] == pytest.approx(192 + 76 + 192 + 2 / 3 * 192)   # 588 B
-    assert b["filter"] == 192 + 108 + 192                                  # 492 B
+    assert b["residual"] == pytest.approx(640.0)
+    assert b["filter"] == 544
     m = bench.algorithmic_bytes_per_cell(2, "mixed")
-    assert m["residual"] == pytest.approx(112 + 76 + 112 + 2 / 3 * 112)
-    assert m["filter"] == 112 + 108 + 112
+    assert m["residual"] == pytest.approx(112 * (2 + 2 / 3) + 128)
+    assert m["filter"] == 2 * 112 + 160
     p1 = bench.algorithmic_bytes_per_cell(1, "fp64")
-    assert p1["filter"] == 96 + 108 + 96
-    # per DOF-stage at P2 FP64 (24 DOF per cell): 1080 B / 24 = 45 B
-    assert sum(b.values()) / 24 == pytest.approx(45.0)
+    assert p1["filter"] == 2 * 96 + 160
+    # per DOF-stage at P2 FP64 (24 DOF per cell): 1184 B / 24 = 49.3 B
+    assert sum(b.values()) / 24 == pytest.approx(1184 / 24)
+    st = bench.stored_bytes_per_cell(2, "fp64")
+    assert st["residual"] == pytest.approx(192 * (2 + 2 / 3) + 52) and st["filter"] == 2 * 192 + 108
 
 
 def test_roofline_from_profile():
@@ -38,13 +41,19 @@ def test_roofline_from_profile():
     prof = {"residual": (50e-3 * 30, 30), "filter": (60e-3 * 30, 30)}
     roof, per_k = bench.roofline(prof, 2, n_cell, "no_such_workload", "fp64")
     assert roof["kernel"] == "filter" and roof["bound"] == "hbm" and roof["unit"] == "GB/s"
-    alg = 492 * n_cell
+    alg = 544 * n_cell
     assert roof["alg_bytes_per_launch"] == alg
     assert roof["achieved"] == pytest.approx(alg / 60e-6 / 1e9, rel=1e-3)
     assert roof["peak"] == 8000.0
     assert roof["frac"] == pytest.approx(roof["achieved"] / 8000.0, rel=1e-3)
     assert roof["traffic"] is None                  # no counters for this workload
+    assert roof["as_stored"]["bytes_per_cell"] == 492
     assert set(per_k) == {"residual", "filter"}
+
+
+def test_cpu_model_and_threads():
+    model, usable = bench.host_cpu()
+    assert isinstance(model, str) and model and usable >= 1
 
 
 def test_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):

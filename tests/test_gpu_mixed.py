@@ -195,3 +195,67 @@ def test_precision_switch_on_one_context():
     c.init_problem(kind, p, precision="mixed")
     c.step()
     assert np.array_equal(a.readback()[0], c.readback()[0])
+
+
+def _totals(s, area):
+    """sum_K |K| ubar_K per conservative variable, summed exactly (math.fsum of the
+    rounded products)."""
+    import math
+    u = s.readback()[0]
+    return np.array([math.fsum(area * u[v, 0, :]) for v in range(4)])
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_conservation_of_averages_periodic(precision):
+    """Periodic vortex: both cells of an edge take its flux from the same traces,
+    normal and operand order, so the averages' update conserves sum |K| ubar to the
+    FP64 rounding of each cell's update (both forms keep the averages in FP64):
+    drift <= 1e-14 of the largest total per step."""
+    k, m, kind, p = CASES["p2_periodic_vortex"]()
+    say(f"[gpu case] conservation {precision} cells={m.n_cell}")
+    s = Solver(m, k)
+    s.init_problem(kind, p, precision=precision)
+    area = oracle.Oracle(m, k).mesh_arrays()["area"]
+    tot0 = _totals(s, area)
+    steps = 20
+    s.step_to(float("inf"), steps)
+    tot = _totals(s, area)
+    drift = np.abs(tot - tot0).max() / np.abs(tot0).max()
+    say(f"  {precision}: relative drift of sum |K| ubar after {steps} steps: {drift:.2e}")
+    assert drift <= 1e-14 * steps
+
+
+def test_mixed_norms_of_small_perturbation():
+    """A 1e-6 perturbation of the higher modes on a uniform state: the mixed form
+    forms the OE normalisations ||u - ubar|| and |||m - mbar||| from the FP64
+    averages plus the FP32 higher modes' part, so they match the FP64 form to the
+    FP32 rounding of the perturbation (not of the background), and so do the damped
+    modes."""
+    k, m, kind, p = CASES["p2_quadrant_3k"]()
+    nm = 6
+    rng = np.random.default_rng(7)
+    u = np.zeros((4, nm, m.n_cell))
+    u[0, 0] = 1.0
+    u[1, 0] = 0.3
+    u[2, 0] = -0.2
+    u[3, 0] = 2.5 + 0.5 * (0.3 ** 2 + 0.2 ** 2)
+    u[:, 1:, :] = 1e-6 * rng.standard_normal((4, nm - 1, m.n_cell))
+    res = {}
+    for prec in ("fp64", "mixed"):
+        s = Solver(m, k)
+        s.init_modal(u, precision=prec)
+        s.stage(0)
+        res[prec] = (s.diag(), s.read_state(1))
+        s.close()
+    d64, dmx = res["fp64"][0], res["mixed"][0]
+    for v in range(4):
+        e = abs(dmx["nrm"][v] - d64["nrm"][v]) / d64["nrm"][v]
+        say(f"  norm of variable {v}: fp64 {d64['nrm'][v]:.6e} mixed {dmx['nrm'][v]:.6e} rel {e:.1e}")
+        assert d64["nrm"][v] > 1e-7 and e <= 1e-3
+    e = abs(dmx["nrm_m"] - d64["nrm_m"]) / d64["nrm_m"]
+    assert e <= 1e-3, (dmx["nrm_m"], d64["nrm_m"])
+    # the stage outputs' higher modes agree to a small fraction of the perturbation
+    hi64, himx = res["fp64"][1][:, 1:, :], res["mixed"][1][:, 1:, :]
+    rel = np.abs(himx - hi64).max() / np.abs(hi64).max()
+    say(f"  higher modes after the stage: rel {rel:.1e}")
+    assert rel <= 1e-3

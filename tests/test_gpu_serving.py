@@ -8,6 +8,8 @@ import sys
 import numpy as np
 import pytest
 
+import oracle
+from synth import mesh as smesh
 from synth import workloads
 
 torch = pytest.importorskip("torch")
@@ -24,14 +26,15 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_requests(n=12, rate=400.0):
+def make_requests(n=12, rate=400.0, precision=None):
     specs = workloads.serving_requests(n_req=n, rate=rate, lo=300, hi=6000, t_lo=0.01, t_hi=0.05)
     built = {s["id"]: workloads.serving_request(s) for s in specs}
     reqs = []
-    for s in specs:
+    for i, s in enumerate(specs):
         m = built[s["id"]][0]
+        prec = "fp64" if precision is None else precision(i)
         reqs.append(Request(id=s["id"], k=s["k"], n_cell=m.n_cell, t_end=s["t_end"],
-                            build=(lambda b=built[s["id"]]: b), arrival=s["arrival"]))
+                            build=(lambda b=built[s["id"]]: b), arrival=s["arrival"], precision=prec))
     return reqs, built
 
 
@@ -77,3 +80,41 @@ def test_admission_respects_budget():
     Server(steps_per_tick=5).run(again)
     for a, b in zip(reqs, again):
         assert np.array_equal(a.result, b.result)
+
+
+def rel_l1(a, b):
+    return np.abs(a - b).sum() / np.abs(b).sum()
+
+
+def test_served_results_match_oracle():
+    """Six served requests (mixed sizes, P1 and P2, Riemann and vortex data) against
+    the oracle run alone to the same t_end: same step count, rel. L1 <= 1e-11."""
+    reqs, built = make_requests(n=6, rate=2000.0)
+    say(f"[gpu case] serving vs oracle, cells {[r.n_cell for r in reqs]}")
+    stats = Server(steps_per_tick=4).run(reqs)
+    assert stats.peak_members > 1 and stats.errors == 0
+    for r in reqs:
+        m, kind, p = built[r.id]
+        o = oracle.Oracle(m, r.k)
+        assert o.init_problem(kind, p) == 0
+        rc, done = o.run(r.t_end)
+        e = rel_l1(r.result, o.state(0))
+        say(f"  request {r.id}: P{r.k} {r.n_cell} cells, {r.steps} steps, rel L1 {e:.2e}")
+        assert rc == 0 and done == r.steps and abs(o.scalars()["t"] - r.t) <= 1e-14
+        assert e <= 1e-11
+
+
+def test_mixed_precision_stream_and_failed_admission():
+    """FP64 and mixed requests in one stream are served by a batch per precision;
+    a request whose mesh is invalid fails alone and the others complete."""
+    reqs, built = make_requests(n=8, rate=2000.0, precision=lambda i: "mixed" if i % 2 else "fp64")
+    bad_mesh = smesh.Mesh(xy=np.array([[0.0, 0.0], [1.0, 0.0], [2.0, 0.0]]), tri=np.array([[0, 1, 2]], np.int32))
+    bad = Request(id=999, k=2, n_cell=1, t_end=0.01, arrival=0.0,
+                  build=lambda: (bad_mesh, built[reqs[0].id][1], built[reqs[0].id][2]))
+    stats = Server(steps_per_tick=4).run(reqs + [bad])
+    assert bad.error is not None and bad.done is not None and stats.errors == 1
+    for r in reqs:
+        assert r.error is None and abs(r.t - r.t_end) < 1e-14
+        alone = Request(id=r.id, k=r.k, n_cell=r.n_cell, t_end=r.t_end, build=r.build, precision=r.precision)
+        Server(steps_per_tick=3).run([alone])
+        assert np.array_equal(alone.result, r.result), r.id

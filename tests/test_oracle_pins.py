@@ -752,3 +752,23 @@ def test_alpha_hand_computed_point_set(k):
     s1 = 0.5 - math.sqrt(3) / 6 if k == 1 else 0.5 - math.sqrt(15) / 10
     want = w + math.sqrt(g / (1 + s1))
     assert abs(o.alpha_of(u) - want) < 1e-14 * want, (o.alpha_of(u), want)
+
+
+# ----------------------------------------------------------------------------- threads
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_threads_bitwise_equal_to_one(k):
+    """The cell loops under OpenMP give, bit for bit, the one-thread result: every
+    floating-point reduction over cells is taken serially in cell order."""
+    m, kind, p = workloads.quadrant_delaunay(n_cells=3000, seed=31)
+    runs = []
+    for n in (1, 4):
+        oracle.set_threads(n)
+        o = oracle.Oracle(m, k)
+        o.init_problem(kind, p)
+        for _ in range(3):
+            assert o.step() == 0
+        runs.append((o.state(0), o.scalars()))
+    oracle.set_threads(0)
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert runs[0][1] == runs[1][1]
