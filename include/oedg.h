@@ -233,6 +233,9 @@ typedef struct {
     int64_t n_flat;               /* DG_PREC_MIXED: cell-stages reset to their average by the
                                      check of the stored (FP32-rounded) coefficients */
     int64_t n_restarts;           /* steps retried with half the time step */
+    double alpha_stage;           /* LF viscosity of the next stage's input (eq. 1250):
+                                     alpha of u^n before stage 0, of the last stage
+                                     output after stages 0 and 1 */
 } dg_diag_t;
 
 /* Diagnostics of the context (synchronises). */

@@ -674,6 +674,7 @@ dg_status dg_diag(dg_ctx* c, dg_diag_t* out) {
     out->n_cfl_excursions = h.n_cfl_exc;
     out->n_flat = h.n_flat;
     out->n_restarts = h.n_restarts;
+    out->alpha_stage = h.alpha;
     for (int v = 0; v < 4; ++v) {
         out->ubar[v] = h.ubar[v];
         out->nrm[v] = h.nrm[v];

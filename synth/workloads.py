@@ -40,15 +40,16 @@ def blast_delaunay(n_cells=1_000_000, seed=3):
     return m, PROBLEM_BLAST, blast_params(ov)
 
 
-def implosion(n_cells=20_000, seed=6, rotate=False):
+def implosion(n_cells=20_000, seed=6, rotate=False, inner=(0.125, 0.14)):
     """Example EulerImp on a seeded Delaunay stand-in for its mesh: (rho, v, p) =
     (0.125, 0, 0.14) where x + y < 0.15, (1, 0, 1) elsewhere, every wall reflective.
+    inner: (rho, p) of the region x + y < 0.15 in place of the example's.
     rotate: the mesh turned clockwise by pi/4, x' = M x with M = [[c, c], [-c, c]],
     c = sqrt(2)/2 (same cells and ids); the data turn with it (v = 0, so only the
     dividing line moves)."""
     m = poisson_delaunay(n_cells, lo=(0.0, 0.0), hi=(0.3, 0.3), seed=seed, name=f"implosion{n_cells}")
     m.edge_bc = np.ones((m.n_cell, 3), np.int32)       # every boundary edge is a wall
-    lo_state, hi_state = [0.125, 0.0, 0.0, 0.14], [1.0, 0.0, 0.0, 1.0]
+    lo_state, hi_state = [float(inner[0]), 0.0, 0.0, float(inner[1])], [1.0, 0.0, 0.0, 1.0]
     if not rotate:
         p = np.array([0.15, 0.0, 1.0, 1.0] + lo_state + hi_state)
         return m, PROBLEM_TWO_STATE, p

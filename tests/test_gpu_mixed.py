@@ -226,11 +226,17 @@ def test_conservation_of_averages_periodic(precision):
 
 
 def test_mixed_norms_of_small_perturbation():
-    """A 1e-6 perturbation of the higher modes on a uniform state: the mixed form
-    forms the OE normalisations ||u - ubar|| and |||m - mbar||| from the FP64
-    averages plus the FP32 higher modes' part, so they match the FP64 form to the
-    FP32 rounding of the perturbation (not of the background), and so do the damped
-    modes."""
+    """A 1e-6 perturbation of the higher modes on a uniform state.  The norm of such
+    a state is the difference of two O(1) values (a node value and the domain
+    average), so its FP64 conditioning is that of the average's sum over the cells,
+    n u64 max|ubar| absolutely: the FP64 path's norms match the oracle's norms of
+    the same state (read back) to that.  The mixed form forms them from the FP64
+    averages plus the FP32 higher modes' part, so it adds only the FP32 rounding of
+    the perturbation, 1e-5 relative, where an FP32 evaluation of the whole value
+    would be off by u32 |ubar| / 1e-6 ~ 1e-1.  Against the FP64 path the pre-filter
+    states themselves differ: the FP32 residual rounds the O(1) background flux,
+    which moves the 1e-6 modes by u32 |F| Delta t / h ~ 2e-2 of their size (bounded
+    at 1e-1 in the norms and the outputs' higher modes)."""
     k, m, kind, p = CASES["p2_quadrant_3k"]()
     nm = 6
     rng = np.random.default_rng(7)
@@ -240,22 +246,35 @@ def test_mixed_norms_of_small_perturbation():
     u[2, 0] = -0.2
     u[3, 0] = 2.5 + 0.5 * (0.3 ** 2 + 0.2 ** 2)
     u[:, 1:, :] = 1e-6 * rng.standard_normal((4, nm - 1, m.n_cell))
+    o = oracle.Oracle(m, k)
     res = {}
     for prec in ("fp64", "mixed"):
         s = Solver(m, k)
         s.init_modal(u, precision=prec)
         s.stage(0)
-        res[prec] = (s.diag(), s.read_state(1))
+        d, pre = s.diag(), s.read_state(2)
+        o.oe(pre, d["dt"])
+        res[prec] = (d, s.read_state(1), o.scalars())
         s.close()
+    sum_abs = m.n_cell * 2.0 ** -53 * np.abs(u[:, 0, :]).max(axis=1)   # per variable
+    for prec, extra in (("fp64", 0.0), ("mixed", 1e-5)):
+        d, _, so = res[prec]
+        names = ("nrm_rho", "nrm_m1", "nrm_m2", "nrm_E")
+        for v in range(4):
+            e = abs(d["nrm"][v] - so[names[v]]) / so[names[v]]
+            bound = sum_abs[v] / so[names[v]] + extra
+            say(f"  {prec} norm of variable {v}: {d['nrm'][v]:.9e}, oracle on the same state {so[names[v]]:.9e}, "
+                f"rel {e:.1e} (bound {bound:.1e})")
+            assert so[names[v]] > 1e-7 and e <= bound
+        e = abs(d["nrm_m"] - so["nrm_m"]) / so["nrm_m"]
+        assert e <= sum_abs[1:3].max() / so["nrm_m"] + extra, (prec, d["nrm_m"], so["nrm_m"])
     d64, dmx = res["fp64"][0], res["mixed"][0]
     for v in range(4):
         e = abs(dmx["nrm"][v] - d64["nrm"][v]) / d64["nrm"][v]
-        say(f"  norm of variable {v}: fp64 {d64['nrm'][v]:.6e} mixed {dmx['nrm'][v]:.6e} rel {e:.1e}")
-        assert d64["nrm"][v] > 1e-7 and e <= 1e-3
-    e = abs(dmx["nrm_m"] - d64["nrm_m"]) / d64["nrm_m"]
-    assert e <= 1e-3, (dmx["nrm_m"], d64["nrm_m"])
+        say(f"  mixed against fp64, norm of variable {v}: rel {e:.1e}")
+        assert e <= 1e-1
     # the stage outputs' higher modes agree to a small fraction of the perturbation
     hi64, himx = res["fp64"][1][:, 1:, :], res["mixed"][1][:, 1:, :]
     rel = np.abs(himx - hi64).max() / np.abs(hi64).max()
     say(f"  higher modes after the stage: rel {rel:.1e}")
-    assert rel <= 1e-3
+    assert rel <= 1e-1

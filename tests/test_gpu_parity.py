@@ -2,8 +2,8 @@
 
 Tolerances: both codes compute in FP64 but round differently (FMA contraction,
 summation order), so after one stage the element-wise difference is a few ulps of
-the largest coefficient of a variable; the FP64 path is held to rel. L1 <= 1e-11
-after 100 steps.
+each variable's scale; stages are held to 1e-12 outside the cells set aside at a
+limiter floor (floor_mask), and the FP64 path to rel. L1 <= 1e-11 after 100 steps.
 """
 
 import math
@@ -23,6 +23,8 @@ if not torch.cuda.is_available():   # collected on CPU-only hosts, skipped there
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_2409_09620_amd import DgError, Solver  # noqa: E402
+from floor_mask import (alpha_tolerance, independent_mask, masked_err, near_floor,  # noqa: E402
+                        same_input_stages)
 
 
 def say(*a):
@@ -63,19 +65,6 @@ def make(case, **cfg):
     return s, o, m
 
 
-def alpha_tolerance(o, limited, floor=1e-13):
-    """Relative bound for the max wave speed of a limited state.
-
-    The density at an edge Gauss point is a sum of O(rho_bar) terms; where the
-    limiter pinned it near its 1e-13 floor two FP64 evaluation orders differ by
-    about 1e-16 rho_bar absolutely, and the sound speed (~ rho^-1/2) inherits
-    half that relative error.  Bound: 1e-15 * max_K rho_bar_K / rho_min_K."""
-    npt = 3 * (o.k + 1)
-    vals = o.limiter_node_values(limited)[:, :npt, 0]
-    ratio = (np.abs(limited[0, 0, :]) / np.maximum(vals.min(axis=1), 1e-13)).max()
-    return max(floor, 1e-15 * ratio)
-
-
 @pytest.mark.parametrize("case", list(CASES))
 def test_initial_state_parity(case):
     s, o, m = make(case)
@@ -90,50 +79,12 @@ def test_initial_state_parity(case):
     assert abs(d["dt"] - so["dt"]) <= a_tol * so["dt"]
 
 
-def oracle_sensitivity(m, k, u, seed=0):
-    """How far the oracle's own residual moves when its input is perturbed by a
-    relative 1e-15 (round-off level): the floor of any two FP64 codes' agreement."""
-    o = oracle.Oracle(m, k)
-    rng = np.random.default_rng(seed)
-    up = u * (1.0 + 1e-15 * rng.standard_normal(u.shape))
-    return rel_err(o.residual(up, o.alpha_of(up)), o.residual(u, o.alpha_of(u)))
-
-
 @pytest.mark.parametrize("case", list(CASES))
 def test_stage_by_stage_parity(case):
-    """Pre-filter state and limited output after every stage of two steps.
-
-    Where the limiter pins density at its 1e-13 floor while the pressure stays
-    O(0.1) (strong two-state data), the wave speed reaches ~1e6 and the scheme
-    amplifies round-off; there the bound is scaled by the oracle's own response
-    to a round-off perturbation of the stage input."""
+    """Every stage of two steps against the oracle's stage from the GPU's own
+    inputs, at 1e-12 outside the cells set aside at a limiter floor (floor_mask)."""
     s, o, m = make(case)
-    k = s.k
-    for step in range(2):
-        for st in range(3):
-            u_in = o.state(0 if st == 0 else 1)
-            # the stage's LF viscosity is alpha of its input: its conditioning bounds
-            # the state agreement too (relative alpha error enters the dissipation)
-            tol = max(1e-12, 100.0 * oracle_sensitivity(m, k, u_in), 10.0 * alpha_tolerance(o, u_in))
-            s.stage(st)
-            o.stage(st)
-            pre, out = s.read_state(2), s.read_state(1)
-            e_pre = rel_err(pre, o.state(2))
-            e_out = rel_err(out, o.state(1))
-            assert e_pre < tol and e_out < tol, (step, st, e_pre, e_out, tol)
-            # ||| m - mbar |||_inf of the pre-filter state: the GPU takes mbar from the
-            # conservation bookkeeping, the oracle sums the averages directly
-            n_gpu, n_orc = s.diag()["nrm_m"], o.scalars()["nrm_m"]
-            assert abs(n_gpu - n_orc) <= 10.0 * tol * np.abs(o.state(2)[1:3]).max(), (step, st, n_gpu, n_orc)
-        o.finish_step()
-        d, so = s.diag(), o.scalars()
-        assert abs(d["t"] - so["t"]) <= 1e-14 * max(1.0, so["t"])
-        # alpha at a node whose density the limiter pinned to its floor is the
-        # difference of O(1) terms: bound it by the oracle's own round-off response
-        a_tol = alpha_tolerance(o, o.state(0), floor=1e-12)
-        assert abs(d["alpha"] - so["alpha"]) <= a_tol * so["alpha"], (d["alpha"], so["alpha"], a_tol)
-        assert abs(d["dt"] - so["dt"]) <= a_tol * so["dt"]
-        assert d["step"] == so["step"]
+    same_input_stages(s, o, 2, say)
 
 
 @pytest.mark.parametrize("flags", [dict(oe=False), dict(bp=False), dict(oe_mode=1), dict(oe=False, bp=False)])
@@ -273,29 +224,28 @@ def test_full_size_quadrant_one_step(n_cells):
 
 
 def test_full_size_blast_one_step():
-    """The ~1M-cell P2 blast (near vacuum, the large workload the benchmark times): one
-    full step against the oracle.  Nodes pinned at the density floor amplify round-off,
-    so the bound is the oracle's own response to a relative 1e-15 perturbation of u^0
-    (its one step from the perturbed state), with a 1e-11 floor."""
+    """The ~1M-cell P2 blast (near vacuum, the large workload the benchmark times): the
+    three stages of one step, each code stepping on its own, at 1e-12 outside the
+    cells set aside at a limiter floor (floor_mask), the set-aside count reported."""
     m, kind, p = workloads.blast_delaunay()
     say(f"[gpu case] full-size blast cells={m.n_cell}")
     s = Solver(m, 2)
     s.init_problem(kind, p)
     o = oracle.Oracle(m, 2)
     o.init_problem(kind, p)
-    u0 = o.state(0)
-    s.step()
-    assert o.step() == 0
-    u, ref = s.readback()[0], o.state(0)
-    rng = np.random.default_rng(11)
-    op = oracle.Oracle(m, 2)
-    op.init_modal(u0 * (1.0 + 1e-15 * rng.standard_normal(u0.shape)))
-    assert op.step() == 0
-    sens, sens_l1 = rel_err(op.state(0), ref), rel_l1(op.state(0), ref)
-    e, e_l1 = rel_err(u, ref), rel_l1(u, ref)
-    say(f"blast 1M one step: max {e:.2e} (self {sens:.2e}), L1 {e_l1:.2e} (self {sens_l1:.2e})")
-    assert e < max(1e-11, 100.0 * sens)
-    assert e_l1 < max(1e-13, 100.0 * sens_l1)
+    aux = oracle.Oracle(m, 2)
+    nbr = o.mesh_arrays()["nbr"]
+    mask = near_floor(aux, o.state(0)) | near_floor(aux, s.read_state(0))
+    for st in range(3):
+        s.stage(st)
+        assert o.stage(st) == 0
+        pre, out, ref_pre, ref_out = s.read_state(2), s.read_state(1), o.state(2), o.state(1)
+        mask = independent_mask(aux, [ref_pre, pre], [ref_out, out], o.scalars()["dt"], nbr, mask)
+        e_pre, e_out = masked_err(pre, ref_pre, mask), masked_err(out, ref_out, mask)
+        say(f"  stage {st}: pre {e_pre:.2e} out {e_out:.2e}, set aside {int(mask.sum())} of {m.n_cell}, "
+            f"rel L1 of the output over all cells {rel_l1(out, ref_out):.2e}")
+        assert e_pre <= 1e-12 and e_out <= 1e-12
+    assert mask.sum() <= 0.05 * m.n_cell
     assert s.diag()["n_bad"] == 0
 
 
@@ -378,14 +328,19 @@ def test_strong_riemann_member_restarts_in_batch():
     assert s.diag()["n_restarts"] == o.scalars()["n_restarts"] == 1
     # Where the density limiter pins a node at 1e-13 while the momentum there is not
     # small, theta_2 hangs on that pinned value, so two FP64 codes agree only as
-    # well as the oracle agrees with itself under a round-off perturbation of u^n.
+    # well as the oracle agrees with itself under a round-off perturbation of u^n:
+    # bound 3x the largest of three draws.
     o2 = oracle.Oracle(m, int(degree[34]))
     o2.init_problem(kind, p)
-    rng = np.random.default_rng(34)
-    u_pert = o2.state(0) * (1.0 + 1e-15 * rng.standard_normal(o2.state(0).shape))
-    o2.init_modal(u_pert)
-    assert o2.step() == 0
-    sens = rel_err(o2.state(0), o.state(0))
-    e, tol = rel_err(s.readback()[0], o.state(0)), max(1e-10, 100.0 * sens)
-    say(f"member 34 after one restarted step: rel err {e:.2e}, oracle self-sensitivity {sens:.1e}")
-    assert e < tol
+    u0 = o2.state(0)
+    sens = []
+    for seed in range(3):
+        rng = np.random.default_rng(34 + seed)
+        op = oracle.Oracle(m, int(degree[34]))
+        op.init_modal(u0 * (1.0 + 1e-15 * rng.standard_normal(u0.shape)), limit=False)
+        assert op.step() == 0
+        sens.append(rel_l1(op.state(0), o.state(0)))
+    e = rel_l1(s.readback()[0], o.state(0))
+    say(f"member 34 after one restarted step: rel L1 {e:.2e}, oracle self-difference {max(sens):.1e}")
+    assert max(sens) <= 1e-6
+    assert e <= max(1e-11, 3.0 * max(sens))
