@@ -195,11 +195,12 @@ def serving_tasks(n_req, scale, t_scale):
     return specs, [(workloads.serving_request, (sp,)) for sp in specs]
 
 
-def run_serving(specs, built, rates, scale, t_scale, steps_per_tick=8):
+def run_serving(specs, built, rates, scale, t_scale, steps_per_tick=8, max_wall=120.0):
     """The continuous-batching server on a seeded request stream (sizes 1k-2M
     divided by `scale`, t_end in [0.05, 0.5] times `t_scale`), once per arrival
     rate.  Request meshes are built before the clock starts (the client's
-    payload); upload, host precompute, projection and stepping are timed."""
+    payload); upload, host precompute, projection and stepping are timed.  A run
+    stops after max_wall seconds (its unfinished requests count as errors)."""
     from paper_2409_09620_amd.serving import Request, Server
     from synth import workloads
     n_req = len(specs)
@@ -209,7 +210,8 @@ def run_serving(specs, built, rates, scale, t_scale, steps_per_tick=8):
                         build=(lambda b=built[sp["id"]]: b), arrival=sp["arrival"])
                 for sp in workloads.serving_requests(n_req=n_req, rate=rate, scale=scale, t_scale=t_scale)]
         log(f"serving: {n_req} requests at {rate:g}/s")
-        st = Server(steps_per_tick=steps_per_tick, keep_results=False).run(reqs)
+        st = Server(steps_per_tick=steps_per_tick, keep_results=False, progress=lambda m: log("serving", m),
+                    max_wall=max_wall).run(reqs)
         out[f"rate_{rate:g}_per_s"] = {
             "p50_ms": st.p50 * 1e3, "p99_ms": st.p99 * 1e3, "mean_ms": st.mean * 1e3,
             "dof_stage_per_s": st.dof_stage_per_s, "wall_s": st.wall, "peak_members": st.peak_members,
@@ -386,6 +388,7 @@ def main():
     ap.add_argument("--blast-steps", type=int, default=10, help="timed steps of the ~1M-cell blast; 0 skips it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work per CPU figure")
+    ap.add_argument("--only-serving", action="store_true", help="run the serving workload alone")
     ap.add_argument("--only-blast", action="store_true",
                     help="run only the ~1M-cell blast, FP64 and mixed (for counter runs)")
     ap.add_argument("--serving-requests", type=int, default=8, metavar="N",
@@ -434,11 +437,12 @@ def main():
     # spawned processes)
     t_build = time.perf_counter()
     tasks = []
-    if not args.only_blast:
+    only = args.only_blast or args.only_serving
+    if not only:
         tasks.append((workloads.quadrant_delaunay, (args.cells,)))
-    if args.blast_steps > 0 or args.only_blast:
+    if (args.blast_steps > 0 and not only) or args.only_blast:
         tasks.append((workloads.blast_delaunay, ()))
-    if not args.only_blast and args.batch_scale > 0:
+    if not only and args.batch_scale > 0:
         btasks, bdeg = batch_tasks(args.batch_scale)
         tasks += btasks
     else:
@@ -453,10 +457,10 @@ def main():
     log(f"meshes built in {time.perf_counter() - t_build:.1f} s")
     pos = 0
     quad = blastw = None
-    if not args.only_blast:
+    if not only:
         quad = built[pos]
         pos += 1
-    if args.blast_steps > 0 or args.only_blast:
+    if (args.blast_steps > 0 and not only) or args.only_blast:
         blastw = built[pos]
         pos += 1
     binst = built[pos:pos + len(btasks)]
@@ -489,6 +493,11 @@ def main():
 
     if args.only_blast:
         print(json.dumps({"blast": blast(max(args.steps, 1))}), flush=True)
+        return
+    if args.only_serving:
+        rates = [float(x) for x in args.serving_rates.split(",") if x]
+        print(json.dumps({"serving": run_serving(sspecs, sbuilt, rates, args.serving_scale,
+                                                 args.serving_t_scale)}), flush=True)
         return
 
     mesh, kind, params = quad

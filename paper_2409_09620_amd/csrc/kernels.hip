@@ -1078,6 +1078,113 @@ __device__ __forceinline__ double internal_energy(const double (&q)[4]) {
     return fma(-0.5 * frcp(q[0]), fma(q[1], q[1], q[2] * q[2]), q[3]);
 }
 
+// The filter's tile image: every cell's polynomial as physical monomials about its
+// vertex 0 (the reference origin), u(x0 + X) = c0 + cX X + cY Y + cXX X^2 +
+// cXY X Y + cYY Y^2 per variable (P2; P1 stops at the linear part), and
+// the edge vectors d1 = x1 - x0, d2 = x2 - x0 that place its other two vertices.
+// Values, physical gradients and the (constant) Hessian at a vertex then cost a
+// few FMAs each, which is most of what the OE's jumps need; a slot takes as many
+// bytes as modes plus J^-1 would.  FP64: c0 is the whole value at x0; mixed: c0
+// is the higher modes' part (float) and the FP64 averages sit beside it, so a
+// value jump is the FP64 difference of the averages plus the float one of the rest.
+template <int K, typename T>
+struct MonoLds {
+    static constexpr int NC = K == 2 ? 6 : 3, S = kTileCells + kHaloCap;
+    static constexpr bool kMixed = std::is_same<T, float>::value;
+    double avg[kMixed ? 4 : 1][kMixed ? S : 1];
+    T c[4][NC][S];
+    T d[4][S];
+};
+
+// the filter's tile image of a batched pass: one per degree present
+template <int KM, typename T>
+union MonoLdsKM {
+    typename std::conditional<(KM & 1) != 0, MonoLds<1, T>, char>::type p1;
+    typename std::conditional<(KM & 2) != 0, MonoLds<2, T>, char>::type p2;
+};
+
+// the monomials of one variable (modes u, u[0] its average in T) from J^-1; with
+// `full`, c0 includes the average
+template <int K, typename T>
+__device__ __forceinline__ void to_mono(const T (&u)[Rule<K>::NM], T xx, T xy, T ex, T ey, bool full,
+                                        T (&c)[MonoLds<K, T>::NC]) {
+    T a, dx, de;
+    vertex_eval_ct<K, 0, T>(u, a, dx, de);
+    c[0] = full ? u[0] + a : a;
+    c[1] = fma(dx, xx, de * ex);
+    c[2] = fma(dx, xy, de * ey);
+    if constexpr (K == 2) {
+        T h[3];
+        hessian(u, xx, xy, ex, ey, h);
+        c[3] = (T)0.5 * h[0];
+        c[4] = h[1];
+        c[5] = (T)0.5 * h[2];
+    }
+}
+// d1 = J e1, d2 = J e2 from J^-1 = [[xx, xy], [ex, ey]]
+template <typename T>
+__device__ __forceinline__ void edge_vectors(T xx, T xy, T ex, T ey, T (&d)[4]) {
+    const T id = Fp<T>::rcp(fma(xx, ey, -(xy * ex)));
+    d[0] = ey * id;
+    d[1] = -(ex * id);
+    d[2] = -(xy * id);
+    d[3] = xx * id;
+}
+// the offset P = (X, Y) of vertex vt (0, 1, 2; a per-lane index) from vertex 0 of a
+// cell with edge vectors d
+template <typename T>
+__device__ __forceinline__ void vertex_point(const T (&d)[4], int vt, T (&P)[2]) {
+    P[0] = vt == 0 ? (T)0.0 : (vt == 1 ? d[0] : d[2]);
+    P[1] = vt == 0 ? (T)0.0 : (vt == 1 ? d[1] : d[3]);
+}
+// value (c0's part of it) and physical gradient at offset P
+template <int K, typename T>
+__device__ __forceinline__ void mono_at(const T (&c)[MonoLds<K, T>::NC], const T (&P)[2], T& val, T& gx, T& gy) {
+    if constexpr (K == 2) {
+        val = fma(P[0], fma(c[3], P[0], fma(c[4], P[1], c[1])), fma(P[1], fma(c[5], P[1], c[2]), c[0]));
+        gx = fma(c[3], P[0] + P[0], fma(c[4], P[1], c[1]));
+        gy = fma(c[5], P[1] + P[1], fma(c[4], P[0], c[2]));
+    } else {
+        val = fma(c[2], P[1], fma(c[1], P[0], c[0]));
+        gx = c[1];
+        gy = c[2];
+    }
+}
+// a cell's slot of the image from its FP64 averages, modes and J^-1
+template <int K, typename T>
+__device__ __forceinline__ void mono_put(MonoLds<K, T>& L, int s, const double (&avg)[4],
+                                         const T (&u)[4][Rule<K>::NM], const T (&geo)[4]) {
+    constexpr int NC = MonoLds<K, T>::NC;
+    constexpr bool kMixed = MonoLds<K, T>::kMixed;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        T c[NC];
+        to_mono<K, T>(u[v], geo[0], geo[1], geo[2], geo[3], !kMixed, c);
+        if constexpr (kMixed) L.avg[v][s] = avg[v];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) L.c[v][k][s] = c[k];
+    }
+    T d[4];
+    edge_vectors(geo[0], geo[1], geo[2], geo[3], d);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) L.d[k][s] = d[k];
+}
+// the tile's halo cells into slots kTileCells.. (every thread takes some)
+template <int K, typename T>
+__device__ __forceinline__ void mono_halo(MonoLds<K, T>& L, const StageArgs& a, int tile,
+                                          const SView<Rule<K>::NM, T>& sv, const MView& mv) {
+    constexpr int NM = Rule<K>::NM;
+    const int h0 = a.m.halo_ptr[tile], hn = a.m.halo_ptr[tile + 1] - h0;
+    for (int h = threadIdx.x; h < hn; h += kPassThreads) {
+        const int cell = a.m.halo_cell[h0 + h];
+        double avg[4];
+        T u[4][NM];
+        T geo[4];
+        load_cell<NM, T>(sv, cell, avg, u);
+        geo_of<T, 4>(mv, (unsigned)cell * 8u, geo);
+        mono_put<K, T>(L, kTileCells + h, avg, u, geo);
+    }
+}
 // record of the filter pass: max wave speed, limited, bad and flattened counts,
 // sum |K| m1bar, sum |K| m2bar, the boundary momentum flux A_1, A_2, B_1, B_2
 constexpr int kFilCols = kFilterCols;
@@ -1086,7 +1193,7 @@ static_assert(kNumPartial + 1 + kFilCols <= kPartCols && kColBad < kPartCols && 
 __device__ constexpr int kFilOps[kFilCols] = {2, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 
 template <int K, typename T, bool kBatch>
-__device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, TileLds<K, T, 4>& L,
+__device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, MonoLds<K, T>& L,
                                            WaveAcc<kFilCols>& W) {
     using R = Rule<K>;
     using F = Fp<T>;
@@ -1127,10 +1234,10 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, T
             geo_of<T, 4>(mv, c8, geo);
 #pragma unroll
             for (int i = 0; i < 3; ++i) lk[i] = bld<int>(mv.llink, c4, (unsigned)i * mv.n4);
-            if (oe) stage_put<K, T, 4>(L, threadIdx.x, wa, w, geo);
+            if (oe) mono_put<K, T>(L, threadIdx.x, wa, w, geo);
         }
         if (oe) {
-            stage_halo<K, T, 4>(L, a, tile, wp, mv);
+            mono_halo<K, T>(L, a, tile, wp, mv);
             __syncthreads();
         }
         double part[kFilCols];
@@ -1147,159 +1254,182 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, T
                 for (int v = 0; v < 4; ++v)
 #pragma unroll
                     for (int jj = 0; jj <= K; ++jj) sig[v][jj] = (T)0.0;
+                constexpr int NC = MonoLds<K, T>::NC;
+                T od[4];   // the own cell's edge vectors
+                edge_vectors(xx, xy, ex, ey, od);
+                // sum over both ends of the squared jumps of order j: j = 0 value, 1
+                // gradient; 2: the Hessian's jump, the same at both ends, weighted by
+                // C_2 = (1, 2, 1), i.e. 2 (jxx^2 + 2 jxy^2 + jyy^2)
+                auto energies = [&](const T (&jv)[2], const T (&jx)[2], const T (&jy)[2], const T (&dh)[3],
+                                    T (&Sv)[K + 1]) __attribute__((always_inline)) {
+                    Sv[0] = fma(jv[0], jv[0], jv[1] * jv[1]);
+                    Sv[1] = fma(jx[0], jx[0], fma(jy[0], jy[0], fma(jx[1], jx[1], jy[1] * jy[1])));
+                    if constexpr (K == 2) Sv[2] = (T)2.0 * fma(dh[0], dh[0], fma((T)2.0 * dh[1], dh[1], dh[2] * dh[2]));
+                };
+                // sigma^j += beta/h delta^j, delta^j = A^{k,j} h^j / ||.|| sqrt(S_j / 2)
+                auto accumulate = [&](const T (&Sv)[K + 1], T inv, T bh, T h, T (&sg)[K + 1])
+                                      __attribute__((always_inline)) {
+                    T hj = (T)1.0;
+#pragma unroll
+                    for (int jj = 0; jj <= K; ++jj) {
+                        sg[jj] = fma(bh, (T)kA[K][jj] * hj * inv * F::sqrt((T)0.5 * Sv[jj]), sg[jj]);
+                        hj *= h;
+                    }
+                };
 #pragma unroll 1
                 for (int i = 0; i < 3; ++i) {
                     const int ll = i == 0 ? lk[0] : (i == 1 ? lk[1] : lk[2]);
                     if (ll < 0) continue;   // boundary edge: zero jump
-                    // The own cell's vertex values, gradients and Hessian are formed anew
-                    // for every edge: hoisted out of the edge loop they would hold about 70
-                    // more registers through it.  An empty asm marks the modes as changed.
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-#pragma unroll
-                        for (int l = 0; l < NM; ++l) asm volatile("" : "+v"(w[v][l]));
                     const int j = ll & 3;
-                    T nxx, nxy, nex, ney;
-                    if (ll & kLinkGlobal) {
-                        const unsigned n8 = (unsigned)((ll & ~kLinkGlobal) >> 3) * 8u;
-                        nxx = (T)mv.J(0, n8);
-                        nxy = (T)mv.J(1, n8);
-                        nex = (T)mv.J(2, n8);
-                        ney = (T)mv.J(3, n8);
-                    } else {
-                        const int s = ll >> 3;
-                        nxx = L.geo[0][s];
-                        nxy = L.geo[1][s];
-                        nex = L.geo[2][s];
-                        ney = L.geo[3][s];
-                    }
                     const T len = (T)mv.L(i, c8);
                     T nx, ny;
                     unit_normal(xx, xy, ex, ey, area, i, len, nx, ny);
                     const T h = (T)2.0 * area * F::rcp(len);   // h_K^(i) = 2|K| / l_i
-                    // beta^(i): the max spectral radius over both ends of the edge and both
-                    // sides (own vertex i+1, then i+2, meets the neighbour's vertex j+2,
-                    // then j+1), with K's normal
-                    T beta = (T)0.0;
-                    {
-                        T qo[2][4], qn[2][4];
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            T t[NM];
-                            double tna;
-                            nb_var<K, T, 4>(L, ll, wp, v, tna, t);
-#pragma unroll
+                    // The edge's work, with the neighbour's coefficients from the image
+                    // or (beyond the halo cap) converted from global memory: two copies of
+                    // the code, so that the rare path costs the common one no registers.
+                    auto edge = [&](auto&& nbc, const T (&dn)[4]) __attribute__((always_inline)) {
+                        // the edge's two ends: own vertex i+1, then i+2, meets the
+                        // neighbour's vertex j+2, then j+1
+                        T Po[2][2], Pn[2][2];
+    #pragma unroll
+                        for (int e = 0; e < 2; ++e) {
+                            vertex_point(od, (i + 1 + e) % 3, Po[e]);
+                            vertex_point(dn, (j + 2 - e) % 3, Pn[e]);
+                        }
+                        // beta^(i): the max spectral radius over both ends of the edge and both
+                        // sides, with K's normal, from the four variables' values there
+                        T beta = (T)0.0;
+                        {
+                            T qo[2][4], qn[2][4];
+    #pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                T co[NC], cn[NC];
+    #pragma unroll
+                                for (int k2 = 0; k2 < NC; ++k2) co[k2] = L.c[v][k2][threadIdx.x];
+                                double na;
+                                nbc(v, na, cn);
+    #pragma unroll
+                                for (int e = 0; e < 2; ++e) {
+                                    T vo, vn, g0, g1;
+                                    mono_at<K, T>(co, Po[e], vo, g0, g1);
+                                    mono_at<K, T>(cn, Pn[e], vn, g0, g1);
+                                    qo[e][v] = kMixed ? w[v][0] + vo : vo;
+                                    qn[e][v] = kMixed ? (T)na + vn : vn;
+                                }
+                                // one variable's coefficients in registers at a time
+                                asm volatile("" ::: "memory");
+                            }
+    #pragma unroll
+                            for (int e = 0; e < 2; ++e)
+                                beta = fmax(beta,
+                                            fmax(spectral_radius(qo[e][0], qo[e][1], qo[e][2], qo[e][3], nx, ny, gammaT),
+                                                 spectral_radius(qn[e][0], qn[e][1], qn[e][2], qn[e][3], nx, ny, gammaT)));
+                        }
+                        const T bh = F::div(beta, h);
+                        // the coefficients are read again below rather than kept from above
+                        asm volatile("" ::: "memory");
+                        // Jumps (neighbour minus own) of variable v's value and physical
+                        // gradient at the two ends, and of its (constant) Hessian.
+                        auto jumps = [&](int v, T (&jv)[2], T (&jx)[2], T (&jy)[2], T (&dh)[3])
+                                         __attribute__((always_inline)) {
+                            T co[NC], cn[NC];
+    #pragma unroll
+                            for (int k2 = 0; k2 < NC; ++k2) co[k2] = L.c[v][k2][threadIdx.x];
+                            double na;
+                            nbc(v, na, cn);
+    #pragma unroll
                             for (int e = 0; e < 2; ++e) {
-                                const int ov = (i + 1 + e) % 3, nv = (j + 2 - e) % 3;
-                                T qh, qhn, d0, d1;
-                                vertex_eval<K, T>(w[v], ov == 1 ? (T)1.0 : (T)0.0, ov == 2 ? (T)1.0 : (T)0.0, qh, d0, d1);
-                                vertex_eval<K, T>(t, nv == 1 ? (T)1.0 : (T)0.0, nv == 2 ? (T)1.0 : (T)0.0, qhn, d0,
-                                                  d1);
-                                qo[e][v] = w[v][0] + qh;
-                                qn[e][v] = t[0] + qhn;
+                                T vo, gxo, gyo, vn, gxn, gyn;
+                                mono_at<K, T>(co, Po[e], vo, gxo, gyo);
+                                mono_at<K, T>(cn, Pn[e], vn, gxn, gyn);
+                                // mixed: the FP64 difference of averages plus the float one of the rest
+                                if constexpr (kMixed) jv[e] = (T)(na - wa[v]) + (vn - vo);
+                                else jv[e] = vn - vo;
+                                jx[e] = gxn - gxo;
+                                jy[e] = gyn - gyo;
+                            }
+                            // the Hessian (2 cXX, cXY, 2 cYY)
+                            if constexpr (K == 2) {
+                                dh[0] = (T)2.0 * (cn[3] - co[3]);
+                                dh[1] = cn[4] - co[4];
+                                dh[2] = (T)2.0 * (cn[5] - co[5]);
+                            }
+                        };
+                        {
+                            T jv[2], jx[2], jy[2], dh[3], Sv[K + 1];
+                            jumps(0, jv, jx, jy, dh);
+                            energies(jv, jx, jy, dh, Sv);
+                            accumulate(Sv, inv0, bh, h, sig[0]);
+                            jumps(3, jv, jx, jy, dh);
+                            energies(jv, jx, jy, dh, Sv);
+                            accumulate(Sv, inv3, bh, h, sig[3]);
+                        }
+                        asm volatile("" ::: "memory");
+                        {
+                            // RIOE: the momentum enters as m_n = m.n and m_t = m.(-n_y, n_x), with
+                            // K's normal on both sides, and delta(m) = max(delta(m_n), delta(m_t)),
+                            // one root of the larger energy; component-wise: m_1, m_2 apart
+                            T jv1[2], jx1[2], jy1[2], dh1[3], jv2[2], jx2[2], jy2[2], dh2[3];
+                            jumps(1, jv1, jx1, jy1, dh1);
+                            jumps(2, jv2, jx2, jy2, dh2);
+                            const T ca = ri ? nx : (T)1.0, cb = ri ? ny : (T)0.0;
+                            auto rot = [&](T& a1, T& a2) __attribute__((always_inline)) {
+                                const T b1 = fma(ca, a1, cb * a2), b2 = fma(ca, a2, -(cb * a1));
+                                a1 = b1;
+                                a2 = b2;
+                            };
+    #pragma unroll
+                            for (int e = 0; e < 2; ++e) {
+                                rot(jv1[e], jv2[e]);
+                                rot(jx1[e], jx2[e]);
+                                rot(jy1[e], jy2[e]);
+                            }
+                            if constexpr (K == 2) {
+    #pragma unroll
+                                for (int k2 = 0; k2 < 3; ++k2) rot(dh1[k2], dh2[k2]);
+                            }
+                            T S1[K + 1], S2[K + 1];
+                            energies(jv1, jx1, jy1, dh1, S1);
+                            energies(jv2, jx2, jy2, dh2, S2);
+                            if (ri) {
+    #pragma unroll
+                                for (int jj = 0; jj <= K; ++jj) S1[jj] = fmax(S1[jj], S2[jj]);
+                                accumulate(S1, inv1, bh, h, sig[1]);
+                            } else {
+                                accumulate(S1, inv1, bh, h, sig[1]);
+                                accumulate(S2, inv2, bh, h, sig[2]);
                             }
                         }
-#pragma unroll
-                        for (int e = 0; e < 2; ++e)
-                            beta = fmax(beta,
-                                        fmax(spectral_radius(qo[e][0], qo[e][1], qo[e][2], qo[e][3], nx, ny, gammaT),
-                                             spectral_radius(qn[e][0], qn[e][1], qn[e][2], qn[e][3], nx, ny, gammaT)));
-                    }
-                    // the neighbour's modes are read again below rather than kept in registers
-                    asm volatile("" ::: "memory");
-                    const T bh = F::div(beta, h);
-                    // Jumps (neighbour minus own) of variable v's value and physical
-                    // gradient at the two ends, and of its (constant) P2 Hessian.
-                    auto jumps = [&](int v, T (&jv)[2], T (&jx)[2], T (&jy)[2], T (&dh)[3])
-                                     __attribute__((always_inline)) {
-                        T t[NM];
-                        double tna;
-                        nb_var<K, T, 4>(L, ll, wp, v, tna, t);
-#pragma unroll
-                        for (int e = 0; e < 2; ++e) {
-                            const int ov = (i + 1 + e) % 3, nv = (j + 2 - e) % 3;
-                            T qh, dxo, deo, qhn, dxn, den;
-                            vertex_eval<K, T>(w[v], ov == 1 ? (T)1.0 : (T)0.0, ov == 2 ? (T)1.0 : (T)0.0, qh, dxo, deo);
-                            vertex_eval<K, T>(t, nv == 1 ? (T)1.0 : (T)0.0, nv == 2 ? (T)1.0 : (T)0.0, qhn, dxn, den);
-                            // value jump; mixed: the FP64 difference of averages plus the
-                            // float higher modes'
-                            if constexpr (kMixed) jv[e] = (T)(tna - wa[v]) + (qhn - qh);
-                            else jv[e] = (t[0] + qhn) - (w[v][0] + qh);
-                            jx[e] = fma(dxn, nxx, den * nex) - fma(dxo, xx, deo * ex);
-                            jy[e] = fma(dxn, nxy, den * ney) - fma(dxo, xy, deo * ey);
-                        }
-                        if constexpr (K == 2) {
-                            T hn[3], ho[3];
-                            hessian(t, nxx, nxy, nex, ney, hn);
-                            hessian(w[v], xx, xy, ex, ey, ho);
-#pragma unroll
-                            for (int k2 = 0; k2 < 3; ++k2) dh[k2] = hn[k2] - ho[k2];
-                        }
                     };
-                    // sum over both ends of the squared jumps of order j: j = 0 value, 1
-                    // gradient; 2: the Hessian's jump, the same at both ends, weighted by
-                    // C_2 = (1, 2, 1), i.e. 2 (jxx^2 + 2 jxy^2 + jyy^2)
-                    auto energies = [&](const T (&jv)[2], const T (&jx)[2], const T (&jy)[2], const T (&dh)[3],
-                                        T (&Sv)[K + 1]) __attribute__((always_inline)) {
-                        Sv[0] = fma(jv[0], jv[0], jv[1] * jv[1]);
-                        Sv[1] = fma(jx[0], jx[0], fma(jy[0], jy[0], fma(jx[1], jx[1], jy[1] * jy[1])));
-                        if constexpr (K == 2)
-                            Sv[2] = (T)2.0 * fma(dh[0], dh[0], fma((T)2.0 * dh[1], dh[1], dh[2] * dh[2]));
-                    };
-                    // sigma^j += beta/h delta^j, delta^j = A^{k,j} h^j / ||.|| sqrt(S_j / 2)
-                    auto accumulate = [&](const T (&Sv)[K + 1], T inv, T (&sg)[K + 1]) __attribute__((always_inline)) {
-                        T hj = (T)1.0;
+                    if (ll & kLinkGlobal) {
+                        const int cell = (ll & ~kLinkGlobal) >> 3;
+                        const unsigned n8 = (unsigned)cell * 8u, nT = (unsigned)cell * (unsigned)sizeof(T);
+                        const T nxx = (T)mv.J(0, n8), nxy = (T)mv.J(1, n8), nex = (T)mv.J(2, n8), ney = (T)mv.J(3, n8);
+                        T dn[4];
+                        edge_vectors(nxx, nxy, nex, ney, dn);
+                        edge(
+                            [&](int v, double& na, T (&cn)[NC]) __attribute__((always_inline)) {
+                                T u[NM];
+                                na = wp.a(v, n8);
+                                u[0] = (T)na;
 #pragma unroll
-                        for (int jj = 0; jj <= K; ++jj) {
-                            sg[jj] = fma(bh, (T)kA[K][jj] * hj * inv * F::sqrt((T)0.5 * Sv[jj]), sg[jj]);
-                            hj *= h;
-                        }
-                    };
-                    {
-                        T jv[2], jx[2], jy[2], dh[3], Sv[K + 1];
-                        jumps(0, jv, jx, jy, dh);
-                        energies(jv, jx, jy, dh, Sv);
-                        accumulate(Sv, inv0, sig[0]);
-                        asm volatile("" ::: "memory");
-                        jumps(3, jv, jx, jy, dh);
-                        energies(jv, jx, jy, dh, Sv);
-                        accumulate(Sv, inv3, sig[3]);
-                    }
-                    asm volatile("" ::: "memory");
-                    {
-                        // RIOE: the momentum enters as m_n = m.n and m_t = m.(-n_y, n_x), with
-                        // K's normal on both sides, and delta(m) = max(delta(m_n), delta(m_t)),
-                        // one root of the larger energy; component-wise: m_1, m_2 apart
-                        T jv1[2], jx1[2], jy1[2], dh1[3], jv2[2], jx2[2], jy2[2], dh2[3];
-                        jumps(1, jv1, jx1, jy1, dh1);
-                        jumps(2, jv2, jx2, jy2, dh2);
-                        const T ca = ri ? nx : (T)1.0, cb = ri ? ny : (T)0.0;
-                        auto rot = [&](T& a1, T& a2) __attribute__((always_inline)) {
-                            const T b1 = fma(ca, a1, cb * a2), b2 = fma(ca, a2, -(cb * a1));
-                            a1 = b1;
-                            a2 = b2;
-                        };
+                                for (int l = 1; l < NM; ++l) u[l] = wp.h(v, l, nT);
+                                to_mono<K, T>(u, nxx, nxy, nex, ney, !kMixed, cn);
+                            },
+                            dn);
+                    } else {
+                        const int sl = ll >> 3;
+                        T dn[4];
 #pragma unroll
-                        for (int e = 0; e < 2; ++e) {
-                            rot(jv1[e], jv2[e]);
-                            rot(jx1[e], jx2[e]);
-                            rot(jy1[e], jy2[e]);
-                        }
-                        if constexpr (K == 2) {
+                        for (int k2 = 0; k2 < 4; ++k2) dn[k2] = L.d[k2][sl];
+                        edge(
+                            [&](int v, double& na, T (&cn)[NC]) __attribute__((always_inline)) {
+                                na = kMixed ? L.avg[kMixed ? v : 0][kMixed ? sl : 0] : 0.0;
 #pragma unroll
-                            for (int k2 = 0; k2 < 3; ++k2) rot(dh1[k2], dh2[k2]);
-                        }
-                        T S1[K + 1], S2[K + 1];
-                        energies(jv1, jx1, jy1, dh1, S1);
-                        energies(jv2, jx2, jy2, dh2, S2);
-                        if (ri) {
-#pragma unroll
-                            for (int jj = 0; jj <= K; ++jj) S1[jj] = fmax(S1[jj], S2[jj]);
-                            accumulate(S1, inv1, sig[1]);
-                        } else {
-                            accumulate(S1, inv1, sig[1]);
-                            accumulate(S2, inv2, sig[2]);
-                        }
+                                for (int k2 = 0; k2 < NC; ++k2) cn[k2] = L.c[v][k2][sl];
+                            },
+                            dn);
                     }
                 }
                 if (ri) {
@@ -1485,14 +1615,14 @@ template <int K, typename T>
 __global__ __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(OEDG_FIL_WAVES))) void k_filter(
     StageArgs a) {
     if (!a.g->active || a.g->skip) return;
-    __shared__ TileLds<K, T, 4> L;
+    __shared__ MonoLds<K, T> L;
     __shared__ WaveAcc<kFilCols> W;
     filter_run<K, T, false>(a, 0, 0, L, W);
 }
 template <int KM, typename T>
 __global__ __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(OEDG_FIL_WAVES))) void k_filter_batch(
     const StageArgs* desc, const Chunk* chunks, ChunkSplit cs) {
-    __shared__ TileLdsKM<KM, T, 4> L;
+    __shared__ MonoLdsKM<KM, T> L;
     __shared__ WaveAcc<kFilCols> W;
     for_each_chunk(desc, chunks, cs, [&](const StageArgs& a, int g0, int g1) {
         if constexpr (KM == 1) filter_run<1, T, true>(a, g0, g1, L.p1, W);

@@ -108,10 +108,16 @@ class Server:
     """hbm_budget: bytes the admitted requests may hold together; steps_per_tick:
     batched steps between polls; keep_results: read each finished state back to
     the host; prepare_threads: threads that build, upload and project new
-    requests."""
+    requests; progress: a callable given one line of text at every admission,
+    join and completion and every progress_every seconds (the members' t and step
+    counts); max_wall: seconds after which the run stops and the unfinished
+    requests end with an error."""
 
     def __init__(self, device=0, hbm_budget=8 << 30, steps_per_tick=8, keep_results=True, autotune=False,
-                 prepare_threads=2):
+                 prepare_threads=2, progress=None, progress_every=5.0, max_wall=None):
+        self.progress = progress
+        self.progress_every = float(progress_every)
+        self.max_wall = max_wall
         self.device = int(device)
         self.budget = int(hbm_budget)
         self.steps_per_tick = int(steps_per_tick)
@@ -153,6 +159,12 @@ class Server:
         peak = rebuilds = launched = 0
         pool = ThreadPoolExecutor(max_workers=self.prepare_threads)
         t0 = clock()
+        last_report = 0.0
+        last_status = {}
+
+        def say(msg):
+            if self.progress is not None:
+                self.progress(f"[{clock() - t0:8.3f} s] {msg}")
         def compact(g, new_members=()):
             # (re)builds g's batch from its active members and the joining ones; the
             # finished members, already read back, are freed.  Returns the bytes freed.
@@ -178,6 +190,20 @@ class Server:
         try:
             while pending or preparing or any(g.active_count() for g in groups.values()):
                 now = clock() - t0
+                elapsed = now
+                if elapsed - last_report >= self.progress_every:
+                    last_report = elapsed
+                    act = [f"{i}: t {v[0]:.4g}/{v[2]:.4g} step {v[1]}" for i, v in sorted(last_status.items())
+                           if any(m[0].id == i and m[0].done is None for g in groups.values() for m in g.members)]
+                    say(f"{launched} batched steps launched; active {act}; {len(pending)} pending, "
+                        f"{len(preparing)} preparing")
+                if self.max_wall is not None and elapsed > self.max_wall:
+                    for r in requests:
+                        if r.done is None:
+                            r.error = f"not finished within {self.max_wall} s"
+                            r.done = elapsed
+                    say(f"stopped after {elapsed:.1f} s: {sum(1 for r in requests if r.error)} requests unfinished")
+                    break
                 # admission: arrived requests in arrival order while they fit; when the
                 # budget blocks one, the finished members still held are freed first
                 while pending and pending[0].arrival <= now:
@@ -196,6 +222,8 @@ class Server:
                     r.admitted = now
                     preparing.append((r, pool.submit(self._prepare, r), fp))
                     used += fp
+                    say(f"admit request {r.id}: {r.n_cell} cells P{r.k} {r.precision}, t_end {r.t_end:.4g}, "
+                        f"{fp / 2**20:.0f} MiB, {used / 2**20:.0f} MiB held")
                 # prepared requests join their group; failed ones finish with their error
                 joined = {p: [] for p in groups}
                 still = []
@@ -209,6 +237,7 @@ class Server:
                         r.error = f"admission failed: {e}"
                         r.done = clock() - t0
                         used -= fp
+                        say(f"request {r.id} failed in preparation: {e}")
                 preparing = still
                 for p, g in groups.items():
                     if joined[p]:
@@ -216,6 +245,8 @@ class Server:
                         now2 = clock() - t0
                         for r, _, _ in joined[p]:
                             r.joined = now2
+                        say(f"{p} batch rebuilt: joined {[r.id for r, _, _ in joined[p]]}, "
+                            f"members {[m[0].id for m in g.members]}")
                     elif g.members and not g.active_count():
                         used -= compact(g)   # nothing left to step: free the finished ones
                 peak = max(peak, sum(g.active_count() for g in groups.values()))
@@ -240,6 +271,7 @@ class Server:
                         continue
                     _, status = g.batch.status()
                     for (r, s, fp), st in zip(g.members, status):
+                        last_status[r.id] = (float(st[2]), int(st[3]), r.t_end)
                         if r.done is None and st[0] == 0.0:
                             r.done = clock() - t0
                             r.t, r.steps = float(st[2]), int(st[3])
@@ -247,8 +279,13 @@ class Server:
                                 r.error = "a cell average left the admissible set"
                             if self.keep_results:
                                 r.result = s.readback()[0]
+                            say(f"request {r.id} done: {r.steps} steps to t = {r.t:.4g}, latency "
+                                f"{r.latency * 1e3:.1f} ms{'' if r.error is None else ', ' + r.error}")
         finally:
             pool.shutdown(wait=True)
+            for r, fut, _ in preparing:          # prepared after a stop: never joined
+                if fut.exception() is None:
+                    fut.result().close()
             for g in groups.values():
                 if g.batch is not None:
                     g.batch.close()
