@@ -18,16 +18,21 @@
 //
 // Lane layout of the two passes: one lane per cell, all four conservative
 // variables and their modes in that lane's registers, so every point value,
-// 1/rho, pressure and flux is formed once.  A pass workgroup is one wave of 64
-// cells; workgroups are spread so that each XCD walks a contiguous range of the
-// (Hilbert-ordered) cells, which keeps neighbour gathers inside that XCD's L2.
+// 1/rho, pressure and flux is formed once.  A pass workgroup takes tiles of 256
+// consecutive (Hilbert-ordered) cells, one per thread, and stages each tile with
+// its halo of out-of-tile neighbours in LDS before computing it.  The image holds
+// every cell's polynomial as physical monomials about its vertex 0 plus the two
+// edge vectors from that vertex, so a neighbour's value, gradient and Hessian at
+// any point (an edge Gauss point, a shared vertex) cost a few FMAs.  Workgroups
+// are spread so that each XCD walks a contiguous range of the tiles, which keeps
+// neighbour gathers inside that XCD's L2.
 //
 // Edge fluxes are conservative to the last bit: both cells of an interior edge
-// evaluate its LF flux from the same two traces (each cell's trace computed by the
-// same arithmetic from the same table, whichever lane asks), with the lower-index
-// cell's scaled normal and length, and in a fixed operand order, so the two
-// contributions are exact negatives of each other.  The file is compiled with FMA
-// contraction off; every fused multiply-add is written out.
+// evaluate its LF flux from the same two traces (each cell's trace formed by the
+// same arithmetic from the same monomials and edge vectors, whichever lane asks),
+// with the lower-index cell's scaled normal and length, and in a fixed operand
+// order, so the two contributions are exact negatives of each other.  The file is
+// compiled with FMA contraction off; every fused multiply-add is written out.
 //
 // Precision: every pass is instantiated for a bulk type T, double (FP64) or
 // float (mixed).  Cell averages are stored, updated and reduced in FP64 in both
@@ -527,21 +532,6 @@ __device__ __forceinline__ double uniform(double x) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
 }
 
-// The edge Gauss point rows of the basis in LDS, for the exterior trace: a
-// neighbour's local edge is a per-lane index, so its rows cannot come from the
-// scalar path.  Filled by the workgroup before the first cell.
-template <int K, typename T>
-struct EdgeRowsLds {
-    T r[3 * Rule<K>::NE][Rule<K>::NM];
-};
-template <int K, typename T>
-__device__ __forceinline__ void fill_edge_rows(EdgeRowsLds<K, T>& dst) {
-    constexpr int N = 3 * Rule<K>::NE * Rule<K>::NM;
-    const T* src = &tab<K, T>().ep[0][0];
-    T* d = &dst.r[0][0];
-    for (int t = threadIdx.x; t < N; t += blockDim.x) d[t] = src[t];
-}
-
 #ifndef OEDG_RES_WAVES
 #define OEDG_RES_WAVES 2
 #endif
@@ -551,31 +541,6 @@ __device__ __forceinline__ void fill_edge_rows(EdgeRowsLds<K, T>& dst) {
 
 // ------------------------------------------------------------------------- tiles in LDS
 
-// LDS image of a tile and its halo for one pass: per slot the four FP64 averages,
-// the modes l >= 1 in the bulk type and NG geometry entries in the bulk type (the
-// rows of J^-1, then |K| for the residual).  Slot s < kTileCells holds cell
-// tile * kTileCells + s, slot kTileCells + h the tile's halo cell h.  SoA per
-// entry, so a lane's slot reads are 8-byte (4-byte) strided accesses.
-template <int K, typename T, int NG>
-struct TileLds {
-    static constexpr int NM = Rule<K>::NM, S = kTileCells + kHaloCap;
-    double avg[4][S];
-    T hi[4][NM - 1][S];
-    T geo[NG][S];
-};
-template <int K, typename T, int NG>
-__device__ __forceinline__ void stage_put(TileLds<K, T, NG>& L, int s, const double (&avg)[4],
-                                          const T (&u)[4][Rule<K>::NM], const T (&geo)[NG]) {
-    constexpr int NM = Rule<K>::NM;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        L.avg[v][s] = avg[v];
-#pragma unroll
-        for (int l = 1; l < NM; ++l) L.hi[v][l - 1][s] = u[v][l];
-    }
-#pragma unroll
-    for (int g = 0; g < NG; ++g) L.geo[g][s] = geo[g];
-}
 // the geometry entries of cell c (byte offset c8) in the bulk type
 template <typename T, int NG>
 __device__ __forceinline__ void geo_of(const MView& mv, unsigned c8, T (&geo)[NG]) {
@@ -583,65 +548,140 @@ __device__ __forceinline__ void geo_of(const MView& mv, unsigned c8, T (&geo)[NG
     for (int g = 0; g < 4; ++g) geo[g] = (T)mv.J(g, c8);
     if constexpr (NG == 5) geo[4] = (T)mv.A(c8);
 }
-// The tile's halo cells into slots kTileCells.. (every thread takes some).
-template <int K, typename T, int NG>
-__device__ __forceinline__ void stage_halo(TileLds<K, T, NG>& L, const StageArgs& a, int tile,
-                                           const SView<Rule<K>::NM, T>& sv, const MView& mv) {
+// P2 physical Hessian (xx, xy, yy) of one variable with modes u[0..5] (constant per
+// cell): J^-T H_ref J^-1 with H_ref = (48 u3, 24 u3 + 20 u4, 8 u3 + 20 u4 + 20 u5)
+template <typename T>
+__device__ __forceinline__ void hessian(const T* u, T xx, T xy, T ex, T ey, T (&h)[3]) {
+    const T hxx = (T)48.0 * u[3];
+    const T hxe = fma((T)24.0, u[3], (T)20.0 * u[4]);
+    const T hee = fma((T)8.0, u[3], (T)20.0 * (u[4] + u[5]));
+    const T ax = fma(hxx, xx, hxe * ex), ae = fma(hxe, xx, hee * ex);   // (H_ref J^-1) column x
+    const T bx = fma(hxx, xy, hxe * ey), be = fma(hxe, xy, hee * ey);   // column y
+    h[0] = fma(xx, ax, ex * ae);
+    h[1] = fma(xy, ax, ey * ae);
+    h[2] = fma(xy, bx, ey * be);
+}
+
+// The filter's tile image: every cell's polynomial as physical monomials about its
+// vertex 0 (the reference origin), u(x0 + X) = c0 + cX X + cY Y + cXX X^2 +
+// cXY X Y + cYY Y^2 per variable (P2; P1 stops at the linear part), and
+// the edge vectors d1 = x1 - x0, d2 = x2 - x0 that place its other two vertices.
+// Values, physical gradients and the (constant) Hessian at a vertex then cost a
+// few FMAs each, which is most of what the OE's jumps need; a slot takes as many
+// bytes as modes plus J^-1 would.  FP64: c0 is the whole value at x0; mixed: c0
+// is the higher modes' part (float) and the FP64 averages sit beside it, so a
+// value jump is the FP64 difference of the averages plus the float one of the rest.
+template <int K, typename T>
+struct MonoLds {
+    static constexpr int NC = K == 2 ? 6 : 3, S = kTileCells + kHaloCap;
+    static constexpr bool kMixed = std::is_same<T, float>::value;
+    double avg[kMixed ? 4 : 1][kMixed ? S : 1];
+    T c[4][NC][S];
+    T d[4][S];
+};
+
+// the filter's tile image of a batched pass: one per degree present
+template <int KM, typename T>
+union MonoLdsKM {
+    typename std::conditional<(KM & 1) != 0, MonoLds<1, T>, char>::type p1;
+    typename std::conditional<(KM & 2) != 0, MonoLds<2, T>, char>::type p2;
+};
+
+// the monomials of one variable (modes u, u[0] its average in T) from J^-1; with
+// `full`, c0 includes the average
+template <int K, typename T>
+__device__ __forceinline__ void to_mono(const T (&u)[Rule<K>::NM], T xx, T xy, T ex, T ey, bool full,
+                                        T (&c)[MonoLds<K, T>::NC]) {
+    T a, dx, de;
+    vertex_eval_ct<K, 0, T>(u, a, dx, de);
+    c[0] = full ? u[0] + a : a;
+    c[1] = fma(dx, xx, de * ex);
+    c[2] = fma(dx, xy, de * ey);
+    if constexpr (K == 2) {
+        T h[3];
+        hessian(u, xx, xy, ex, ey, h);
+        c[3] = (T)0.5 * h[0];
+        c[4] = h[1];
+        c[5] = (T)0.5 * h[2];
+    }
+}
+// d1 = J e1, d2 = J e2 from J^-1 = [[xx, xy], [ex, ey]]
+template <typename T>
+__device__ __forceinline__ void edge_vectors(T xx, T xy, T ex, T ey, T (&d)[4]) {
+    const T id = Fp<T>::rcp(fma(xx, ey, -(xy * ex)));
+    d[0] = ey * id;
+    d[1] = -(ex * id);
+    d[2] = -(xy * id);
+    d[3] = xx * id;
+}
+// the offset P = (X, Y) of vertex vt (0, 1, 2; a per-lane index) from vertex 0 of a
+// cell with edge vectors d
+template <typename T>
+__device__ __forceinline__ void vertex_point(const T (&d)[4], int vt, T (&P)[2]) {
+    P[0] = vt == 0 ? (T)0.0 : (vt == 1 ? d[0] : d[2]);
+    P[1] = vt == 0 ? (T)0.0 : (vt == 1 ? d[1] : d[3]);
+}
+// unit outward normal and length of local edge e (counter-clockwise, from vertex
+// e+1 to e+2) of a cell with edge vectors d
+template <typename T>
+__device__ __forceinline__ void edge_normal(const T (&d)[4], int e, T& nx, T& ny, T& len) {
+    T A[2], B[2];
+    vertex_point(d, (e + 1) % 3, A);
+    vertex_point(d, (e + 2) % 3, B);
+    const T dx = B[0] - A[0], dy = B[1] - A[1];
+    len = Fp<T>::sqrt(fma(dx, dx, dy * dy));
+    const T il = Fp<T>::rcp(len);
+    nx = dy * il;
+    ny = -(dx * il);
+}
+// value (c0's part of it) and physical gradient at offset P
+template <int K, typename T>
+__device__ __forceinline__ void mono_at(const T (&c)[MonoLds<K, T>::NC], const T (&P)[2], T& val, T& gx, T& gy) {
+    if constexpr (K == 2) {
+        val = fma(P[0], fma(c[3], P[0], fma(c[4], P[1], c[1])), fma(P[1], fma(c[5], P[1], c[2]), c[0]));
+        gx = fma(c[3], P[0] + P[0], fma(c[4], P[1], c[1]));
+        gy = fma(c[5], P[1] + P[1], fma(c[4], P[0], c[2]));
+    } else {
+        val = fma(c[2], P[1], fma(c[1], P[0], c[0]));
+        gx = c[1];
+        gy = c[2];
+    }
+}
+// a cell's slot of the image from its FP64 averages, modes and J^-1
+template <int K, typename T>
+__device__ __forceinline__ void mono_put(MonoLds<K, T>& L, int s, const double (&avg)[4],
+                                         const T (&u)[4][Rule<K>::NM], const T (&geo)[4]) {
+    constexpr int NC = MonoLds<K, T>::NC;
+    constexpr bool kMixed = MonoLds<K, T>::kMixed;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        T c[NC];
+        to_mono<K, T>(u[v], geo[0], geo[1], geo[2], geo[3], !kMixed, c);
+        if constexpr (kMixed) L.avg[v][s] = avg[v];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) L.c[v][k][s] = c[k];
+    }
+    T d[4];
+    edge_vectors(geo[0], geo[1], geo[2], geo[3], d);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) L.d[k][s] = d[k];
+}
+// the tile's halo cells into slots kTileCells.. (every thread takes some)
+template <int K, typename T>
+__device__ __forceinline__ void mono_halo(MonoLds<K, T>& L, const StageArgs& a, int tile,
+                                          const SView<Rule<K>::NM, T>& sv, const MView& mv) {
     constexpr int NM = Rule<K>::NM;
     const int h0 = a.m.halo_ptr[tile], hn = a.m.halo_ptr[tile + 1] - h0;
     for (int h = threadIdx.x; h < hn; h += kPassThreads) {
         const int cell = a.m.halo_cell[h0 + h];
         double avg[4];
         T u[4][NM];
-        T geo[NG];
+        T geo[4];
         load_cell<NM, T>(sv, cell, avg, u);
-        geo_of<T, NG>(mv, (unsigned)cell * 8u, geo);
-        stage_put<K, T, NG>(L, kTileCells + h, avg, u, geo);
+        geo_of<T, 4>(mv, (unsigned)cell * 8u, geo);
+        mono_put<K, T>(L, kTileCells + h, avg, u, geo);
     }
 }
-// The neighbour across an interior edge with llink value ll: its averages, modes and
-// geometry, from the tile image or, beyond the halo cap, from global memory.
-template <int K, typename T, int NG>
-__device__ __forceinline__ void nb_get(const TileLds<K, T, NG>& L, int ll, const SView<Rule<K>::NM, T>& sv,
-                                       const MView& mv, double (&avg)[4], T (&u)[4][Rule<K>::NM], T (&geo)[NG]) {
-    constexpr int NM = Rule<K>::NM;
-    if (ll & kLinkGlobal) {
-        const int cell = (ll & ~kLinkGlobal) >> 3;
-        load_cell<NM, T>(sv, cell, avg, u);
-        geo_of<T, NG>(mv, (unsigned)cell * 8u, geo);
-    } else {
-        const int s = ll >> 3;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            avg[v] = L.avg[v][s];
-            u[v][0] = (T)avg[v];
-#pragma unroll
-            for (int l = 1; l < NM; ++l) u[v][l] = L.hi[v][l - 1][s];
-        }
-#pragma unroll
-        for (int g = 0; g < NG; ++g) geo[g] = L.geo[g][s];
-    }
-}
-// one variable of that neighbour (its FP64 average and modes in the bulk type)
-template <int K, typename T, int NG>
-__device__ __forceinline__ void nb_var(const TileLds<K, T, NG>& L, int ll, const SView<Rule<K>::NM, T>& sv, int v,
-                                       double& avg, T (&u)[Rule<K>::NM]) {
-    constexpr int NM = Rule<K>::NM;
-    if (ll & kLinkGlobal) {
-        const int cell = (ll & ~kLinkGlobal) >> 3;
-        const unsigned c8 = (unsigned)cell * 8u, cT = (unsigned)cell * (unsigned)sizeof(T);
-        avg = sv.a(v, c8);
-#pragma unroll
-        for (int l = 1; l < NM; ++l) u[l] = sv.h(v, l, cT);
-    } else {
-        const int s = ll >> 3;
-        avg = L.avg[v][s];
-#pragma unroll
-        for (int l = 1; l < NM; ++l) u[l] = L.hi[v][l - 1][s];
-    }
-    u[0] = (T)avg;
-}
-
 // Running reductions of a pass workgroup over its tiles: after each tile every wave
 // reduces its lanes' contributions (one cell each) and lane 0 combines the result
 // into its wave's entry; the flush combines the waves in order.  op(k): 0 sum,
@@ -723,8 +763,8 @@ constexpr int kResCols = 14;   // sums, minima, maxima (4 each), |m - mbar|^2 ma
 __device__ constexpr int kResOps[kResCols] = {0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 2, 2, 0};
 
 template <int K, typename T, bool kBatch>
-__device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1, const EdgeRowsLds<K, T>& er,
-                                             TileLds<K, T, 5>& L, WaveAcc<kResCols>& W) {
+__device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1, MonoLds<K, T>& L,
+                                             WaveAcc<kResCols>& W) {
     using R = Rule<K>;
     constexpr int NM = R::NM, NE = R::NE;
     constexpr bool kMixed = std::is_same<T, float>::value;
@@ -779,9 +819,9 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
             geo_of<T, 5>(mv, c8, geo);
 #pragma unroll
             for (int i = 0; i < 3; ++i) lk[i] = bld<int>(mv.llink, c4, (unsigned)i * mv.n4);
-            stage_put<K, T, 5>(L, threadIdx.x, ua, u, geo);
+            mono_put<K, T>(L, threadIdx.x, ua, u, reinterpret_cast<const T(&)[4]>(geo));
         }
-        stage_halo<K, T, 5>(L, a, tile, up, mv);
+        mono_halo<K, T>(L, a, tile, up, mv);
         __syncthreads();
         double part[kResCols];
 #pragma unroll
@@ -822,7 +862,34 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
             // lower-index cell ("low") and l = |l n|, from the same two traces in
             // commuted order, so their contributions are exact negatives (sgn = +1 on the
             // low side):  Fhat_low = 1/2 (F(u_i).n + F(u_e).n - sgn alpha l (u_e - u_i)),
-            // and the own cell adds -sgn w_nu Fhat_low Psi_l.
+            // and the own cell adds -sgn w_nu Fhat_low Psi_l.  Every trace comes from the
+            // cell's monomials in the tile image at its own offset of the Gauss point,
+            // and every scaled normal from its edge vectors (l n = (dy, -dx) along the
+            // counter-clockwise edge), by the same arithmetic whichever lane asks.
+            constexpr int NC = MonoLds<K, T>::NC;
+            T od[4];
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) od[k2] = L.d[k2][threadIdx.x];
+            // the Gauss points of local edge e of a cell with edge vectors d: from
+            // vertex e+1 towards e+2, parameter s_nu
+            auto edge_pts = [&](const T (&d)[4], int e, T (&P)[NE][2], T& lnx, T& lny) __attribute__((always_inline)) {
+                T A[2], B[2];
+                vertex_point(d, (e + 1) % 3, A);
+                vertex_point(d, (e + 2) % 3, B);
+                const T dx = B[0] - A[0], dy = B[1] - A[1];
+                lnx = dy;
+                lny = -dx;
+#pragma unroll
+                for (int nu = 0; nu < NE; ++nu) {
+                    P[nu][0] = fma((T)R::s[nu], dx, A[0]);
+                    P[nu][1] = fma((T)R::s[nu], dy, A[1]);
+                }
+            };
+            auto trace = [&](const T (&cf)[NC], const T (&P)[2], T avg) __attribute__((always_inline)) {
+                T val, g0, g1;
+                mono_at<K, T>(cf, P, val, g0, g1);
+                return kMixed ? avg + val : val;
+            };
 #pragma unroll 1
             for (int i = 0; i < 3; ++i) {
                 const int ll = i == 0 ? lk[0] : (i == 1 ? lk[1] : lk[2]);
@@ -831,31 +898,68 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
                 const int j = has ? (ll & 3) : i;
                 const bool low = !has || (ll & 4) != 0;
                 const T sgn = low ? (T)1.0 : (T)-1.0;
-                // the neighbour (the own cell at a boundary, replaced below)
-                double una[4];
-                T un[4][NM];
-                T ng[5];
+                T Po[NE][2], lnx_o, lny_o;
+                edge_pts(od, i, Po, lnx_o, lny_o);
+                // the own traces, then the neighbour's (the own cell's at a boundary,
+                // replaced below); the neighbour runs the shared edge the other way, so
+                // its point for nu is its own point NE-1-nu (symmetric Gauss nodes)
+                T qi[NE][4], qe[NE][4];
+                T lnx_n = lnx_o, lny_n = lny_o;
+                auto own_traces = [&]() __attribute__((always_inline)) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        T co[NC];
+#pragma unroll
+                        for (int k2 = 0; k2 < NC; ++k2) co[k2] = L.c[v][k2][threadIdx.x];
+#pragma unroll
+                        for (int nu = 0; nu < NE; ++nu) qi[nu][v] = trace(co, Po[nu], u[v][0]);
+                    }
+                };
+                own_traces();
                 if (has) {
-                    nb_get<K, T, 5>(L, ll, up, mv, una, un, ng);
-                } else {
+                    auto nb_traces = [&](auto&& nbc, const T (&dn)[4]) __attribute__((always_inline)) {
+                        T Pn[NE][2];
+                        edge_pts(dn, j, Pn, lnx_n, lny_n);
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
+                        for (int v = 0; v < 4; ++v) {
+                            T cn[NC], na;
+                            nbc(v, na, cn);
 #pragma unroll
-                        for (int l = 0; l < NM; ++l) un[v][l] = u[v][l];
+                            for (int nu = 0; nu < NE; ++nu) qe[nu][v] = trace(cn, Pn[NE - 1 - nu], na);
+                        }
+                    };
+                    if (ll & kLinkGlobal) {
+                        // beyond the halo cap: the neighbour's coefficients from global memory
+                        const int cell = (ll & ~kLinkGlobal) >> 3;
+                        const unsigned n8 = (unsigned)cell * 8u, nT = (unsigned)cell * (unsigned)sizeof(T);
+                        const T nxx = (T)mv.J(0, n8), nxy = (T)mv.J(1, n8), nex = (T)mv.J(2, n8), ney = (T)mv.J(3, n8);
+                        T dn[4];
+                        edge_vectors(nxx, nxy, nex, ney, dn);
+                        nb_traces(
+                            [&](int v, T& na, T (&cn)[NC]) __attribute__((always_inline)) {
+                                T un[NM];
+                                const double a0 = up.a(v, n8);
+                                un[0] = (T)a0;
 #pragma unroll
-                    for (int k2 = 0; k2 < 5; ++k2) ng[k2] = geo[k2];
+                                for (int l = 1; l < NM; ++l) un[l] = up.h(v, l, nT);
+                                to_mono<K, T>(un, nxx, nxy, nex, ney, !kMixed, cn);
+                                na = un[0];
+                            },
+                            dn);
+                    } else {
+                        const int sl = ll >> 3;
+                        T dn[4];
+#pragma unroll
+                        for (int k2 = 0; k2 < 4; ++k2) dn[k2] = L.d[k2][sl];
+                        nb_traces(
+                            [&](int v, T& na, T (&cn)[NC]) __attribute__((always_inline)) {
+                                na = kMixed ? (T)L.avg[kMixed ? v : 0][kMixed ? sl : 0] : (T)0.0;
+#pragma unroll
+                                for (int k2 = 0; k2 < NC; ++k2) cn[k2] = L.c[v][k2][sl];
+                            },
+                            dn);
+                    }
                 }
-                // the exterior trace at the edge's Gauss points: the neighbour runs the
-                // shared edge the other way, so its parameter is 1 - s_nu = s_{NE-1-nu}
-                // (symmetric Gauss nodes)
-                T qe[NE][4];
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-#pragma unroll
-                    for (int nu = 0; nu < NE; ++nu) qe[nu][v] = dot<NM>(un[v], er.r[j * NE + NE - 1 - nu]);
-                T lnx_o, lny_o, lnx_n, lny_n;
-                scaled_normal(xx, xy, ex, ey, areaT, i, lnx_o, lny_o);
-                scaled_normal(ng[0], ng[1], ng[2], ng[3], ng[4], j, lnx_n, lny_n);
                 const T lnx = low ? lnx_o : lnx_n, lny = low ? lny_o : lny_n;
                 const T lc = Fp<T>::sqrt(fma(lnx, lnx, lny * lny));   // the edge length, from the same bits on both sides
                 const T al = (T)alpha * lc;
@@ -865,28 +969,25 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
 #pragma unroll
                 for (int nu = 0; nu < NE; ++nu) {
                     const T* p = TB.ep[i * NE + nu];
-                    T qi[4];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) qi[v] = dot<NM>(u[v], p);
                     if (!has) {
                         // transmissive: the exterior trace is the interior one; reflective:
                         // its normal momentum reversed, m - 2 (m.n) n
-                        const T mn2 = (T)-2.0 * fma(qi[1], nxu, qi[2] * nyu);
-                        qe[nu][0] = qi[0];
-                        qe[nu][1] = wall ? fma(mn2, nxu, qi[1]) : qi[1];
-                        qe[nu][2] = wall ? fma(mn2, nyu, qi[2]) : qi[2];
-                        qe[nu][3] = qi[3];
+                        const T mn2 = (T)-2.0 * fma(qi[nu][1], nxu, qi[nu][2] * nyu);
+                        qe[nu][0] = qi[nu][0];
+                        qe[nu][1] = wall ? fma(mn2, nxu, qi[nu][1]) : qi[nu][1];
+                        qe[nu][2] = wall ? fma(mn2, nyu, qi[nu][2]) : qi[nu][2];
+                        qe[nu][3] = qi[nu][3];
                     }
                     T iri, pi, ire, pe;
-                    euler_ip(qi, gm1, iri, pi);
+                    euler_ip(qi[nu], gm1, iri, pi);
                     euler_ip(qe[nu], gm1, ire, pe);
                     T fi[4], fe[4];
-                    euler_flux_n(qi, iri, pi, lnx, lny, fi);
+                    euler_flux_n(qi[nu], iri, pi, lnx, lny, fi);
                     euler_flux_n(qe[nu], ire, pe, lnx, lny, fe);
                     const T wsn = (T)R::ws[nu];
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const T d = qe[nu][v] - qi[v];
+                        const T d = qe[nu][v] - qi[nu][v];
                         const T fh = sgn * (wsn * ((T)0.5 * ((fi[v] + fe[v]) - sgn * (al * d))));
                         r0[v] -= (double)fh;
 #pragma unroll
@@ -901,10 +1002,14 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
             double wavg[4];   // the pre-filter averages
             T w[4][NM];
             const T iaT = (T)ia, dtT = (T)dt, saT = (T)sa, sbT = (T)sb;
+            // u^n of the second and third stages, all its loads in flight together
+            double una[4] = {0.0, 0.0, 0.0, 0.0};
+            T unh[4][NM] = {};
+            if (a.stage != 0) load_cell<NM, T>(u0p, c, una, unh);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const double adv0 = fma(dt, r0[v] * ia, ua[v]);
-                const double w0 = a.stage == 0 ? adv0 : fma(sa, u0p.a(v, c8), sb * adv0);
+                const double w0 = a.stage == 0 ? adv0 : fma(sa, una[v], sb * adv0);
                 wp.put_a(v, c8, w0);
                 part[v] = area * w0;
                 wavg[v] = w0;
@@ -912,7 +1017,7 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
 #pragma unroll
                 for (int l = 1; l < NM; ++l) {
                     const T adv = fma(dtT, r[v][l] * iaT * (T)kInvMass[l], u[v][l]);
-                    const T wl = a.stage == 0 ? adv : fma(saT, u0p.h(v, l, cT), sbT * adv);
+                    const T wl = a.stage == 0 ? adv : fma(saT, unh[v][l], sbT * adv);
                     w[v][l] = wl;
                     wp.put_h(v, l, cT, wl);
                 }
@@ -968,12 +1073,9 @@ template <int K, typename T>
 __global__ __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(OEDG_RES_WAVES))) void k_residual(
     StageArgs a) {
     if (!a.g->active || a.g->skip) return;
-    __shared__ EdgeRowsLds<K, T> er;
-    __shared__ TileLds<K, T, 5> L;
+    __shared__ MonoLds<K, T> L;
     __shared__ WaveAcc<kResCols> W;
-    fill_edge_rows<K, T>(er);
-    __syncthreads();
-    residual_run<K, T, false>(a, 0, 0, er, L, W);
+    residual_run<K, T, false>(a, 0, 0, L, W);
 }
 
 // Batched passes: workgroup b walks its XCD's range of the chunk table; each
@@ -991,46 +1093,20 @@ __device__ __forceinline__ void for_each_chunk(const StageArgs* desc, const Chun
     }
 }
 
-// the tile image of a batched pass: one per degree present (KM: 1 P1, 2 P2, 3 both)
-template <int KM, typename T, int NG>
-union TileLdsKM {
-    typename std::conditional<(KM & 1) != 0, TileLds<1, T, NG>, char>::type p1;
-    typename std::conditional<(KM & 2) != 0, TileLds<2, T, NG>, char>::type p2;
-};
-
 template <int KM, typename T>
 __global__ __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(OEDG_RES_WAVES))) void k_residual_batch(
     const StageArgs* desc, const Chunk* chunks, ChunkSplit cs) {
-    __shared__ EdgeRowsLds<1, T> er1;
-    __shared__ EdgeRowsLds<2, T> er2;
-    __shared__ TileLdsKM<KM, T, 5> L;
+    __shared__ MonoLdsKM<KM, T> L;
     __shared__ WaveAcc<kResCols> W;
-    if constexpr (KM & 1) fill_edge_rows<1, T>(er1);
-    if constexpr (KM & 2) fill_edge_rows<2, T>(er2);
-    __syncthreads();
     for_each_chunk(desc, chunks, cs, [&](const StageArgs& a, int g0, int g1) {
-        if constexpr (KM == 1) residual_run<1, T, true>(a, g0, g1, er1, L.p1, W);
-        else if constexpr (KM == 2) residual_run<2, T, true>(a, g0, g1, er2, L.p2, W);
-        else if (a.k == 1) residual_run<1, T, true>(a, g0, g1, er1, L.p1, W);
-        else residual_run<2, T, true>(a, g0, g1, er2, L.p2, W);
+        if constexpr (KM == 1) residual_run<1, T, true>(a, g0, g1, L.p1, W);
+        else if constexpr (KM == 2) residual_run<2, T, true>(a, g0, g1, L.p2, W);
+        else if (a.k == 1) residual_run<1, T, true>(a, g0, g1, L.p1, W);
+        else residual_run<2, T, true>(a, g0, g1, L.p2, W);
     });
 }
 
 // ------------------------------------------------------------------------- pass 2: OE, limiter, alpha
-
-// P2 physical Hessian (xx, xy, yy) of one variable with modes u[0..5] (constant per
-// cell): J^-T H_ref J^-1 with H_ref = (48 u3, 24 u3 + 20 u4, 8 u3 + 20 u4 + 20 u5)
-template <typename T>
-__device__ __forceinline__ void hessian(const T* u, T xx, T xy, T ex, T ey, T (&h)[3]) {
-    const T hxx = (T)48.0 * u[3];
-    const T hxe = fma((T)24.0, u[3], (T)20.0 * u[4]);
-    const T hee = fma((T)8.0, u[3], (T)20.0 * (u[4] + u[5]));
-    const T ax = fma(hxx, xx, hxe * ex), ae = fma(hxe, xx, hee * ex);   // (H_ref J^-1) column x
-    const T bx = fma(hxx, xy, hxe * ey), be = fma(hxe, xy, hee * ey);   // column y
-    h[0] = fma(xx, ax, ex * ae);
-    h[1] = fma(xy, ax, ey * ae);
-    h[2] = fma(xy, bx, ey * be);
-}
 
 // The full state (FP64) at the NP-point limiter node set of a cell with averages
 // wa and modes w: the 3Q edge Gauss points, then two extra slots.  Optimal
@@ -1078,113 +1154,6 @@ __device__ __forceinline__ double internal_energy(const double (&q)[4]) {
     return fma(-0.5 * frcp(q[0]), fma(q[1], q[1], q[2] * q[2]), q[3]);
 }
 
-// The filter's tile image: every cell's polynomial as physical monomials about its
-// vertex 0 (the reference origin), u(x0 + X) = c0 + cX X + cY Y + cXX X^2 +
-// cXY X Y + cYY Y^2 per variable (P2; P1 stops at the linear part), and
-// the edge vectors d1 = x1 - x0, d2 = x2 - x0 that place its other two vertices.
-// Values, physical gradients and the (constant) Hessian at a vertex then cost a
-// few FMAs each, which is most of what the OE's jumps need; a slot takes as many
-// bytes as modes plus J^-1 would.  FP64: c0 is the whole value at x0; mixed: c0
-// is the higher modes' part (float) and the FP64 averages sit beside it, so a
-// value jump is the FP64 difference of the averages plus the float one of the rest.
-template <int K, typename T>
-struct MonoLds {
-    static constexpr int NC = K == 2 ? 6 : 3, S = kTileCells + kHaloCap;
-    static constexpr bool kMixed = std::is_same<T, float>::value;
-    double avg[kMixed ? 4 : 1][kMixed ? S : 1];
-    T c[4][NC][S];
-    T d[4][S];
-};
-
-// the filter's tile image of a batched pass: one per degree present
-template <int KM, typename T>
-union MonoLdsKM {
-    typename std::conditional<(KM & 1) != 0, MonoLds<1, T>, char>::type p1;
-    typename std::conditional<(KM & 2) != 0, MonoLds<2, T>, char>::type p2;
-};
-
-// the monomials of one variable (modes u, u[0] its average in T) from J^-1; with
-// `full`, c0 includes the average
-template <int K, typename T>
-__device__ __forceinline__ void to_mono(const T (&u)[Rule<K>::NM], T xx, T xy, T ex, T ey, bool full,
-                                        T (&c)[MonoLds<K, T>::NC]) {
-    T a, dx, de;
-    vertex_eval_ct<K, 0, T>(u, a, dx, de);
-    c[0] = full ? u[0] + a : a;
-    c[1] = fma(dx, xx, de * ex);
-    c[2] = fma(dx, xy, de * ey);
-    if constexpr (K == 2) {
-        T h[3];
-        hessian(u, xx, xy, ex, ey, h);
-        c[3] = (T)0.5 * h[0];
-        c[4] = h[1];
-        c[5] = (T)0.5 * h[2];
-    }
-}
-// d1 = J e1, d2 = J e2 from J^-1 = [[xx, xy], [ex, ey]]
-template <typename T>
-__device__ __forceinline__ void edge_vectors(T xx, T xy, T ex, T ey, T (&d)[4]) {
-    const T id = Fp<T>::rcp(fma(xx, ey, -(xy * ex)));
-    d[0] = ey * id;
-    d[1] = -(ex * id);
-    d[2] = -(xy * id);
-    d[3] = xx * id;
-}
-// the offset P = (X, Y) of vertex vt (0, 1, 2; a per-lane index) from vertex 0 of a
-// cell with edge vectors d
-template <typename T>
-__device__ __forceinline__ void vertex_point(const T (&d)[4], int vt, T (&P)[2]) {
-    P[0] = vt == 0 ? (T)0.0 : (vt == 1 ? d[0] : d[2]);
-    P[1] = vt == 0 ? (T)0.0 : (vt == 1 ? d[1] : d[3]);
-}
-// value (c0's part of it) and physical gradient at offset P
-template <int K, typename T>
-__device__ __forceinline__ void mono_at(const T (&c)[MonoLds<K, T>::NC], const T (&P)[2], T& val, T& gx, T& gy) {
-    if constexpr (K == 2) {
-        val = fma(P[0], fma(c[3], P[0], fma(c[4], P[1], c[1])), fma(P[1], fma(c[5], P[1], c[2]), c[0]));
-        gx = fma(c[3], P[0] + P[0], fma(c[4], P[1], c[1]));
-        gy = fma(c[5], P[1] + P[1], fma(c[4], P[0], c[2]));
-    } else {
-        val = fma(c[2], P[1], fma(c[1], P[0], c[0]));
-        gx = c[1];
-        gy = c[2];
-    }
-}
-// a cell's slot of the image from its FP64 averages, modes and J^-1
-template <int K, typename T>
-__device__ __forceinline__ void mono_put(MonoLds<K, T>& L, int s, const double (&avg)[4],
-                                         const T (&u)[4][Rule<K>::NM], const T (&geo)[4]) {
-    constexpr int NC = MonoLds<K, T>::NC;
-    constexpr bool kMixed = MonoLds<K, T>::kMixed;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        T c[NC];
-        to_mono<K, T>(u[v], geo[0], geo[1], geo[2], geo[3], !kMixed, c);
-        if constexpr (kMixed) L.avg[v][s] = avg[v];
-#pragma unroll
-        for (int k = 0; k < NC; ++k) L.c[v][k][s] = c[k];
-    }
-    T d[4];
-    edge_vectors(geo[0], geo[1], geo[2], geo[3], d);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) L.d[k][s] = d[k];
-}
-// the tile's halo cells into slots kTileCells.. (every thread takes some)
-template <int K, typename T>
-__device__ __forceinline__ void mono_halo(MonoLds<K, T>& L, const StageArgs& a, int tile,
-                                          const SView<Rule<K>::NM, T>& sv, const MView& mv) {
-    constexpr int NM = Rule<K>::NM;
-    const int h0 = a.m.halo_ptr[tile], hn = a.m.halo_ptr[tile + 1] - h0;
-    for (int h = threadIdx.x; h < hn; h += kPassThreads) {
-        const int cell = a.m.halo_cell[h0 + h];
-        double avg[4];
-        T u[4][NM];
-        T geo[4];
-        load_cell<NM, T>(sv, cell, avg, u);
-        geo_of<T, 4>(mv, (unsigned)cell * 8u, geo);
-        mono_put<K, T>(L, kTileCells + h, avg, u, geo);
-    }
-}
 // record of the filter pass: max wave speed, limited, bad and flattened counts,
 // sum |K| m1bar, sum |K| m2bar, the boundary momentum flux A_1, A_2, B_1, B_2
 constexpr int kFilCols = kFilterCols;
@@ -1229,9 +1198,11 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
         T w[4][NM];
         T geo[4];
         int lk[3];
+        double area_d = 0.0;
         if (live) {
             load_cell<NM, T>(wp, c, wa, w);
             geo_of<T, 4>(mv, c8, geo);
+            area_d = mv.A(c8);
 #pragma unroll
             for (int i = 0; i < 3; ++i) lk[i] = bld<int>(mv.llink, c4, (unsigned)i * mv.n4);
             if (oe) mono_put<K, T>(L, threadIdx.x, wa, w, geo);
@@ -1245,8 +1216,9 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
         for (int k = 0; k < kFilCols; ++k) part[k] = acc_ident(kFilOps[k]);
         if (live) {
             const T xx = geo[0], xy = geo[1], ex = geo[2], ey = geo[3];
-            const double area_d = mv.A(c8);
             const T area = (T)area_d;
+            T od[4];   // the cell's edge vectors: its edges' lengths and normals
+            edge_vectors(xx, xy, ex, ey, od);
 
             if (oe) {
                 T sig[4][K + 1];
@@ -1255,8 +1227,6 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
 #pragma unroll
                     for (int jj = 0; jj <= K; ++jj) sig[v][jj] = (T)0.0;
                 constexpr int NC = MonoLds<K, T>::NC;
-                T od[4];   // the own cell's edge vectors
-                edge_vectors(xx, xy, ex, ey, od);
                 // sum over both ends of the squared jumps of order j: j = 0 value, 1
                 // gradient; 2: the Hessian's jump, the same at both ends, weighted by
                 // C_2 = (1, 2, 1), i.e. 2 (jxx^2 + 2 jxy^2 + jyy^2)
@@ -1281,9 +1251,8 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
                     const int ll = i == 0 ? lk[0] : (i == 1 ? lk[1] : lk[2]);
                     if (ll < 0) continue;   // boundary edge: zero jump
                     const int j = ll & 3;
-                    const T len = (T)mv.L(i, c8);
-                    T nx, ny;
-                    unit_normal(xx, xy, ex, ey, area, i, len, nx, ny);
+                    T nx, ny, len;
+                    edge_normal(od, i, nx, ny, len);
                     const T h = (T)2.0 * area * F::rcp(len);   // h_K^(i) = 2|K| / l_i
                     // The edge's work, with the neighbour's coefficients from the image
                     // or (beyond the halo cap) converted from global memory: two copies of
@@ -1567,15 +1536,15 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
 #pragma unroll
             for (int t = 0; t < 3 * NE; ++t) {
                 const int i = t / NE, nu = t % NE;
-                T nxT, nyT;
-                unit_normal(xx, xy, ex, ey, area, i, (T)mv.L(i, c8), nxT, nyT);
+                T nxT, nyT, lenT;
+                edge_normal(od, i, nxT, nyT, lenT);
                 const double nx = (double)nxT, ny = (double)nyT;
                 const double q0 = fma(ta, pv[t][0] - ub0, ub0), q1 = fma(ta, pv[t][1] - ub1, ub1);
                 const double q2 = fma(ta, pv[t][2] - ub2, ub2), q3 = fma(ta, pv[t][3] - ub3, ub3);
                 const double rr = spectral_radius(q0, q1, q2, q3, nx, ny, gamma);
                 amax = (rr > amax || rr != rr) ? rr : amax;
                 if (any_bnd && lk[i] < 0) {
-                    const double lw = mv.L(i, c8) * R::ws[nu];
+                    const double lw = (double)lenT * R::ws[nu];
                     const double ir = frcp(q0);
                     const double mn = fma(q1, nx, q2 * ny);
                     const double p = (gamma - 1.0) * fma(-0.5 * ir, fma(q1, q1, q2 * q2), q3);
