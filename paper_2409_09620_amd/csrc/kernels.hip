@@ -666,21 +666,31 @@ __device__ __forceinline__ void mono_put(MonoLds<K, T>& L, int s, const double (
 #pragma unroll
     for (int k = 0; k < 4; ++k) L.d[k][s] = d[k];
 }
-// the tile's halo cells into slots kTileCells.. (every thread takes some)
-template <int K, typename T>
-__device__ __forceinline__ void mono_halo(MonoLds<K, T>& L, const StageArgs& a, int tile,
-                                          const SView<Rule<K>::NM, T>& sv, const MView& mv) {
-    constexpr int NM = Rule<K>::NM;
+// The halo cell that thread threadIdx.x stages for a tile (halo index threadIdx.x),
+// or -1.  Read one tile ahead, so that staging a tile waits on one round trip.
+static_assert(kHaloCap <= kPassThreads, "one halo cell per thread");
+__device__ __forceinline__ int halo_cell_of(const StageArgs& a, int tile) {
     const int h0 = a.m.halo_ptr[tile], hn = a.m.halo_ptr[tile + 1] - h0;
-    for (int h = threadIdx.x; h < hn; h += kPassThreads) {
-        const int cell = a.m.halo_cell[h0 + h];
-        double avg[4];
-        T u[4][NM];
-        T geo[4];
-        load_cell<NM, T>(sv, cell, avg, u);
-        geo_of<T, 4>(mv, (unsigned)cell * 8u, geo);
-        mono_put<K, T>(L, kTileCells + h, avg, u, geo);
+    return (int)threadIdx.x < hn ? a.m.halo_cell[h0 + (int)threadIdx.x] : -1;
+}
+// this thread's halo cell (hc >= 0): its loads, then its slot kTileCells + threadIdx.x
+template <int K, typename T>
+struct HaloCell {
+    double avg[4];
+    T u[4][Rule<K>::NM];
+    T geo[4];
+};
+template <int K, typename T>
+__device__ __forceinline__ void halo_load(HaloCell<K, T>& h, int hc, const SView<Rule<K>::NM, T>& sv,
+                                          const MView& mv) {
+    if (hc >= 0) {
+        load_cell<Rule<K>::NM, T>(sv, hc, h.avg, h.u);
+        geo_of<T, 4>(mv, (unsigned)hc * 8u, h.geo);
     }
+}
+template <int K, typename T>
+__device__ __forceinline__ void halo_put(MonoLds<K, T>& L, const HaloCell<K, T>& h, int hc) {
+    if (hc >= 0) mono_put<K, T>(L, kTileCells + (int)threadIdx.x, h.avg, h.u, h.geo);
 }
 // Running reductions of a pass workgroup over its tiles: after each tile every wave
 // reduces its lanes' contributions (one cell each) and lane 0 combines the result
@@ -738,21 +748,30 @@ __device__ __forceinline__ void wave_acc_flush(const WaveAcc<NC>& W, const int (
 }
 
 // Persistent walk of a pass: workgroup b takes its XCD's tiles in turn (single
-// instance), or the tiles (= reduction groups) of its chunks (batch); body(a, tile)
-// computes one tile, flush(a, g) writes the record of group g (batch) or of the
-// workgroup (g < 0).
+// instance), or the tiles (= reduction groups) of its chunks (batch); body(tile, hc)
+// computes one tile, hc the halo cell this thread stages for it, read while the
+// previous tile was computed; flush(g) writes the record of group g (batch) or of
+// the workgroup (g < 0).
 template <bool kBatch, typename Body, typename Reset, typename Flush>
 __device__ __forceinline__ void walk_tiles(const StageArgs& a, int g0, int g1, Body body, Reset reset, Flush flush) {
     if constexpr (!kBatch) {
         reset();
         const TileWalk tw = tile_walk(n_tiles_of(a.m.n_cell));
-        for (int tile = tw.first; tile < tw.end; tile += tw.stride) body(tile);
+        int hc = tw.first < tw.end ? halo_cell_of(a, tw.first) : -1;
+        for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
+            const int hn = tile + tw.stride < tw.end ? halo_cell_of(a, tile + tw.stride) : -1;
+            body(tile, hc);
+            hc = hn;
+        }
         flush(-1);
     } else {
+        int hc = g0 < g1 ? halo_cell_of(a, g0) : -1;
         for (int gi = g0; gi < g1; ++gi) {
+            const int hn = gi + 1 < g1 ? halo_cell_of(a, gi + 1) : -1;
             reset();
-            body(gi);
+            body(gi, hc);
             flush(gi);
+            hc = hn;
         }
     }
 }
@@ -805,7 +824,7 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
         mb[j] = uniform((first ? s_w : sa * g->mom_n[j] + sb * s_w) / g->area_sum);
     }
 
-    auto tile_body = [&](int tile) __attribute__((always_inline)) {
+    auto tile_body = [&](int tile, int hc) __attribute__((always_inline)) {
         const int c = tile * kTileCells + (int)threadIdx.x;
         const bool live = c < nc;
         const unsigned c8 = (unsigned)c * 8u, c4 = (unsigned)c * 4u, cT = (unsigned)c * (unsigned)sizeof(T);
@@ -814,6 +833,9 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
         T u[4][NM];
         T geo[5];
         int lk[3];
+        // both cells' loads are in flight before either is written to the image
+        HaloCell<K, T> hcell;
+        halo_load<K, T>(hcell, hc, up, mv);
         if (live) {
             load_cell<NM, T>(up, c, ua, u);
             geo_of<T, 5>(mv, c8, geo);
@@ -821,7 +843,7 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
             for (int i = 0; i < 3; ++i) lk[i] = bld<int>(mv.llink, c4, (unsigned)i * mv.n4);
             mono_put<K, T>(L, threadIdx.x, ua, u, reinterpret_cast<const T(&)[4]>(geo));
         }
-        mono_halo<K, T>(L, a, tile, up, mv);
+        halo_put<K, T>(L, hcell, hc);
         __syncthreads();
         double part[kResCols];
 #pragma unroll
@@ -1190,7 +1212,7 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
         cols[k] = kNumPartial + 1 + k;
     }
 
-    auto tile_body = [&](int tile) __attribute__((always_inline)) {
+    auto tile_body = [&](int tile, int hc) __attribute__((always_inline)) {
         const int c = tile * kTileCells + (int)threadIdx.x;
         const bool live = c < nc;
         const unsigned c8 = (unsigned)c * 8u, c4 = (unsigned)c * 4u, cT = (unsigned)c * (unsigned)sizeof(T);
@@ -1199,6 +1221,8 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
         T geo[4];
         int lk[3];
         double area_d = 0.0;
+        HaloCell<K, T> hcell;
+        if (oe) halo_load<K, T>(hcell, hc, wp, mv);
         if (live) {
             load_cell<NM, T>(wp, c, wa, w);
             geo_of<T, 4>(mv, c8, geo);
@@ -1208,7 +1232,7 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
             if (oe) mono_put<K, T>(L, threadIdx.x, wa, w, geo);
         }
         if (oe) {
-            mono_halo<K, T>(L, a, tile, wp, mv);
+            halo_put<K, T>(L, hcell, hc);
             __syncthreads();
         }
         double part[kFilCols];
