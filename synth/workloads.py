@@ -90,7 +90,8 @@ def serving_requests(n_req=32, rate=50.0, seed=5, lo=1_000, hi=2_000_000, scale=
 
     Sizes log-uniform in [lo, hi] / scale triangles, degree 1 or 2 and Riemann
     (two states at rest across a random line in the unit square, rho and p
-    log-uniform in [0.03, 1.5]) or vortex data (Delaunay mesh of [0,10]^2) with
+    log-uniform in [0.14, 1.5], reflective walls) or vortex data (Delaunay mesh of
+    [0,10]^2) with
     probability 1/2 each, t_end uniform in [t_lo, t_hi] times t_scale, arrivals a
     Poisson process of the given rate per second (exponential gaps by inversion)."""
     st = Stream(seed * 53 + 7)
@@ -110,5 +111,8 @@ def serving_request(spec):
         m = poisson_delaunay(spec["n_cells"], lo=(0.0, 0.0), hi=(10.0, 10.0), seed=spec["seed"],
                              name=f"req{spec['id']}")
         return m, PROBLEM_VORTEX, vortex_params()
+    # walls: a discontinuity that meets a transmissive (extrapolated) boundary can
+    # grow there on fine meshes, which would stall the request's time step
     m = poisson_delaunay(spec["n_cells"], seed=spec["seed"], name=f"req{spec['id']}")
-    return m, PROBLEM_TWO_STATE, two_state_params(spec["seed"], lo=0.03, hi=1.5)
+    m.edge_bc = np.ones((m.n_cell, 3), np.int32)
+    return m, PROBLEM_TWO_STATE, two_state_params(spec["seed"], lo=0.14, hi=1.5)
