@@ -20,19 +20,21 @@
 // variables and their modes in that lane's registers, so every point value,
 // 1/rho, pressure and flux is formed once.  A pass workgroup takes tiles of 256
 // consecutive (Hilbert-ordered) cells, one per thread, and stages each tile with
-// its halo of out-of-tile neighbours in LDS before computing it.  The image holds
-// every cell's polynomial as physical monomials about its vertex 0 plus the two
-// edge vectors from that vertex, so a neighbour's value, gradient and Hessian at
-// any point (an edge Gauss point, a shared vertex) cost a few FMAs.  Workgroups
+// its halo of out-of-tile neighbours in LDS before computing it.  The residual's
+// image holds every cell's averages, modes and geometry, from which a neighbour's
+// traces at the edge Gauss points are formed with the basis rows of its local
+// edge.  The filter's image holds every cell's polynomial as physical monomials
+// about its vertex 0 plus the two edge vectors from that vertex, so a neighbour's
+// value, gradient and Hessian at a shared vertex cost a few FMAs.  Workgroups
 // are spread so that each XCD walks a contiguous range of the tiles, which keeps
 // neighbour gathers inside that XCD's L2.
 //
 // Edge fluxes are conservative to the last bit: both cells of an interior edge
-// evaluate its LF flux from the same two traces (each cell's trace formed by the
-// same arithmetic from the same monomials and edge vectors, whichever lane asks),
-// with the lower-index cell's scaled normal and length, and in a fixed operand
-// order, so the two contributions are exact negatives of each other.  The file is
-// compiled with FMA contraction off; every fused multiply-add is written out.
+// evaluate its LF flux from the same two traces (each cell's trace computed by the
+// same arithmetic from the same basis rows, whichever lane asks), with the
+// lower-index cell's scaled normal and length, and in a fixed operand order, so
+// the two contributions are exact negatives of each other.  The file is compiled
+// with FMA contraction off; every fused multiply-add is written out.
 //
 // Precision: every pass is instantiated for a bulk type T, double (FP64) or
 // float (mixed).  Cell averages are stored, updated and reduced in FP64 in both
@@ -532,6 +534,21 @@ __device__ __forceinline__ double uniform(double x) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
 }
 
+// The edge Gauss point rows of the basis in LDS, for the exterior trace: a
+// neighbour's local edge is a per-lane index, so its rows cannot come from the
+// scalar path.  Filled by the workgroup before the first cell.
+template <int K, typename T>
+struct EdgeRowsLds {
+    T r[3 * Rule<K>::NE][Rule<K>::NM];
+};
+template <int K, typename T>
+__device__ __forceinline__ void fill_edge_rows(EdgeRowsLds<K, T>& dst) {
+    constexpr int N = 3 * Rule<K>::NE * Rule<K>::NM;
+    const T* src = &tab<K, T>().ep[0][0];
+    T* d = &dst.r[0][0];
+    for (int t = threadIdx.x; t < N; t += blockDim.x) d[t] = src[t];
+}
+
 #ifndef OEDG_RES_WAVES
 #define OEDG_RES_WAVES 2
 #endif
@@ -541,6 +558,31 @@ __device__ __forceinline__ double uniform(double x) {
 
 // ------------------------------------------------------------------------- tiles in LDS
 
+// LDS image of a tile and its halo for one pass: per slot the four FP64 averages,
+// the modes l >= 1 in the bulk type and NG geometry entries in the bulk type (the
+// rows of J^-1, then |K| for the residual).  Slot s < kTileCells holds cell
+// tile * kTileCells + s, slot kTileCells + h the tile's halo cell h.  SoA per
+// entry, so a lane's slot reads are 8-byte (4-byte) strided accesses.
+template <int K, typename T, int NG>
+struct TileLds {
+    static constexpr int NM = Rule<K>::NM, S = kTileCells + kHaloCap;
+    double avg[4][S];
+    T hi[4][NM - 1][S];
+    T geo[NG][S];
+};
+template <int K, typename T, int NG>
+__device__ __forceinline__ void stage_put(TileLds<K, T, NG>& L, int s, const double (&avg)[4],
+                                          const T (&u)[4][Rule<K>::NM], const T (&geo)[NG]) {
+    constexpr int NM = Rule<K>::NM;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        L.avg[v][s] = avg[v];
+#pragma unroll
+        for (int l = 1; l < NM; ++l) L.hi[v][l - 1][s] = u[v][l];
+    }
+#pragma unroll
+    for (int g = 0; g < NG; ++g) L.geo[g][s] = geo[g];
+}
 // the geometry entries of cell c (byte offset c8) in the bulk type
 template <typename T, int NG>
 __device__ __forceinline__ void geo_of(const MView& mv, unsigned c8, T (&geo)[NG]) {
@@ -548,6 +590,50 @@ __device__ __forceinline__ void geo_of(const MView& mv, unsigned c8, T (&geo)[NG
     for (int g = 0; g < 4; ++g) geo[g] = (T)mv.J(g, c8);
     if constexpr (NG == 5) geo[4] = (T)mv.A(c8);
 }
+// The neighbour across an interior edge with llink value ll: its averages, modes and
+// geometry, from the tile image or, beyond the halo cap, from global memory.
+template <int K, typename T, int NG>
+__device__ __forceinline__ void nb_get(const TileLds<K, T, NG>& L, int ll, const SView<Rule<K>::NM, T>& sv,
+                                       const MView& mv, double (&avg)[4], T (&u)[4][Rule<K>::NM], T (&geo)[NG]) {
+    constexpr int NM = Rule<K>::NM;
+    if (ll & kLinkGlobal) {
+        const int cell = (ll & ~kLinkGlobal) >> 3;
+        load_cell<NM, T>(sv, cell, avg, u);
+        geo_of<T, NG>(mv, (unsigned)cell * 8u, geo);
+    } else {
+        const int s = ll >> 3;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            avg[v] = L.avg[v][s];
+            u[v][0] = (T)avg[v];
+#pragma unroll
+            for (int l = 1; l < NM; ++l) u[v][l] = L.hi[v][l - 1][s];
+        }
+#pragma unroll
+        for (int g = 0; g < NG; ++g) geo[g] = L.geo[g][s];
+    }
+}
+// The residual's halo cell (hc >= 0): its loads, then its slot kTileCells + threadIdx.x
+// of the modal image.
+template <int K, typename T, int NG>
+struct HaloCellG {
+    double avg[4];
+    T u[4][Rule<K>::NM];
+    T geo[NG];
+};
+template <int K, typename T, int NG>
+__device__ __forceinline__ void halo_load_g(HaloCellG<K, T, NG>& h, int hc, const SView<Rule<K>::NM, T>& sv,
+                                            const MView& mv) {
+    if (hc >= 0) {
+        load_cell<Rule<K>::NM, T>(sv, hc, h.avg, h.u);
+        geo_of<T, NG>(mv, (unsigned)hc * 8u, h.geo);
+    }
+}
+template <int K, typename T, int NG>
+__device__ __forceinline__ void halo_put_g(TileLds<K, T, NG>& L, const HaloCellG<K, T, NG>& h, int hc) {
+    if (hc >= 0) stage_put<K, T, NG>(L, kTileCells + (int)threadIdx.x, h.avg, h.u, h.geo);
+}
+
 // P2 physical Hessian (xx, xy, yy) of one variable with modes u[0..5] (constant per
 // cell): J^-T H_ref J^-1 with H_ref = (48 u3, 24 u3 + 20 u4, 8 u3 + 20 u4 + 20 u5)
 template <typename T>
@@ -781,9 +867,13 @@ __device__ __forceinline__ void walk_tiles(const StageArgs& a, int g0, int g1, B
 constexpr int kResCols = 14;   // sums, minima, maxima (4 each), |m - mbar|^2 max, bad averages
 __device__ constexpr int kResOps[kResCols] = {0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 2, 2, 0};
 
-template <int K, typename T, bool kBatch>
-__device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1, MonoLds<K, T>& L,
+// Img: TileLds<K, T, 5> (the modal image: averages, modes and geometry, the
+// neighbour's traces from the basis rows er) or MonoLds<K, T> (monomials and edge
+// vectors); the batched FP64 pass takes the second, the others the first.
+template <int K, typename T, bool kBatch, typename Img>
+__device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1, const EdgeRowsLds<K, T>& er, Img& L,
                                              WaveAcc<kResCols>& W) {
+    constexpr bool kMono = std::is_same<Img, MonoLds<K, T>>::value;
     using R = Rule<K>;
     constexpr int NM = R::NM, NE = R::NE;
     constexpr bool kMixed = std::is_same<T, float>::value;
@@ -834,16 +924,29 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
         T geo[5];
         int lk[3];
         // both cells' loads are in flight before either is written to the image
-        HaloCell<K, T> hcell;
-        halo_load<K, T>(hcell, hc, up, mv);
-        if (live) {
-            load_cell<NM, T>(up, c, ua, u);
-            geo_of<T, 5>(mv, c8, geo);
+        if constexpr (kMono) {
+            HaloCell<K, T> hcell;
+            halo_load<K, T>(hcell, hc, up, mv);
+            if (live) {
+                load_cell<NM, T>(up, c, ua, u);
+                geo_of<T, 5>(mv, c8, geo);
 #pragma unroll
-            for (int i = 0; i < 3; ++i) lk[i] = bld<int>(mv.llink, c4, (unsigned)i * mv.n4);
-            mono_put<K, T>(L, threadIdx.x, ua, u, reinterpret_cast<const T(&)[4]>(geo));
+                for (int i = 0; i < 3; ++i) lk[i] = bld<int>(mv.llink, c4, (unsigned)i * mv.n4);
+                mono_put<K, T>(L, threadIdx.x, ua, u, reinterpret_cast<const T(&)[4]>(geo));
+            }
+            halo_put<K, T>(L, hcell, hc);
+        } else {
+            HaloCellG<K, T, 5> hcell;
+            halo_load_g<K, T, 5>(hcell, hc, up, mv);
+            if (live) {
+                load_cell<NM, T>(up, c, ua, u);
+                geo_of<T, 5>(mv, c8, geo);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) lk[i] = bld<int>(mv.llink, c4, (unsigned)i * mv.n4);
+                stage_put<K, T, 5>(L, threadIdx.x, ua, u, geo);
+            }
+            halo_put_g<K, T, 5>(L, hcell, hc);
         }
-        halo_put<K, T>(L, hcell, hc);
         __syncthreads();
         double part[kResCols];
 #pragma unroll
@@ -879,141 +982,221 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
                         r[v][l] = fma(TB.vdx[m][l], g1[v], fma(TB.vde[m][l], g2[v], r[v][l]));
             }
 
-            // surface term - sum_i l_i sum_nu w_nu Fhat(u_int, u_ext, n_i) Psi_l.  Both
-            // cells of an interior edge form Fhat with the scaled normal l n of the
-            // lower-index cell ("low") and l = |l n|, from the same two traces in
-            // commuted order, so their contributions are exact negatives (sgn = +1 on the
-            // low side):  Fhat_low = 1/2 (F(u_i).n + F(u_e).n - sgn alpha l (u_e - u_i)),
-            // and the own cell adds -sgn w_nu Fhat_low Psi_l.  Every trace comes from the
-            // cell's monomials in the tile image at its own offset of the Gauss point,
-            // and every scaled normal from its edge vectors (l n = (dy, -dx) along the
-            // counter-clockwise edge), by the same arithmetic whichever lane asks.
-            constexpr int NC = MonoLds<K, T>::NC;
-            T od[4];
-#pragma unroll
-            for (int k2 = 0; k2 < 4; ++k2) od[k2] = L.d[k2][threadIdx.x];
-            // the Gauss points of local edge e of a cell with edge vectors d: from
-            // vertex e+1 towards e+2, parameter s_nu
-            auto edge_pts = [&](const T (&d)[4], int e, T (&P)[NE][2], T& lnx, T& lny) __attribute__((always_inline)) {
-                T A[2], B[2];
-                vertex_point(d, (e + 1) % 3, A);
-                vertex_point(d, (e + 2) % 3, B);
-                const T dx = B[0] - A[0], dy = B[1] - A[1];
-                lnx = dy;
-                lny = -dx;
-#pragma unroll
-                for (int nu = 0; nu < NE; ++nu) {
-                    P[nu][0] = fma((T)R::s[nu], dx, A[0]);
-                    P[nu][1] = fma((T)R::s[nu], dy, A[1]);
-                }
-            };
-            auto trace = [&](const T (&cf)[NC], const T (&P)[2], T avg) __attribute__((always_inline)) {
-                T val, g0, g1;
-                mono_at<K, T>(cf, P, val, g0, g1);
-                return kMixed ? avg + val : val;
-            };
-#pragma unroll 1
-            for (int i = 0; i < 3; ++i) {
-                const int ll = i == 0 ? lk[0] : (i == 1 ? lk[1] : lk[2]);
-                const bool has = ll >= 0;
-                const bool wall = ll == kLinkWall;
-                const int j = has ? (ll & 3) : i;
-                const bool low = !has || (ll & 4) != 0;
-                const T sgn = low ? (T)1.0 : (T)-1.0;
-                T Po[NE][2], lnx_o, lny_o;
-                edge_pts(od, i, Po, lnx_o, lny_o);
-                // the own traces, then the neighbour's (the own cell's at a boundary,
-                // replaced below); the neighbour runs the shared edge the other way, so
-                // its point for nu is its own point NE-1-nu (symmetric Gauss nodes)
-                T qi[NE][4], qe[NE][4];
-                T lnx_n = lnx_o, lny_n = lny_o;
-                auto own_traces = [&]() __attribute__((always_inline)) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        T co[NC];
-#pragma unroll
-                        for (int k2 = 0; k2 < NC; ++k2) co[k2] = L.c[v][k2][threadIdx.x];
-#pragma unroll
-                        for (int nu = 0; nu < NE; ++nu) qi[nu][v] = trace(co, Po[nu], u[v][0]);
+            if constexpr (kMono) {
+                // surface term - sum_i l_i sum_nu w_nu Fhat(u_int, u_ext, n_i) Psi_l.  Both
+                // cells of an interior edge form Fhat with the scaled normal l n of the
+                // lower-index cell ("low") and l = |l n|, from the same two traces in
+                // commuted order, so their contributions are exact negatives (sgn = +1 on the
+                // low side):  Fhat_low = 1/2 (F(u_i).n + F(u_e).n - sgn alpha l (u_e - u_i)),
+                // and the own cell adds -sgn w_nu Fhat_low Psi_l.  Every trace comes from the
+                // cell's monomials in the tile image at its own offset of the Gauss point,
+                // and every scaled normal from its edge vectors (l n = (dy, -dx) along the
+                // counter-clockwise edge), by the same arithmetic whichever lane asks.
+                constexpr int NC = MonoLds<K, T>::NC;
+                T od[4];
+    #pragma unroll
+                for (int k2 = 0; k2 < 4; ++k2) od[k2] = L.d[k2][threadIdx.x];
+                // the Gauss points of local edge e of a cell with edge vectors d: from
+                // vertex e+1 towards e+2, parameter s_nu
+                auto edge_pts = [&](const T (&d)[4], int e, T (&P)[NE][2], T& lnx, T& lny) __attribute__((always_inline)) {
+                    T A[2], B[2];
+                    vertex_point(d, (e + 1) % 3, A);
+                    vertex_point(d, (e + 2) % 3, B);
+                    const T dx = B[0] - A[0], dy = B[1] - A[1];
+                    lnx = dy;
+                    lny = -dx;
+    #pragma unroll
+                    for (int nu = 0; nu < NE; ++nu) {
+                        P[nu][0] = fma((T)R::s[nu], dx, A[0]);
+                        P[nu][1] = fma((T)R::s[nu], dy, A[1]);
                     }
                 };
-                own_traces();
-                if (has) {
-                    auto nb_traces = [&](auto&& nbc, const T (&dn)[4]) __attribute__((always_inline)) {
-                        T Pn[NE][2];
-                        edge_pts(dn, j, Pn, lnx_n, lny_n);
-#pragma unroll
+                auto trace = [&](const T (&cf)[NC], const T (&P)[2], T avg) __attribute__((always_inline)) {
+                    T val, g0, g1;
+                    mono_at<K, T>(cf, P, val, g0, g1);
+                    return kMixed ? avg + val : val;
+                };
+    #pragma unroll 1
+                for (int i = 0; i < 3; ++i) {
+                    const int ll = i == 0 ? lk[0] : (i == 1 ? lk[1] : lk[2]);
+                    const bool has = ll >= 0;
+                    const bool wall = ll == kLinkWall;
+                    const int j = has ? (ll & 3) : i;
+                    const bool low = !has || (ll & 4) != 0;
+                    const T sgn = low ? (T)1.0 : (T)-1.0;
+                    T Po[NE][2], lnx_o, lny_o;
+                    edge_pts(od, i, Po, lnx_o, lny_o);
+                    // the own traces, then the neighbour's (the own cell's at a boundary,
+                    // replaced below); the neighbour runs the shared edge the other way, so
+                    // its point for nu is its own point NE-1-nu (symmetric Gauss nodes)
+                    T qi[NE][4], qe[NE][4];
+                    T lnx_n = lnx_o, lny_n = lny_o;
+                    auto own_traces = [&]() __attribute__((always_inline)) {
+    #pragma unroll
                         for (int v = 0; v < 4; ++v) {
-                            T cn[NC], na;
-                            nbc(v, na, cn);
-#pragma unroll
-                            for (int nu = 0; nu < NE; ++nu) qe[nu][v] = trace(cn, Pn[NE - 1 - nu], na);
+                            T co[NC];
+    #pragma unroll
+                            for (int k2 = 0; k2 < NC; ++k2) co[k2] = L.c[v][k2][threadIdx.x];
+    #pragma unroll
+                            for (int nu = 0; nu < NE; ++nu) qi[nu][v] = trace(co, Po[nu], u[v][0]);
                         }
                     };
-                    if (ll & kLinkGlobal) {
-                        // beyond the halo cap: the neighbour's coefficients from global memory
-                        const int cell = (ll & ~kLinkGlobal) >> 3;
-                        const unsigned n8 = (unsigned)cell * 8u, nT = (unsigned)cell * (unsigned)sizeof(T);
-                        const T nxx = (T)mv.J(0, n8), nxy = (T)mv.J(1, n8), nex = (T)mv.J(2, n8), ney = (T)mv.J(3, n8);
-                        T dn[4];
-                        edge_vectors(nxx, nxy, nex, ney, dn);
-                        nb_traces(
-                            [&](int v, T& na, T (&cn)[NC]) __attribute__((always_inline)) {
-                                T un[NM];
-                                const double a0 = up.a(v, n8);
-                                un[0] = (T)a0;
-#pragma unroll
-                                for (int l = 1; l < NM; ++l) un[l] = up.h(v, l, nT);
-                                to_mono<K, T>(un, nxx, nxy, nex, ney, !kMixed, cn);
-                                na = un[0];
-                            },
-                            dn);
-                    } else {
-                        const int sl = ll >> 3;
-                        T dn[4];
-#pragma unroll
-                        for (int k2 = 0; k2 < 4; ++k2) dn[k2] = L.d[k2][sl];
-                        nb_traces(
-                            [&](int v, T& na, T (&cn)[NC]) __attribute__((always_inline)) {
-                                na = kMixed ? (T)L.avg[kMixed ? v : 0][kMixed ? sl : 0] : (T)0.0;
-#pragma unroll
-                                for (int k2 = 0; k2 < NC; ++k2) cn[k2] = L.c[v][k2][sl];
-                            },
-                            dn);
+                    own_traces();
+                    if (has) {
+                        auto nb_traces = [&](auto&& nbc, const T (&dn)[4]) __attribute__((always_inline)) {
+                            T Pn[NE][2];
+                            edge_pts(dn, j, Pn, lnx_n, lny_n);
+    #pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                T cn[NC], na;
+                                nbc(v, na, cn);
+    #pragma unroll
+                                for (int nu = 0; nu < NE; ++nu) qe[nu][v] = trace(cn, Pn[NE - 1 - nu], na);
+                            }
+                        };
+                        if (ll & kLinkGlobal) {
+                            // beyond the halo cap: the neighbour's coefficients from global memory
+                            const int cell = (ll & ~kLinkGlobal) >> 3;
+                            const unsigned n8 = (unsigned)cell * 8u, nT = (unsigned)cell * (unsigned)sizeof(T);
+                            const T nxx = (T)mv.J(0, n8), nxy = (T)mv.J(1, n8), nex = (T)mv.J(2, n8), ney = (T)mv.J(3, n8);
+                            T dn[4];
+                            edge_vectors(nxx, nxy, nex, ney, dn);
+                            nb_traces(
+                                [&](int v, T& na, T (&cn)[NC]) __attribute__((always_inline)) {
+                                    T un[NM];
+                                    const double a0 = up.a(v, n8);
+                                    un[0] = (T)a0;
+    #pragma unroll
+                                    for (int l = 1; l < NM; ++l) un[l] = up.h(v, l, nT);
+                                    to_mono<K, T>(un, nxx, nxy, nex, ney, !kMixed, cn);
+                                    na = un[0];
+                                },
+                                dn);
+                        } else {
+                            const int sl = ll >> 3;
+                            T dn[4];
+    #pragma unroll
+                            for (int k2 = 0; k2 < 4; ++k2) dn[k2] = L.d[k2][sl];
+                            nb_traces(
+                                [&](int v, T& na, T (&cn)[NC]) __attribute__((always_inline)) {
+                                    na = kMixed ? (T)L.avg[kMixed ? v : 0][kMixed ? sl : 0] : (T)0.0;
+    #pragma unroll
+                                    for (int k2 = 0; k2 < NC; ++k2) cn[k2] = L.c[v][k2][sl];
+                                },
+                                dn);
+                        }
+                    }
+                    const T lnx = low ? lnx_o : lnx_n, lny = low ? lny_o : lny_n;
+                    const T lc = Fp<T>::sqrt(fma(lnx, lnx, lny * lny));   // the edge length, from the same bits on both sides
+                    const T al = (T)alpha * lc;
+                    // unit normal of a reflective wall (own edge, so own is low)
+                    const T il = Fp<T>::rcp(lc);
+                    const T nxu = lnx * il, nyu = lny * il;
+    #pragma unroll
+                    for (int nu = 0; nu < NE; ++nu) {
+                        const T* p = TB.ep[i * NE + nu];
+                        if (!has) {
+                            // transmissive: the exterior trace is the interior one; reflective:
+                            // its normal momentum reversed, m - 2 (m.n) n
+                            const T mn2 = (T)-2.0 * fma(qi[nu][1], nxu, qi[nu][2] * nyu);
+                            qe[nu][0] = qi[nu][0];
+                            qe[nu][1] = wall ? fma(mn2, nxu, qi[nu][1]) : qi[nu][1];
+                            qe[nu][2] = wall ? fma(mn2, nyu, qi[nu][2]) : qi[nu][2];
+                            qe[nu][3] = qi[nu][3];
+                        }
+                        T iri, pi, ire, pe;
+                        euler_ip(qi[nu], gm1, iri, pi);
+                        euler_ip(qe[nu], gm1, ire, pe);
+                        T fi[4], fe[4];
+                        euler_flux_n(qi[nu], iri, pi, lnx, lny, fi);
+                        euler_flux_n(qe[nu], ire, pe, lnx, lny, fe);
+                        const T wsn = (T)R::ws[nu];
+    #pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const T d = qe[nu][v] - qi[nu][v];
+                            const T fh = sgn * (wsn * ((T)0.5 * ((fi[v] + fe[v]) - sgn * (al * d))));
+                            r0[v] -= (double)fh;
+    #pragma unroll
+                            for (int l = 1; l < NM; ++l) r[v][l] = fma(-fh, p[l], r[v][l]);
+                        }
                     }
                 }
-                const T lnx = low ? lnx_o : lnx_n, lny = low ? lny_o : lny_n;
-                const T lc = Fp<T>::sqrt(fma(lnx, lnx, lny * lny));   // the edge length, from the same bits on both sides
-                const T al = (T)alpha * lc;
-                // unit normal of a reflective wall (own edge, so own is low)
-                const T il = Fp<T>::rcp(lc);
-                const T nxu = lnx * il, nyu = lny * il;
-#pragma unroll
-                for (int nu = 0; nu < NE; ++nu) {
-                    const T* p = TB.ep[i * NE + nu];
-                    if (!has) {
-                        // transmissive: the exterior trace is the interior one; reflective:
-                        // its normal momentum reversed, m - 2 (m.n) n
-                        const T mn2 = (T)-2.0 * fma(qi[nu][1], nxu, qi[nu][2] * nyu);
-                        qe[nu][0] = qi[nu][0];
-                        qe[nu][1] = wall ? fma(mn2, nxu, qi[nu][1]) : qi[nu][1];
-                        qe[nu][2] = wall ? fma(mn2, nyu, qi[nu][2]) : qi[nu][2];
-                        qe[nu][3] = qi[nu][3];
+            } else {
+                // surface term - sum_i l_i sum_nu w_nu Fhat(u_int, u_ext, n_i) Psi_l.  Both
+                // cells of an interior edge form Fhat with the scaled normal l n of the
+                // lower-index cell ("low") and l = |l n|, from the same two traces in
+                // commuted order, so their contributions are exact negatives (sgn = +1 on the
+                // low side):  Fhat_low = 1/2 (F(u_i).n + F(u_e).n - sgn alpha l (u_e - u_i)),
+                // and the own cell adds -sgn w_nu Fhat_low Psi_l.
+    #pragma unroll 1
+                for (int i = 0; i < 3; ++i) {
+                    const int ll = i == 0 ? lk[0] : (i == 1 ? lk[1] : lk[2]);
+                    const bool has = ll >= 0;
+                    const bool wall = ll == kLinkWall;
+                    const int j = has ? (ll & 3) : i;
+                    const bool low = !has || (ll & 4) != 0;
+                    const T sgn = low ? (T)1.0 : (T)-1.0;
+                    // the neighbour (the own cell at a boundary, replaced below)
+                    double una[4];
+                    T un[4][NM];
+                    T ng[5];
+                    if (has) {
+                        nb_get<K, T, 5>(L, ll, up, mv, una, un, ng);
+                    } else {
+    #pragma unroll
+                        for (int v = 0; v < 4; ++v)
+    #pragma unroll
+                            for (int l = 0; l < NM; ++l) un[v][l] = u[v][l];
+    #pragma unroll
+                        for (int k2 = 0; k2 < 5; ++k2) ng[k2] = geo[k2];
                     }
-                    T iri, pi, ire, pe;
-                    euler_ip(qi[nu], gm1, iri, pi);
-                    euler_ip(qe[nu], gm1, ire, pe);
-                    T fi[4], fe[4];
-                    euler_flux_n(qi[nu], iri, pi, lnx, lny, fi);
-                    euler_flux_n(qe[nu], ire, pe, lnx, lny, fe);
-                    const T wsn = (T)R::ws[nu];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const T d = qe[nu][v] - qi[nu][v];
-                        const T fh = sgn * (wsn * ((T)0.5 * ((fi[v] + fe[v]) - sgn * (al * d))));
-                        r0[v] -= (double)fh;
-#pragma unroll
-                        for (int l = 1; l < NM; ++l) r[v][l] = fma(-fh, p[l], r[v][l]);
+                    // the exterior trace at the edge's Gauss points: the neighbour runs the
+                    // shared edge the other way, so its parameter is 1 - s_nu = s_{NE-1-nu}
+                    // (symmetric Gauss nodes)
+                    T qe[NE][4];
+    #pragma unroll
+                    for (int v = 0; v < 4; ++v)
+    #pragma unroll
+                        for (int nu = 0; nu < NE; ++nu) qe[nu][v] = dot<NM>(un[v], er.r[j * NE + NE - 1 - nu]);
+                    T lnx_o, lny_o, lnx_n, lny_n;
+                    scaled_normal(xx, xy, ex, ey, areaT, i, lnx_o, lny_o);
+                    scaled_normal(ng[0], ng[1], ng[2], ng[3], ng[4], j, lnx_n, lny_n);
+                    const T lnx = low ? lnx_o : lnx_n, lny = low ? lny_o : lny_n;
+                    const T lc = Fp<T>::sqrt(fma(lnx, lnx, lny * lny));   // the edge length, from the same bits on both sides
+                    const T al = (T)alpha * lc;
+                    // unit normal of a reflective wall (own edge, so own is low)
+                    const T il = Fp<T>::rcp(lc);
+                    const T nxu = lnx * il, nyu = lny * il;
+    #pragma unroll
+                    for (int nu = 0; nu < NE; ++nu) {
+                        const T* p = TB.ep[i * NE + nu];
+                        T qi[4];
+    #pragma unroll
+                        for (int v = 0; v < 4; ++v) qi[v] = dot<NM>(u[v], p);
+                        if (!has) {
+                            // transmissive: the exterior trace is the interior one; reflective:
+                            // its normal momentum reversed, m - 2 (m.n) n
+                            const T mn2 = (T)-2.0 * fma(qi[1], nxu, qi[2] * nyu);
+                            qe[nu][0] = qi[0];
+                            qe[nu][1] = wall ? fma(mn2, nxu, qi[1]) : qi[1];
+                            qe[nu][2] = wall ? fma(mn2, nyu, qi[2]) : qi[2];
+                            qe[nu][3] = qi[3];
+                        }
+                        T iri, pi, ire, pe;
+                        euler_ip(qi, gm1, iri, pi);
+                        euler_ip(qe[nu], gm1, ire, pe);
+                        T fi[4], fe[4];
+                        euler_flux_n(qi, iri, pi, lnx, lny, fi);
+                        euler_flux_n(qe[nu], ire, pe, lnx, lny, fe);
+                        const T wsn = (T)R::ws[nu];
+    #pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const T d = qe[nu][v] - qi[v];
+                            const T fh = sgn * (wsn * ((T)0.5 * ((fi[v] + fe[v]) - sgn * (al * d))));
+                            r0[v] -= (double)fh;
+    #pragma unroll
+                            for (int l = 1; l < NM; ++l) r[v][l] = fma(-fh, p[l], r[v][l]);
+                        }
                     }
                 }
             }
@@ -1095,9 +1278,12 @@ template <int K, typename T>
 __global__ __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(OEDG_RES_WAVES))) void k_residual(
     StageArgs a) {
     if (!a.g->active || a.g->skip) return;
-    __shared__ MonoLds<K, T> L;
+    __shared__ EdgeRowsLds<K, T> er;
+    __shared__ TileLds<K, T, 5> L;
     __shared__ WaveAcc<kResCols> W;
-    residual_run<K, T, false>(a, 0, 0, L, W);
+    fill_edge_rows<K, T>(er);
+    __syncthreads();
+    residual_run<K, T, false>(a, 0, 0, er, L, W);
 }
 
 // Batched passes: workgroup b walks its XCD's range of the chunk table; each
@@ -1115,16 +1301,31 @@ __device__ __forceinline__ void for_each_chunk(const StageArgs* desc, const Chun
     }
 }
 
+// the tile image of a batched pass: one per degree present (KM: 1 P1, 2 P2, 3 both)
+template <int KM, typename T, int NG>
+union TileLdsKM {
+    typename std::conditional<(KM & 1) != 0, TileLds<1, T, NG>, char>::type p1;
+    typename std::conditional<(KM & 2) != 0, TileLds<2, T, NG>, char>::type p2;
+};
+
 template <int KM, typename T>
 __global__ __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(OEDG_RES_WAVES))) void k_residual_batch(
     const StageArgs* desc, const Chunk* chunks, ChunkSplit cs) {
-    __shared__ MonoLdsKM<KM, T> L;
+    // FP64: the monomial image (faster in the batched pass); mixed: the modal image,
+    // whose float traces keep the rounding within the limiter's margin
+    using Img = typename std::conditional<std::is_same<T, double>::value, MonoLdsKM<KM, T>, TileLdsKM<KM, T, 5>>::type;
+    __shared__ EdgeRowsLds<1, T> er1;
+    __shared__ EdgeRowsLds<2, T> er2;
+    __shared__ Img L;
     __shared__ WaveAcc<kResCols> W;
+    if constexpr (KM & 1) fill_edge_rows<1, T>(er1);
+    if constexpr (KM & 2) fill_edge_rows<2, T>(er2);
+    __syncthreads();
     for_each_chunk(desc, chunks, cs, [&](const StageArgs& a, int g0, int g1) {
-        if constexpr (KM == 1) residual_run<1, T, true>(a, g0, g1, L.p1, W);
-        else if constexpr (KM == 2) residual_run<2, T, true>(a, g0, g1, L.p2, W);
-        else if (a.k == 1) residual_run<1, T, true>(a, g0, g1, L.p1, W);
-        else residual_run<2, T, true>(a, g0, g1, L.p2, W);
+        if constexpr (KM == 1) residual_run<1, T, true>(a, g0, g1, er1, L.p1, W);
+        else if constexpr (KM == 2) residual_run<2, T, true>(a, g0, g1, er2, L.p2, W);
+        else if (a.k == 1) residual_run<1, T, true>(a, g0, g1, er1, L.p1, W);
+        else residual_run<2, T, true>(a, g0, g1, er2, L.p2, W);
     });
 }
 
