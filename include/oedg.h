@@ -188,8 +188,8 @@ dg_status dg_stage(dg_ctx* ctx, int s);
  * kernels in the same order, with the per-workgroup partial records of the two
  * domain reductions in a device array of the library instead of the context's
  * workspace.  Results are bit-identical to dg_stage.
- *   The array holds the records of at most 4096 workgroups per pass (24 doubles
- * each, 786,432 bytes per GPU); each GPU the library runs on keeps its own copy
+ *   The array holds the records of at most 4096 workgroups per pass (26 doubles
+ * each, 851,968 bytes per GPU); each GPU the library runs on keeps its own copy
  * until the process ends.  Its address is looked up once per device, at
  * dg_create (or at the first call on the device).  The passes size their grids
  * by occupancy, at most 4096 workgroups, so every mesh fits; a grid beyond the
@@ -236,6 +236,9 @@ typedef struct {
     double alpha_stage;           /* LF viscosity of the next stage's input (eq. 1250):
                                      alpha of u^n before stage 0, of the last stage
                                      output after stages 0 and 1 */
+    double min_rho_node;          /* min density over every limiter node (Sec. 4.4) of
+                                     the last stage output, evaluated in FP64 */
+    double min_p_node;            /* min pressure there */
 } dg_diag_t;
 
 /* Diagnostics of the context (synchronises). */

@@ -46,7 +46,8 @@ class DgDiag(ctypes.Structure):
     _fields_ = [("t", _c_d), ("dt", _c_d), ("alpha", _c_d), ("step", _c_i64),
                 ("n_limited", _c_i64), ("n_bad", _c_i64), ("n_cfl_excursions", _c_i64),
                 ("ubar", _c_d * 4), ("nrm", _c_d * 4), ("nrm_m", _c_d), ("active", _c_i),
-                ("n_flat", _c_i64), ("n_restarts", _c_i64), ("alpha_stage", _c_d)]
+                ("n_flat", _c_i64), ("n_restarts", _c_i64), ("alpha_stage", _c_d),
+                ("min_rho_node", _c_d), ("min_p_node", _c_d)]
 
 
 class DgError(RuntimeError):

@@ -675,6 +675,8 @@ dg_status dg_diag(dg_ctx* c, dg_diag_t* out) {
     out->n_flat = h.n_flat;
     out->n_restarts = h.n_restarts;
     out->alpha_stage = h.alpha;
+    out->min_rho_node = h.min_rho_node;
+    out->min_p_node = h.min_p_node;
     for (int v = 0; v < 4; ++v) {
         out->ubar[v] = h.ubar[v];
         out->nrm[v] = h.nrm[v];

@@ -1378,11 +1378,12 @@ __device__ __forceinline__ double internal_energy(const double (&q)[4]) {
 }
 
 // record of the filter pass: max wave speed, limited, bad and flattened counts,
-// sum |K| m1bar, sum |K| m2bar, the boundary momentum flux A_1, A_2, B_1, B_2
+// sum |K| m1bar, sum |K| m2bar, the boundary momentum flux A_1, A_2, B_1, B_2, and
+// the minimum density and pressure over the limiter nodes of the output
 constexpr int kFilCols = kFilterCols;
 static_assert(kNumPartial + 1 + kFilCols <= kPartCols && kColBad < kPartCols && kResCols == kNumPartial + 2,
               "record columns");
-__device__ constexpr int kFilOps[kFilCols] = {2, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+__device__ constexpr int kFilOps[kFilCols] = {2, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1};
 
 template <int K, typename T, bool kBatch>
 __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, MonoLds<K, T>& L,
@@ -1758,6 +1759,15 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
             const double ta = kMixed ? 1.0 : th2;
             const bool any_bnd = lk[0] < 0 || lk[1] < 0 || lk[2] < 0;
             double amax = 0.0;
+            // the output's density and pressure at every limiter node, for the diagnostics
+            double rmin_o = INFINITY, pmin_o = INFINITY;
+#pragma unroll
+            for (int t = 0; t < NP; ++t) {
+                const double q0 = fma(ta, pv[t][0] - ub0, ub0), q1 = fma(ta, pv[t][1] - ub1, ub1);
+                const double q2 = fma(ta, pv[t][2] - ub2, ub2), q3 = fma(ta, pv[t][3] - ub3, ub3);
+                rmin_o = fmin(rmin_o, q0);
+                pmin_o = fmin(pmin_o, (gamma - 1.0) * fma(-0.5 * frcp(q0), fma(q1, q1, q2 * q2), q3));
+            }
 #pragma unroll
             for (int t = 0; t < 3 * NE; ++t) {
                 const int i = t / NE, nu = t % NE;
@@ -1788,6 +1798,8 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
             part[0] = amax;
             part[4] = area_d * wa[1];
             part[5] = area_d * wa[2];
+            part[10] = rmin_o;
+            part[11] = pmin_o;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 op.put_a(v, c8, wa[v]);
@@ -1928,9 +1940,12 @@ __device__ __forceinline__ void fin_filter(const double* base, size_t cstride, i
         return;
     }
     double r[kFilterCols];
-    reduce_columns<kFilterCols>(base, cstride, G, kNumPartial + 1, 2u, r);   // max, then sums
+    // max, sums, then two minima
+    reduce_columns<kFilterCols>(base, cstride, G, kNumPartial + 1, 2u | (1u << 20) | (1u << 22), r);
     if (threadIdx.x != 0) return;
     const double alpha = r[0], lim = r[1], bad = r[2];
+    g->min_rho_node = r[10];
+    g->min_p_node = r[11];
     // the output's momentum bookkeeping; after the third stage (or the initial
     // limiter pass) the output is u^n
 #pragma unroll

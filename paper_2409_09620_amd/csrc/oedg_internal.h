@@ -18,7 +18,7 @@ constexpr int n_tiles_of(int n_cell) { return (n_cell + kTileCells - 1) / kTileC
 constexpr int kMaxBlocks = 4096;       // upper bound of a single-instance pass grid (= partials)
 constexpr int kGroupCells = 256;       // cells per reduction group of the batched passes
 constexpr int kNumPartial = 12;        // partials of the residual pass per group
-constexpr int kFilterCols = 10;        // partials of the filter pass per group
+constexpr int kFilterCols = 12;        // partials of the filter pass per group
 constexpr int kPartCols = kNumPartial + 1 + kFilterCols + 1;   // + momentum norm, filter, bad averages
 constexpr int kColBad = kPartCols - 1;   // residual pass: cells whose average left the admissible set
 
@@ -87,6 +87,8 @@ struct Glob {
     long long n_cfl_exc;
     long long n_flat;    // mixed precision: cells reset to their average by the rounding check
     long long n_restarts;   // steps retried with half the time step
+    double min_rho_node;    // min over the limiter nodes of the last stage output: density
+    double min_p_node;      // and pressure
     // Momentum bookkeeping that gives the residual pass the domain average of the
     // state it is about to write (see the residual kernel): sum_K |K| mbar_K of a
     // limited state, and the momentum flux through the boundary edges that the

@@ -36,8 +36,8 @@ import numpy as np
 
 from .binding import PRECISION, Batch, Solver, load_library
 
-# partial records of a batch: 24 doubles per 256-cell group
-_BATCH_BYTES_PER_CELL = 24 * 8 / 256.0
+# partial records of a batch: 26 doubles per 256-cell group
+_BATCH_BYTES_PER_CELL = 26 * 8 / 256.0
 
 
 def footprint_bytes(n_cell, k):

@@ -344,3 +344,28 @@ def test_strong_riemann_member_restarts_in_batch():
     say(f"member 34 after one restarted step: rel L1 {e:.2e}, oracle self-difference {max(sens):.1e}")
     assert max(sens) <= 1e-6
     assert e <= max(1e-11, 3.0 * max(sens))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_diag_node_minima(precision):
+    """dg_diag's min density and pressure over the limiter nodes of the last stage
+    output: positive on the near-vacuum blast, and the oracle's evaluation of the same
+    stored state at its limiter nodes gives the same minima (to the rounding of an
+    O(rho_bar) sum)."""
+    k, m, kind, p = CASES["p2_blast_3k"]()
+    say(f"[gpu case] node minima, blast {m.n_cell} cells, {precision}")
+    s = Solver(m, k)
+    s.init_problem(kind, p, precision=precision)
+    o = oracle.Oracle(m, k)
+    for st in range(3):
+        s.stage(st)
+        d = s.diag()
+        v = o.limiter_node_values(s.read_state(1))
+        rho = v[..., 0]
+        pr = 0.4 * (v[..., 3] - 0.5 * (v[..., 1] ** 2 + v[..., 2] ** 2) / rho)
+        scale_r, scale_p = np.abs(s.read_state(1)[0, 0]).max(), np.abs(s.read_state(1)[3, 0]).max()
+        say(f"  stage {st}: min rho {d['min_rho_node']:.6e} (oracle {rho.min():.6e}), "
+            f"min p {d['min_p_node']:.6e} (oracle {pr.min():.6e})")
+        assert d["min_rho_node"] > 0 and d["min_p_node"] > 0
+        assert abs(d["min_rho_node"] - rho.min()) <= 1e-14 * scale_r
+        assert abs(d["min_p_node"] - pr.min()) <= 1e-13 * scale_p
