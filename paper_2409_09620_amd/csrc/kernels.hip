@@ -601,7 +601,7 @@ __device__ __forceinline__ void nb_get(const TileLds<K, T, NG>& L, int ll, const
         load_cell<NM, T>(sv, cell, avg, u);
         geo_of<T, NG>(mv, (unsigned)cell * 8u, geo);
     } else {
-        const int s = ll >> 3;
+        const int s = (ll >> 3) & kLinkSlotMask;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             avg[v] = L.avg[v][s];
@@ -665,6 +665,19 @@ struct MonoLds {
     T c[4][NC][S];
     T d[4][S];
 };
+
+// whether the cell receives the filter's edge work of this link from its partner: an
+// in-tile edge that the partner owns (kLinkRecv is not a flag of global links, whose
+// neighbour index covers that bit)
+__device__ __forceinline__ bool link_recv(int ll) { return ll >= 0 && !(ll & kLinkGlobal) && (ll & kLinkRecv); }
+// The filter's OE records: the damping rates that a lane forms for a partner cell
+// (per variable, degree m - 1 and the partner's local edge, at the partner's slot),
+// written over the image once no lane reads it any more.
+template <int K, typename T>
+__device__ __forceinline__ T (&oe_records(MonoLds<K, T>& L))[4][K][3][kTileCells] {
+    static_assert(sizeof(T[4][K][3][kTileCells]) <= sizeof(MonoLds<K, T>), "records fit in the image");
+    return *reinterpret_cast<T(*)[4][K][3][kTileCells]>(&L);
+}
 
 // the filter's tile image of a batched pass: one per degree present
 template <int KM, typename T>
@@ -1073,7 +1086,7 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
                                 },
                                 dn);
                         } else {
-                            const int sl = ll >> 3;
+                            const int sl = (ll >> 3) & kLinkSlotMask;
                             T dn[4];
     #pragma unroll
                             for (int k2 = 0; k2 < 4; ++k2) dn[k2] = L.d[k2][sl];
@@ -1440,19 +1453,36 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
         double part[kFilCols];
 #pragma unroll
         for (int k = 0; k < kFilCols; ++k) part[k] = acc_ident(kFilOps[k]);
-        if (live) {
-            const T xx = geo[0], xy = geo[1], ex = geo[2], ey = geo[3];
-            const T area = (T)area_d;
-            T od[4];   // the cell's edge vectors: its edges' lengths and normals
-            edge_vectors(xx, xy, ex, ey, od);
+        const T xx = geo[0], xy = geo[1], ex = geo[2], ey = geo[3];
+        T od[4];   // the cell's edge vectors: its edges' lengths and normals
+        if (live) edge_vectors(xx, xy, ex, ey, od);
 
-            if (oe) {
-                T sig[4][K + 1];
+        // OE damping rates: ||.||^-1 acc[v][m - 1] = sum over the cell's edges of
+        // sum_{j <= m} beta/h delta^j (eq. OEScalar:Coef2; eqs. RIOESys:Coef1/Coef2),
+        // the rate of the degree-m modes of variable v
+        T acc[4][K];
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
+        for (int v = 0; v < 4; ++v)
 #pragma unroll
-                    for (int jj = 0; jj <= K; ++jj) sig[v][jj] = (T)0.0;
-                constexpr int NC = MonoLds<K, T>::NC;
+            for (int m = 0; m < K; ++m) acc[v][m] = (T)0.0;
+        if (oe) {
+            // Every edge inside the tile is worked once, by its owner (the other side
+            // carries kLinkRecv): beta and the jump energies are the same from either
+            // side (squares of jumps that change sign, a max over both sides), so the
+            // owner forms both cells' rates, each with its own h, and hands the other
+            // one its share through the tile's LDS once the image is no longer read.
+            // A cell owns at most two in-tile edges (records kept in registers) and
+            // every edge to a cell outside the tile.
+            constexpr int NC = MonoLds<K, T>::NC;
+            T rec[2][4][K];   // rates for the partners of this lane's in-tile edges
+            int rto[2] = {-1, -1};   // their record index: local edge * kTileCells + slot
+            if (live) {
+                const bool own0 = lk[0] >= 0 && !link_recv(lk[0]);
+                const bool own1 = lk[1] >= 0 && !link_recv(lk[1]);
+                const bool own2 = lk[2] >= 0 && !link_recv(lk[2]);
+                const int n_own = (int)own0 + (int)own1 + (int)own2;
+                const T area = (T)area_d;
+                const T i2a = F::rcp((T)2.0 * area);
                 // sum over both ends of the squared jumps of order j: j = 0 value, 1
                 // gradient; 2: the Hessian's jump, the same at both ends, weighted by
                 // C_2 = (1, 2, 1), i.e. 2 (jxx^2 + 2 jxy^2 + jyy^2)
@@ -1462,32 +1492,39 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
                     Sv[1] = fma(jx[0], jx[0], fma(jy[0], jy[0], fma(jx[1], jx[1], jy[1] * jy[1])));
                     if constexpr (K == 2) Sv[2] = (T)2.0 * fma(dh[0], dh[0], fma((T)2.0 * dh[1], dh[1], dh[2] * dh[2]));
                 };
-                // sigma^j += beta/h delta^j, delta^j = A^{k,j} h^j / ||.|| sqrt(S_j / 2)
-                auto accumulate = [&](const T (&Sv)[K + 1], T inv, T bh, T h, T (&sg)[K + 1])
-                                      __attribute__((always_inline)) {
-                    T hj = (T)1.0;
+                // delta^j = A^{k,j} h^j / ||.|| sqrt(S_j / 2); a side with h and beta/h = bh
+                // adds sum_{j <= m} bh delta^j to the rate of its degree-m modes (the
+                // factor 1/||.||, the same for every edge, is applied to the sums)
+                auto rates = [&](const T (&Sv)[K + 1], T bh, T h, T (&p)[K]) __attribute__((always_inline)) {
+                    T s = bh * ((T)kA[K][0] * F::sqrt((T)0.5 * Sv[0]));
+                    T hj = h;
 #pragma unroll
-                    for (int jj = 0; jj <= K; ++jj) {
-                        sg[jj] = fma(bh, (T)kA[K][jj] * hj * inv * F::sqrt((T)0.5 * Sv[jj]), sg[jj]);
+                    for (int jj = 1; jj <= K; ++jj) {
+                        s = fma(bh * hj, (T)kA[K][jj] * F::sqrt((T)0.5 * Sv[jj]), s);
+                        p[jj - 1] = s;
                         hj *= h;
                     }
                 };
+                int nrec = 0;
 #pragma unroll 1
-                for (int i = 0; i < 3; ++i) {
+                for (int r = 0; r < n_own; ++r) {
+                    // this lane's r-th owned edge
+                    const int i = r == 0 ? (own0 ? 0 : (own1 ? 1 : 2)) : ((r == 1 && own0 && own1) ? 1 : 2);
                     const int ll = i == 0 ? lk[0] : (i == 1 ? lk[1] : lk[2]);
-                    if (ll < 0) continue;   // boundary edge: zero jump
                     const int j = ll & 3;
                     T nx, ny, len;
                     edge_normal(od, i, nx, ny, len);
-                    const T h = (T)2.0 * area * F::rcp(len);   // h_K^(i) = 2|K| / l_i
+                    const T il = F::rcp(len);
+                    const T h = (T)2.0 * area * il, bh_len = len * i2a;   // h_K^(i) = 2|K| / l_i; 1/h = l_i / (2|K|)
                     // The edge's work, with the neighbour's coefficients from the image
                     // or (beyond the halo cap) converted from global memory: two copies of
                     // the code, so that the rare path costs the common one no registers.
-                    auto edge = [&](auto&& nbc, const T (&dn)[4]) __attribute__((always_inline)) {
+                    // partner: the neighbour is a tile cell, whose rates are formed here too
+                    auto edge = [&](auto&& nbc, const T (&dn)[4], bool partner) __attribute__((always_inline)) {
                         // the edge's two ends: own vertex i+1, then i+2, meets the
                         // neighbour's vertex j+2, then j+1
                         T Po[2][2], Pn[2][2];
-    #pragma unroll
+#pragma unroll
                         for (int e = 0; e < 2; ++e) {
                             vertex_point(od, (i + 1 + e) % 3, Po[e]);
                             vertex_point(dn, (j + 2 - e) % 3, Pn[e]);
@@ -1497,31 +1534,39 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
                         T beta = (T)0.0;
                         {
                             T qo[2][4], qn[2][4];
-    #pragma unroll
+#pragma unroll
                             for (int v = 0; v < 4; ++v) {
                                 T co[NC], cn[NC];
-    #pragma unroll
+#pragma unroll
                                 for (int k2 = 0; k2 < NC; ++k2) co[k2] = L.c[v][k2][threadIdx.x];
+                                const T oa = kMixed ? (T)L.avg[kMixed ? v : 0][kMixed ? threadIdx.x : 0] : (T)0.0;
                                 double na;
                                 nbc(v, na, cn);
-    #pragma unroll
+#pragma unroll
                                 for (int e = 0; e < 2; ++e) {
                                     T vo, vn, g0, g1;
                                     mono_at<K, T>(co, Po[e], vo, g0, g1);
                                     mono_at<K, T>(cn, Pn[e], vn, g0, g1);
-                                    qo[e][v] = kMixed ? w[v][0] + vo : vo;
+                                    qo[e][v] = kMixed ? oa + vo : vo;
                                     qn[e][v] = kMixed ? (T)na + vn : vn;
                                 }
                                 // one variable's coefficients in registers at a time
                                 asm volatile("" ::: "memory");
                             }
-    #pragma unroll
+#pragma unroll
                             for (int e = 0; e < 2; ++e)
                                 beta = fmax(beta,
                                             fmax(spectral_radius(qo[e][0], qo[e][1], qo[e][2], qo[e][3], nx, ny, gammaT),
                                                  spectral_radius(qn[e][0], qn[e][1], qn[e][2], qn[e][3], nx, ny, gammaT)));
                         }
-                        const T bh = F::div(beta, h);
+                        const T bh = beta * bh_len;
+                        // the neighbour's side: h = 2|N| / l_i, 2|N| = d1 x d2 of its edge vectors
+                        T hn = (T)0.0, bhn = (T)0.0;
+                        if (partner) {
+                            const T a2 = fma(dn[0], dn[3], -(dn[1] * dn[2]));
+                            hn = a2 * il;
+                            bhn = beta * len * F::rcp(a2);
+                        }
                         // the coefficients are read again below rather than kept from above
                         asm volatile("" ::: "memory");
                         // Jumps (neighbour minus own) of variable v's value and physical
@@ -1529,17 +1574,17 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
                         auto jumps = [&](int v, T (&jv)[2], T (&jx)[2], T (&jy)[2], T (&dh)[3])
                                          __attribute__((always_inline)) {
                             T co[NC], cn[NC];
-    #pragma unroll
+#pragma unroll
                             for (int k2 = 0; k2 < NC; ++k2) co[k2] = L.c[v][k2][threadIdx.x];
                             double na;
                             nbc(v, na, cn);
-    #pragma unroll
+#pragma unroll
                             for (int e = 0; e < 2; ++e) {
                                 T vo, gxo, gyo, vn, gxn, gyn;
                                 mono_at<K, T>(co, Po[e], vo, gxo, gyo);
                                 mono_at<K, T>(cn, Pn[e], vn, gxn, gyn);
                                 // mixed: the FP64 difference of averages plus the float one of the rest
-                                if constexpr (kMixed) jv[e] = (T)(na - wa[v]) + (vn - vo);
+                                if constexpr (kMixed) jv[e] = (T)(na - L.avg[kMixed ? v : 0][kMixed ? threadIdx.x : 0]) + (vn - vo);
                                 else jv[e] = vn - vo;
                                 jx[e] = gxn - gxo;
                                 jy[e] = gyn - gyo;
@@ -1551,14 +1596,26 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
                                 dh[2] = (T)2.0 * (cn[5] - co[5]);
                             }
                         };
+                        T pn[4][K];   // the partner's rates from this edge
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+#pragma unroll
+                            for (int m = 0; m < K; ++m) pn[v][m] = (T)0.0;
+                        auto both = [&](int v, const T (&Sv)[K + 1]) __attribute__((always_inline)) {
+                            T p[K];
+                            rates(Sv, bh, h, p);
+#pragma unroll
+                            for (int m = 0; m < K; ++m) acc[v][m] += p[m];
+                            if (partner) rates(Sv, bhn, hn, pn[v]);
+                        };
                         {
                             T jv[2], jx[2], jy[2], dh[3], Sv[K + 1];
                             jumps(0, jv, jx, jy, dh);
                             energies(jv, jx, jy, dh, Sv);
-                            accumulate(Sv, inv0, bh, h, sig[0]);
+                            both(0, Sv);
                             jumps(3, jv, jx, jy, dh);
                             energies(jv, jx, jy, dh, Sv);
-                            accumulate(Sv, inv3, bh, h, sig[3]);
+                            both(3, Sv);
                         }
                         asm volatile("" ::: "memory");
                         {
@@ -1574,27 +1631,40 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
                                 a1 = b1;
                                 a2 = b2;
                             };
-    #pragma unroll
+#pragma unroll
                             for (int e = 0; e < 2; ++e) {
                                 rot(jv1[e], jv2[e]);
                                 rot(jx1[e], jx2[e]);
                                 rot(jy1[e], jy2[e]);
                             }
                             if constexpr (K == 2) {
-    #pragma unroll
+#pragma unroll
                                 for (int k2 = 0; k2 < 3; ++k2) rot(dh1[k2], dh2[k2]);
                             }
                             T S1[K + 1], S2[K + 1];
                             energies(jv1, jx1, jy1, dh1, S1);
                             energies(jv2, jx2, jy2, dh2, S2);
                             if (ri) {
-    #pragma unroll
+#pragma unroll
                                 for (int jj = 0; jj <= K; ++jj) S1[jj] = fmax(S1[jj], S2[jj]);
-                                accumulate(S1, inv1, bh, h, sig[1]);
-                            } else {
-                                accumulate(S1, inv1, bh, h, sig[1]);
-                                accumulate(S2, inv2, bh, h, sig[2]);
                             }
+                            both(1, S1);
+                            if (!ri) both(2, S2);
+                        }
+                        if (partner) {
+                            // kept for the partner (at most two per lane, by the edge orientation)
+                            const bool r0 = nrec == 0;
+#pragma unroll
+                            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                                for (int m = 0; m < K; ++m) {
+                                    rec[0][v][m] = r0 ? pn[v][m] : rec[0][v][m];
+                                    rec[1][v][m] = r0 ? rec[1][v][m] : pn[v][m];
+                                }
+                            const int to = j * kTileCells + ((ll >> 3) & kLinkSlotMask);
+                            rto[0] = r0 ? to : rto[0];
+                            rto[1] = r0 ? rto[1] : to;
+                            ++nrec;
                         }
                     };
                     if (ll & kLinkGlobal) {
@@ -1612,9 +1682,9 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
                                 for (int l = 1; l < NM; ++l) u[l] = wp.h(v, l, nT);
                                 to_mono<K, T>(u, nxx, nxy, nex, ney, !kMixed, cn);
                             },
-                            dn);
+                            dn, false);
                     } else {
-                        const int sl = ll >> 3;
+                        const int sl = (ll >> 3) & kLinkSlotMask;
                         T dn[4];
 #pragma unroll
                         for (int k2 = 0; k2 < 4; ++k2) dn[k2] = L.d[k2][sl];
@@ -1624,22 +1694,55 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
 #pragma unroll
                                 for (int k2 = 0; k2 < NC; ++k2) cn[k2] = L.c[v][k2][sl];
                             },
-                            dn);
+                            dn, sl < kTileCells);
                     }
                 }
+            }
+            // the state again (from cache; not kept in registers through the edge work),
+            // in flight while the partners' shares go through LDS
+            if (live) load_cell<NM, T>(wp, c, wa, w);
+            // the partners' shares: written over the image once every lane is done with it
+            T (&R)[4][K][3][kTileCells] = oe_records<K, T>(L);
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                if (rto[q] >= 0) {
+                    const int e = rto[q] / kTileCells, s = rto[q] % kTileCells;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        if (ri && v == 2) continue;   // RIOE: m_2's rates are m_1's
+#pragma unroll
+                        for (int m = 0; m < K; ++m) R[v][m][e][s] = rec[q][v][m];
+                    }
+                }
+            __syncthreads();
+            if (live) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    if (link_recv(lk[i])) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            if (ri && v == 2) continue;
+#pragma unroll
+                            for (int m = 0; m < K; ++m) acc[v][m] += R[v][m][i][threadIdx.x];
+                        }
+                    }
                 if (ri) {
 #pragma unroll
-                    for (int jj = 0; jj <= K; ++jj) sig[2][jj] = sig[1][jj];
+                    for (int m = 0; m < K; ++m) acc[2][m] = acc[1][m];
                 }
+            }
+        }
+        if (live) {
+            if (oe) {
                 // exact solution of the damping ODE: degree-m modes scaled by
                 // exp(-dt sum_{j<=m} sigma^j); the cell average is untouched (eq. OE:m0)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    T acc = sig[v][0];
+                    const T inv = v == 0 ? inv0 : (v == 1 ? inv1 : (v == 2 ? inv2 : inv3));
 #pragma unroll
                     for (int m = 1; m <= K; ++m) {
-                        acc += sig[v][m];
-                        const T fct = F::exp(-dt * acc);
+                        const T fct = F::exp(-dt * (inv * acc[v][m - 1]));
 #pragma unroll
                         for (int l = m * (m + 1) / 2; l < (m + 1) * (m + 2) / 2; ++l) w[v][l] *= fct;
                     }

@@ -31,6 +31,77 @@ struct HalfEdge {
     int32_t edge;
 };
 
+// Which cell of each interior edge inside a tile does the filter's edge work (the
+// "owner"; the other one receives its share through the tile's LDS).  A cell owns
+// every edge to a neighbour outside the tile, and the in-tile edges are oriented so
+// that a cell owns at most two edges where the forced ones allow it (the lanes of a
+// wave then run two rounds of edge work instead of three) and at most two in-tile
+// edges in any case (what a lane keeps in registers for its partners).  Start: the
+// lower index owns; then, while a cell is over a bound, reverse a shortest path of
+// owned in-tile edges from it to a cell under the bound (one edge less at the start,
+// one more at the end, the same in between).  Every subgraph of a mesh of triangles
+// has at most 3/2 edges per cell, so two per cell is always reachable for the in-tile
+// edges (Hakimi's orientation theorem).  own[3 * (c - c0) + i] = 1 when cell c owns
+// its local edge i (i an in-tile edge); deterministic for a given mesh.
+void orient_tile(const std::vector<int32_t>& nbr, size_t c0, size_t c1, std::vector<uint8_t>& own) {
+    const size_t n = c1 - c0;
+    own.assign(3 * n, 0);
+    std::vector<int> out(n, 0), in_tile(n, 0);
+    auto inside = [&](int32_t x) { return x >= 0 && (size_t)x >= c0 && (size_t)x < c1; };
+    for (size_t c = 0; c < n; ++c)
+        for (int i = 0; i < 3; ++i) {
+            const int32_t x = nbr[3 * (c0 + c) + i];
+            if (x < 0) continue;
+            if (!inside(x)) {
+                ++out[c];
+            } else if (c0 + c < (size_t)x) {
+                own[3 * c + i] = 1;
+                ++out[c];
+                ++in_tile[c];
+            }
+        }
+    std::vector<int> prev_cell(n), prev_edge(n), queue;
+    std::vector<char> seen(n);
+    // cnt: the count to bring down to `cap`
+    auto reduce = [&](std::vector<int>& cnt, int cap) {
+        for (size_t s = 0; s < n; ++s) {
+            while (cnt[s] > cap) {
+                std::fill(seen.begin(), seen.end(), 0);
+                queue.assign(1, (int)s);
+                seen[s] = 1;
+                int found = -1;
+                for (size_t q = 0; q < queue.size() && found < 0; ++q) {
+                    const int u = queue[q];
+                    for (int i = 0; i < 3 && found < 0; ++i) {
+                        if (!own[3 * u + i]) continue;
+                        const int v = nbr[3 * (c0 + u) + i] - (int)c0;
+                        if (seen[v]) continue;
+                        seen[v] = 1;
+                        prev_cell[v] = u;
+                        prev_edge[v] = i;
+                        queue.push_back(v);
+                        if (cnt[v] < cap) found = v;
+                    }
+                }
+                if (found < 0) break;
+                for (int v = found; v != (int)s;) {
+                    const int u = prev_cell[v], i = prev_edge[v];
+                    own[3 * u + i] = 0;
+                    for (int j = 0; j < 3; ++j)
+                        if (nbr[3 * (c0 + v) + j] == (int32_t)(c0 + u)) own[3 * v + j] = 1;
+                    v = u;
+                }
+                --out[s];
+                --in_tile[s];
+                ++out[found];
+                ++in_tile[found];
+            }
+        }
+    };
+    reduce(out, 2);
+    reduce(in_tile, 2);
+}
+
 // barycentric coordinates of the two P2 internal nodes, in the sorted labelling
 void p2_nodes(double l1, double l2, double l3, double beta[2][3], double* cdcw) {
     const double s3 = std::sqrt(3.0);
@@ -164,6 +235,7 @@ int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const in
         m.halo_cell.clear();
         m.llink.assign(3 * nc, 0);
         std::vector<int32_t> halo;
+        std::vector<uint8_t> own;
         for (size_t t = 0; t < n_tiles; ++t) {
             const size_t c0 = t * kTileCells, c1 = std::min(nc, c0 + kTileCells);
             halo.clear();
@@ -177,6 +249,7 @@ int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const in
             if (halo.size() > (size_t)kHaloCap) halo.resize(kHaloCap);
             m.halo_cell.insert(m.halo_cell.end(), halo.begin(), halo.end());
             m.halo_ptr[t + 1] = (int32_t)m.halo_cell.size();
+            orient_tile(m.nbr, c0, c1, own);
             for (size_t c = c0; c < c1; ++c)
                 for (int i = 0; i < 3; ++i) {
                     const int32_t nb = m.nbr[3 * c + i];
@@ -184,7 +257,7 @@ int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const in
                     if (nb >= 0) {
                         const int32_t tag = ((size_t)nb < c ? 0 : 4) | m.nbe[3 * c + i];
                         if ((size_t)nb >= c0 && (size_t)nb < c1) {
-                            v = ((int32_t)(nb - c0) << 3) | tag;
+                            v = ((int32_t)(nb - c0) << 3) | tag | (own[3 * (c - c0) + i] ? 0 : kLinkRecv);
                         } else {
                             const auto it = std::lower_bound(halo.begin(), halo.end(), nb);
                             if (it != halo.end() && *it == nb)
@@ -195,6 +268,20 @@ int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const in
                     }
                     m.llink[i * nc + c] = v;
                 }
+            // every in-tile edge has exactly one owner, and no cell keeps more than two
+            // records for partners (the filter's registers)
+            for (size_t c = c0; c < c1; ++c) {
+                int kept = 0;
+                for (int i = 0; i < 3; ++i) {
+                    const int32_t nb = m.nbr[3 * c + i];
+                    if (nb < 0 || (size_t)nb < c0 || (size_t)nb >= c1) continue;
+                    const bool recv = (m.llink[i * nc + c] & kLinkRecv) != 0;
+                    const bool recv_nb = (m.llink[m.nbe[3 * c + i] * nc + (size_t)nb] & kLinkRecv) != 0;
+                    if (recv == recv_nb) { err = "internal: edge orientation"; return -1; }
+                    kept += recv ? 0 : 1;
+                }
+                if (kept > 2) { err = "internal: edge orientation"; return -1; }
+            }
         }
     }
 

@@ -56,10 +56,15 @@ constexpr int32_t kLinkOpen = -1;
 constexpr int32_t kLinkWall = -2;
 // llink of an interior edge: (slot << 3) | (low << 2) | nbe, slot the neighbour's LDS
 // slot in the tile image (its offset in the tile, or kTileCells + its halo index),
-// low = 1 when this cell's index is below the neighbour's.  A neighbour beyond the
-// halo cap is read from global memory: kLinkGlobal | (nbr << 3) | (low << 2) | nbe.
-// Boundary edges carry kLinkOpen / kLinkWall.
+// low = 1 when this cell's index is below the neighbour's; an edge inside the tile
+// also carries kLinkRecv on the side that does not own it (the filter's edge work is
+// done once, by the owner).  A neighbour beyond the halo cap is read from global
+// memory: kLinkGlobal | (nbr << 3) | (low << 2) | nbe.  Boundary edges carry
+// kLinkOpen / kLinkWall.
 constexpr int32_t kLinkGlobal = 1 << 30;
+constexpr int32_t kLinkRecv = 1 << 12;
+constexpr int32_t kLinkSlotMask = 0x1FF;   // (llink >> 3) & mask: the slot of a link without kLinkGlobal
+static_assert(kTileCells + kHaloCap <= kLinkSlotMask + 1, "slots fit below kLinkRecv");
 
 int build_mesh(int k, int32_t n_vert, const double* xy, int32_t n_cell, const int32_t* tri,
                const double* cell_xy, const int32_t* edge_bc, HostMesh& m, std::string& err);

@@ -84,6 +84,19 @@ def hilbert_order(points: np.ndarray, order: int = 16) -> np.ndarray:
     return np.argsort(d, kind="stable")
 
 
+def shuffle_cells(mesh: Mesh, seed: int) -> Mesh:
+    """The same mesh with its cells in a seeded random order (vertex ids and each
+    cell's vertex order kept).  Without locality most of a tile's neighbours fall
+    outside its halo, which exercises the stage kernels' global-memory path."""
+    keys = Stream(seed).bits(mesh.n_cell)
+    p = np.argsort(keys, kind="stable")
+    return Mesh(xy=mesh.xy, tri=np.ascontiguousarray(mesh.tri[p]),
+                cell_xy=None if mesh.cell_xy is None else np.ascontiguousarray(mesh.cell_xy[p]),
+                periodic=mesh.periodic,
+                edge_bc=None if mesh.edge_bc is None else np.ascontiguousarray(mesh.edge_bc[p]),
+                name=mesh.name + "_shuffled", meta=dict(mesh.meta))
+
+
 # --------------------------------------------------------------------------- periodic grid
 
 def periodic_jittered_grid(n: int = 32, length: float = 10.0, jitter: float = 0.1,

@@ -183,3 +183,19 @@ def test_library_loads_after_torch_in_a_fresh_process():
             "assert len(hip) == 1 and 'torch' in next(iter(hip)), hip\n" % root)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
+
+
+@pytest.mark.parametrize("maker", ["quadrant", "periodic"])
+def test_host_precompute_on_many_tiles(maker):
+    """The precompute of a mesh of many 256-cell tiles: the library checks its own
+    tables as it builds them (each edge inside a tile owned by exactly one of its two
+    cells for the filter's edge work, at most two owned inside the tile per cell) and
+    fails the upload if they do not hold; the integer tables still match the oracle."""
+    if maker == "quadrant":
+        m = workloads.quadrant_delaunay(20_000)[0]
+    else:
+        m = smesh.periodic_jittered_grid(n=64, seed=9)
+    lib = pkg.host_mesh_tables(m, 2)
+    o = oracle.Oracle(m, 2).mesh_arrays()
+    for key in ("nbr", "nbe"):
+        assert np.array_equal(lib[key], o[key]), key

@@ -52,7 +52,15 @@ CASES = {
     "p2_blast_3k": lambda: (2,) + workloads.blast_delaunay(n_cells=3000, seed=23),
     "p2_two_state_2k": lambda: (2, smesh.poisson_delaunay(2100, seed=24), problems.PROBLEM_TWO_STATE,
                                 problems.two_state_params(24)),
+    # cells in random order: most neighbours beyond the tiles' halo cap (global-memory path)
+    "p2_quadrant_3k_shuffled": lambda: _shuffled(2, workloads.quadrant_delaunay(n_cells=3000, seed=21), 31),
+    "p1_blast_3k_shuffled": lambda: _shuffled(1, workloads.blast_delaunay(n_cells=3000, seed=23), 32),
 }
+
+
+def _shuffled(k, w, seed):
+    m, kind, p = w
+    return (k, smesh.shuffle_cells(m, seed), kind, p)
 
 
 def make(case, **cfg):
