@@ -810,12 +810,18 @@ __device__ __forceinline__ void wave_acc_reset(WaveAcc<NC>& W, const int (&ops)[
         for (int k = 0; k < NC; ++k) W.x[threadIdx.x >> 6][k] = acc_ident(ops[k]);
     }
 }
+// A sum column that is zero in every lane (counts and boundary fluxes, mostly) skips
+// its reduction.
 template <int NC>
 __device__ __forceinline__ void wave_acc_add(WaveAcc<NC>& W, const int (&ops)[NC], const double (&val)[NC]) {
     double r[NC];
 #pragma unroll
-    for (int k = 0; k < NC; ++k)
-        r[k] = ops[k] == 0 ? wave_sum(val[k]) : (ops[k] == 1 ? wave_min(val[k]) : wave_max(val[k]));
+    for (int k = 0; k < NC; ++k) {
+        if (ops[k] == 0)
+            r[k] = __builtin_amdgcn_ballot_w64(val[k] != 0.0) != 0 ? wave_sum(val[k]) : 0.0;
+        else
+            r[k] = ops[k] == 1 ? wave_min(val[k]) : wave_max(val[k]);
+    }
     if ((threadIdx.x & 63) == 0) {
         const int w = threadIdx.x >> 6;
 #pragma unroll
@@ -1862,30 +1868,31 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
             const double ta = kMixed ? 1.0 : th2;
             const bool any_bnd = lk[0] < 0 || lk[1] < 0 || lk[2] < 0;
             double amax = 0.0;
-            // the output's density and pressure at every limiter node, for the diagnostics
+            // the output's density and pressure at every limiter node, for the diagnostics;
+            // at the edge points the same 1/rho and p serve the wave speed and the flux
             double rmin_o = INFINITY, pmin_o = INFINITY;
 #pragma unroll
             for (int t = 0; t < NP; ++t) {
                 const double q0 = fma(ta, pv[t][0] - ub0, ub0), q1 = fma(ta, pv[t][1] - ub1, ub1);
                 const double q2 = fma(ta, pv[t][2] - ub2, ub2), q3 = fma(ta, pv[t][3] - ub3, ub3);
+                const double ir = frcp(q0), mm = fma(q1, q1, q2 * q2);
+                const double p = (gamma - 1.0) * fma(-0.5 * ir, mm, q3);
                 rmin_o = fmin(rmin_o, q0);
-                pmin_o = fmin(pmin_o, (gamma - 1.0) * fma(-0.5 * frcp(q0), fma(q1, q1, q2 * q2), q3));
-            }
-#pragma unroll
-            for (int t = 0; t < 3 * NE; ++t) {
+                pmin_o = fmin(pmin_o, p);
+                if (t >= 3 * NE) continue;   // the two inner nodes
                 const int i = t / NE, nu = t % NE;
                 T nxT, nyT, lenT;
                 edge_normal(od, i, nxT, nyT, lenT);
                 const double nx = (double)nxT, ny = (double)nyT;
-                const double q0 = fma(ta, pv[t][0] - ub0, ub0), q1 = fma(ta, pv[t][1] - ub1, ub1);
-                const double q2 = fma(ta, pv[t][2] - ub2, ub2), q3 = fma(ta, pv[t][3] - ub3, ub3);
-                const double rr = spectral_radius(q0, q1, q2, q3, nx, ny, gamma);
+                const double mn = fma(q1, nx, q2 * ny);
+                // |v.n| + c, guarded below the floor as spectral_radius is
+                const bool ok = q0 >= kEpsBP;
+                const double irs = ok ? ir : 1.0 / kEpsBP;
+                const double ps = ok ? p : (gamma - 1.0) * fma(-0.5 * irs, mm, q3);
+                const double rr = fma(fabs(mn), irs, fsqrt(gamma * fmax(ps, 0.0) * irs));
                 amax = (rr > amax || rr != rr) ? rr : amax;
                 if (any_bnd && lk[i] < 0) {
                     const double lw = (double)lenT * R::ws[nu];
-                    const double ir = frcp(q0);
-                    const double mn = fma(q1, nx, q2 * ny);
-                    const double p = (gamma - 1.0) * fma(-0.5 * ir, fma(q1, q1, q2 * q2), q3);
                     if (lk[i] == kLinkWall) {
                         const double ca = lw * fma(mn * mn, ir, p), cb = lw * mn;
                         part[6] = fma(ca, nx, part[6]);
