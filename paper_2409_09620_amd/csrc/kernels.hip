@@ -23,11 +23,16 @@
 // its halo of out-of-tile neighbours in LDS before computing it.  The residual's
 // image holds every cell's averages, modes and geometry, from which a neighbour's
 // traces at the edge Gauss points are formed with the basis rows of its local
-// edge.  The filter's image holds every cell's polynomial as physical monomials
-// about its vertex 0 plus the two edge vectors from that vertex, so a neighbour's
-// value, gradient and Hessian at a shared vertex cost a few FMAs.  Workgroups
-// are spread so that each XCD walks a contiguous range of the tiles, which keeps
-// neighbour gathers inside that XCD's L2.
+// edge (the batched FP64 pass uses the filter's image instead).  The filter's
+// image holds every cell's polynomial as physical monomials about its vertex 0
+// plus the two edge vectors from that vertex, so a neighbour's value, gradient
+// and Hessian at a shared vertex cost a few FMAs.  The filter works every edge
+// inside a tile once: the mesh precompute makes one cell of it the owner (at most
+// two in-tile edges per cell, and in most waves at most two edges of any kind per
+// lane), and the owner hands the other cell its damping rates through LDS once
+// the image is no longer read.  Workgroups are spread so that each XCD walks a
+// contiguous range of the tiles, which keeps neighbour gathers inside that XCD's
+// L2.
 //
 // Edge fluxes are conservative to the last bit: both cells of an interior edge
 // evaluate its LF flux from the same two traces (each cell's trace computed by the
