@@ -1319,7 +1319,15 @@ __device__ __forceinline__ void for_each_chunk(const StageArgs* desc, const Chun
     const TileWalk w = chunk_walk(cs);
     for (int ci = w.first; ci < w.end; ci += w.stride) {
         const Chunk ch = chunks[ci];
-        const StageArgs& a = desc[ch.inst];
+        // read as constant memory (as a kernel's own arguments are): the compiler may
+        // load a field again where it would otherwise keep it in registers or spill it
+        typedef const __attribute__((address_space(4))) unsigned ConstWord;
+        static_assert(sizeof(StageArgs) % 4 == 0, "whole words");
+        StageArgs a;
+        ConstWord* src = (ConstWord*)(desc + ch.inst);
+        unsigned* dst = reinterpret_cast<unsigned*>(&a);
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(StageArgs) / 4); ++i) dst[i] = src[i];
         if (!a.g->active || a.g->skip) continue;
         run(a, ch.g0, ch.g1);
     }

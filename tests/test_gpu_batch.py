@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+from synth import mesh as smesh
 from synth import workloads
 
 torch = pytest.importorskip("torch")
@@ -41,7 +42,15 @@ MEMBERS = {
     "p2_vortex": lambda: (2,) + workloads.periodic_vortex(n=10),
     "p2_two_state_1k": lambda: (2,) + workloads.batch_instance(3, 1000),
     "p1_two_state_700": lambda: (1,) + workloads.batch_instance(4, 700),
+    # cells in random order: most neighbours beyond the tiles' halo cap (global-memory path)
+    "p2_quadrant_3k_shuffled": lambda: _shuffled(2, workloads.quadrant_delaunay(n_cells=3000, seed=21), 33),
+    "p1_quadrant_2k_shuffled": lambda: _shuffled(1, workloads.quadrant_delaunay(n_cells=2000, seed=22), 34),
 }
+
+
+def _shuffled(k, w, seed):
+    m, kind, p = w
+    return (k, smesh.shuffle_cells(m, seed), kind, p)
 _CACHE = {}
 
 
@@ -54,8 +63,9 @@ def member(name, precision="fp64"):
     return s
 
 
-def test_members_match_oracle():
-    names = ["p2_quadrant_3k", "p1_quadrant_2k", "p1_vortex", "p2_vortex"]
+@pytest.mark.parametrize("names", [["p2_quadrant_3k", "p1_quadrant_2k", "p1_vortex", "p2_vortex"],
+                                   ["p2_quadrant_3k_shuffled", "p1_quadrant_2k_shuffled", "p2_vortex"]])
+def test_members_match_oracle(names):
     say(f"[gpu case] batch of {names}")
     sols = [member(n) for n in names]
     b = Batch(sols)
@@ -92,7 +102,7 @@ def test_alone_and_in_mix_bitwise():
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_schedule_does_not_change_results(precision):
-    names = ["p2_quadrant_3k", "p1_quadrant_2k", "p2_two_state_1k"]
+    names = ["p2_quadrant_3k", "p1_quadrant_2k", "p2_two_state_1k", "p2_quadrant_3k_shuffled"]
     ref = None
     for cg, occ in ((1, 100), (8, 100), (3, 50), (16, 25)):
         sols = [member(n, precision) for n in names]
@@ -109,10 +119,10 @@ def test_schedule_does_not_change_results(precision):
                 assert np.array_equal(x, y), (n, cg, occ)
 
 
-def test_batch_matches_single_instance_path():
+@pytest.mark.parametrize("n", ["p2_quadrant_3k", "p1_quadrant_2k_shuffled"])
+def test_batch_matches_single_instance_path(n):
     """dg_step groups its reductions per workgroup, the batch per 256 cells: the two
     agree to round-off."""
-    n = "p2_quadrant_3k"
     a, b_ = member(n), member(n)
     for _ in range(5):
         a.step()
