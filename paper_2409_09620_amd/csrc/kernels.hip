@@ -799,26 +799,28 @@ __device__ __forceinline__ void halo_put(MonoLds<K, T>& L, const HaloCell<K, T>&
 // Running reductions of a pass workgroup over its tiles: after each tile every wave
 // reduces its lanes' contributions (one cell each) and lane 0 combines the result
 // into its wave's entry; the flush combines the waves in order.  op(k): 0 sum,
-// 1 min, 2 max.
+// 1 min, 2 max.  Two sets of entries, used by alternate tiles of a batched pass
+// (each tile is a group with a record of its own): a set is reset again two tiles
+// later, after a barrier that every wave reaches only once the flush has read it.
 template <int NC>
 struct WaveAcc {
-    double x[kPassThreads / 64][NC];
+    double x[2][kPassThreads / 64][NC];
 };
 __device__ __forceinline__ double acc_op(int op, double a, double b) {
     return op == 0 ? a + b : (op == 1 ? fmin(a, b) : fmax(a, b));
 }
 __device__ __forceinline__ double acc_ident(int op) { return op == 0 ? 0.0 : (op == 1 ? INFINITY : -INFINITY); }
 template <int NC>
-__device__ __forceinline__ void wave_acc_reset(WaveAcc<NC>& W, const int (&ops)[NC]) {
+__device__ __forceinline__ void wave_acc_reset(WaveAcc<NC>& W, const int (&ops)[NC], int par) {
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-        for (int k = 0; k < NC; ++k) W.x[threadIdx.x >> 6][k] = acc_ident(ops[k]);
+        for (int k = 0; k < NC; ++k) W.x[par][threadIdx.x >> 6][k] = acc_ident(ops[k]);
     }
 }
 // A sum column that is zero in every lane (counts and boundary fluxes, mostly) skips
 // its reduction.
 template <int NC>
-__device__ __forceinline__ void wave_acc_add(WaveAcc<NC>& W, const int (&ops)[NC], const double (&val)[NC]) {
+__device__ __forceinline__ void wave_acc_add(WaveAcc<NC>& W, const int (&ops)[NC], const double (&val)[NC], int par) {
     double r[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
@@ -830,16 +832,17 @@ __device__ __forceinline__ void wave_acc_add(WaveAcc<NC>& W, const int (&ops)[NC
     if ((threadIdx.x & 63) == 0) {
         const int w = threadIdx.x >> 6;
 #pragma unroll
-        for (int k = 0; k < NC; ++k) W.x[w][k] = acc_op(ops[k], W.x[w][k], r[k]);
+        for (int k = 0; k < NC; ++k) W.x[par][w][k] = acc_op(ops[k], W.x[par][w][k], r[k]);
     }
 }
 // Writes entry k of the record to dst[col[k] * stride], dst the record's column 0
-// and col[k] < kPartCols the absolute column (call with every thread; synchronises
-// the workgroup first).
+// and col[k] < kPartCols the absolute column (call with every thread).  sync: the
+// workgroup synchronises before (the entries are complete) and after (they may be
+// reset); a batched pass's tile already ends with a barrier and alternates sets.
 template <int NC>
 __device__ __forceinline__ void wave_acc_flush(const WaveAcc<NC>& W, const int (&ops)[NC], const int (&col)[NC],
-                                               double* dst, size_t stride) {
-    __syncthreads();
+                                               double* dst, size_t stride, int par, bool sync) {
+    if (sync) __syncthreads();
     const int t = threadIdx.x;
     if (t < NC) {
         int op = 0, cl = 0;
@@ -849,38 +852,40 @@ __device__ __forceinline__ void wave_acc_flush(const WaveAcc<NC>& W, const int (
                 op = ops[k];
                 cl = col[k];
             }
-        double v = W.x[0][t];
+        double v = W.x[par][0][t];
 #pragma unroll
-        for (int w = 1; w < kPassThreads / 64; ++w) v = acc_op(op, v, W.x[w][t]);
+        for (int w = 1; w < kPassThreads / 64; ++w) v = acc_op(op, v, W.x[par][w][t]);
         dst[(size_t)cl * stride] = v;
     }
-    __syncthreads();   // the entries are reset for the next group after every thread has read them
+    if (sync) __syncthreads();
 }
 
 // Persistent walk of a pass: workgroup b takes its XCD's tiles in turn (single
-// instance), or the tiles (= reduction groups) of its chunks (batch); body(tile, hc)
-// computes one tile, hc the halo cell this thread stages for it, read while the
-// previous tile was computed; flush(g) writes the record of group g (batch) or of
-// the workgroup (g < 0).
+// instance), or the tiles (= reduction groups) of its chunks (batch); body(tile, hc,
+// par) computes one tile and ends with a barrier, hc the halo cell this thread
+// stages for it, read while the previous tile was computed, par the set of
+// reduction entries; flush(g, par) writes the record of group g (batch) or of the
+// workgroup (g < 0).
 template <bool kBatch, typename Body, typename Reset, typename Flush>
 __device__ __forceinline__ void walk_tiles(const StageArgs& a, int g0, int g1, Body body, Reset reset, Flush flush) {
     if constexpr (!kBatch) {
-        reset();
+        reset(0);
         const TileWalk tw = tile_walk(n_tiles_of(a.m.n_cell));
         int hc = tw.first < tw.end ? halo_cell_of(a, tw.first) : -1;
         for (int tile = tw.first; tile < tw.end; tile += tw.stride) {
             const int hn = tile + tw.stride < tw.end ? halo_cell_of(a, tile + tw.stride) : -1;
-            body(tile, hc);
+            body(tile, hc, 0);
             hc = hn;
         }
-        flush(-1);
+        flush(-1, 0);
     } else {
         int hc = g0 < g1 ? halo_cell_of(a, g0) : -1;
         for (int gi = g0; gi < g1; ++gi) {
             const int hn = gi + 1 < g1 ? halo_cell_of(a, gi + 1) : -1;
-            reset();
-            body(gi, hc);
-            flush(gi);
+            const int par = (gi - g0) & 1;
+            reset(par);
+            body(gi, hc, par);
+            flush(gi, par);
             hc = hn;
         }
     }
@@ -938,7 +943,7 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
         mb[j] = uniform((first ? s_w : sa * g->mom_n[j] + sb * s_w) / g->area_sum);
     }
 
-    auto tile_body = [&](int tile, int hc) __attribute__((always_inline)) {
+    auto tile_body = [&](int tile, int hc, int par) __attribute__((always_inline)) {
         const int c = tile * kTileCells + (int)threadIdx.x;
         const bool live = c < nc;
         const unsigned c8 = (unsigned)c * 8u, c4 = (unsigned)c * 4u, cT = (unsigned)c * (unsigned)sizeof(T);
@@ -1287,14 +1292,14 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
             }
             part[12] = cnm;
         }
-        wave_acc_add<kResCols>(W, ops, part);
+        wave_acc_add<kResCols>(W, ops, part, par);
         __syncthreads();   // the tile image is rewritten by the next tile
     };
     walk_tiles<kBatch>(
-        a, g0, g1, tile_body, [&]() { wave_acc_reset<kResCols>(W, ops); },
-        [&](int gi) {
-            if (gi < 0) wave_acc_flush<kResCols>(W, ops, cols, a.part + blockIdx.x, kMaxBlocks);
-            else wave_acc_flush<kResCols>(W, ops, cols, a.part + a.gbase + gi, a.gstride);
+        a, g0, g1, tile_body, [&](int par) { wave_acc_reset<kResCols>(W, ops, par); },
+        [&](int gi, int par) {
+            if (gi < 0) wave_acc_flush<kResCols>(W, ops, cols, a.part + blockIdx.x, kMaxBlocks, par, true);
+            else wave_acc_flush<kResCols>(W, ops, cols, a.part + a.gbase + gi, a.gstride, par, false);
         });
 }
 
@@ -1446,7 +1451,7 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
         cols[k] = kNumPartial + 1 + k;
     }
 
-    auto tile_body = [&](int tile, int hc) __attribute__((always_inline)) {
+    auto tile_body = [&](int tile, int hc, int par) __attribute__((always_inline)) {
         const int c = tile * kTileCells + (int)threadIdx.x;
         const bool live = c < nc;
         const unsigned c8 = (unsigned)c * 8u, c4 = (unsigned)c * 4u, cT = (unsigned)c * (unsigned)sizeof(T);
@@ -1930,14 +1935,16 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
                 for (int l = 1; l < NM; ++l) op.put_h(v, l, cT, w[v][l]);
             }
         }
-        wave_acc_add<kFilCols>(W, ops, part);
-        if (oe) __syncthreads();   // the tile image is rewritten by the next tile
+        wave_acc_add<kFilCols>(W, ops, part, par);
+        // the tile image is rewritten by the next tile; a batched tile's record is
+        // flushed next
+        if (oe || kBatch) __syncthreads();
     };
     walk_tiles<kBatch>(
-        a, g0, g1, tile_body, [&]() { wave_acc_reset<kFilCols>(W, ops); },
-        [&](int gi) {
-            if (gi < 0) wave_acc_flush<kFilCols>(W, ops, cols, a.part + blockIdx.x, kMaxBlocks);
-            else wave_acc_flush<kFilCols>(W, ops, cols, a.part + a.gbase + gi, a.gstride);
+        a, g0, g1, tile_body, [&](int par) { wave_acc_reset<kFilCols>(W, ops, par); },
+        [&](int gi, int par) {
+            if (gi < 0) wave_acc_flush<kFilCols>(W, ops, cols, a.part + blockIdx.x, kMaxBlocks, par, true);
+            else wave_acc_flush<kFilCols>(W, ops, cols, a.part + a.gbase + gi, a.gstride, par, false);
         });
 }
 template <int K, typename T>
