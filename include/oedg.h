@@ -263,7 +263,8 @@ dg_status dg_set_t_end(dg_ctx* ctx, double t_end);
 /* ---------------------------------------------------------------------------
  * Batches: several initialised contexts on one device (meshes of any size,
  * degrees 1 and 2 mixed, one precision) stepped together, each pass of a
- * stage one persistent launch over all members (the method is per instance;
+ * stage one persistent launch over all members of a degree (two launches on
+ * parallel streams when both degrees are present; the method is per instance,
  * batching is this library's scheduling).  A chunk table cuts every member into
  * runs of 256-cell reduction groups, split into one contiguous range per XCD by
  * estimated cost; every group writes its own partial record and a
@@ -276,7 +277,8 @@ dg_status dg_set_t_end(dg_ctx* ctx, double t_end);
  * must outlive it, must not be stepped on other streams while it runs, and
  * re-initialising one (dg_init, dg_init_problem, dg_mesh_upload) makes the
  * batch return DG_E_STATE.  The batch allocates its own device memory (stage
- * arguments, chunk table, 17 doubles per 256 cells of partial records). */
+ * arguments, chunk table, 26 doubles per 256 cells of partial records) and,
+ * with both degrees present, a second stream and two events. */
 typedef struct dg_batch dg_batch;
 
 /* Builds a batch of n contexts on hip_stream (may be NULL).  Errors: DG_E_ARG
@@ -289,7 +291,7 @@ dg_status dg_batch_create(dg_batch** out, dg_ctx* const* ctxs, int n, void* hip_
  * pass grids at occupancy_pct percent of the resident workgroups. */
 dg_status dg_batch_set_schedule(dg_batch* b, int chunk_groups, int occupancy_pct);
 dg_status dg_batch_get_schedule(const dg_batch* b, int* chunk_groups, int* occupancy_pct, int* n_chunks,
-                                int* grid /* 2: residual, filter */);
+                                int* grid /* 2: residual, filter; workgroups over both degrees' launches */);
 
 /* Times stage 0 of the batch for chunk_groups in {1,2,4,8,16} and occupancy in
  * {100, 50} percent (reps timed runs each, after a warm-up), keeps the fastest

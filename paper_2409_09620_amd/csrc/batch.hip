@@ -26,12 +26,18 @@ struct dg_batch {
     int n = 0, mixed = 0, kmask = 0;
     long long total_groups = 0;
 
-    // schedule
+    // schedule: one launch per pass, or (both degrees present) one per degree,
+    // each over its own part of the chunk table
     int chunk_groups = 1;
     int occupancy_pct = 100;
     std::vector<oedg::Chunk> chunks;
-    oedg::ChunkSplit split{};
-    int grid[oedg::kNumPasses] = {8, 8};
+    int n_launch = 1;
+    int launch_k[2] = {0, 0};     // degree mask of each launch
+    int chunk_off[2] = {0, 0};    // its first chunk
+    oedg::ChunkSplit split[2]{};
+    int grid[2][oedg::kNumPasses] = {{8, 8}, {8, 8}};
+    hipStream_t side = nullptr;   // the second degree's launches, beside the first
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
     // device memory (one library allocation): stage arguments [3][n], chunk
     // table (one chunk per group at most), partial records, status words
@@ -97,12 +103,25 @@ dg_status plan(dg_batch* b) {
         nc[i] = b->ctx[i]->mesh.n_cell;
         k[i] = b->ctx[i]->cfg.k;
     }
-    if (oedg::plan_chunks(b->n, nc.data(), k.data(), b->chunk_groups, b->chunks, b->split) != 0)
-        return bfail(b, DG_E_ARG, "bad schedule");
-    for (int w = 0; w < oedg::kNumPasses; ++w) {
-        const int resident = oedg::resident_grid_batch(w, b->kmask, b->mixed);
-        const int cap = std::max(8, (int)((long long)resident * b->occupancy_pct / 100) / 8 * 8);
-        b->grid[w] = oedg::grid_for_split(b->split, cap);
+    // A batch of both degrees launches the single-degree kernels, one per degree:
+    // the kernel that takes both holds the larger register and LDS footprint for
+    // every chunk (in the mixed form 255 VGPRs against 119 and 167).
+    b->n_launch = b->kmask == 3 ? 2 : 1;
+    b->launch_k[0] = b->kmask == 3 ? 1 : b->kmask;
+    b->launch_k[1] = 2;
+    b->chunks.clear();
+    std::vector<oedg::Chunk> part;
+    for (int l = 0; l < b->n_launch; ++l) {
+        if (oedg::plan_chunks(b->n, nc.data(), k.data(), b->chunk_groups, part, b->split[l],
+                              b->n_launch == 2 ? b->launch_k[l] : 0) != 0)
+            return bfail(b, DG_E_ARG, "bad schedule");
+        b->chunk_off[l] = (int)b->chunks.size();
+        b->chunks.insert(b->chunks.end(), part.begin(), part.end());
+        for (int w = 0; w < oedg::kNumPasses; ++w) {
+            const int resident = oedg::resident_grid_batch(w, b->launch_k[l], b->mixed);
+            const int cap = std::max(8, (int)((long long)resident * b->occupancy_pct / 100) / 8 * 8);
+            b->grid[l][w] = oedg::grid_for_split(b->split[l], cap);
+        }
     }
     BHIP_TRY(b, hipMemcpyAsync(b->d_chunks, b->chunks.data(), b->chunks.size() * sizeof(oedg::Chunk),
                                hipMemcpyHostToDevice, b->stream));
@@ -114,8 +133,21 @@ dg_status plan(dg_batch* b) {
 dg_status run_stage(dg_batch* b, int s) {
     const oedg::StageArgs* d = b->d_desc + (size_t)s * b->n;
     for (int w = 0; w < oedg::kNumPasses; ++w) {
-        BLAUNCH_TRY(b, oedg::launch_pass_batch(w, b->kmask, b->mixed, d, b->d_chunks, b->split, b->grid[w],
-                                               b->stream));
+        if (b->n_launch == 1) {
+            BLAUNCH_TRY(b, oedg::launch_pass_batch(w, b->launch_k[0], b->mixed, d, b->d_chunks, b->split[0],
+                                                   b->grid[0][w], b->stream));
+        } else {
+            // the P2 launch on a second stream beside the P1 one (forked from and joined
+            // back into the batch's stream: graph capture records two parallel nodes)
+            BHIP_TRY(b, hipEventRecord(b->ev_fork, b->stream));
+            BHIP_TRY(b, hipStreamWaitEvent(b->side, b->ev_fork, 0));
+            BLAUNCH_TRY(b, oedg::launch_pass_batch(w, b->launch_k[0], b->mixed, d, b->d_chunks + b->chunk_off[0],
+                                                   b->split[0], b->grid[0][w], b->stream));
+            BLAUNCH_TRY(b, oedg::launch_pass_batch(w, b->launch_k[1], b->mixed, d, b->d_chunks + b->chunk_off[1],
+                                                   b->split[1], b->grid[1][w], b->side));
+            BHIP_TRY(b, hipEventRecord(b->ev_join, b->side));
+            BHIP_TRY(b, hipStreamWaitEvent(b->stream, b->ev_join, 0));
+        }
         BLAUNCH_TRY(b, oedg::launch_finalize_batch(w, d, b->n, b->stream));
     }
     return DG_OK;
@@ -251,6 +283,11 @@ dg_status dg_batch_create(dg_batch** out, dg_ctx* const* ctxs, int n, void* hip_
     const size_t o_stat = o_part + al((size_t)oedg::kPartCols * b->total_groups * sizeof(double));
     const size_t total = o_stat + al(oedg::kStatusCols * (size_t)n * sizeof(double));
     if (hipMalloc(&b->mem, total) != hipSuccess) return bfail(b, DG_E_NOMEM, "hipMalloc of the batch memory failed");
+    if (b->kmask == 3) {   // one launch per degree: the second on a stream of its own
+        BHIP_TRY(b, hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+        BHIP_TRY(b, hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+        BHIP_TRY(b, hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
+    }
     char* base = (char*)b->mem;
     b->d_desc = (oedg::StageArgs*)(base + o_desc);
     b->d_chunks = (oedg::Chunk*)(base + o_chunk);
@@ -288,7 +325,7 @@ dg_status dg_batch_get_schedule(const dg_batch* b, int* chunk_groups, int* occup
     if (occupancy_pct) *occupancy_pct = b->occupancy_pct;
     if (n_chunks) *n_chunks = (int)b->chunks.size();
     if (grid)
-        for (int w = 0; w < oedg::kNumPasses; ++w) grid[w] = b->grid[w];
+        for (int w = 0; w < oedg::kNumPasses; ++w) grid[w] = b->grid[0][w] + (b->n_launch == 2 ? b->grid[1][w] : 0);
     return DG_OK;
 }
 
@@ -411,6 +448,9 @@ void dg_batch_destroy(dg_batch* b) {
     (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     if (b->mem) (void)hipFree(b->mem);
     delete b;
 }

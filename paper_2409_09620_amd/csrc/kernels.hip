@@ -2288,10 +2288,10 @@ BatchSet batch_set() {
     return {{reinterpret_cast<const void*>(&k_residual_batch<KM, T>),
              reinterpret_cast<const void*>(&k_filter_batch<KM, T>)}};
 }
+// single-degree kernels only: a batch of both degrees launches each of them
 const BatchSet& batch_kernels(int kmask, int mixed) {
-    static const BatchSet sets[3][2] = {{batch_set<1, double>(), batch_set<1, float>()},
-                                        {batch_set<2, double>(), batch_set<2, float>()},
-                                        {batch_set<3, double>(), batch_set<3, float>()}};
+    static const BatchSet sets[2][2] = {{batch_set<1, double>(), batch_set<1, float>()},
+                                        {batch_set<2, double>(), batch_set<2, float>()}};
     return sets[kmask - 1][mixed ? 1 : 0];
 }
 
@@ -2389,7 +2389,7 @@ int resident_grid_batch(int which, int kmask, int mixed) {
 
 int launch_pass_batch(int which, int kmask, int mixed, const StageArgs* desc, const Chunk* chunks,
                       const ChunkSplit& cs, int grid, void* stream) {
-    if (kmask < 1 || kmask > 3 || grid < 8 || (grid & 7) != 0) return (int)hipErrorInvalidValue;
+    if (kmask < 1 || kmask > 2 || grid < 8 || (grid & 7) != 0) return (int)hipErrorInvalidValue;
     ChunkSplit split = cs;
     void* argv[] = {&desc, &chunks, &split};
     return (int)hipLaunchKernel(batch_kernels(kmask, mixed).pass[which], dim3(grid), dim3(kPassThreads), argv, 0,

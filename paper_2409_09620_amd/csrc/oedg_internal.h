@@ -187,9 +187,10 @@ constexpr size_t kScratchDoubles = (size_t)kPartCols * kMaxBlocks;
 // as int; *out is null on failure.
 int scratch_address(int device, double** out);
 
-// ---- batch: passes over a chunk table of several instances
-// Workgroups of batched pass `which` resident at once for degree mask kmask
-// (1: P1, 2: P2, 3: both) and precision `mixed`; a multiple of 8.
+// ---- batch: passes over a chunk table of several instances (a batch that holds
+// both degrees launches each pass once per degree)
+// Workgroups of batched pass `which` resident at once for degree kmask (1: P1,
+// 2: P2) and precision `mixed`; a multiple of 8.
 int resident_grid_batch(int which, int kmask, int mixed);
 // Launches batched pass `which`: desc[i] are the device stage arguments of
 // instance i, chunks the device chunk table split by XCD as in cs; grid a
@@ -207,11 +208,12 @@ int launch_set_end(Glob* g, double t_end, void* stream);
 constexpr int kStatusCols = 6;
 int launch_gather_status(const StageArgs* desc, int n, double* out, void* stream);
 
-// schedule.cpp: chunks of chunk_groups groups over the instances in order, and
-// their split into 8 contiguous ranges of equal estimated cost (one per XCD).
-// Returns 0, or -1 for invalid sizes or degrees.
+// schedule.cpp: chunks of chunk_groups groups over the instances in order (only
+// those of degree only_k unless it is 0), and their split into 8 contiguous
+// ranges of equal estimated cost (one per XCD).  Returns 0, or -1 for invalid
+// sizes or degrees.
 int plan_chunks(int n_inst, const int32_t* n_cell, const int* k, int chunk_groups, std::vector<Chunk>& chunks,
-                ChunkSplit& split);
+                ChunkSplit& split, int only_k = 0);
 // Grid of a pass over a split: 8 times the widest XCD range, at most `resident`.
 int grid_for_split(const ChunkSplit& split, int resident);
 

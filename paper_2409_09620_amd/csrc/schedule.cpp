@@ -13,12 +13,13 @@ namespace oedg {
 static double cell_cost(int k) { return k == 2 ? 2.0 : 1.0; }
 
 int plan_chunks(int n_inst, const int32_t* n_cell, const int* k, int chunk_groups, std::vector<Chunk>& chunks,
-                ChunkSplit& split) {
+                ChunkSplit& split, int only_k) {
     if (n_inst <= 0 || chunk_groups <= 0) return -1;
     chunks.clear();
     std::vector<double> prefix(1, 0.0);
     for (int i = 0; i < n_inst; ++i) {
         if (n_cell[i] <= 0 || (k[i] != 1 && k[i] != 2)) return -1;
+        if (only_k != 0 && k[i] != only_k) continue;
         const int ng = n_groups(n_cell[i]);
         for (int g0 = 0; g0 < ng; g0 += chunk_groups) {
             const int g1 = std::min(g0 + chunk_groups, ng);
