@@ -684,13 +684,6 @@ __device__ __forceinline__ T (&oe_records(MonoLds<K, T>& L))[4][K][3][kTileCells
     return *reinterpret_cast<T(*)[4][K][3][kTileCells]>(&L);
 }
 
-// the filter's tile image of a batched pass: one per degree present
-template <int KM, typename T>
-union MonoLdsKM {
-    typename std::conditional<(KM & 1) != 0, MonoLds<1, T>, char>::type p1;
-    typename std::conditional<(KM & 2) != 0, MonoLds<2, T>, char>::type p2;
-};
-
 // the monomials of one variable (modes u, u[0] its average in T) from J^-1; with
 // `full`, c0 includes the average
 template <int K, typename T>
@@ -1338,32 +1331,23 @@ __device__ __forceinline__ void for_each_chunk(const StageArgs* desc, const Chun
     }
 }
 
-// the tile image of a batched pass: one per degree present (KM: 1 P1, 2 P2, 3 both)
-template <int KM, typename T, int NG>
-union TileLdsKM {
-    typename std::conditional<(KM & 1) != 0, TileLds<1, T, NG>, char>::type p1;
-    typename std::conditional<(KM & 2) != 0, TileLds<2, T, NG>, char>::type p2;
-};
-
-template <int KM, typename T>
+// Batched passes over the chunks of the members of degree K (a batch of both
+// degrees launches each).
+template <int K, typename T>
 __global__ __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(OEDG_RES_WAVES))) void k_residual_batch(
     const StageArgs* desc, const Chunk* chunks, ChunkSplit cs) {
-    // FP64: the monomial image (faster in the batched pass); mixed: the modal image,
-    // whose float traces keep the rounding within the limiter's margin
-    using Img = typename std::conditional<std::is_same<T, double>::value, MonoLdsKM<KM, T>, TileLdsKM<KM, T, 5>>::type;
-    __shared__ EdgeRowsLds<1, T> er1;
-    __shared__ EdgeRowsLds<2, T> er2;
+    // FP64 P2: the monomial image (no slower here, and it spills less in the
+    // batched kernel); P1 FP64: the modal image (three waves per SIMD instead of
+    // two); mixed: the modal image, whose float traces keep the rounding within the
+    // limiter's margin.  The P1 filters ask for three waves as well.
+    using Img = typename std::conditional<std::is_same<T, double>::value && K == 2, MonoLds<K, T>, TileLds<K, T, 5>>::type;
+    __shared__ EdgeRowsLds<K, T> er;
     __shared__ Img L;
     __shared__ WaveAcc<kResCols> W;
-    if constexpr (KM & 1) fill_edge_rows<1, T>(er1);
-    if constexpr (KM & 2) fill_edge_rows<2, T>(er2);
+    fill_edge_rows<K, T>(er);
     __syncthreads();
-    for_each_chunk(desc, chunks, cs, [&](const StageArgs& a, int g0, int g1) {
-        if constexpr (KM == 1) residual_run<1, T, true>(a, g0, g1, er1, L.p1, W);
-        else if constexpr (KM == 2) residual_run<2, T, true>(a, g0, g1, er2, L.p2, W);
-        else if (a.k == 1) residual_run<1, T, true>(a, g0, g1, er1, L.p1, W);
-        else residual_run<2, T, true>(a, g0, g1, er2, L.p2, W);
-    });
+    for_each_chunk(desc, chunks, cs,
+                   [&](const StageArgs& a, int g0, int g1) { residual_run<K, T, true>(a, g0, g1, er, L, W); });
 }
 
 // ------------------------------------------------------------------------- pass 2: OE, limiter, alpha
@@ -1948,24 +1932,20 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
         });
 }
 template <int K, typename T>
-__global__ __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(OEDG_FIL_WAVES))) void k_filter(
+__global__ __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(K == 1 ? 3 : OEDG_FIL_WAVES))) void k_filter(
     StageArgs a) {
     if (!a.g->active || a.g->skip) return;
     __shared__ MonoLds<K, T> L;
     __shared__ WaveAcc<kFilCols> W;
     filter_run<K, T, false>(a, 0, 0, L, W);
 }
-template <int KM, typename T>
-__global__ __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(OEDG_FIL_WAVES))) void k_filter_batch(
+template <int K, typename T>
+__global__ __launch_bounds__(kPassThreads) __attribute__((amdgpu_waves_per_eu(K == 1 ? 3 : OEDG_FIL_WAVES))) void k_filter_batch(
     const StageArgs* desc, const Chunk* chunks, ChunkSplit cs) {
-    __shared__ MonoLdsKM<KM, T> L;
+    __shared__ MonoLds<K, T> L;
     __shared__ WaveAcc<kFilCols> W;
-    for_each_chunk(desc, chunks, cs, [&](const StageArgs& a, int g0, int g1) {
-        if constexpr (KM == 1) filter_run<1, T, true>(a, g0, g1, L.p1, W);
-        else if constexpr (KM == 2) filter_run<2, T, true>(a, g0, g1, L.p2, W);
-        else if (a.k == 1) filter_run<1, T, true>(a, g0, g1, L.p1, W);
-        else filter_run<2, T, true>(a, g0, g1, L.p2, W);
-    });
+    for_each_chunk(desc, chunks, cs,
+                   [&](const StageArgs& a, int g0, int g1) { filter_run<K, T, true>(a, g0, g1, L, W); });
 }
 
 // ------------------------------------------------------------------------- finalize (one workgroup)
@@ -2279,16 +2259,15 @@ const KernelSet& kernels_for(int k, int mixed) {
     return sets[k == 2 ? 1 : 0][mixed ? 1 : 0];
 }
 
-// host handles of the batched pass instantiations of one (degree mask, precision)
+// host handles of the batched pass instantiations of one (degree, precision)
 struct BatchSet {
     const void* pass[kNumPasses];   // residual, filter
 };
-template <int KM, typename T>
+template <int K, typename T>
 BatchSet batch_set() {
-    return {{reinterpret_cast<const void*>(&k_residual_batch<KM, T>),
-             reinterpret_cast<const void*>(&k_filter_batch<KM, T>)}};
+    return {{reinterpret_cast<const void*>(&k_residual_batch<K, T>),
+             reinterpret_cast<const void*>(&k_filter_batch<K, T>)}};
 }
-// single-degree kernels only: a batch of both degrees launches each of them
 const BatchSet& batch_kernels(int kmask, int mixed) {
     static const BatchSet sets[2][2] = {{batch_set<1, double>(), batch_set<1, float>()},
                                         {batch_set<2, double>(), batch_set<2, float>()}};
