@@ -2003,29 +2003,35 @@ __device__ __forceinline__ void reduce_columns(const double* base, size_t cstrid
     }
 }
 
+// The finalize kernels read the scalars they need before the reduction, so that
+// their loads overlap it instead of following one another in thread 0 after it;
+// an inactive instance's records are reduced and dropped.
+
 // domain averages and L-infinity norms (eq. normOmg): ||u - ubar|| = max(max u - ubar, ubar - min u)
+// and ||| m - mbar |||_inf (eqs. normOmg, RIOESys:Coef1) with its zero branch.
 // An inadmissible average ends this attempt of the step: `skip` turns the rest
 // of it into no-ops (u^n is untouched) until the third stage's finalize.
-// and ||| m - mbar |||_inf (eqs. normOmg, RIOESys:Coef1) with its zero branch
 __device__ __forceinline__ void fin_residual(const double* base, size_t cstride, int G, Glob* g) {
+    const int active = g->active;
+    const double area_sum = g->area_sum;
     // 4 sums, 4 mins, 4 maxima, the max of |m - mbar|^2, then the bad-average count
     double tot[kNumPartial + 2];
     reduce_columns<kNumPartial + 2>(base, cstride, G, 0, 0x2AA5500u, tot, kColBad);
-    if (threadIdx.x == 0) {
-        if (tot[kNumPartial + 1] > 0.0) g->skip = 1;
+    if (threadIdx.x != 0 || !active) return;
+    if (tot[kNumPartial + 1] > 0.0) g->skip = 1;
+    double ub[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const double ub = tot[v] / g->area_sum;
-            const double n = fmax(tot[8 + v] - ub, ub - tot[4 + v]);
-            g->ubar[v] = ub;
-            g->nrm[v] = n;
-            g->inv_nrm[v] = n <= kEpsOE * fmax(1.0, fabs(ub)) ? 0.0 : 1.0 / n;
-        }
-        const double n = sqrt(tot[kNumPartial]);
-        const double mb = sqrt(g->ubar[1] * g->ubar[1] + g->ubar[2] * g->ubar[2]);
-        g->nrm_m = n;
-        g->inv_nrm_m = n <= kEpsOE * fmax(1.0, mb) ? 0.0 : 1.0 / n;
+    for (int v = 0; v < 4; ++v) {
+        ub[v] = tot[v] / area_sum;
+        const double n = fmax(tot[8 + v] - ub[v], ub[v] - tot[4 + v]);
+        g->ubar[v] = ub[v];
+        g->nrm[v] = n;
+        g->inv_nrm[v] = n <= kEpsOE * fmax(1.0, fabs(ub[v])) ? 0.0 : 1.0 / n;
     }
+    const double n = sqrt(tot[kNumPartial]);
+    const double mb = sqrt(ub[1] * ub[1] + ub[2] * ub[2]);
+    g->nrm_m = n;
+    g->inv_nrm_m = n <= kEpsOE * fmax(1.0, mb) ? 0.0 : 1.0 / n;
 }
 
 // alpha of the stage output; after the third stage (or the initial limiter pass)
@@ -2033,26 +2039,48 @@ __device__ __forceinline__ void fin_residual(const double* base, size_t cstride,
 // After the third stage of a skipped attempt: the step is retried from u^n with
 // half the time step, or the run stops once max_restarts retries are used.
 __device__ __forceinline__ void fin_filter(const double* base, size_t cstride, int G, Glob* g, int stage) {
-    const int skip = g->skip;
-    __syncthreads();   // every thread has read `skip` before thread 0 may clear it
+    const int active = g->active, skip = g->skip;
+    double t = 0.0, dt = 0.0, t_end = 0.0, minck = 0.0, c_ssp = 0.0, alpha_step = 0.0;
+    long long step = 0, n_lim = 0, n_bad = 0, n_flat = 0, n_cfl = 0, n_restarts = 0;
+    int err = 0, restarts = 0, max_restarts = 0;
+    if (threadIdx.x == 0) {
+        t = g->t;
+        dt = g->dt;
+        t_end = g->t_end;
+        minck = g->minck;
+        c_ssp = g->c_ssp;
+        alpha_step = g->alpha_step;
+        step = g->step;
+        n_lim = g->n_limited;
+        n_bad = g->n_bad;
+        n_flat = g->n_flat;
+        n_cfl = g->n_cfl_exc;
+        n_restarts = g->n_restarts;
+        err = g->err;
+        restarts = g->restarts;
+        max_restarts = g->max_restarts;
+    }
+    double r[kFilterCols];
+    // max, sums, then two minima; its barrier also orders every thread's read of
+    // `skip` before thread 0 may clear it
+    reduce_columns<kFilterCols>(base, cstride, G, kNumPartial + 1, 2u | (1u << 20) | (1u << 22), r);
+    if (threadIdx.x != 0 || !active) return;
     if (skip) {
-        if (threadIdx.x == 0 && stage == 2) {
+        if (stage == 2) {
             g->skip = 0;
-            if (++g->restarts > g->max_restarts) {
+            if (restarts + 1 > max_restarts) {
+                g->restarts = restarts + 1;
                 g->err = 1;
                 g->active = 0;
             } else {
-                g->dt *= 0.5;
-                g->alpha = g->alpha_step;   // the retry's first stage starts from u^n again
-                g->n_restarts += 1;
+                g->restarts = restarts + 1;
+                g->dt = 0.5 * dt;
+                g->alpha = alpha_step;   // the retry's first stage starts from u^n again
+                g->n_restarts = n_restarts + 1;
             }
         }
         return;
     }
-    double r[kFilterCols];
-    // max, sums, then two minima
-    reduce_columns<kFilterCols>(base, cstride, G, kNumPartial + 1, 2u | (1u << 20) | (1u << 22), r);
-    if (threadIdx.x != 0) return;
     const double alpha = r[0], lim = r[1], bad = r[2];
     g->min_rho_node = r[10];
     g->min_p_node = r[11];
@@ -2069,47 +2097,51 @@ __device__ __forceinline__ void fin_filter(const double* base, size_t cstride, i
             g->bfb_n[j] = r[8 + j];
         }
     }
-    g->n_limited += (long long)lim;
-    g->n_bad += (long long)bad;
-    g->n_flat += (long long)r[3];
-    if (bad > 0) g->err = 1;
+    g->n_limited = n_lim + (long long)lim;
+    g->n_bad = n_bad + (long long)bad;
+    g->n_flat = n_flat + (long long)r[3];
+    if (bad > 0) err = 1;
+    g->err = err;
     if (stage < 2) {
         g->alpha = alpha;
         if (stage < 0) g->alpha_step = alpha;
-        else if (alpha > g->alpha_step * (1.0 + 1e-12)) g->n_cfl_exc += 1;
+        else if (alpha > alpha_step * (1.0 + 1e-12)) g->n_cfl_exc = n_cfl + 1;
     } else {
-        g->t += g->dt;
-        g->step += 1;
+        t += dt;
+        g->t = t;
+        g->step = step + 1;
         g->alpha = alpha;
         g->alpha_step = alpha;
         g->restarts = 0;
     }
+    int act = 1;
     if (stage < 0 || stage == 2) {
-        double dt = g->c_ssp * g->minck / alpha;
-        const double rem = g->t_end - g->t;
-        if (rem < dt) dt = rem;
-        g->dt = dt;
-        if (!(isinf(g->t_end) || rem > 1e-12 * fmax(1.0, fabs(g->t_end)))) g->active = 0;
+        double ndt = c_ssp * minck / alpha;
+        const double rem = t_end - t;
+        if (rem < ndt) ndt = rem;
+        g->dt = ndt;
+        if (!(isinf(t_end) || rem > 1e-12 * fmax(1.0, fabs(t_end)))) act = 0;
     }
-    if (g->err) g->active = 0;
+    if (err) act = 0;
+    if (!act) g->active = 0;
 }
 
 // One instance: the partials of the G workgroups of its passes.
 __global__ __launch_bounds__(kFinThreads) void k_fin_residual(const double* part, int G, Glob* g) {
-    if (g->active) fin_residual(part, kMaxBlocks, G, g);
+    fin_residual(part, kMaxBlocks, G, g);
 }
 __global__ __launch_bounds__(kFinThreads) void k_fin_filter(const double* part, int G, Glob* g, int stage) {
-    if (g->active) fin_filter(part, kMaxBlocks, G, g, stage);
+    fin_filter(part, kMaxBlocks, G, g, stage);
 }
 
 // A batch: workgroup i reduces the group records of instance desc[i].
 __global__ __launch_bounds__(kFinThreads) void k_fin_residual_batch(const StageArgs* desc) {
     const StageArgs& a = desc[blockIdx.x];
-    if (a.g->active) fin_residual(a.part + a.gbase, a.gstride, n_groups(a.m.n_cell), a.g);
+    fin_residual(a.part + a.gbase, a.gstride, n_groups(a.m.n_cell), a.g);
 }
 __global__ __launch_bounds__(kFinThreads) void k_fin_filter_batch(const StageArgs* desc) {
     const StageArgs& a = desc[blockIdx.x];
-    if (a.g->active) fin_filter(a.part + a.gbase, a.gstride, n_groups(a.m.n_cell), a.g, a.stage);
+    fin_filter(a.part + a.gbase, a.gstride, n_groups(a.m.n_cell), a.g, a.stage);
 }
 
 // ------------------------------------------------------------------------- initial data
