@@ -1707,8 +1707,9 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
                 }
             }
             // the state again (from cache; not kept in registers through the edge work),
-            // in flight while the partners' shares go through LDS
-            if (live) load_cell<NM, T>(wp, c, wa, w);
+            // in flight while the partners' shares go through LDS.  The mixed P2 form
+            // keeps it: its float modes fit beside the edge work without spilling.
+            if (live && !(kMixed && K == 2)) load_cell<NM, T>(wp, c, wa, w);
             // the partners' shares: written over the image once every lane is done with it
             T (&R)[4][K][3][kTileCells] = oe_records<K, T>(L);
             __syncthreads();
