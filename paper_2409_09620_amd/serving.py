@@ -11,8 +11,11 @@ of a precision, every request with its own alpha, Delta t and t_end.
   projects the initial data on a stream of its own, so a large request does not
   stall the requests already stepping.  A request that fails there (a bad mesh,
   no memory) is finished with its error; the others go on.
-* Stepping.  Prepared requests join their precision's batch at the next poll;
-  each batch advances steps_per_tick steps between polls.
+* Stepping.  A precision's requests are batched by size class (meshes below
+  small_cells cells, and the rest), each class's batch on a stream of its own,
+  so that a small request's steps do not wait on a large one's: the batches'
+  kernels run side by side and each batch is polled when its last steps_per_tick
+  steps have finished.  Prepared requests join their batch when it is idle.
 * Retirement.  A request that reached its t_end is read back at the poll that
   sees it finished.  It stays in its batch, skipped by the kernels, until
   requests join that batch: the batch (and its captured step) is rebuilt only
@@ -93,12 +96,18 @@ class ServeStats:
 
 
 class _Group:
-    """The batch of one precision: its members (request, solver, footprint) and
-    whether each is still active."""
+    """The batch of one precision and size class: its members (request, solver,
+    footprint), its stream and the event of its last launched steps."""
 
-    def __init__(self):
+    def __init__(self, device):
+        import torch
         self.members = []
         self.batch = None
+        self.stream = torch.cuda.Stream(device)
+        self.event = None
+
+    def idle(self):
+        return self.event is None or self.event.query()
 
     def active_count(self):
         return sum(1 for m in self.members if m[0].done is None)
@@ -108,13 +117,14 @@ class Server:
     """hbm_budget: bytes the admitted requests may hold together; steps_per_tick:
     batched steps between polls; keep_results: read each finished state back to
     the host; prepare_threads: threads that build, upload and project new
-    requests; progress: a callable given one line of text at every admission,
+    requests; small_cells: meshes below this many cells are batched apart from
+    the larger ones; progress: a callable given one line of text at every admission,
     join and completion and every progress_every seconds (the members' t and step
     counts); max_wall: seconds after which the run stops and the unfinished
     requests end with an error."""
 
     def __init__(self, device=0, hbm_budget=8 << 30, steps_per_tick=8, keep_results=True, autotune=False,
-                 prepare_threads=2, progress=None, progress_every=5.0, max_wall=None):
+                 prepare_threads=2, small_cells=100_000, progress=None, progress_every=5.0, max_wall=None):
         self.progress = progress
         self.progress_every = float(progress_every)
         self.max_wall = max_wall
@@ -124,6 +134,7 @@ class Server:
         self.keep_results = keep_results
         self.autotune = autotune
         self.prepare_threads = max(1, int(prepare_threads))
+        self.small_cells = int(small_cells)
         self._tls = threading.local()
 
     def _prepare(self, req):
@@ -154,7 +165,11 @@ class Server:
                 raise ValueError(f"request {r.id}: precision must be one of {sorted(PRECISION)}")
         pending = sorted(requests, key=lambda r: r.arrival)
         preparing = []                   # (request, future, footprint)
-        groups = {p: _Group() for p in PRECISION}
+        import torch
+        groups = {(p, c): _Group(self.device) for p in PRECISION for c in (0, 1)}
+
+        def key(r):
+            return (r.precision, 0 if r.n_cell < self.small_cells else 1)
         used = 0
         peak = rebuilds = launched = 0
         pool = ThreadPoolExecutor(max_workers=self.prepare_threads)
@@ -172,6 +187,7 @@ class Server:
             if g.batch is not None:
                 g.batch.close()
                 g.batch = None
+                g.event = None
             keep, freed = [], 0
             for m in g.members:
                 if m[0].done is None:
@@ -181,14 +197,35 @@ class Server:
                     freed += m[2]
             g.members = keep + list(new_members)
             if g.members:
-                g.batch = Batch([s for _, s, _ in g.members])
+                with torch.cuda.stream(g.stream):
+                    g.batch = Batch([s for _, s, _ in g.members])
                 if self.autotune:
                     g.batch.autotune(reps=1)
                 rebuilds += 1
             return freed
 
+        def retire(g):
+            # read back the members that finished since the group's last poll (its
+            # steps have finished, so the status read does not wait)
+            if g.batch is None:
+                return
+            _, status = g.batch.status()
+            for (r, s, fp), st in zip(g.members, status):
+                last_status[r.id] = (float(st[2]), int(st[3]), r.t_end)
+                if r.done is None and st[0] == 0.0:
+                    r.done = clock() - t0
+                    r.t, r.steps = float(st[2]), int(st[3])
+                    if st[1] != 0.0:
+                        r.error = "a cell average left the admissible set"
+                    if self.keep_results:
+                        r.result = s.readback()[0]
+                    say(f"request {r.id} done: {r.steps} steps to t = {r.t:.4g}, latency "
+                        f"{r.latency * 1e3:.1f} ms{'' if r.error is None else ', ' + r.error}")
+
+        ready = []                       # prepared, waiting for their group to be idle
         try:
-            while pending or preparing or any(g.active_count() for g in groups.values()):
+            while pending or preparing or ready or any(g.active_count() or g.event is not None
+                                                       for g in groups.values()):
                 now = clock() - t0
                 elapsed = now
                 if elapsed - last_report >= self.progress_every:
@@ -213,7 +250,7 @@ class Server:
                     if held and used + fp > self.budget:
                         freed = 0
                         for g in groups.values():
-                            if any(m[0].done is not None for m in g.members):
+                            if g.idle() and any(m[0].done is not None for m in g.members):
                                 freed += compact(g)
                         used -= freed
                         if freed == 0 or used + fp > self.budget:
@@ -224,68 +261,63 @@ class Server:
                     used += fp
                     say(f"admit request {r.id}: {r.n_cell} cells P{r.k} {r.precision}, t_end {r.t_end:.4g}, "
                         f"{fp / 2**20:.0f} MiB, {used / 2**20:.0f} MiB held")
-                # prepared requests join their group; failed ones finish with their error
-                joined = {p: [] for p in groups}
+                # prepared requests wait for their group; failed ones finish with their error
                 still = []
                 for r, fut, fp in preparing:
                     if not fut.done():
                         still.append((r, fut, fp))
                         continue
                     try:
-                        joined[r.precision].append((r, fut.result(), fp))
+                        ready.append((r, fut.result(), fp))
                     except Exception as e:   # noqa: BLE001 - reported per request
                         r.error = f"admission failed: {e}"
                         r.done = clock() - t0
                         used -= fp
                         say(f"request {r.id} failed in preparation: {e}")
                 preparing = still
-                for p, g in groups.items():
-                    if joined[p]:
-                        used -= compact(g, joined[p])
+                # every group whose last steps have finished: retire the members that
+                # reached their t_end, let the waiting requests join, step again
+                stepped = busy = False
+                for gk, g in groups.items():
+                    if not g.idle():
+                        busy = True
+                        continue
+                    if g.event is not None:
+                        g.event = None
+                        retire(g)
+                    joining = [x for x in ready if key(x[0]) == gk]
+                    if joining:
+                        ready = [x for x in ready if key(x[0]) != gk]
+                        used -= compact(g, joining)
                         now2 = clock() - t0
-                        for r, _, _ in joined[p]:
+                        for r, _, _ in joining:
                             r.joined = now2
-                        say(f"{p} batch rebuilt: joined {[r.id for r, _, _ in joined[p]]}, "
-                            f"members {[m[0].id for m in g.members]}")
+                        say(f"{gk[0]} batch {'small' if gk[1] == 0 else 'large'} rebuilt: joined "
+                            f"{[r.id for r, _, _ in joining]}, members {[m[0].id for m in g.members]}")
                     elif g.members and not g.active_count():
                         used -= compact(g)   # nothing left to step: free the finished ones
-                peak = max(peak, sum(g.active_count() for g in groups.values()))
-                stepped = False
-                for g in groups.values():
                     if g.batch is not None and g.active_count():
-                        g.batch.step(self.steps_per_tick)
+                        with torch.cuda.stream(g.stream):
+                            g.batch.step(self.steps_per_tick)
+                            g.event = torch.cuda.Event()
+                            g.event.record(g.stream)
+                        launched += self.steps_per_tick
                         stepped = True
-                if stepped:
-                    launched += self.steps_per_tick
-                else:
-                    if preparing:
-                        time.sleep(0.0005)
+                peak = max(peak, sum(g.active_count() for g in groups.values()))
+                if not stepped:
+                    if busy or preparing or ready:
+                        time.sleep(0.0002)
                     elif pending:
                         wait = pending[0].arrival - (clock() - t0)
                         if wait > 0:
                             time.sleep(min(wait, 0.01))
-                    continue
-                # retirement: read back the members that finished since the last poll
-                for g in groups.values():
-                    if g.batch is None:
-                        continue
-                    _, status = g.batch.status()
-                    for (r, s, fp), st in zip(g.members, status):
-                        last_status[r.id] = (float(st[2]), int(st[3]), r.t_end)
-                        if r.done is None and st[0] == 0.0:
-                            r.done = clock() - t0
-                            r.t, r.steps = float(st[2]), int(st[3])
-                            if st[1] != 0.0:
-                                r.error = "a cell average left the admissible set"
-                            if self.keep_results:
-                                r.result = s.readback()[0]
-                            say(f"request {r.id} done: {r.steps} steps to t = {r.t:.4g}, latency "
-                                f"{r.latency * 1e3:.1f} ms{'' if r.error is None else ', ' + r.error}")
         finally:
             pool.shutdown(wait=True)
             for r, fut, _ in preparing:          # prepared after a stop: never joined
                 if fut.exception() is None:
                     fut.result().close()
+            for r, sol, _ in ready:
+                sol.close()
             for g in groups.values():
                 if g.batch is not None:
                     g.batch.close()
