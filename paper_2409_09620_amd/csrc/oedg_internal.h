@@ -27,6 +27,9 @@ constexpr int kColBad = kPartCols - 1;   // residual pass: cells whose average l
 // instance's reductions depend only on its own cells, whatever the schedule or
 // the other instances of the launch.
 constexpr int n_groups(int n_cell) { return (n_cell + kGroupCells - 1) / kGroupCells; }
+// a batched pass walks a member's groups as its tiles (halo map, tile-image slots and
+// edge ownership of the mesh precompute are per tile)
+static_assert(kGroupCells == kTileCells, "groups are the tiles");
 
 // Host-side mesh tables built once per mesh (see mesh_host.cpp).  Per-cell arrays
 // that go to the device are structure-of-arrays: component-major, cell fastest.
