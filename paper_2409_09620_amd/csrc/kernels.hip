@@ -1465,9 +1465,11 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
         T od[4];   // the cell's edge vectors: its edges' lengths and normals
         if (live) edge_vectors(xx, xy, ex, ey, od);
 
-        // OE damping rates: ||.||^-1 acc[v][m - 1] = sum over the cell's edges of
-        // sum_{j <= m} beta/h delta^j (eq. OEScalar:Coef2; eqs. RIOESys:Coef1/Coef2),
-        // the rate of the degree-m modes of variable v
+        // OE damping rates: the degree-m modes of variable v decay at the rate
+        // sum_{j <= m} sigma^j = inv_v * acc[v][m - 1], where acc sums over the cell's
+        // edges beta/h A^{k,j} h^j sqrt(S_j / 2) for j <= m (eq. OEScalar:Coef2; eqs.
+        // RIOESys:Coef1/Coef2) and inv_v, the reciprocal of the variable's norm, is the
+        // same for every edge
         T acc[4][K];
 #pragma unroll
         for (int v = 0; v < 4; ++v)
