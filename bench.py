@@ -393,7 +393,7 @@ def main():
                     help="run only the ~1M-cell blast, FP64 and mixed (for counter runs)")
     ap.add_argument("--serving-requests", type=int, default=8, metavar="N",
                     help="serving run with N requests per arrival rate; 0 skips it")
-    ap.add_argument("--serving-rates", type=str, default="1,4", help="arrival rates per second")
+    ap.add_argument("--serving-rates", type=str, default="1,4,16", help="arrival rates per second")
     ap.add_argument("--serving-scale", type=int, default=1, metavar="S",
                     help="serving request sizes 1k-2M divided by S")
     ap.add_argument("--serving-t-scale", type=float, default=1.0,
