@@ -23,7 +23,7 @@
 // its halo of out-of-tile neighbours in LDS before computing it.  The residual's
 // image holds every cell's averages, modes and geometry, from which a neighbour's
 // traces at the edge Gauss points are formed with the basis rows of its local
-// edge (the batched FP64 pass uses the filter's image instead).  The filter's
+// edge (the batched FP64 P2 pass uses the filter's image instead).  The filter's
 // image holds every cell's polynomial as physical monomials about its vertex 0
 // plus the two edge vectors from that vertex, so a neighbour's value, gradient
 // and Hessian at a shared vertex cost a few FMAs.  The filter works every edge
@@ -891,7 +891,7 @@ __device__ constexpr int kResOps[kResCols] = {0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 2
 
 // Img: TileLds<K, T, 5> (the modal image: averages, modes and geometry, the
 // neighbour's traces from the basis rows er) or MonoLds<K, T> (monomials and edge
-// vectors); the batched FP64 pass takes the second, the others the first.
+// vectors); the batched FP64 P2 pass takes the second, the others the first.
 template <int K, typename T, bool kBatch, typename Img>
 __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1, const EdgeRowsLds<K, T>& er, Img& L,
                                              WaveAcc<kResCols>& W) {
