@@ -23,7 +23,8 @@ import numpy as np
 import pytest
 
 import oracle
-from synth import workloads
+from synth import mesh as smesh
+from synth import problems, workloads
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -59,6 +60,9 @@ CASES = {
     "p2_periodic_vortex": lambda: (2,) + workloads.periodic_vortex(n=12),
     "p2_quadrant_3k": lambda: (2,) + workloads.quadrant_delaunay(n_cells=3000, seed=21),
     "p1_quadrant_3k": lambda: (1,) + workloads.quadrant_delaunay(n_cells=3000, seed=22),
+    # fewer cells than a wave
+    "p2_quadrant_40": lambda: (2, smesh.poisson_delaunay(40, seed=27), problems.PROBLEM_QUADRANT,
+                               problems.quadrant_riemann_params(53)),
 }
 
 

@@ -55,12 +55,27 @@ CASES = {
     # cells in random order: most neighbours beyond the tiles' halo cap (global-memory path)
     "p2_quadrant_3k_shuffled": lambda: _shuffled(2, workloads.quadrant_delaunay(n_cells=3000, seed=21), 31),
     "p1_blast_3k_shuffled": lambda: _shuffled(1, workloads.blast_delaunay(n_cells=3000, seed=23), 32),
+    # meshes below one tile and one wave: every edge of the one cell is a boundary
+    # edge; a square cut along its diagonal; 40 cells (a part of a wave); 66 cells
+    # (a wave and two lanes)
+    "p2_quadrant_one_cell": lambda: _quadrant(2, smesh.Mesh(xy=np.array([[0.1, 0.2], [0.9, 0.3], [0.4, 0.8]]),
+                                                             tri=np.array([[0, 1, 2]], np.int32), name="one"), 51),
+    "p1_quadrant_two_cells": lambda: _quadrant(1, smesh.Mesh(xy=np.array([[0.0, 0.0], [1.0, 0.0], [1.0, 1.0],
+                                                                           [0.0, 1.0]]),
+                                                              tri=np.array([[0, 1, 2], [0, 2, 3]], np.int32),
+                                                              name="two"), 52),
+    "p2_quadrant_40": lambda: _quadrant(2, smesh.poisson_delaunay(40, seed=27), 53),
+    "p1_quadrant_66": lambda: _quadrant(1, smesh.poisson_delaunay(60, seed=26), 54),
 }
 
 
 def _shuffled(k, w, seed):
     m, kind, p = w
     return (k, smesh.shuffle_cells(m, seed), kind, p)
+
+
+def _quadrant(k, m, seed):
+    return (k, m, problems.PROBLEM_QUADRANT, problems.quadrant_riemann_params(seed))
 
 
 def make(case, **cfg):
