@@ -128,12 +128,17 @@ void dg_config_default(dg_config* cfg);
 dg_status dg_create(dg_ctx** out, int hip_device, void* hip_stream);
 
 /* Device bytes the library needs for a mesh of n_cell cells at degree k (enough
- * for either precision). */
+ * for either precision).  DG_E_ARG beyond DG_MAX_CELLS(k). */
 dg_status dg_workspace_bytes(int32_t n_cell, int k, size_t* bytes);
 
 /* Hands the library caller-owned device memory (at least dg_workspace_bytes),
  * used by the next dg_mesh_upload instead of its own allocation. */
 dg_status dg_bind_workspace(dg_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Largest mesh at degree k: the kernels address a state buffer (4 variables x
+ * (k+1)(k+2)/2 modes x n_cell doubles) with 32-bit byte offsets, so it stays
+ * below 4 GiB: 44,739,242 cells at P1, 22,369,621 at P2. */
+#define DG_MAX_CELLS(k) ((int32_t)(0xffffffffu / (32u * (unsigned)(((k) + 1) * ((k) + 2) / 2))))
 
 /* Uploads a mesh and builds, on the host, what the paper's notation fixes
  * (Sec. 2 and Sec. 4.3): counter-clockwise orientation, the edge table (local
@@ -151,7 +156,8 @@ dg_status dg_bind_workspace(dg_ctx* ctx, void* dev_ptr, size_t bytes);
  *            vertices 1 and 2, and its tags move with them)
  *   k        degree (1 or 2) the decomposition and the buffers are built for;
  *            dg_init must be called with the same degree
- * Errors: DG_E_ARG, DG_E_MESH (the context is then unusable), DG_E_NOMEM, DG_E_HIP. */
+ * Errors: DG_E_ARG (also n_cell > DG_MAX_CELLS(k)), DG_E_MESH (the context is then
+ * unusable), DG_E_NOMEM, DG_E_HIP. */
 dg_status dg_mesh_upload(dg_ctx* ctx, int k, int32_t n_vert, const double* xy, int32_t n_cell,
                          const int32_t* tri, const double* cell_xy, const int32_t* edge_bc);
 

@@ -28,6 +28,14 @@ DG_LIMITER_USTAR = 1
 LIMITER_FORM = {"nodes": DG_LIMITER_NODES, "ustar": DG_LIMITER_USTAR}
 DG_BC_TRANSMISSIVE = 0
 DG_BC_REFLECTIVE = 1
+
+
+def max_cells(k):
+    """DG_MAX_CELLS(k): the largest mesh at degree k (its FP64 state buffer of
+    4 (k+1)(k+2)/2 doubles per cell stays below 4 GiB)."""
+    return 0xFFFFFFFF // (32 * ((k + 1) * (k + 2) // 2))
+
+
 STATUS = {0: "DG_OK", -1: "DG_E_ARG", -2: "DG_E_MESH", -3: "DG_E_NOMEM", -4: "DG_E_HIP",
           -5: "DG_E_BOUNDS", -6: "DG_E_STATE"}
 

@@ -142,6 +142,32 @@ def periodic_jittered_grid(n: int = 32, length: float = 10.0, jitter: float = 0.
                 meta=dict(n=n, length=length, jitter=jitter, seed=seed, h=h))
 
 
+def tile_periodic_grid(base: Mesh, a: int, b: int) -> Mesh:
+    """a x b copies of a `periodic_jittered_grid` block, itself periodic: block
+    (A, B) is the base shifted by (A L, B L), and block q = A + a B holds cells
+    q n_base ... (q + 1) n_base - 1 in the base's order, each with the base cell's
+    vertex order.  Data periodic with the base's period therefore has, on the
+    tiling, the base's solution in every block."""
+    n, h, L = base.meta["n"], base.meta["h"], base.meta["length"]
+    N, M = n * a, n * b                                  # squares of the tiling
+    cxy = base.cell_xy.reshape(-1, 3, 2)
+    ij = np.rint(cxy / h).astype(np.int64)               # grid indices 0..n of each vertex (jitter < h/2)
+    blk = np.arange(a * b, dtype=np.int64)
+    A, B = blk % a, blk // a
+    I = (A[:, None, None] * n + ij[None, :, :, 0]) % N
+    J = (B[:, None, None] * n + ij[None, :, :, 1]) % M
+    tri = (I + N * J).astype(np.int32).reshape(-1, 3)
+    del I, J
+    shift = np.stack([A * L, B * L], axis=1).astype(np.float64)            # (a b, 2)
+    cell_xy = (cxy[None, :, :, :] + shift[:, None, None, :]).reshape(-1, 6)
+    vi, vj = np.meshgrid(np.arange(N), np.arange(M), indexing="xy")
+    vi, vj = vi.ravel(), vj.ravel()                      # vertex I + N J, row-major in J
+    xy = base.xy[(vi % n) + n * (vj % n)] + np.stack([(vi // n) * L, (vj // n) * L], axis=1)
+    return Mesh(xy=np.ascontiguousarray(xy), tri=np.ascontiguousarray(tri),
+                cell_xy=np.ascontiguousarray(cell_xy), periodic=True,
+                name=f"{base.name}_tiled{a}x{b}", meta=dict(base.meta, tiles=(a, b)))
+
+
 # --------------------------------------------------------------------------- Poisson disk
 
 def _boundary_points(lo, hi, r):

@@ -33,6 +33,28 @@ def test_workspace_bytes():
     assert L.dg_workspace_bytes(10, 3, ctypes.byref(b1)) == -1
 
 
+def test_size_limit():
+    """DG_MAX_CELLS(k) cells are accepted, one more is refused before any array is read."""
+    L = pkg.load_library()
+    text = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                             "oedg.h")).read()
+    assert "#define DG_MAX_CELLS(k) ((int32_t)(0xffffffffu / (32u * (unsigned)(((k) + 1) * ((k) + 2) / 2))))" in text
+    b = ctypes.c_size_t(0)
+    for k, n_max in ((1, 44_739_242), (2, 22_369_621)):
+        assert binding.max_cells(k) == n_max
+        assert n_max * 32 * ((k + 1) * (k + 2) // 2) < 2 ** 32 <= (n_max + 1) * 32 * ((k + 1) * (k + 2) // 2)
+        assert L.dg_workspace_bytes(n_max, k, ctypes.byref(b)) == 0
+        assert L.dg_workspace_bytes(n_max + 1, k, ctypes.byref(b)) == -1
+    h = ctypes.c_void_p()
+    assert L.dg_create(ctypes.byref(h), -1, None) == 0
+    n = binding.max_cells(2) + 1
+    tri = np.zeros((n, 3), np.int32)
+    xy = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    assert L.dg_mesh_upload(h, 2, 3, binding._ptr(xy), n, binding._ptr(tri), None, None) == -1
+    assert b"too large" in L.dg_last_error(h)
+    L.dg_destroy(h)
+
+
 def _meshes():
     return [("periodic", smesh.periodic_jittered_grid(n=7, seed=4)),
             ("delaunay", smesh.poisson_delaunay(900, seed=12)),
