@@ -124,7 +124,8 @@ class Oracle:
         lib().orc_set_limiter_form(h, 1 if limiter_form == "ustar" else 0)
 
     def __del__(self):
-        if getattr(self, "h", None):
+        # at interpreter exit the module's globals may already be gone
+        if getattr(self, "h", None) and callable(lib):
             lib().orc_destroy(self.h)
             self.h = None
 
