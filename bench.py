@@ -425,7 +425,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the stage is not sharded across GPUs in this build.", file=sys.stderr)
+              "the stage runs on one GPU and is not sharded across GPUs.", file=sys.stderr)
         sys.exit(2)
 
     from synth import workloads

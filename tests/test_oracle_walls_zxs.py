@@ -181,7 +181,7 @@ def _mirrored(m):
 def test_wall_is_the_method_of_images(k):
     """Reflective wall on y = 0 versus the mirror-symmetric problem on the doubled
     domain (mirrored mesh, m2 reversed): every step of the scheme without the OE filter
-    (whose wall jump is zero by this build's reading, while the mirror has a jump)
+    (whose jump at a wall is zero in the reading both codes take, while the mirror has a jump)
     maps the one onto the other, so the upper halves agree to round-off."""
     half, _, _ = workloads.quadrant_delaunay(n_cells=700, seed=37)
     full = _mirrored(half)
