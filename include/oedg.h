@@ -200,7 +200,9 @@ dg_status dg_stage(dg_ctx* ctx, int s);
  * dg_create (or at the first call on the device).  The passes size their grids
  * by occupancy, at most 4096 workgroups, so every mesh fits; a grid beyond the
  * array returns DG_E_ARG.  Every workgroup writes its whole record before the
- * reduction reads it, so nothing needs clearing between calls.
+ * reduction reads it (the passes of a step skipped after an inadmissible stage
+ * write none, and their reductions then use none of what they read), so nothing
+ * needs clearing between calls.
  *   The call performs no hipMalloc, hipFree or other allocation and does not
  * synchronise.  All calls on one GPU share its array: calls that overlap on
  * that GPU (other streams, other host threads, other contexts) race and give
