@@ -2008,19 +2008,21 @@ __device__ __forceinline__ void reduce_columns(const double* base, size_t cstrid
 
 // The finalize kernels read the scalars they need before the reduction, so that
 // their loads overlap it instead of following one another in thread 0 after it;
-// an inactive instance's records are reduced and dropped.
+// an inactive or skipped instance's records are reduced and dropped.
 
 // domain averages and L-infinity norms (eq. normOmg): ||u - ubar|| = max(max u - ubar, ubar - min u)
 // and ||| m - mbar |||_inf (eqs. normOmg, RIOESys:Coef1) with its zero branch.
 // An inadmissible average ends this attempt of the step: `skip` turns the rest
 // of it into no-ops (u^n is untouched) until the third stage's finalize.
 __device__ __forceinline__ void fin_residual(const double* base, size_t cstride, int G, Glob* g) {
-    const int active = g->active;
+    const int active = g->active, skip = g->skip;
     const double area_sum = g->area_sum;
     // 4 sums, 4 mins, 4 maxima, the max of |m - mbar|^2, then the bad-average count
     double tot[kNumPartial + 2];
     reduce_columns<kNumPartial + 2>(base, cstride, G, 0, 0x2AA5500u, tot, kColBad);
-    if (threadIdx.x != 0 || !active) return;
+    // skipped (an earlier stage of this attempt failed): the pass wrote no records,
+    // and the domain values of the last state it did run stay in place
+    if (threadIdx.x != 0 || !active || skip) return;
     if (tot[kNumPartial + 1] > 0.0) g->skip = 1;
     double ub[4];
 #pragma unroll
