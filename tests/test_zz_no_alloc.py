@@ -65,3 +65,28 @@ def test_noalloc_rejects_bad_stage():
     with pytest.raises(Exception):
         s.stage_noalloc(3)
     s.close()
+
+
+def test_skipped_stages_keep_their_domain_values():
+    """A stage that leaves the admissible set makes the rest of its attempt skip
+    their passes; their reductions then read whatever the shared array holds (here
+    another context's records, written in between) and must leave this context's
+    domain averages and norms as dg_stage leaves them."""
+    m, kind, p = workloads.blast_delaunay(n_cells=3000, seed=23)
+    a, b = _pair(m, 2, kind, p, c_ssp=4.0)
+    mo, kind_o, p_o = workloads.quadrant_delaunay(n_cells=5000, seed=44)
+    other = Solver(mo, 2)
+    other.init_problem(kind_o, p_o)
+    say(f"[gpu case] noalloc skipped stages, blast cells={m.n_cell}, other cells={mo.n_cell}")
+    for it in range(4):
+        for s in range(3):
+            a.stage(s)
+            b.stage_noalloc(s)
+            other.stage_noalloc(s)
+            da, db = a.diag(), b.diag()
+            assert da["ubar"] == db["ubar"] and da["nrm"] == db["nrm"] and da["nrm_m"] == db["nrm_m"], (it, s)
+    assert a.diag()["n_restarts"] >= 1 and b.diag()["n_restarts"] == a.diag()["n_restarts"]
+    for which in (0, 1, 2):
+        assert np.array_equal(a.read_state(which), b.read_state(which)), which
+    for s in (a, b, other):
+        s.close()
