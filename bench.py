@@ -389,6 +389,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work per CPU figure")
     ap.add_argument("--only-serving", action="store_true", help="run the serving workload alone")
+    ap.add_argument("--only-largest", action="store_true",
+                    help="run only the largest P2 mesh (22,368,256 periodic cells), FP64 and mixed")
     ap.add_argument("--only-blast", action="store_true",
                     help="run only the ~1M-cell blast, FP64 and mixed (for counter runs)")
     ap.add_argument("--serving-requests", type=int, default=8, metavar="N",
@@ -437,7 +439,7 @@ def main():
     # spawned processes)
     t_build = time.perf_counter()
     tasks = []
-    only = args.only_blast or args.only_serving
+    only = args.only_blast or args.only_serving or args.only_largest
     if not only:
         tasks.append((workloads.quadrant_delaunay, (args.cells,)))
     if (args.blast_steps > 0 and not only) or args.only_blast:
@@ -447,7 +449,7 @@ def main():
         tasks += btasks
     else:
         btasks, bdeg = [], []
-    if not args.only_blast and args.serving_requests > 0:
+    if not (args.only_blast or args.only_largest) and args.serving_requests > 0:
         sspecs, stasks = serving_tasks(args.serving_requests, args.serving_scale, args.serving_t_scale)
         tasks += stasks
     else:
@@ -493,6 +495,12 @@ def main():
 
     if args.only_blast:
         print(json.dumps({"blast": blast(max(args.steps, 1))}), flush=True)
+        return
+    if args.only_largest:
+        lm, lk, lp = workloads.largest_periodic()
+        log(f"largest mesh: {lm.n_cell} cells, {max(args.steps, 1)} steps per precision")
+        print(json.dumps({"largest": {pr: dict(measure(lm, lk, lp, pr, max(args.steps, 1), 2, "p2_periodic_vortex_22m"),
+                                               cells=lm.n_cell) for pr in ("fp64", "mixed")}}), flush=True)
         return
     if args.only_serving:
         rates = [float(x) for x in args.serving_rates.split(",") if x]

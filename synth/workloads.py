@@ -11,11 +11,14 @@
 * implosion          the implosion quadrant [0,0.3]^2 with reflective walls, low state
                      in x + y <= 0.15 (Example EulerImp), optionally turned clockwise
                      by pi/4 with its data (the rotation-invariance test)
+* largest_periodic   86 x 127 copies of the periodic vortex block: 22,368,256 cells,
+                     the most whole blocks within the largest P2 mesh (22,369,621 cells,
+                     a state buffer below 4 GiB), vortex data
 """
 
 import numpy as np
 
-from .mesh import periodic_jittered_grid, poisson_delaunay, find_vertex
+from .mesh import periodic_jittered_grid, poisson_delaunay, find_vertex, tile_periodic_grid
 from .problems import (PROBLEM_VORTEX, PROBLEM_QUADRANT, PROBLEM_BLAST, PROBLEM_TWO_STATE,
                        vortex_params, quadrant_riemann_params, blast_params, two_state_params)
 from .rng import Stream
@@ -24,6 +27,11 @@ from .rng import Stream
 def periodic_vortex(n=32, seed=1):
     m = periodic_jittered_grid(n=n, length=10.0, jitter=0.1, seed=seed)
     return m, PROBLEM_VORTEX, vortex_params()
+
+
+def largest_periodic(seed=1):
+    base = periodic_jittered_grid(n=32, length=10.0, jitter=0.1, seed=seed)
+    return tile_periodic_grid(base, 86, 127), PROBLEM_VORTEX, vortex_params()
 
 
 def quadrant_delaunay(n_cells=200_000, seed=2):
