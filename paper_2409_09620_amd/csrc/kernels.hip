@@ -409,20 +409,43 @@ __device__ __forceinline__ TileWalk chunk_walk(const ChunkSplit& cs) {
     return {cs.b[x] + r, cs.b[x + 1], per_x};
 }
 
+// Wave reductions over the 64 lanes (all active) by DPP: within each row of 16
+// lanes two quad permutes and two rotations leave the row's result in every lane,
+// then the two row broadcasts of gfx9 carry rows 0 and 2 into rows 1 and 3 and
+// rows 0-1 into rows 2-3, so lane 63 holds the result, which every lane reads.
+// No LDS traffic, and a fixed order of operations (deterministic results).
+// DPP moves 32 bits: a double goes as its two halves; the rows a broadcast does
+// not write receive `fill`, the operation's identity.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ double dpp_d(double v, double fill) {
+    const long long b = __builtin_bit_cast(long long, v), f = __builtin_bit_cast(long long, fill);
+    const int lo = __builtin_amdgcn_update_dpp((int)f, (int)b, Ctrl, RowMask, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(f >> 32), (int)(b >> 32), Ctrl, RowMask, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+__device__ __forceinline__ double lane63(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+template <typename Op>
+__device__ __forceinline__ double wave_reduce(double v, double ident, Op op) {
+    v = op(v, dpp_d<0xB1, 0xF>(v, ident));    // quad_perm [1,0,3,2]
+    v = op(v, dpp_d<0x4E, 0xF>(v, ident));    // quad_perm [2,3,0,1]
+    v = op(v, dpp_d<0x124, 0xF>(v, ident));   // row_ror:4
+    v = op(v, dpp_d<0x128, 0xF>(v, ident));   // row_ror:8
+    v = op(v, dpp_d<0x142, 0xA>(v, ident));   // row_bcast:15 into rows 1 and 3
+    v = op(v, dpp_d<0x143, 0xC>(v, ident));   // row_bcast:31 into rows 2 and 3
+    return lane63(v);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return wave_reduce(v, 0.0, [](double a, double b) { return a + b; });
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    return wave_reduce(v, -INFINITY, [](double a, double b) { return fmax(a, b); });
 }
 __device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
+    return wave_reduce(v, INFINITY, [](double a, double b) { return fmin(a, b); });
 }
 
 // Raw buffer access.  Every load and store of the two passes goes through a
@@ -1984,11 +2007,7 @@ __device__ __forceinline__ void reduce_columns(const double* base, size_t cstrid
             for (int i = 0; i < kBatchLoads; ++i)
                 acc = op == 0 ? acc + x[i] : (op == 1 ? fmin(acc, x[i]) : fmax(acc, x[i]));
         }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const double y = __shfl_xor(acc, o, 64);
-            acc = op == 0 ? acc + y : (op == 1 ? fmin(acc, y) : fmax(acc, y));
-        }
+        acc = op == 0 ? wave_sum(acc) : (op == 1 ? wave_min(acc) : wave_max(acc));
         if (lane == 0) lds[w] = acc;
     }
     __syncthreads();
