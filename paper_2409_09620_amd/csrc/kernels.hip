@@ -996,16 +996,17 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
         double part[kResCols];
 #pragma unroll
         for (int k = 0; k < kResCols; ++k) part[k] = acc_ident(kResOps[k]);
+        // mode 0 accumulates in FP64 in both forms (its volume term is zero)
+        double r0[4] = {0.0, 0.0, 0.0, 0.0};
+        T r[4][NM];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int l = 0; l < NM; ++l) r[v][l] = (T)0.0;
+        double area = 0.0;
         if (live) {
             const T xx = geo[0], xy = geo[1], ex = geo[2], ey = geo[3], areaT = geo[4];
-            const double area = mv.A(c8);
-            // mode 0 accumulates in FP64 in both forms (its volume term is zero)
-            double r0[4] = {0.0, 0.0, 0.0, 0.0};
-            T r[4][NM];
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-#pragma unroll
-                for (int l = 0; l < NM; ++l) r[v][l] = (T)0.0;
+            area = mv.A(c8);
 
             // volume term |K| sum_mu w_mu F(u).grad Psi_l with grad Psi = J^{-T} grad_ref Psi,
             // i.e. dPsi/dxi (F.grad xi) + dPsi/deta (F.grad eta)
@@ -1245,7 +1246,11 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
                     }
                 }
             }
-
+        }
+        // the tile's last read of the image: from here a wave may go on to the next
+        // tile (a batched tile keeps its barrier at the end, before its record flush)
+        if constexpr (!kBatch) __syncthreads();
+        if (live) {
             // diagonal mass a_K^(l) = |K| (a_l/|K|), then the SSP-RK3 combination; the
             // average in FP64, the higher modes in the bulk type
             const double ia = frcp(area);
@@ -1309,7 +1314,8 @@ __device__ __forceinline__ void residual_run(const StageArgs& a, int g0, int g1,
             part[12] = cnm;
         }
         wave_acc_add<kResCols>(W, ops, part, par);
-        __syncthreads();   // the tile image is rewritten by the next tile
+        // a batched tile's record is flushed next, and the image rewritten by the next tile
+        if constexpr (kBatch) __syncthreads();
     };
     walk_tiles<kBatch>(
         a, g0, g1, tile_body, [&](int par) { wave_acc_reset<kResCols>(W, ops, par); },
@@ -1766,6 +1772,9 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
                     for (int m = 0; m < K; ++m) acc[2][m] = acc[1][m];
                 }
             }
+            // the tile's last read of the image: from here a wave may go on to the next
+            // tile (a batched tile keeps its barrier at the end, before its record flush)
+            if constexpr (!kBatch) __syncthreads();
         }
         if (live) {
             if (oe) {
@@ -1946,9 +1955,8 @@ __device__ __forceinline__ void filter_run(const StageArgs& a, int g0, int g1, M
             }
         }
         wave_acc_add<kFilCols>(W, ops, part, par);
-        // the tile image is rewritten by the next tile; a batched tile's record is
-        // flushed next
-        if (oe || kBatch) __syncthreads();
+        // a batched tile's record is flushed next, and the image rewritten by the next tile
+        if constexpr (kBatch) __syncthreads();
     };
     walk_tiles<kBatch>(
         a, g0, g1, tile_body, [&](int par) { wave_acc_reset<kFilCols>(W, ops, par); },
