@@ -13,6 +13,7 @@ Workloads (every mesh is built before the GPU is touched, in spawned processes):
   averages and limiter; "mixed");
 * "blast": the near-vacuum blast on a ~1M-cell mesh, FP64 and mixed, each with its
   own roofline object (its state does not fit the 256 MB Infinity Cache);
+* "largest": the largest P2 mesh (22,368,256 periodic cells), FP64 and mixed;
 * "batch": 64 uneven P1/P2 instances stepped as one batch (full sizes by default);
 * "serving": the continuous-batching server on a Poisson request stream of
   1k-2M-cell requests at two arrival rates (p50/p99 latency, aggregate DOF-stage/s);
@@ -391,6 +392,8 @@ def main():
     ap.add_argument("--only-serving", action="store_true", help="run the serving workload alone")
     ap.add_argument("--only-largest", action="store_true",
                     help="run only the largest P2 mesh (22,368,256 periodic cells), FP64 and mixed")
+    ap.add_argument("--largest-steps", type=int, default=5,
+                    help="timed steps of the largest P2 mesh per precision; 0 skips it")
     ap.add_argument("--only-blast", action="store_true",
                     help="run only the ~1M-cell blast, FP64 and mixed (for counter runs)")
     ap.add_argument("--serving-requests", type=int, default=8, metavar="N",
@@ -496,11 +499,14 @@ def main():
     if args.only_blast:
         print(json.dumps({"blast": blast(max(args.steps, 1))}), flush=True)
         return
-    if args.only_largest:
+    def largest(steps):
         lm, lk, lp = workloads.largest_periodic()
-        log(f"largest mesh: {lm.n_cell} cells, {max(args.steps, 1)} steps per precision")
-        print(json.dumps({"largest": {pr: dict(measure(lm, lk, lp, pr, max(args.steps, 1), 2, "p2_periodic_vortex_22m"),
-                                               cells=lm.n_cell) for pr in ("fp64", "mixed")}}), flush=True)
+        log(f"largest mesh: {lm.n_cell} cells, {steps} steps per precision")
+        return {pr: dict(measure(lm, lk, lp, pr, steps, 2, "p2_periodic_vortex_22m"), cells=lm.n_cell, steps=steps)
+                for pr in ("fp64", "mixed")}
+
+    if args.only_largest:
+        print(json.dumps({"largest": largest(max(args.steps, 1))}), flush=True)
         return
     if args.only_serving:
         rates = [float(x) for x in args.serving_rates.split(",") if x]
@@ -538,6 +544,8 @@ def main():
     }
     if blastw is not None:
         out["blast"] = blast(args.blast_steps)
+    if args.largest_steps > 0:
+        out["largest"] = largest(args.largest_steps)
     if not args.no_copy_bandwidth:
         out["measured_copy_bandwidth"] = copy_bandwidth()
     if not args.no_decompositions:
